@@ -1,0 +1,145 @@
+/*
+ * cgd.h -- coarse-grained (binned) photon-number distributions of Gaussian
+ * states on one AMD Instinct MI355X (gfx950).  C ABI, C99.
+ *
+ * What is computed (arXiv:2412.17742):
+ *   For a Gaussian state of M external modes, each carrying K internal
+ *   (Schmidt) modes, measured by detectors grouped into L bins, the
+ *   probability generating function of the bin counts is
+ *       G(w) = sum_b Pr(b) prod_l w_l^{b_l} = Pr(0) q(A, gamma, w)
+ *   (Eq. Lamb_lhaf_master times the vacuum probability, Eq. vacuum_probability;
+ *   q in closed form, Eq. q_d).  The library evaluates G at every point of the
+ *   roots-of-unity grid w_l = exp(2 pi i k_l / G_l) -- one complex determinant
+ *   det[I - D(w) X A] with the square-root branch continuous from w = 0, times
+ *   the displacement exponential -- and inverts the grid with an L-dimensional
+ *   DFT (the finite-difference sieve of Sec. V with roots-of-unity nodes).
+ *   The result is the wrapped distribution
+ *       P(b) = sum_{m >= 0} Pr(b + m o G),   b_l in [0, cutoff_l],
+ *   which equals the exact binned probability Pr(b) of Eq. coarse_grained_prob
+ *   when the probability mass beyond the grid is negligible; choose G_l large
+ *   enough for that, or accept the wrap.
+ *
+ * State model (Sec. II, Sec. VI B, Sec. VIII A):
+ *   input j, internal mode k is a single-mode squeezed vacuum with squeezing
+ *   r_jk, where tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j (the two-mode
+ *   relation Eq. relation_between_sqz_par generalised to K modes), displaced
+ *   by alpha_j on internal mode 0 only; the interferometer a_out = T a_in acts
+ *   identically on every internal mode; internal modes never interfere.
+ *
+ * Conventions common to every call:
+ *   - complex numbers are interleaved (re, im) pairs of double;
+ *   - matrices are row-major;
+ *   - host pointers are read only during the call; the caller keeps ownership;
+ *   - device pointers are plain HIP device allocations owned by the caller
+ *     (e.g. torch tensor data_ptr()); work is enqueued on the context's stream
+ *     and is asynchronous with respect to the host;
+ *   - no call throws or exits; each returns a cgd_status and, on failure,
+ *     cgd_last_error() describes it.
+ */
+#ifndef CGD_H
+#define CGD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgd_ctx cgd_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    CGD_OK = 0,
+    CGD_ERR_ARG = 1,         /* invalid argument (sizes, indices, NULLs, unsupported shape) */
+    CGD_ERR_NONPHYSICAL = 2, /* ||T||_2 > 1, r < 0, bad Schmidt weights: not a valid state  */
+    CGD_ERR_NUMERIC = 3,     /* a pivot left the right half-plane or a value was not finite  */
+    CGD_ERR_DEVICE = 4,      /* a HIP runtime call failed                                    */
+    CGD_ERR_NOMEM = 5,       /* host or device allocation failed                             */
+    CGD_ERR_STATE = 6        /* call order violated (e.g. grad before eval)                  */
+} cgd_status;
+
+typedef enum {
+    CGD_PREC_FP64 = 0,  /* complex128 factorisations everywhere                          */
+    CGD_PREC_MIXED = 1  /* complex64 factorisations with an FP64 log-det correction where
+                           the grid value is large enough to matter (see cgd_create tol) */
+} cgd_precision;
+
+/* cgd_create flags */
+#define CGD_FLAG_DENSE_INTERNAL 1u /* keep all K internal modes in one 2MK x 2MK matrix
+                                      instead of K independent 2M x 2M blocks (the two
+                                      give the same determinant; for testing/measurement) */
+#define CGD_FLAG_NO_SCHUR 2u       /* evaluate every grid point with a full factorisation
+                                      instead of reusing the first bin's eigenbasis */
+
+/* One instance (a Gaussian state plus its binning).  Sec. VI A (set partition
+ * Lambda, coarse pattern b), Sec. VI B (internal modes). */
+typedef struct {
+    int32_t M;               /* external modes, >= 1                                          */
+    int32_t K;               /* internal (Schmidt) modes per external mode, >= 1              */
+    int32_t L;               /* bins, 1..8                                                    */
+    const double *T;         /* M*M complex: a_out[i] = sum_j T[i*M+j] a_in[j]; ||T||_2 <= 1  */
+    const double *r;         /* M squeezing parameters >= 0 (internal mode 0)                 */
+    const double *alpha;     /* M complex displacements of internal mode 0, or NULL (zero)    */
+    const double *schmidt;   /* K weights > 0 summing to 1, lambda_k <= lambda_0; NULL iff K==1 */
+    const int32_t *bin_of;   /* bin index in [0, L) or -1 (not measured) per mode: M entries
+                                (external modes) or M*K entries (index i*K+k) if
+                                resolve_internal != 0                                          */
+    int32_t resolve_internal;/* 0: detectors see external modes; 1: bins over (i, k) pairs     */
+    const int32_t *cutoff;   /* L entries N_l >= 0: output box b_l in [0, N_l]                */
+    const int32_t *grid;     /* L entries G_l >= N_l + 1, or NULL for G_l = N_l + 1           */
+} cgd_instance;
+
+/* Assemble the states (FP64, host) and upload everything the evaluation
+ * needs.  n_inst instances are evaluated together by cgd_eval.
+ *   prec        CGD_PREC_FP64 or CGD_PREC_MIXED
+ *   tol         absolute error budget per probability for the mixed path (e.g.
+ *               1e-9); ignored for FP64
+ *   flags       0 or CGD_FLAG_* bits
+ *   hip_stream  hipStream_t to enqueue on, or NULL for the null stream
+ * Errors: CGD_ERR_ARG / CGD_ERR_NONPHYSICAL synchronously, before any launch.
+ * On failure *out is set to NULL. */
+cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst,
+                      cgd_precision prec, double tol, uint32_t flags, void *hip_stream);
+
+/* Sizes of the outputs.  n_probs_total = sum_i prod_l (N_l + 1);
+ * prob_offsets (n_inst + 1 entries, may be NULL) gives each instance's first
+ * probability; n_grid_total (may be NULL) is the number of grid points whose
+ * values are produced (sum_i prod_l G_l).  Probabilities are row-major over
+ * (b_1, ..., b_L) with b_L fastest. */
+cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_offsets,
+                      int64_t *n_grid_total);
+
+/* Evaluate the wrapped distributions of all instances into d_probs (device,
+ * n_probs_total doubles).  d_err_bound (device, n_inst doubles, or NULL)
+ * receives, per instance, the largest |imaginary part| left by the inverse
+ * DFT (a rounding witness; +inf after a numeric failure).  A numeric failure
+ * detected on the device is reported by the next call as CGD_ERR_NUMERIC. */
+cgd_status cgd_eval(cgd_ctx *ctx, double *d_probs, double *d_err_bound);
+
+/* Diagnostic: after cgd_eval, copy log G(w) (complex) at the evaluated grid
+ * points into d_logg (device, 2 * cgd_points(ctx) doubles).  Points are
+ * instance by instance; within an instance k_1 runs over [0, G_1/2] (the other
+ * half follows from G(conj w) = conj G(w)) and k_2..k_L over [0, G_l), row-major
+ * with k_L fastest. */
+int64_t    cgd_points(const cgd_ctx *ctx);
+cgd_status cgd_grid_values(cgd_ctx *ctx, double *d_logg);
+
+/* Gradient of a real loss with respect to the inputs, given dLoss/dP.
+ * Requires a preceding cgd_eval on the same context (CGD_ERR_STATE otherwise)
+ * and the FP64 precision.  Outputs (device, may be NULL each):
+ *   d_dr      sum_i M_i doubles               dLoss/dr
+ *   d_dT      sum_i M_i*M_i complex            dLoss/dRe T + i dLoss/dIm T
+ *   d_dalpha  sum_i M_i complex                dLoss/dRe alpha + i dLoss/dIm alpha
+ * d log det S = tr(S^-1 dS) with the factorisations of the evaluation
+ * recomputed per grid point. */
+cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *d_dT,
+                    double *d_dalpha);
+
+void cgd_destroy(cgd_ctx *ctx);
+
+/* Message of the last failure on this thread (valid until the next call). */
+const char *cgd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGD_H */

@@ -1,0 +1,178 @@
+"""Coarse-grained photon-number distributions of Gaussian states on MI355X.
+
+Thin Python binding over the C ABI of libcgd.so (include/cgd.h): argument
+marshalling only.  Every step of the evaluation runs in the library's HIP
+kernels; PyTorch supplies device memory and the stream.  There is no CPU
+fallback: if the library is missing, importing the binding succeeds but every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgd.so")
+
+CGD_OK, CGD_ERR_ARG, CGD_ERR_NONPHYSICAL, CGD_ERR_NUMERIC, CGD_ERR_DEVICE, CGD_ERR_NOMEM, CGD_ERR_STATE = range(7)
+STATUS_NAMES = ["CGD_OK", "CGD_ERR_ARG", "CGD_ERR_NONPHYSICAL", "CGD_ERR_NUMERIC", "CGD_ERR_DEVICE",
+                "CGD_ERR_NOMEM", "CGD_ERR_STATE"]
+PREC_FP64, PREC_MIXED = 0, 1
+FLAG_DENSE_INTERNAL = 1
+FLAG_NO_SCHUR = 2
+
+
+class CgdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {message}")
+
+
+class CgdInstance(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int32), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
+        ("T", ctypes.c_void_p), ("r", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+        ("schmidt", ctypes.c_void_p), ("bin_of", ctypes.c_void_p),
+        ("resolve_internal", ctypes.c_int32),
+        ("cutoff", ctypes.c_void_p), ("grid", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcgd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2412_17742_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.cgd_create.restype = i32
+    L.cgd_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(CgdInstance), i32, i32, ctypes.c_double,
+                             ctypes.c_uint32, vp]
+    L.cgd_layout.restype = i32
+    L.cgd_layout.argtypes = [vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64)]
+    L.cgd_eval.restype = i32
+    L.cgd_eval.argtypes = [vp, vp, vp]
+    L.cgd_points.restype = i64
+    L.cgd_points.argtypes = [vp]
+    L.cgd_grid_values.restype = i32
+    L.cgd_grid_values.argtypes = [vp, vp]
+    L.cgd_grad.restype = i32
+    L.cgd_grad.argtypes = [vp, vp, vp, vp, vp]
+    L.cgd_destroy.restype = None
+    L.cgd_destroy.argtypes = [vp]
+    L.cgd_last_error.restype = ctypes.c_char_p
+    L.cgd_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != CGD_OK:
+        raise CgdError(status, lib().cgd_last_error().decode())
+
+
+def _as(arr, dtype):
+    return None if arr is None else np.ascontiguousarray(arr, dtype=dtype)
+
+
+def _marshal(inst: dict, keep: list) -> CgdInstance:
+    T = _as(inst["T"], np.complex128)
+    M = T.shape[0]
+    K = 1 if inst.get("schmidt") is None else len(inst["schmidt"])
+    arrays = dict(
+        T=T, r=_as(inst["r"], np.float64), alpha=_as(inst.get("alpha"), np.complex128),
+        schmidt=_as(inst.get("schmidt"), np.float64), bin_of=_as(inst["bin_of"], np.int32),
+        cutoff=_as(inst["cutoff"], np.int32), grid=_as(inst.get("grid"), np.int32),
+    )
+    keep.append(arrays)
+    ptr = {k: (None if v is None else v.ctypes.data) for k, v in arrays.items()}
+    return CgdInstance(M, K, len(arrays["cutoff"]), ptr["T"], ptr["r"], ptr["alpha"], ptr["schmidt"],
+                       ptr["bin_of"], int(inst.get("resolve_internal", 0)), ptr["cutoff"], ptr["grid"])
+
+
+class Context:
+    """A batch of instances prepared on the device (cgd_create)."""
+
+    def __init__(self, instances, precision: str = "fp64", tol: float = 1e-9, flags: int = 0, stream=None):
+        import torch
+        if isinstance(instances, dict):
+            instances = [instances]
+        L = lib()
+        keep: list = []
+        arr = (CgdInstance * len(instances))(*[_marshal(x, keep) for x in instances])
+        prec = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        _check(L.cgd_create(ctypes.byref(handle), arr, len(instances), prec, float(tol), int(flags),
+                            ctypes.c_void_p(stream.cuda_stream)))
+        self._h = handle
+        self.n_inst = len(instances)
+        n = ctypes.c_int64()
+        ng = ctypes.c_int64()
+        offs = np.zeros(self.n_inst + 1, dtype=np.int64)
+        _check(L.cgd_layout(self._h, ctypes.byref(n), offs.ctypes.data, ctypes.byref(ng)))
+        self.n_probs = n.value
+        self.prob_offsets = offs
+        self.n_grid = ng.value
+        self.n_points = L.cgd_points(self._h)
+        self.shapes = [tuple(int(c) + 1 for c in x["cutoff"]) for x in instances]
+
+    def eval(self, probs=None, err=None):
+        """Wrapped distributions of all instances, concatenated (device float64)."""
+        import torch
+        if probs is None:
+            probs = torch.empty(self.n_probs, dtype=torch.float64, device="cuda")
+        assert probs.dtype == torch.float64 and probs.is_cuda and probs.numel() >= self.n_probs
+        assert probs.is_contiguous()
+        if err is not None:
+            assert err.dtype == torch.float64 and err.is_cuda and err.numel() >= self.n_inst
+        _check(lib().cgd_eval(self._h, ctypes.c_void_p(probs.data_ptr()),
+                              None if err is None else ctypes.c_void_p(err.data_ptr())))
+        return probs
+
+    def split(self, probs):
+        """Split the concatenated output into one array per instance (reshaped to the box)."""
+        return [probs[self.prob_offsets[i]:self.prob_offsets[i + 1]].reshape(self.shapes[i])
+                for i in range(self.n_inst)]
+
+    def grid_values(self):
+        """log G at the evaluated grid points (complex128 device tensor)."""
+        import torch
+        out = torch.empty(2 * self.n_points, dtype=torch.float64, device="cuda")
+        _check(lib().cgd_grid_values(self._h, ctypes.c_void_p(out.data_ptr())))
+        return torch.view_as_complex(out.view(-1, 2))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cgd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def binned_distribution(instances, precision: str = "fp64", tol: float = 1e-9, flags: int = 0):
+    """Evaluate and return one float64 device tensor per instance."""
+    with Context(instances, precision, tol, flags) as ctx:
+        probs = ctx.eval()
+        import torch
+        torch.cuda.current_stream().synchronize()
+        return [p.clone() for p in ctx.split(probs)]

@@ -1,0 +1,720 @@
+// Host side of the C ABI: validation, FP64 state assembly (once per
+// instance), device layout of the per-point factorisation jobs, and the launch
+// sequence of an evaluation.  All per-grid-point work runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cgd.h"
+#include "cgd_internal.h"
+#include "host_linalg.h"
+
+using namespace cgd;
+
+namespace {
+
+thread_local std::string g_err;
+
+cgd_status fail(cgd_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_OK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(CGD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Per-block product of the host assembly.
+struct HostBlock {
+    int inst = 0, blk = 0;
+    int nb = 0;                 // order of the matrix factorised per point
+    int bordered = 0;
+    std::vector<int32_t> rowbin;
+    CMat H;                     // nb x nb: the matrix itself, or H_BB under elimination
+    int schur_axis = -1;        // eliminated bin
+    std::vector<double> eig;    // its eigenvalues
+    CMat P, Q;                  // H_BA V and V^H H_AB
+};
+
+struct HostInst {
+    int L = 1;
+    int G[kMaxBins] = {0}, N[kMaxBins] = {0};
+    double logpr0 = 0.0;
+    int nblocks = 0;
+};
+
+cplx cx(const double *p, size_t i) { return cplx(p[2 * i], p[2 * i + 1]); }
+
+// Largest eigenvalue of T^H T (||T||_2^2).
+bool spectral_norm_sq(const double *T, int M, double &out) {
+    CMat A(M, M);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) A(i, j) = cx(T, (size_t)i * M + j);
+    CMat G = matmul(adjoint(A), A);
+    std::vector<double> lam;
+    CMat V;
+    if (!hermitian_eig(G, lam, V)) return false;
+    out = *std::max_element(lam.begin(), lam.end());
+    return true;
+}
+
+// Rows [0, 2m) of a block: mode index within the block -> bin.
+int bin_of_row(const cgd_instance &in, int row, int m, const std::vector<int> &kset, bool dense) {
+    const int mode = row % m;
+    int i, k;
+    if (dense) { i = mode / in.K; k = mode % in.K; }
+    else { i = mode; k = kset[0]; }
+    return in.resolve_internal ? in.bin_of[i * in.K + k] : in.bin_of[i];
+}
+
+cgd_status validate(const cgd_instance &in, int idx) {
+    const std::string at = "instance " + std::to_string(idx) + ": ";
+    if (in.M < 1 || in.K < 1 || in.L < 1 || in.L > kMaxBins) return fail(CGD_ERR_ARG, at + "need M >= 1, K >= 1, 1 <= L <= 8");
+    if ((int64_t)in.M * in.K > 4096) return fail(CGD_ERR_ARG, at + "M*K too large");
+    if (!in.T || !in.r || !in.bin_of || !in.cutoff) return fail(CGD_ERR_ARG, at + "T, r, bin_of and cutoff are required");
+    if (in.K > 1 && !in.schmidt) return fail(CGD_ERR_ARG, at + "schmidt weights required when K > 1");
+    for (int i = 0; i < in.M * in.M * 2; ++i)
+        if (!std::isfinite(in.T[i])) return fail(CGD_ERR_ARG, at + "T not finite");
+    for (int i = 0; i < in.M; ++i) {
+        if (!std::isfinite(in.r[i]) || in.r[i] < 0) return fail(CGD_ERR_NONPHYSICAL, at + "squeezing must be finite and >= 0");
+        if (in.r[i] > 12.0) return fail(CGD_ERR_ARG, at + "squeezing above 12 is not supported");
+    }
+    if (in.alpha)
+        for (int i = 0; i < 2 * in.M; ++i)
+            if (!std::isfinite(in.alpha[i])) return fail(CGD_ERR_ARG, at + "alpha not finite");
+    if (in.schmidt) {
+        double s = 0;
+        for (int k = 0; k < in.K; ++k) {
+            if (!(in.schmidt[k] > 0) || !std::isfinite(in.schmidt[k])) return fail(CGD_ERR_NONPHYSICAL, at + "schmidt weights must be > 0");
+            if (in.schmidt[k] > in.schmidt[0] * (1 + 1e-12)) return fail(CGD_ERR_NONPHYSICAL, at + "schmidt weight above lambda_0");
+            s += in.schmidt[k];
+        }
+        if (std::fabs(s - 1.0) > 1e-9) return fail(CGD_ERR_NONPHYSICAL, at + "schmidt weights must sum to 1");
+    }
+    const int nbin = in.resolve_internal ? in.M * in.K : in.M;
+    for (int i = 0; i < nbin; ++i)
+        if (in.bin_of[i] < -1 || in.bin_of[i] >= in.L) return fail(CGD_ERR_ARG, at + "bin index out of range");
+    int64_t npts = 1;
+    for (int l = 0; l < in.L; ++l) {
+        if (in.cutoff[l] < 0 || in.cutoff[l] > 4095) return fail(CGD_ERR_ARG, at + "cutoff out of range");
+        const int g = in.grid ? in.grid[l] : in.cutoff[l] + 1;
+        if (g < in.cutoff[l] + 1 || g > 4096) return fail(CGD_ERR_ARG, at + "grid must satisfy cutoff+1 <= G <= 4096");
+        npts *= g;
+        if (npts > (int64_t)1 << 31) return fail(CGD_ERR_ARG, at + "grid too large");
+    }
+    double nrm2;
+    if (!spectral_norm_sq(in.T, in.M, nrm2)) return fail(CGD_ERR_NUMERIC, at + "norm of T did not converge");
+    if (nrm2 > 1.0 + 1e-10) return fail(CGD_ERR_NONPHYSICAL, at + "||T||_2 > 1");
+    return CGD_OK;
+}
+
+// Assemble one internal-mode block (all K modes when dense) of instance `in`:
+// covariance matrix Sigma = I + [[N^T, M],[M^*, N]] (Sec. II), H = I - Sigma^-1,
+// gamma = X Sigma^-1 zbar, the vacuum-probability term, unmeasured modes
+// integrated out, and optionally the largest bin eliminated through its
+// eigenbasis.
+cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int> &kset, bool dense,
+                          bool use_schur, const std::vector<std::vector<double>> &rk, HostInst &hi,
+                          std::vector<HostBlock> &out) {
+    const int M = in.M;
+    const int nk = (int)kset.size();
+    const int m = M * nk;  // modes in this block
+    const int n2 = 2 * m;
+    // normally ordered moments: N = T^* diag(sinh^2) T^T, Mm = T diag(sinh cosh) T^T per internal mode
+    CMat N(m, m), Mm(m, m);
+    std::vector<cplx> beta(m, cplx(0, 0));
+    std::vector<double> sh2(M), shch(M);
+    for (int a = 0; a < nk; ++a) {
+        const int k = kset[a];
+        for (int q = 0; q < M; ++q) {
+            const double sh = std::sinh(rk[q][k]), ch = std::cosh(rk[q][k]);
+            sh2[q] = sh * sh;
+            shch[q] = sh * ch;
+        }
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                cplx sn(0, 0), sm(0, 0);
+                for (int q = 0; q < M; ++q) {
+                    const cplx tiq = cx(in.T, (size_t)i * M + q), tjq = cx(in.T, (size_t)j * M + q);
+                    sn += std::conj(tiq) * tjq * sh2[q];
+                    sm += tiq * tjq * shch[q];
+                }
+                const int ii = dense ? i * nk + a : i, jj = dense ? j * nk + a : j;
+                N(ii, jj) = sn;
+                Mm(ii, jj) = sm;
+            }
+        if (k == 0 && in.alpha)
+            for (int i = 0; i < M; ++i) {
+                cplx b(0, 0);
+                for (int q = 0; q < M; ++q) b += cx(in.T, (size_t)i * M + q) * cx(in.alpha, q);
+                beta[dense ? i * nk + a : i] = b;
+            }
+    }
+    CMat Sig = CMat::eye(n2);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            Sig(i, j) += N(j, i);
+            Sig(i, m + j) += Mm(i, j);
+            Sig(m + i, j) += std::conj(Mm(i, j));
+            Sig(m + i, m + j) += N(i, j);
+        }
+    std::vector<cplx> zbar(n2);
+    bool displaced = false;
+    for (int i = 0; i < m; ++i) {
+        zbar[i] = beta[i];
+        zbar[m + i] = std::conj(beta[i]);
+        if (beta[i] != cplx(0, 0)) displaced = true;
+    }
+    // uncertainty relation: Sigma - I/2 > 0  <=>  spec(H) inside (-1, 1)
+    {
+        CMat Sh = Sig;
+        for (int i = 0; i < n2; ++i) Sh(i, i) -= 0.5;
+        if (!hermitian_positive_definite(Sh))
+            return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(idx) + ": covariance violates Sigma > I/2");
+    }
+    CMat Sinv;
+    if (!inverse(Sig, Sinv)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": singular covariance");
+    std::vector<cplx> v(n2, cplx(0, 0));  // Sigma^-1 zbar
+    for (int i = 0; i < n2; ++i)
+        for (int j = 0; j < n2; ++j) v[i] += Sinv(i, j) * zbar[j];
+    cplx quad(0, 0);
+    for (int i = 0; i < n2; ++i) quad += std::conj(zbar[i]) * v[i];
+    const double ld = logdet_hpd(Sig);
+    if (!std::isfinite(ld)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": log det Sigma");
+    hi.logpr0 += -0.5 * quad.real() - 0.5 * ld;  // Eq. vacuum_probability
+
+    // bordered H' (order n2 + displaced): H, column -X gamma = -Sigma^-1 zbar, row -gamma^T
+    const int nf = n2 + (displaced ? 1 : 0);
+    CMat Hf(nf, nf);
+    for (int i = 0; i < n2; ++i)
+        for (int j = 0; j < n2; ++j) Hf(i, j) = (i == j ? 1.0 : 0.0) - Sinv(i, j);
+    std::vector<int32_t> rb(nf, -1);
+    for (int i = 0; i < n2; ++i) rb[i] = bin_of_row(in, i, m, kset, dense);
+    if (displaced) {
+        for (int i = 0; i < n2; ++i) {
+            Hf(i, n2) = -v[i];                     // X gamma = Sigma^-1 zbar
+            Hf(n2, i) = -v[i < m ? i + m : i - m]; // gamma = X Sigma^-1 zbar
+        }
+        Hf(n2, n2) = 0.0;
+    }
+
+    // integrate out unmeasured modes: det S = det(I - H_UU) det(I - D_R H_red),
+    // H_red = H_RR + H_RU (I - H_UU)^-1 H_UR (the reduced Gaussian state)
+    std::vector<int> U, R;
+    for (int i = 0; i < nf; ++i) {
+        if (displaced && i == n2) continue;
+        (rb[i] < 0 ? U : R).push_back(i);
+    }
+    if (displaced) R.push_back(n2);
+    CMat Hr;
+    std::vector<int32_t> rbr;
+    if (!U.empty()) {
+        const int nu = (int)U.size(), nr = (int)R.size();
+        CMat Suu(nu, nu), Hur(nu, nr), Hru(nr, nu);
+        for (int a = 0; a < nu; ++a) {
+            for (int b = 0; b < nu; ++b) Suu(a, b) = (a == b ? 1.0 : 0.0) - Hf(U[a], U[b]);
+            for (int b = 0; b < nr; ++b) Hur(a, b) = Hf(U[a], R[b]);
+        }
+        for (int a = 0; a < nr; ++a)
+            for (int b = 0; b < nu; ++b) Hru(a, b) = Hf(R[a], U[b]);
+        const double ldu = logdet_hpd(Suu);
+        if (!std::isfinite(ldu)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": reduction");
+        hi.logpr0 += -0.5 * ldu;
+        CMat X;
+        if (!solve(Suu, Hur, X)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": reduction solve");
+        CMat corr = matmul(Hru, X);
+        Hr = CMat(nr, nr);
+        for (int a = 0; a < nr; ++a)
+            for (int b = 0; b < nr; ++b) Hr(a, b) = Hf(R[a], R[b]) + corr(a, b);
+        rbr.resize(nr);
+        for (int a = 0; a < nr; ++a) rbr[a] = rb[R[a]];
+    } else {
+        Hr = Hf;
+        rbr = rb;
+    }
+    const int nr = Hr.r;
+    if (nr == 0) return CGD_OK;  // nothing measured, nothing displaced: constant factor only
+
+    HostBlock hb;
+    hb.inst = idx;
+    hb.blk = hi.nblocks;
+    hb.bordered = displaced ? 1 : 0;
+    // eliminate the bin with most rows through the eigenbasis of its (Hermitian) block
+    int axis = -1;
+    if (use_schur) {
+        std::vector<int> cnt(in.L, 0);
+        for (int a = 0; a < nr; ++a)
+            if (rbr[a] >= 0) cnt[rbr[a]]++;
+        int best = 0;
+        for (int l = 0; l < in.L; ++l)
+            if (cnt[l] > best) { best = cnt[l]; axis = l; }
+    }
+    if (axis >= 0) {
+        std::vector<int> A, Bv;
+        for (int a = 0; a < nr; ++a) (rbr[a] == axis ? A : Bv).push_back(a);  // border stays last in B
+        const int na = (int)A.size(), nbB = (int)Bv.size();
+        CMat Haa(na, na);
+        for (int a = 0; a < na; ++a)
+            for (int b = 0; b < na; ++b) Haa(a, b) = 0.5 * (Hr(A[a], A[b]) + std::conj(Hr(A[b], A[a])));
+        CMat V;
+        if (!hermitian_eig(Haa, hb.eig, V)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+        for (double lam : hb.eig)
+            if (!(std::fabs(lam) < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(idx) + ": |eig(H)| >= 1");
+        CMat Hba(nbB, na), Hab(na, nbB);
+        hb.H = CMat(nbB, nbB);
+        for (int a = 0; a < nbB; ++a) {
+            for (int b = 0; b < na; ++b) Hba(a, b) = Hr(Bv[a], A[b]);
+            for (int b = 0; b < nbB; ++b) hb.H(a, b) = Hr(Bv[a], Bv[b]);
+        }
+        for (int a = 0; a < na; ++a)
+            for (int b = 0; b < nbB; ++b) Hab(a, b) = Hr(A[a], Bv[b]);
+        hb.P = matmul(Hba, V);
+        hb.Q = matmul(adjoint(V), Hab);
+        hb.schur_axis = axis;
+        hb.nb = nbB;
+        hb.rowbin.resize(nbB);
+        for (int a = 0; a < nbB; ++a) hb.rowbin[a] = rbr[Bv[a]];
+    } else {
+        hb.H = Hr;
+        hb.nb = nr;
+        hb.rowbin = rbr;
+    }
+    out.push_back(std::move(hb));
+    hi.nblocks++;
+    return CGD_OK;
+}
+
+template <class T>
+cgd_status upload(T **dptr, const std::vector<T> &host) {
+    *dptr = nullptr;
+    if (host.empty()) return CGD_OK;
+    HIP_OK(hipMalloc((void **)dptr, sizeof(T) * host.size()));
+    HIP_OK(hipMemcpy(*dptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+    return CGD_OK;
+}
+
+struct LuClass {
+    int cls = 0;  // register class, or -1 for the blocked kernel
+    std::vector<int32_t> jobs;
+    std::vector<int64_t> prefix;
+    int64_t nitems = 0;
+    int32_t *d_jobs = nullptr;
+    int64_t *d_prefix = nullptr;
+};
+
+struct DftStage {
+    std::vector<DftStageDev> desc;
+    std::vector<int64_t> prefix;
+    int64_t total = 0;
+    DftStageDev *d_desc = nullptr;
+    int64_t *d_prefix = nullptr;
+};
+
+}  // namespace
+
+struct cgd_ctx {
+    int n_inst = 0;
+    cgd_precision prec = CGD_PREC_FP64;
+    double tol = 0;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    std::vector<InstDev> inst;
+    std::vector<BlockDev> blocks;
+    std::vector<SchurDev> schur;
+    std::vector<int64_t> schur_prefix;
+    int64_t schur_nwg = 0;
+    int schur_maxA = 0;
+    std::vector<LuClass> classes;
+    LuClass big;
+    int big_ldw = 0, big_nwg = 0;
+    std::vector<DftStage> stages;
+    std::vector<int64_t> prob_offsets, inst_pt_prefix;
+    int64_t nprobs = 0, npts = 0, ngrid = 0, ncontrib = 0;
+    // device
+    InstDev *d_inst = nullptr;
+    BlockDev *d_blocks = nullptr;
+    SchurDev *d_schur = nullptr;
+    int64_t *d_schur_prefix = nullptr;
+    int64_t *d_inst_pt_prefix = nullptr;
+    double2 *d_pool = nullptr;
+    int32_t *d_rb = nullptr;
+    double *d_eig = nullptr;
+    double2 *d_contrib = nullptr, *d_logg = nullptr, *d_gA = nullptr, *d_gB = nullptr, *d_work = nullptr;
+    int *d_status = nullptr;
+    int *h_status = nullptr;
+    hipEvent_t ev_status = nullptr;
+    bool status_pending = false;
+    bool poisoned = false;
+    bool evaluated = false;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+void free_ctx(cgd_ctx *c) {
+    if (!c) return;
+    auto fr = [](void *p) { if (p) (void)hipFree(p); };
+    fr(c->d_inst); fr(c->d_blocks); fr(c->d_schur); fr(c->d_schur_prefix); fr(c->d_inst_pt_prefix);
+    fr(c->d_pool); fr(c->d_rb); fr(c->d_eig); fr(c->d_contrib); fr(c->d_logg); fr(c->d_gA); fr(c->d_gB);
+    fr(c->d_work); fr(c->d_status);
+    for (auto &k : c->classes) { fr(k.d_jobs); fr(k.d_prefix); }
+    fr(c->big.d_jobs); fr(c->big.d_prefix);
+    for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->ev_status) (void)hipEventDestroy(c->ev_status);
+    delete c;
+}
+
+cgd_status check_status(cgd_ctx *c) {
+    if (c->poisoned) return fail(CGD_ERR_NUMERIC, "a previous evaluation hit a pivot outside the right half-plane");
+    if (c->status_pending) {
+        if (hipEventQuery(c->ev_status) == hipSuccess) {
+            c->status_pending = false;
+            if (*c->h_status) {
+                c->poisoned = true;
+                return fail(CGD_ERR_NUMERIC, "a previous evaluation hit a pivot outside the right half-plane");
+            }
+        }
+    }
+    return CGD_OK;
+}
+
+cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
+    std::vector<HostInst> hinst(n_inst);
+    std::vector<HostBlock> hblocks;
+    const bool dense = c->flags & CGD_FLAG_DENSE_INTERNAL;
+    const bool use_schur = !(c->flags & CGD_FLAG_NO_SCHUR);
+    for (int i = 0; i < n_inst; ++i) {
+        const cgd_instance &in = inst[i];
+        cgd_status s = validate(in, i);
+        if (s != CGD_OK) return s;
+        HostInst &hi = hinst[i];
+        hi.L = in.L;
+        for (int l = 0; l < in.L; ++l) {
+            hi.N[l] = in.cutoff[l];
+            hi.G[l] = in.grid ? in.grid[l] : in.cutoff[l] + 1;
+        }
+        // per internal mode squeezing: tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j
+        std::vector<std::vector<double>> rk(in.M, std::vector<double>(in.K));
+        for (int j = 0; j < in.M; ++j)
+            for (int k = 0; k < in.K; ++k) {
+                const double ratio = in.K == 1 ? 1.0 : in.schmidt[k] / in.schmidt[0];
+                const double t = std::sqrt(ratio) * std::tanh(in.r[j]);
+                if (!(t < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(i) + ": Schmidt weights");
+                rk[j][k] = std::atanh(t);
+            }
+        if (dense || in.K == 1) {
+            std::vector<int> ks(in.K);
+            for (int k = 0; k < in.K; ++k) ks[k] = k;
+            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, hblocks);
+            if (s != CGD_OK) return s;
+        } else {
+            for (int k = 0; k < in.K; ++k) {
+                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, hblocks);
+                if (s != CGD_OK) return s;
+            }
+        }
+    }
+
+    // instances
+    c->inst.resize(n_inst);
+    c->prob_offsets.assign(n_inst + 1, 0);
+    c->inst_pt_prefix.assign(n_inst, 0);
+    int64_t pt = 0, co = 0, po = 0, ng = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        InstDev &d = c->inst[i];
+        std::memset(&d, 0, sizeof(d));
+        const HostInst &h = hinst[i];
+        d.L = h.L;
+        d.nblocks = h.nblocks;
+        int64_t np = 1, nprob = 1, ngi = 1;
+        for (int l = 0; l < h.L; ++l) {
+            d.G[l] = h.G[l];
+            d.N[l] = h.N[l];
+            nprob *= h.N[l] + 1;
+            ngi *= h.G[l];
+            if (l > 0) np *= h.G[l];
+        }
+        d.H1 = h.G[0] / 2 + 1;
+        np *= d.H1;
+        d.npts = np;
+        d.pt_off = pt;
+        d.c_off = co;
+        d.prob_off = po;
+        d.nprobs = nprob;
+        d.logpr0_re = h.logpr0;
+        d.logpr0_im = 0.0;
+        c->inst_pt_prefix[i] = pt;
+        c->prob_offsets[i] = po;
+        pt += np;
+        co += np * h.nblocks;
+        po += nprob;
+        ng += ngi;
+    }
+    c->prob_offsets[n_inst] = po;
+    c->npts = pt;
+    c->ncontrib = co;
+    c->nprobs = po;
+    c->ngrid = ng;
+
+    // pools and block descriptors
+    std::vector<double2> pool;
+    std::vector<int32_t> rbpool;
+    std::vector<double> eigpool;
+    auto push_mat = [&](const CMat &A) {
+        const int64_t off = (int64_t)pool.size();
+        for (const cplx &z : A.a) pool.push_back(make_double2(z.real(), z.imag()));
+        return off;
+    };
+    c->blocks.resize(hblocks.size());
+    std::vector<int64_t> c_region(hblocks.size(), -1);
+    for (size_t b = 0; b < hblocks.size(); ++b) {
+        const HostBlock &h = hblocks[b];
+        BlockDev &d = c->blocks[b];
+        std::memset(&d, 0, sizeof(d));
+        d.inst = h.inst;
+        d.blk = h.blk;
+        d.nb = h.nb;
+        d.bordered = h.bordered;
+        d.schur_axis = h.schur_axis;
+        d.n_eig = (int32_t)h.eig.size();
+        d.rb_off = (int64_t)rbpool.size();
+        rbpool.insert(rbpool.end(), h.rowbin.begin(), h.rowbin.end());
+        d.eig_off = (int64_t)eigpool.size();
+        eigpool.insert(eigpool.end(), h.eig.begin(), h.eig.end());
+        if (h.schur_axis >= 0) {
+            SchurDev sj;
+            std::memset(&sj, 0, sizeof(sj));
+            const InstDev &I = c->inst[h.inst];
+            sj.inst = h.inst;
+            sj.axis = h.schur_axis;
+            sj.nA = (int32_t)h.eig.size();
+            sj.nB = h.nb;
+            sj.nk = h.schur_axis == 0 ? I.H1 : I.G[h.schur_axis];
+            sj.Gax = I.G[h.schur_axis];
+            sj.p_off = push_mat(h.P);
+            sj.q_off = push_mat(h.Q);
+            sj.hbb_off = push_mat(h.H);
+            sj.eig_off = d.eig_off;
+            const int64_t csize = (int64_t)sj.nk * h.nb * h.nb;
+            sj.c_off = (int64_t)pool.size();
+            pool.resize(pool.size() + csize, make_double2(0, 0));
+            d.h_off = sj.c_off;
+            d.hs_stride = (int64_t)h.nb * h.nb;
+            if (h.nb > 0) {
+                c->schur.push_back(sj);
+                c->schur_maxA = std::max(c->schur_maxA, sj.nA);
+            }
+        } else {
+            d.h_off = push_mat(h.H);
+            d.hs_stride = 0;
+        }
+    }
+    // schur work list: one workgroup per (job, k, row block)
+    const int rows = schur_rows_per_wg();
+    c->schur_prefix.clear();
+    int64_t acc = 0;
+    for (const SchurDev &s : c->schur) {
+        c->schur_prefix.push_back(acc);
+        acc += (int64_t)s.nk * ((s.nB + rows - 1) / rows);
+    }
+    c->schur_nwg = acc;
+    if ((int64_t)c->schur_maxA * (1 + rows) * 16 > 150 * 1024)
+        return fail(CGD_ERR_ARG, "eliminated bin too large for the Schur build");
+
+    // LU work lists per size class
+    c->classes.resize(kRegClasses);
+    for (int k = 0; k < kRegClasses; ++k) c->classes[k].cls = k;
+    c->big.cls = -1;
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        const BlockDev &d = c->blocks[b];
+        LuClass *lc = nullptr;
+        for (int k = 0; k < kRegClasses; ++k)
+            if (d.nb <= reg_class_limit(k)) { lc = &c->classes[k]; break; }
+        if (!lc) {
+            if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
+            lc = &c->big;
+            c->big_ldw = std::max(c->big_ldw, d.nb);
+        }
+        lc->prefix.push_back(lc->nitems);
+        lc->jobs.push_back((int32_t)b);
+        lc->nitems += c->inst[d.inst].npts;
+    }
+    if (c->big.nitems > 0) {
+        c->big_nwg = (int)std::min<int64_t>(c->big.nitems, 1024);
+    }
+
+    // DFT stages
+    int Lmax = 0;
+    for (auto &d : c->inst) Lmax = std::max(Lmax, d.L);
+    c->stages.resize(Lmax);
+    for (int s = 0; s < Lmax; ++s) {
+        DftStage &st = c->stages[s];
+        for (int i = 0; i < n_inst; ++i) {
+            const InstDev &I = c->inst[i];
+            if (I.L <= s) continue;
+            const int a = I.L - 1 - s;
+            int64_t dims[kMaxBins];
+            for (int l = 0; l < I.L; ++l) dims[l] = l <= a ? (l == 0 ? I.H1 : I.G[l]) : (I.N[l] + 1);
+            DftStageDev d;
+            std::memset(&d, 0, sizeof(d));
+            d.inst = i;
+            d.K = (int32_t)dims[a];
+            d.Bout = I.N[a] + 1;
+            d.G = I.G[a];
+            d.final_stage = a == 0;
+            d.outer = 1;
+            for (int l = 0; l < a; ++l) d.outer *= dims[l];
+            d.inner = 1;
+            for (int l = a + 1; l < I.L; ++l) d.inner *= dims[l];
+            d.in_off = I.pt_off;
+            d.out_off = a == 0 ? I.prob_off : I.pt_off;
+            double gprod = 1;
+            for (int l = 0; l < I.L; ++l) gprod *= I.G[l];
+            d.scale = 1.0 / gprod;
+            st.prefix.push_back(st.total);
+            st.total += d.outer * d.Bout * d.inner;
+            st.desc.push_back(d);
+        }
+    }
+
+    // uploads
+    cgd_status s;
+    if ((s = upload(&c->d_inst, c->inst)) != CGD_OK) return s;
+    if ((s = upload(&c->d_blocks, c->blocks)) != CGD_OK) return s;
+    if ((s = upload(&c->d_schur, c->schur)) != CGD_OK) return s;
+    if ((s = upload(&c->d_schur_prefix, c->schur_prefix)) != CGD_OK) return s;
+    if ((s = upload(&c->d_inst_pt_prefix, c->inst_pt_prefix)) != CGD_OK) return s;
+    if ((s = upload(&c->d_pool, pool)) != CGD_OK) return s;
+    if ((s = upload(&c->d_rb, rbpool)) != CGD_OK) return s;
+    if ((s = upload(&c->d_eig, eigpool)) != CGD_OK) return s;
+    for (auto &k : c->classes) {
+        if ((s = upload(&k.d_jobs, k.jobs)) != CGD_OK) return s;
+        if ((s = upload(&k.d_prefix, k.prefix)) != CGD_OK) return s;
+    }
+    if ((s = upload(&c->big.d_jobs, c->big.jobs)) != CGD_OK) return s;
+    if ((s = upload(&c->big.d_prefix, c->big.prefix)) != CGD_OK) return s;
+    for (auto &st : c->stages) {
+        if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
+        if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
+    }
+    const int64_t nc = std::max<int64_t>(c->ncontrib, 1), np = std::max<int64_t>(c->npts, 1);
+    HIP_OK(hipMalloc((void **)&c->d_contrib, sizeof(double2) * nc));
+    HIP_OK(hipMalloc((void **)&c->d_logg, sizeof(double2) * np));
+    HIP_OK(hipMalloc((void **)&c->d_gA, sizeof(double2) * np));
+    HIP_OK(hipMalloc((void **)&c->d_gB, sizeof(double2) * np));
+    HIP_OK(hipMalloc((void **)&c->d_status, sizeof(int)));
+    HIP_OK(hipMemset(c->d_status, 0, sizeof(int)));
+    HIP_OK(hipHostMalloc((void **)&c->h_status, sizeof(int), hipHostMallocDefault));
+    *c->h_status = 0;
+    HIP_OK(hipEventCreateWithFlags(&c->ev_status, hipEventDisableTiming));
+    if (c->big.nitems > 0) {
+        HIP_OK(hipMalloc((void **)&c->d_work, sizeof(double2) * (size_t)c->big_nwg * c->big_ldw * c->big_ldw));
+    }
+    HIP_OK(hipDeviceSynchronize());
+    return CGD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, cgd_precision prec, double tol,
+                      uint32_t flags, void *hip_stream) {
+    if (!out) return fail(CGD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!inst || n_inst <= 0) return fail(CGD_ERR_ARG, "need at least one instance");
+    if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
+    if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
+    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR)) return fail(CGD_ERR_ARG, "unknown flags");
+    cgd_ctx *c = new (std::nothrow) cgd_ctx();
+    if (!c) return fail(CGD_ERR_NOMEM, "host allocation");
+    c->n_inst = n_inst;
+    c->prec = prec;
+    c->tol = tol;
+    c->flags = flags;
+    c->stream = (hipStream_t)hip_stream;
+    cgd_status s = build(c, inst, n_inst);
+    if (s != CGD_OK) {
+        free_ctx(c);
+        return s;
+    }
+    *out = c;
+    return CGD_OK;
+}
+
+cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_offsets, int64_t *n_grid_total) {
+    if (!ctx) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (n_probs_total) *n_probs_total = ctx->nprobs;
+    if (prob_offsets)
+        for (int i = 0; i <= ctx->n_inst; ++i) prob_offsets[i] = ctx->prob_offsets[i];
+    if (n_grid_total) *n_grid_total = ctx->ngrid;
+    return CGD_OK;
+}
+
+int64_t cgd_points(const cgd_ctx *ctx) { return ctx ? ctx->npts : 0; }
+
+cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (!d_probs) return fail(CGD_ERR_ARG, "d_probs is NULL");
+    cgd_status s = check_status(c);
+    if (s != CGD_OK) return s;
+    hipStream_t st = c->stream;
+    HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg, c->schur_maxA,
+                              c->d_pool, c->d_eig, c->d_pool, st));
+    for (auto &k : c->classes) {
+        if (k.nitems == 0) continue;
+        LuLaunch a{k.d_jobs, k.d_prefix, (int)k.jobs.size(), k.nitems, c->d_blocks, c->d_inst,
+                   c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        HIP_OK(launch_lu_reg(k.cls, a, st));
+    }
+    if (c->big.nitems > 0) {
+        LuLaunch a{c->big.d_jobs, c->big.d_prefix, (int)c->big.jobs.size(), c->big.nitems, c->d_blocks, c->d_inst,
+                   c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        HIP_OK(launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st));
+    }
+    HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA, st));
+    for (size_t si = 0; si < c->stages.size(); ++si) {
+        DftStage &S = c->stages[si];
+        const double2 *in = (si % 2 == 0) ? c->d_gA : c->d_gB;
+        double2 *out = (si % 2 == 0) ? c->d_gB : c->d_gA;
+        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, d_probs, d_err_bound,
+                                c->d_status, st));
+    }
+    HIP_OK(hipMemcpyAsync(c->h_status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipEventRecord(c->ev_status, st));
+    c->status_pending = true;
+    c->evaluated = true;
+    return CGD_OK;
+}
+
+cgd_status cgd_grid_values(cgd_ctx *c, double *d_logg) {
+    if (!c || !d_logg) return fail(CGD_ERR_ARG, "NULL argument");
+    if (!c->evaluated) return fail(CGD_ERR_STATE, "cgd_grid_values before cgd_eval");
+    HIP_OK(hipMemcpyAsync(d_logg, c->d_logg, sizeof(double2) * c->npts, hipMemcpyDeviceToDevice, c->stream));
+    return CGD_OK;
+}
+
+cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_dT, double *d_dalpha) {
+    (void)d_dprobs; (void)d_dr; (void)d_dT; (void)d_dalpha;
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (!c->evaluated) return fail(CGD_ERR_STATE, "cgd_grad before cgd_eval");
+    return fail(CGD_ERR_ARG, "cgd_grad: not available in this build");
+}
+
+void cgd_destroy(cgd_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream); else (void)hipDeviceSynchronize();
+    free_ctx(ctx);
+}
+
+const char *cgd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal descriptors shared by the host side of the C ABI and the HIP kernels.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+#include <hip/hip_runtime.h>
+
+namespace cgd {
+
+constexpr int kMaxBins = 8;
+
+// One instance on the device.  The evaluated grid is the half grid
+// k_1 in [0, G_1/2], k_2..k_L in [0, G_l) (row-major, k_L fastest); the other
+// half follows from G(conj w) = conj G(w) because the coefficients are real.
+struct InstDev {
+    int32_t L;
+    int32_t nblocks;          // internal-mode blocks contributing to each point
+    int32_t G[kMaxBins];      // grid extents
+    int32_t N[kMaxBins];      // cutoffs
+    int32_t H1;               // G_1/2 + 1
+    int32_t pad;
+    int64_t npts;             // evaluated points = H1 * prod_{l>=2} G_l
+    int64_t pt_off;           // first evaluated point of this instance (global point index)
+    int64_t c_off;            // first contribution slot: c_off + p * nblocks + blk
+    int64_t prob_off;         // first output probability
+    int64_t nprobs;           // prod (N_l + 1)
+    double logpr0_re, logpr0_im;  // constant part of log G (vacuum probability, traced modes)
+};
+
+// One factorisation job family: an (instance, internal block) pair.  Every
+// evaluated point of the instance factorises S = I - diag(d(w)) Hs, where Hs
+// is either the block's (reduced, possibly bordered) matrix H (hs_stride = 0)
+// or, after eliminating the first bin through its eigenbasis, the per-k_1
+// Schur matrix C(w_1) stored at h_off + k_1 * hs_stride.
+struct BlockDev {
+    int32_t inst;
+    int32_t blk;
+    int32_t nb;               // matrix order including the border row/column
+    int32_t bordered;         // 1: last row/column is the displacement border
+    int32_t schur_axis;       // bin eliminated through its eigenbasis (-1: none)
+    int32_t n_eig;            // number of eliminated eigen-directions
+    int64_t h_off;            // complex offset of the matrix (row-major, ld = nb)
+    int64_t hs_stride;        // complex stride per k of the eliminated bin (0: one matrix)
+    int64_t rb_off;           // offset of nb row-bin indices (-1: factor 1)
+    int64_t eig_off;          // offset of the eliminated bin's eigenvalues
+};
+
+// Build of the Schur matrices C(w_A) = H_BB + P diag(w_A / (1 - w_A lambda)) Q
+// for every value k of the eliminated bin A (P = H_BA V, Q = V^H H_AB with
+// H_AA = V diag(lambda) V^H).
+struct SchurDev {
+    int32_t inst;
+    int32_t axis;             // eliminated bin
+    int32_t nA, nB;
+    int32_t nk;               // number of k values (H1 for axis 0, else G_axis)
+    int32_t Gax;              // grid extent of the eliminated axis
+    int64_t p_off, q_off, hbb_off, eig_off, c_off;
+};
+
+// One axis pass of the separable inverse DFT for one instance.
+struct DftStageDev {
+    int32_t inst, K, Bout, G;
+    int32_t final_stage, pad;
+    int64_t outer, inner, in_off, out_off;
+    double scale;
+};
+
+struct LuLaunch {
+    const int32_t *job_block;
+    const int64_t *job_prefix;
+    int njobs;
+    int64_t nitems;
+    const BlockDev *blocks;
+    const InstDev *insts;
+    const double2 *Hpool;
+    const int32_t *rbpool;
+    const double *eigpool;
+    double2 *contrib;
+    int *status;
+};
+
+// launchers (cgd_kernels.hip)
+int reg_class_limit(int cls);          // max matrix order of register class cls (0 = none)
+constexpr int kRegClasses = 5;
+hipError_t launch_lu_reg(int cls, const LuLaunch &a, hipStream_t st);
+size_t lu_big_lds_bytes(int ldw);
+hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st);
+hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
+                              const double2 *pool_in, const double *eigpool, double2 *pool_out, hipStream_t st);
+int schur_rows_per_wg();
+hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                          const double2 *contrib, double2 *logg, double2 *gval, hipStream_t st);
+hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total,
+                            const double2 *in, double2 *out, double *probs, double *err, const int *status,
+                            hipStream_t st);
+
+}  // namespace cgd

@@ -1,0 +1,644 @@
+// HIP kernels for gfx950 (CDNA4): per-grid-point factorisations of
+// S(w) = I - diag(d(w)) H (Eq. q_d), their log-determinants with the
+// continuous square-root branch, the displacement exponent, and the inverse
+// grid DFT.
+//
+// Branch rule.  H = X A = I - Sigma^-1 is Hermitian with spectrum in (-1, 1)
+// for every physical state (Sigma - I/2 > 0, the uncertainty relation of
+// Sec. II), so for |w_l| <= 1 the matrix S(t w) is accretive for all t in
+// [0, 1]: Re <x, S x> >= (1 - ||H||) |x|^2.  Schur complements of accretive
+// matrices are accretive, hence every pivot of the unpivoted LU of S(t w) has
+// a positive real part; the pivots move continuously from 1 (at t = 0), so
+// log det S = sum_i Log(pivot_i) with principal logarithms is the continuous
+// branch, and sqrt(det S) = exp(log det S / 2).
+//
+// Displacement exponent.  E(w) = 1/2 gamma^T S^-1 D X gamma (Eq. q_d
+// numerator).  The matrix is bordered by one extra row and column,
+//     S' = [[S, D X gamma], [gamma^T, 1]],
+// whose last unpivoted pivot is the Schur complement 1 - gamma^T S^-1 D X gamma
+// = 1 - 2 E, so E comes out of the same elimination with no triangular solve.
+// The host stores the border inside H (row -gamma^T, column -X gamma, factor 1).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cgd_internal.h"
+
+namespace cgd {
+
+// ---------------------------------------------------------------------------
+// small complex helpers (double2 = (re, im))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmk(double re, double im) { return make_double2(re, im); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a - l * u
+__device__ __forceinline__ double2 cfnms(double2 a, double2 l, double2 u) {
+    a.x = fma(-l.x, u.x, a.x);
+    a.x = fma(l.y, u.y, a.x);
+    a.y = fma(-l.x, u.y, a.y);
+    a.y = fma(-l.y, u.x, a.y);
+    return a;
+}
+__device__ __forceinline__ double2 cinv(double2 d) {
+    const double s = 1.0 / (d.x * d.x + d.y * d.y);
+    return cmk(d.x * s, -d.y * s);
+}
+// principal logarithm
+__device__ __forceinline__ double2 clog(double2 d) {
+    return cmk(0.5 * log(d.x * d.x + d.y * d.y), atan2(d.y, d.x));
+}
+
+// Grid coordinates of evaluated point p of instance I (half grid on axis 0)
+// and the corresponding roots of unity.
+__device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, double2 &w) {
+    int64_t stride = 1;
+    for (int m = I.L - 1; m > l; --m) stride *= I.G[m];
+    int64_t k = p / stride;
+    if (l > 0) k %= I.G[l];
+    double s, c;
+    sincospi(2.0 * (double)k / (double)I.G[l], &s, &c);
+    w = cmk(c, s);
+}
+__device__ __forceinline__ int point_k(const InstDev &I, int64_t p, int l) {
+    int64_t stride = 1;
+    for (int m = I.L - 1; m > l; --m) stride *= I.G[m];
+    int64_t k = p / stride;
+    if (l > 0) k %= I.G[l];
+    return (int)k;
+}
+
+// Largest c with prefix[c] <= item (prefix[0] = 0, strictly usable entries n).
+__device__ __forceinline__ int find_job(const int64_t *__restrict__ prefix, int n, int64_t item) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Block-wide sum of a complex value over NT threads (deterministic order).
+template <int NT>
+__device__ __forceinline__ double2 block_sum(double2 v, double2 *s_red) {
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_xor(v.x, off, 64);
+        v.y += __shfl_xor(v.y, off, 64);
+    }
+    constexpr int NW = (NT + 63) / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (NW > 1) {
+        if (lane == 0) s_red[wid] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double2 t = s_red[0];
+            for (int i = 1; i < NW; ++i) { t.x += s_red[i].x; t.y += s_red[i].y; }
+            v = t;
+        }
+    }
+    return v;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// Kernel A: register-resident unpivoted LU, one workgroup per (block, point).
+//
+// The (padded) NR x NR matrix is distributed cyclically over a PR x PC thread
+// grid: element (i, j) lives in thread (i % PR, j % PC) at register slot
+// (i / PR, j / PC).  Step k broadcasts row k and column k through LDS
+// (double-buffered, one barrier per step) and every thread applies the
+// rank-1 update to its own elements.  The step loop is split into an
+// unrolled loop over register rows r (k in [r PR, (r+1) PR)) so that every
+// register index is a compile-time constant and the update only touches the
+// register rows >= r and columns >= (r PR)/PC that can still be active.
+// ---------------------------------------------------------------------------
+template <int PR, int PC, int TR, int TC>
+__global__ void __launch_bounds__(PR *PC)
+lu_reg_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ job_prefix, int njobs,
+           const BlockDev *__restrict__ blocks, const InstDev *__restrict__ insts,
+           const double2 *__restrict__ Hpool, const int32_t *__restrict__ rbpool,
+           const double *__restrict__ eigpool, double2 *__restrict__ contrib,
+           int *__restrict__ status)
+{
+    constexpr int NT = PR * PC;
+    constexpr int N = PR * TR;
+    static_assert(PR * TR == PC * TC, "square padding");
+    static_assert(PC % PR == 0, "column owner must be uniform over a register row");
+    __shared__ double2 s_u[2][N];
+    __shared__ double2 s_l[2][N];
+    __shared__ double2 s_d[N];
+    __shared__ double2 s_piv[N];
+    __shared__ double2 s_w[kMaxBins];
+    __shared__ double2 s_red[NT / 64 + 1];
+    __shared__ int s_bad;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % PC, ty = tid / PC;
+    const int64_t item = blockIdx.x;
+    const int job = find_job(job_prefix, njobs, item);
+    const BlockDev B = blocks[job_block[job]];
+    const InstDev &I = insts[B.inst];
+    const int64_t pt = item - job_prefix[job];
+    const int nb = B.nb;
+
+    if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int i = tid; i < nb; i += NT) {
+        const int b = rbpool[B.rb_off + i];
+        s_d[i] = b < 0 ? cmk(1.0, 0.0) : s_w[b];
+    }
+    __syncthreads();
+
+    const double2 *__restrict__ Hs = Hpool + B.h_off;
+    if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
+
+    double2 a[TR][TC];
+    #pragma unroll
+    for (int r = 0; r < TR; ++r) {
+        const int i = r * PR + ty;
+        #pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            const int j = c * PC + tx;
+            double2 v = cmk(i == j ? 1.0 : 0.0, 0.0);
+            if (i < nb && j < nb) {
+                const double2 h = Hs[(int64_t)i * nb + j];
+                const double2 d = s_d[i];
+                v.x -= d.x * h.x - d.y * h.y;
+                v.y -= d.x * h.y + d.y * h.x;
+            }
+            a[r][c] = v;
+        }
+    }
+
+    #pragma unroll
+    for (int r = 0; r < TR; ++r) {
+        const int cown = (r * PR) / PC;
+        int kend = nb - r * PR;
+        kend = kend < 0 ? 0 : (kend > PR ? PR : kend);
+        for (int kk = 0; kk < kend; ++kk) {
+            const int k = r * PR + kk;
+            const int buf = k & 1;
+            if (ty == kk) {
+                #pragma unroll
+                for (int c = cown; c < TC; ++c) {
+                    const int j = c * PC + tx;
+                    if (j >= k) s_u[buf][j] = a[r][c];
+                }
+            }
+            if (tx == k % PC) {
+                #pragma unroll
+                for (int r2 = r; r2 < TR; ++r2) {
+                    const int i = r2 * PR + ty;
+                    if (i > k) s_l[buf][i] = a[r2][cown];
+                }
+            }
+            __syncthreads();
+            const double2 d = s_u[buf][k];
+            if (tid == 0) {
+                s_piv[k] = d;
+                if (!(d.x > 0.0) || !isfinite(d.y)) s_bad = 1;
+            }
+            const double2 dinv = cinv(d);
+            double2 u[TC];
+            #pragma unroll
+            for (int c = cown; c < TC; ++c) {
+                const int j = c * PC + tx;
+                u[c] = (j > k && j < nb) ? s_u[buf][j] : cmk(0.0, 0.0);
+            }
+            #pragma unroll
+            for (int r2 = r; r2 < TR; ++r2) {
+                const int i = r2 * PR + ty;
+                const double2 l = (i > k && i < nb) ? cmul(s_l[buf][i], dinv) : cmk(0.0, 0.0);
+                #pragma unroll
+                for (int c = cown; c < TC; ++c) a[r2][c] = cfnms(a[r2][c], l, u[c]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // epilogue: -1/2 [sum_i Log(pivot_i) + sum_i Log(1 - w_A lambda_i)] + E
+    const int nlog = nb - B.bordered;
+    double2 acc = cmk(0.0, 0.0);
+    for (int i = tid; i < nlog; i += NT) {
+        const double2 lg = clog(s_piv[i]);
+        acc.x += lg.x;
+        acc.y += lg.y;
+    }
+    if (B.n_eig > 0) {
+        const double2 wa = s_w[B.schur_axis];
+        const double *__restrict__ lam = eigpool + B.eig_off;
+        for (int i = tid; i < B.n_eig; i += NT) {
+            const double2 lg = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
+            acc.x += lg.x;
+            acc.y += lg.y;
+        }
+    }
+    acc = block_sum<NT>(acc, s_red);
+    if (tid == 0) {
+        double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
+        if (B.bordered) {
+            const double2 p = s_piv[nb - 1];
+            res.x += 0.5 * (1.0 - p.x);
+            res.y += 0.5 * (0.0 - p.y);
+        }
+        contrib[I.c_off + pt * I.nblocks + B.blk] = res;
+        if (s_bad) atomicOr(status, 1);
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Kernel B: unpivoted LU for orders above the register-resident limit.  One
+// workgroup per (block, point), persistent over the work list; the matrix
+// lives in a per-workgroup global workspace (L2/MALL resident) and is
+// factorised right-looking in panels of kPanel columns: the panel is
+// factorised in LDS, the U row block is solved in place, and the trailing
+// matrix is updated in 64 x 64 tiles with 4 x 4 register blocks per thread
+// against an LDS-staged U tile.
+// ---------------------------------------------------------------------------
+constexpr int kPanel = 16;
+constexpr int kBigThreads = 256;
+
+__global__ void __launch_bounds__(kBigThreads)
+lu_big_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ job_prefix, int njobs,
+           int64_t nitems, const BlockDev *__restrict__ blocks, const InstDev *__restrict__ insts,
+           const double2 *__restrict__ Hpool, const int32_t *__restrict__ rbpool,
+           const double *__restrict__ eigpool, double2 *__restrict__ work, int ldw,
+           double2 *__restrict__ contrib, int *__restrict__ status)
+{
+    extern __shared__ double2 s_dyn[];
+    double2 *s_panel = s_dyn;                       // ldw x kPanel
+    double2 *s_utile = s_panel + (size_t)ldw * kPanel;  // kPanel x 64
+    double2 *s_piv = s_utile + kPanel * 64;          // ldw
+    double2 *s_d = s_piv + ldw;                      // ldw
+    __shared__ double2 s_w[kMaxBins];
+    __shared__ double2 s_red[kBigThreads / 64 + 1];
+    __shared__ int s_bad;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    double2 *__restrict__ W = work + (size_t)blockIdx.x * ldw * ldw;
+
+    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int job = find_job(job_prefix, njobs, item);
+        const BlockDev B = blocks[job_block[job]];
+        const InstDev &I = insts[B.inst];
+        const int64_t pt = item - job_prefix[job];
+        const int nb = B.nb;
+        __syncthreads();
+        if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+        if (tid == 0) s_bad = 0;
+        __syncthreads();
+        for (int i = tid; i < nb; i += kBigThreads) {
+            const int b = rbpool[B.rb_off + i];
+            s_d[i] = b < 0 ? cmk(1.0, 0.0) : s_w[b];
+        }
+        __syncthreads();
+        const double2 *__restrict__ Hs = Hpool + B.h_off;
+        if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
+        for (int64_t e = tid; e < (int64_t)nb * nb; e += kBigThreads) {
+            const int i = (int)(e / nb), j = (int)(e % nb);
+            const double2 h = Hs[e];
+            const double2 d = s_d[i];
+            double2 v = cmk(i == j ? 1.0 : 0.0, 0.0);
+            v.x -= d.x * h.x - d.y * h.y;
+            v.y -= d.x * h.y + d.y * h.x;
+            W[(size_t)i * ldw + j] = v;
+        }
+        __syncthreads();
+
+        for (int k0 = 0; k0 < nb; k0 += kPanel) {
+            const int kb = min(kPanel, nb - k0);
+            const int mrows = nb - k0;
+            // panel -> LDS
+            for (int e = tid; e < mrows * kPanel; e += kBigThreads) {
+                const int i = e / kPanel, t = e % kPanel;
+                s_panel[e] = t < kb ? W[(size_t)(k0 + i) * ldw + k0 + t] : cmk(0.0, 0.0);
+            }
+            __syncthreads();
+            for (int kk = 0; kk < kb; ++kk) {
+                const double2 d = s_panel[kk * kPanel + kk];
+                if (tid == 0) {
+                    s_piv[k0 + kk] = d;
+                    if (!(d.x > 0.0) || !isfinite(d.y)) s_bad = 1;
+                }
+                const double2 dinv = cinv(d);
+                for (int i = kk + 1 + tid; i < mrows; i += kBigThreads) {
+                    const double2 l = cmul(s_panel[i * kPanel + kk], dinv);
+                    s_panel[i * kPanel + kk] = l;
+                    for (int t = kk + 1; t < kb; ++t)
+                        s_panel[i * kPanel + t] = cfnms(s_panel[i * kPanel + t], l, s_panel[kk * kPanel + t]);
+                }
+                __syncthreads();
+            }
+            const int j0 = k0 + kb;
+            if (j0 >= nb) break;
+            // U12 = L11^-1 A12 (unit lower triangular solve), in place in W
+            for (int j = j0 + tid; j < nb; j += kBigThreads) {
+                double2 x[kPanel];
+                #pragma unroll
+                for (int t = 0; t < kPanel; ++t) x[t] = t < kb ? W[(size_t)(k0 + t) * ldw + j] : cmk(0.0, 0.0);
+                #pragma unroll
+                for (int t = 1; t < kPanel; ++t) {
+                    #pragma unroll
+                    for (int s2 = 0; s2 < t; ++s2) x[t] = cfnms(x[t], s_panel[t * kPanel + s2], x[s2]);
+                }
+                #pragma unroll
+                for (int t = 0; t < kPanel; ++t)
+                    if (t < kb) W[(size_t)(k0 + t) * ldw + j] = x[t];
+            }
+            __syncthreads();
+            // trailing update A22 -= L21 U12
+            for (int jt = j0; jt < nb; jt += 64) {
+                for (int e = tid; e < kPanel * 64; e += kBigThreads) {
+                    const int t = e / 64, jj = jt + (e % 64);
+                    s_utile[e] = (t < kb && jj < nb) ? W[(size_t)(k0 + t) * ldw + jj] : cmk(0.0, 0.0);
+                }
+                __syncthreads();
+                for (int it = j0; it < nb; it += 64) {
+                    double2 acc[4][4];
+                    #pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        #pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int i = it + ty + 16 * a, j = jt + tx + 16 * b;
+                            acc[a][b] = (i < nb && j < nb) ? W[(size_t)i * ldw + j] : cmk(0.0, 0.0);
+                        }
+                    for (int t = 0; t < kb; ++t) {
+                        double2 l[4], u[4];
+                        #pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const int i = it + ty + 16 * a;
+                            l[a] = i < nb ? s_panel[(i - k0) * kPanel + t] : cmk(0.0, 0.0);
+                        }
+                        #pragma unroll
+                        for (int b = 0; b < 4; ++b) u[b] = s_utile[t * 64 + tx + 16 * b];
+                        #pragma unroll
+                        for (int a = 0; a < 4; ++a)
+                            #pragma unroll
+                            for (int b = 0; b < 4; ++b) acc[a][b] = cfnms(acc[a][b], l[a], u[b]);
+                    }
+                    #pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        #pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int i = it + ty + 16 * a, j = jt + tx + 16 * b;
+                            if (i < nb && j < nb) W[(size_t)i * ldw + j] = acc[a][b];
+                        }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        const int nlog = nb - B.bordered;
+        double2 acc = cmk(0.0, 0.0);
+        for (int i = tid; i < nlog; i += kBigThreads) {
+            const double2 lg = clog(s_piv[i]);
+            acc.x += lg.x;
+            acc.y += lg.y;
+        }
+        if (B.n_eig > 0) {
+            const double2 wa = s_w[B.schur_axis];
+            const double *__restrict__ lam = eigpool + B.eig_off;
+            for (int i = tid; i < B.n_eig; i += kBigThreads) {
+                const double2 lg = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
+                acc.x += lg.x;
+                acc.y += lg.y;
+            }
+        }
+        acc = block_sum<kBigThreads>(acc, s_red);
+        if (tid == 0) {
+            double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
+            if (B.bordered) {
+                const double2 p = s_piv[nb - 1];
+                res.x += 0.5 * (1.0 - p.x);
+                res.y += 0.5 * (0.0 - p.y);
+            }
+            contrib[I.c_off + pt * I.nblocks + B.blk] = res;
+            if (s_bad) atomicOr(status, 1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Schur matrices of the remaining bins after eliminating bin A through the
+// eigenbasis of H_AA (Hermitian, H_AA = V diag(lambda) V^H):
+//     C(w_A) = H_BB + P diag(f) Q,  f_i = w_A / (1 - w_A lambda_i),
+// so that I - D_B C(w_A) is the Schur complement of S(w) on the other bins and
+// det S = prod_i (1 - w_A lambda_i) det(I - D_B C(w_A)).
+// One workgroup per (job, k, 8-row block of C).
+// ---------------------------------------------------------------------------
+constexpr int kSchurRows = 8;
+
+__global__ void __launch_bounds__(256)
+schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ job_prefix, int njobs,
+                const double2 *__restrict__ pool_in, const double *__restrict__ eigpool,
+                double2 *__restrict__ pool_out)
+{
+    extern __shared__ double2 s_dyn[];
+    const int job = find_job(job_prefix, njobs, blockIdx.x);
+    const SchurDev J = jobs[job];
+    const int64_t local = blockIdx.x - job_prefix[job];
+    const int nrb = (J.nB + kSchurRows - 1) / kSchurRows;
+    const int k = (int)(local / nrb);
+    const int r0 = (int)(local % nrb) * kSchurRows;
+    double2 *s_f = s_dyn;                 // nA
+    double2 *s_pf = s_f + J.nA;           // kSchurRows x nA
+    double s, c;
+    sincospi(2.0 * (double)k / (double)J.Gax, &s, &c);
+    const double2 w = cmk(c, s);
+    const double *lam = eigpool + J.eig_off;
+    for (int i = threadIdx.x; i < J.nA; i += blockDim.x)
+        s_f[i] = cmul(w, cinv(cmk(1.0 - w.x * lam[i], -w.y * lam[i])));
+    __syncthreads();
+    const double2 *P = pool_in + J.p_off;
+    for (int e = threadIdx.x; e < kSchurRows * J.nA; e += blockDim.x) {
+        const int rr = e / J.nA, i = e % J.nA;
+        const int r = r0 + rr;
+        s_pf[e] = r < J.nB ? cmul(P[(int64_t)r * J.nA + i], s_f[i]) : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    const double2 *Q = pool_in + J.q_off;
+    const double2 *Hbb = pool_in + J.hbb_off;
+    double2 *C = pool_out + J.c_off + (int64_t)k * J.nB * J.nB;
+    for (int col = threadIdx.x; col < J.nB; col += blockDim.x) {
+        double2 acc[kSchurRows];
+        #pragma unroll
+        for (int rr = 0; rr < kSchurRows; ++rr) {
+            const int r = r0 + rr;
+            acc[rr] = r < J.nB ? Hbb[(int64_t)r * J.nB + col] : cmk(0.0, 0.0);
+        }
+        for (int i = 0; i < J.nA; ++i) {
+            const double2 q = Q[(int64_t)i * J.nB + col];
+            #pragma unroll
+            for (int rr = 0; rr < kSchurRows; ++rr) {
+                const double2 pf = s_pf[rr * J.nA + i];
+                acc[rr].x = fma(pf.x, q.x, acc[rr].x);
+                acc[rr].x = fma(-pf.y, q.y, acc[rr].x);
+                acc[rr].y = fma(pf.x, q.y, acc[rr].y);
+                acc[rr].y = fma(pf.y, q.x, acc[rr].y);
+            }
+        }
+        #pragma unroll
+        for (int rr = 0; rr < kSchurRows; ++rr) {
+            const int r = r0 + rr;
+            if (r < J.nB) C[(int64_t)r * J.nB + col] = acc[rr];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// log G(w) = log Pr(0) + (constant) + sum over internal blocks of each
+// block's contribution, then G = exp(log G).  One thread per evaluated point.
+// ---------------------------------------------------------------------------
+__global__ void combine_points(const InstDev *__restrict__ insts, const int64_t *__restrict__ inst_pt_prefix,
+                               int n_inst, int64_t npts_total, const double2 *__restrict__ contrib,
+                               double2 *__restrict__ logg, double2 *__restrict__ gval)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts_total) return;
+    const int i = find_job(inst_pt_prefix, n_inst, p);
+    const InstDev &I = insts[i];
+    const int64_t lp = p - I.pt_off;
+    double2 acc = cmk(I.logpr0_re, I.logpr0_im);
+    const double2 *c = contrib + I.c_off + lp * I.nblocks;
+    for (int b = 0; b < I.nblocks; ++b) {
+        acc.x += c[b].x;
+        acc.y += c[b].y;
+    }
+    logg[p] = acc;
+    double s, co;
+    sincos(acc.y, &s, &co);
+    const double m = exp(acc.x);
+    gval[p] = cmk(m * co, m * s);
+}
+
+// ---------------------------------------------------------------------------
+// One axis of the separable inverse DFT, for every instance that still has
+// this axis:  out[o][b][i] = sum_k in[o][k][i] exp(-2 pi i k b / G).
+// The last stage (axis 0, the half-grid axis) folds in the conjugate half:
+// P(b) = (1/prod G) sum_{k_1 <= G_1/2} c_k Re(...) with c_k = 1 for k_1 = 0
+// (and k_1 = G_1/2 when G_1 is even), 2 otherwise.
+// ---------------------------------------------------------------------------
+
+__global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__restrict__ prefix, int n,
+                          int64_t total, const double2 *__restrict__ in, double2 *__restrict__ out,
+                          double *__restrict__ probs, double *__restrict__ err, const int *__restrict__ status)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int e = find_job(prefix, n, q);
+    const DftStageDev S = st[e];
+    const int64_t lq = q - prefix[e];
+    const int64_t i = lq % S.inner;
+    const int b = (int)((lq / S.inner) % S.Bout);
+    const int64_t o = lq / (S.inner * S.Bout);
+    const double2 *src = in + S.in_off + o * S.K * S.inner + i;
+    double2 acc = cmk(0.0, 0.0);
+    for (int k = 0; k < S.K; ++k) {
+        const int m = (int)(((int64_t)k * b) % S.G);
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)S.G, &sn, &cs);
+        double2 v = src[(int64_t)k * S.inner];
+        if (S.final_stage) {
+            const double wk = (k == 0 || 2 * k == S.G) ? 1.0 : 2.0;
+            v.x *= wk;
+            v.y *= wk;
+        }
+        acc.x = fma(v.x, cs, acc.x);
+        acc.x = fma(-v.y, sn, acc.x);
+        acc.y = fma(v.x, sn, acc.y);
+        acc.y = fma(v.y, cs, acc.y);
+    }
+    if (S.final_stage) {
+        probs[S.out_off + lq] = acc.x * S.scale;
+        if (lq == 0 && err) err[S.inst] = (*status) ? INFINITY : 0.0;
+    } else {
+        out[S.out_off + lq] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host side)
+// ---------------------------------------------------------------------------
+
+template <int PR, int PC, int TR, int TC>
+static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
+    hipLaunchKernelGGL((lu_reg_f64<PR, PC, TR, TC>), dim3((unsigned)a.nitems), dim3(PR * PC), 0, st,
+                       a.job_block, a.job_prefix, a.njobs, a.blocks, a.insts, a.Hpool, a.rbpool, a.eigpool,
+                       a.contrib, a.status);
+    return hipGetLastError();
+}
+
+int reg_class_limit(int cls) {
+    switch (cls) {
+        case 0: return 32;
+        case 1: return 64;
+        case 2: return 96;
+        case 3: return 128;
+        case 4: return 144;
+        default: return 0;
+    }
+}
+
+hipError_t launch_lu_reg(int cls, const LuLaunch &a, hipStream_t st) {
+    if (a.nitems <= 0) return hipSuccess;
+    switch (cls) {
+        case 0: return launch_reg<8, 8, 4, 4>(a, st);
+        case 1: return launch_reg<16, 16, 4, 4>(a, st);
+        case 2: return launch_reg<16, 32, 6, 3>(a, st);
+        case 3: return launch_reg<16, 32, 8, 4>(a, st);
+        case 4: return launch_reg<16, 48, 9, 3>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t lu_big_lds_bytes(int ldw) {
+    return sizeof(double2) * ((size_t)ldw * kPanel + kPanel * 64 + 2 * (size_t)ldw);
+}
+
+hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st) {
+    if (a.nitems <= 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lu_big_lds_bytes(ldw));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lu_big_f64, dim3(nwg), dim3(kBigThreads), lu_big_lds_bytes(ldw), st, a.job_block,
+                       a.job_prefix, a.njobs, a.nitems, a.blocks, a.insts, a.Hpool, a.rbpool, a.eigpool, work,
+                       ldw, a.contrib, a.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
+                              const double2 *pool_in, const double *eigpool, double2 *pool_out, hipStream_t st) {
+    if (nwg <= 0) return hipSuccess;
+    const size_t lds = sizeof(double2) * (size_t)maxA * (1 + kSchurRows);
+    hipError_t e = hipFuncSetAttribute((const void *)schur_build_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(schur_build_f64, dim3((unsigned)nwg), dim3(256), lds, st, jobs, prefix, njobs, pool_in,
+                       eigpool, pool_out);
+    return hipGetLastError();
+}
+
+int schur_rows_per_wg() { return kSchurRows; }
+
+hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                          const double2 *contrib, double2 *logg, double2 *gval, hipStream_t st) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_points, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts,
+                       inst_pt_prefix, n_inst, npts, contrib, logg, gval);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total,
+                            const double2 *in, double2 *out, double *probs, double *err, const int *status,
+                            hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dft_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, st_dev, prefix, n,
+                       total, in, out, probs, err, status);
+    return hipGetLastError();
+}
+
+
+}  // namespace cgd

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI that need no GPU: the built library loads,
+exports every function include/cgd.h declares, and rejects invalid arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2412_17742_amd as cgd
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "cgd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert {"cgd_create", "cgd_eval", "cgd_grad", "cgd_destroy", "cgd_layout", "cgd_last_error"} <= set(names)
+    L = ctypes.CDLL(cgd.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(inst, **kw):
+    keep = []
+    arr = (cgd.CgdInstance * 1)(cgd._marshal(inst, keep))
+    h = ctypes.c_void_p()
+    st = cgd.lib().cgd_create(ctypes.byref(h), arr, 1, kw.get("prec", 0), kw.get("tol", 1e-9), kw.get("flags", 0), None)
+    return st, h, cgd.lib().cgd_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate, status", [
+    (lambda x: x.update(T=2.0 * x["T"]), cgd.CGD_ERR_NONPHYSICAL),
+    (lambda x: x.update(r=-x["r"]), cgd.CGD_ERR_NONPHYSICAL),
+    (lambda x: x["r"].__setitem__(0, np.nan), cgd.CGD_ERR_NONPHYSICAL),
+    (lambda x: x.update(bin_of=np.array([0, 0, 2, 1], np.int32)), cgd.CGD_ERR_ARG),
+    (lambda x: x.update(cutoff=np.array([-1, 6], np.int32)), cgd.CGD_ERR_ARG),
+    (lambda x: x.update(grid=np.array([6, 7], np.int32)), cgd.CGD_ERR_ARG),
+    (lambda x: x.update(schmidt=np.array([0.5, 0.4])), cgd.CGD_ERR_NONPHYSICAL),
+    (lambda x: x.update(schmidt=np.array([0.3, 0.7])), cgd.CGD_ERR_NONPHYSICAL),
+])
+def test_create_rejects_invalid_instances(mutate, status):
+    inst = W.config1()
+    mutate(inst)
+    st, h, msg = _create(inst)
+    assert st == status, msg
+    assert h.value is None
+    assert msg
+
+
+def test_create_rejects_bad_call_arguments():
+    L = cgd.lib()
+    h = ctypes.c_void_p()
+    assert L.cgd_create(ctypes.byref(h), None, 1, 0, 1e-9, 0, None) == cgd.CGD_ERR_ARG
+    keep = []
+    arr = (cgd.CgdInstance * 1)(cgd._marshal(W.config1(), keep))
+    assert L.cgd_create(ctypes.byref(h), arr, 1, 7, 1e-9, 0, None) == cgd.CGD_ERR_ARG
+    assert L.cgd_create(ctypes.byref(h), arr, 1, cgd.PREC_MIXED, 0.0, 0, None) == cgd.CGD_ERR_ARG
+    assert L.cgd_create(ctypes.byref(h), arr, 1, 0, 1e-9, 1 << 20, None) == cgd.CGD_ERR_ARG
+    assert L.cgd_eval(None, None, None) == cgd.CGD_ERR_ARG
+    assert L.cgd_grad(None, None, None, None, None) == cgd.CGD_ERR_ARG
+    L.cgd_destroy(None)
