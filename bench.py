@@ -1,0 +1,179 @@
+#!/usr/bin/env python
+"""Benchmark of the binned photon-number distribution hot path on one MI355X.
+
+One step = one cgd_eval of the workload: every grid point's generating
+function (factorisations, log-determinant with the continuous branch,
+displacement exponent) plus the inverse grid DFT, with the state already
+resident in HBM (cgd_create is outside the timed region).
+
+Prints one JSON line.  value = grid determinants per second: evaluated grid
+points (the Hermitian half grid; the other half is the complex conjugate) per
+second of cgd_eval.  Also reported: binned probabilities/s, the full-grid point
+rate, per-stage device times, the roofline of the dominant kernel and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (= FP64 matrix) peak
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "cfg4a": ("GBS scale: M=144 squeezed inputs (r~U[0.4,1.2]) on sqrt(0.3)*Haar, K=1, "
+              "2 bins of 72 modes, cutoff 120, grid 121x121 (288x288 complex per point)",
+              lambda: [W.config4("a")]),
+    "cfg4b": ("GBS scale: M=144, K=1, 3 bins of 48 modes, cutoff 40, grid 41^3",
+              lambda: [W.config4("b")]),
+    "cfg2": ("M=16, K=3 Schmidt modes, displaced, 4 bins of 4, cutoff 10, grid 11^4 (96x96 complex per point)",
+             lambda: [W.config2()]),
+    "cfg3": ("512 uneven instances: M~U{8..64}, K~U{1..4}, L~U{1..4}, cutoffs~U{4..12}", W.config3),
+    "cfg5": ("64 parameter sets: M=32, K=4, 2 bins of 16, cutoff 12 (256x256 complex per point)", W.config5),
+}
+
+
+def cpu_baseline(instances, seconds: float):
+    """Oracle per-point evaluations (eigenvalue log-det + solve) on a bounded
+    sample of the workload's grid points, as grid dets/s."""
+    from oracle import pgf
+    from oracle import state as st
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    rng = np.random.default_rng(0)
+    states = [st.assemble(x) for x in instances]
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        i = int(rng.integers(len(instances)))
+        G = np.asarray(instances[i]["grid"], dtype=float)
+        k = np.array([rng.integers(int(g)) for g in G])
+        pgf.log_pgf(states[i], np.exp(2j * np.pi * k / G))
+        n += 1
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="grid dets/s", cores=int(cores), kind="oracle",
+                sample=f"{n} random grid points of the same workload, each by eigenvalues of D(w)XA "
+                       f"plus a dense solve (numpy/LAPACK, FP64), {dt:.1f} s")
+
+
+def run(ctx, steps, warmup):
+    import torch
+    probs = torch.empty(ctx.n_probs, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        ctx.eval(probs)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    s.record(ctx.stream)
+    for _ in range(steps):
+        ctx.eval(probs)
+    e.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return s.elapsed_time(e) / steps, wall / steps * 1e3, probs
+
+
+def stage_profile(ctx, steps):
+    import torch
+    ctx.set_timing(True)
+    acc = {}
+    probs = torch.empty(ctx.n_probs, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        ctx.eval(probs)
+        for k, v in ctx.stage_times().items():
+            if v >= 0:
+                acc[k] = acc.get(k, 0.0) + v
+    ctx.set_timing(False)
+    return {k: v / steps for k, v in acc.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg4a", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU layout is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2412_17742_amd as cgd
+
+    desc, make = WORKLOADS[args.workload]
+    instances = make()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    ctx = cgd.Context(instances, precision="fp64")
+    create_s = time.perf_counter() - t0
+    ms, wall_ms, probs = run(ctx, args.steps, args.warmup)
+    stages = stage_profile(ctx, max(3, min(args.steps, 10)))
+    flops, bytes_ = ctx.stage_work()
+
+    n_points = ctx.n_points
+    n_grid = ctx.n_grid
+    n_probs = ctx.n_probs
+    # dominant kernel: the stage with the largest device time
+    dom = max(stages, key=stages.get)
+    dom_ms = stages[dom]
+    if dom == "dft":
+        achieved = bytes_[dom] / (dom_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s")
+    else:
+        achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["work_per_launch"] = flops[dom] if dom != "dft" else bytes_[dom]
+
+    out = {
+        "metric": "grid dets/s & binned probs/s at <=1e-9 abs err, mixed vs FP64 on one MI355X",
+        "value": n_points / (ms * 1e-3),
+        "unit": "grid dets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "instances": len(instances),
+                   "evaluated_points": n_points, "grid_points": n_grid, "probabilities": n_probs,
+                   "precision": "fp64"},
+        "probs_per_s": n_probs / (ms * 1e-3),
+        "grid_points_per_s": n_grid / (ms * 1e-3),
+        "wall_ms_per_step": wall_ms,
+        "create_s": create_s,
+        "stage_ms": stages,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(instances, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

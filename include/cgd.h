@@ -134,6 +134,32 @@ cgd_status cgd_grid_values(cgd_ctx *ctx, double *d_logg);
 cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *d_dT,
                     double *d_dalpha);
 
+/* Profiling.  The evaluation is a fixed sequence of launch stages:
+ *   CGD_STAGE_SCHUR      Schur matrices of the bins left after eliminating one bin
+ *   CGD_STAGE_LU_REG0..4 register-resident factorisations, orders <= 32, 64, 96, 128, 144
+ *   CGD_STAGE_LU_BIG     blocked factorisations, orders 145..480
+ *   CGD_STAGE_COMBINE    log G per point and G = exp(log G)
+ *   CGD_STAGE_DFT        all axis passes of the inverse DFT
+ * With timing enabled, cgd_eval records a HIP event pair on the context's
+ * stream around every stage; cgd_stage_times waits for the last evaluation
+ * and returns each stage's duration in ms (-1 for stages with no work).
+ * cgd_stage_work returns each stage's algorithmic work per evaluation:
+ * flops (complex LU of order n: 8 sum_m m^2 + 6 sum_m m, m = n-1..0, i.e.
+ * about 8n^3/3 real flops; Schur build: 8 nA nB^2 per eliminated-bin value;
+ * DFT: 8 flops per complex multiply-add) and bytes (DFT: each grid value
+ * read once, each probability written once, 16 and 8 bytes). */
+enum {
+    CGD_STAGE_SCHUR = 0,
+    CGD_STAGE_LU_REG0 = 1,
+    CGD_STAGE_LU_BIG = 6,
+    CGD_STAGE_COMBINE = 7,
+    CGD_STAGE_DFT = 8,
+    CGD_NSTAGES = 9
+};
+cgd_status cgd_set_timing(cgd_ctx *ctx, int32_t enable);
+cgd_status cgd_stage_times(cgd_ctx *ctx, double *ms /* CGD_NSTAGES */);
+cgd_status cgd_stage_work(const cgd_ctx *ctx, double *flops /* CGD_NSTAGES */, double *bytes /* CGD_NSTAGES */);
+
 void cgd_destroy(cgd_ctx *ctx);
 
 /* Message of the last failure on this thread (valid until the next call). */

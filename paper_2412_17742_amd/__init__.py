@@ -22,6 +22,7 @@ STATUS_NAMES = ["CGD_OK", "CGD_ERR_ARG", "CGD_ERR_NONPHYSICAL", "CGD_ERR_NUMERIC
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_DENSE_INTERNAL = 1
 FLAG_NO_SCHUR = 2
+STAGES = ["schur", "lu_reg32", "lu_reg64", "lu_reg96", "lu_reg128", "lu_reg144", "lu_big", "combine", "dft"]
 
 
 class CgdError(RuntimeError):
@@ -65,6 +66,12 @@ def lib() -> ctypes.CDLL:
     L.cgd_grid_values.argtypes = [vp, vp]
     L.cgd_grad.restype = i32
     L.cgd_grad.argtypes = [vp, vp, vp, vp, vp]
+    L.cgd_set_timing.restype = i32
+    L.cgd_set_timing.argtypes = [vp, i32]
+    L.cgd_stage_times.restype = i32
+    L.cgd_stage_times.argtypes = [vp, vp]
+    L.cgd_stage_work.restype = i32
+    L.cgd_stage_work.argtypes = [vp, vp, vp]
     L.cgd_destroy.restype = None
     L.cgd_destroy.argtypes = [vp]
     L.cgd_last_error.restype = ctypes.c_char_p
@@ -150,6 +157,22 @@ class Context:
         out = torch.empty(2 * self.n_points, dtype=torch.float64, device="cuda")
         _check(lib().cgd_grid_values(self._h, ctypes.c_void_p(out.data_ptr())))
         return torch.view_as_complex(out.view(-1, 2))
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().cgd_set_timing(self._h, int(enable)))
+
+    def stage_times(self):
+        """ms per stage of the last evaluation (-1: stage had no work); waits for it."""
+        ms = np.zeros(len(STAGES))
+        _check(lib().cgd_stage_times(self._h, ms.ctypes.data))
+        return dict(zip(STAGES, ms))
+
+    def stage_work(self):
+        """(flops, bytes) per stage and evaluation, algorithmic counts."""
+        f = np.zeros(len(STAGES))
+        b = np.zeros(len(STAGES))
+        _check(lib().cgd_stage_work(self._h, f.ctypes.data, b.ctypes.data))
+        return dict(zip(STAGES, f)), dict(zip(STAGES, b))
 
     def close(self):
         if getattr(self, "_h", None):

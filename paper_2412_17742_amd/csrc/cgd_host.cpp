@@ -353,7 +353,10 @@ struct cgd_ctx {
     bool status_pending = false;
     bool poisoned = false;
     bool evaluated = false;
-    std::vector<void *> allocs;
+    bool timing = false;
+    hipEvent_t ev[CGD_NSTAGES][2] = {};
+    bool stage_ran[CGD_NSTAGES] = {};
+    double work_flops[CGD_NSTAGES] = {}, work_bytes[CGD_NSTAGES] = {};
 };
 
 namespace {
@@ -367,6 +370,9 @@ void free_ctx(cgd_ctx *c) {
     for (auto &k : c->classes) { fr(k.d_jobs); fr(k.d_prefix); }
     fr(c->big.d_jobs); fr(c->big.d_prefix);
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
+    for (int i = 0; i < CGD_NSTAGES; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->ev_status) (void)hipEventDestroy(c->ev_status);
     delete c;
@@ -585,6 +591,27 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         }
     }
 
+    // algorithmic work per evaluation
+    auto lu_flops = [](double n) {
+        double f = 0;
+        for (int m = 0; m < (int)n; ++m) f += 8.0 * m * m + 6.0 * m;
+        return f;
+    };
+    for (int k = 0; k < kRegClasses; ++k)
+        for (size_t j = 0; j < c->classes[k].jobs.size(); ++j) {
+            const BlockDev &d = c->blocks[c->classes[k].jobs[j]];
+            c->work_flops[CGD_STAGE_LU_REG0 + k] += lu_flops(d.nb) * c->inst[d.inst].npts;
+        }
+    for (size_t j = 0; j < c->big.jobs.size(); ++j) {
+        const BlockDev &d = c->blocks[c->big.jobs[j]];
+        c->work_flops[CGD_STAGE_LU_BIG] += lu_flops(d.nb) * c->inst[d.inst].npts;
+    }
+    for (const SchurDev &sj : c->schur) c->work_flops[CGD_STAGE_SCHUR] += 8.0 * sj.nA * (double)sj.nB * sj.nB * sj.nk;
+    for (const DftStage &st : c->stages)
+        for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
+    c->work_bytes[CGD_STAGE_DFT] = 16.0 * c->npts + 8.0 * c->nprobs;
+    c->work_bytes[CGD_STAGE_COMBINE] = 16.0 * (c->ncontrib + 2 * c->npts);
+
     // uploads
     cgd_status s;
     if ((s = upload(&c->d_inst, c->inst)) != CGD_OK) return s;
@@ -667,20 +694,37 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
     cgd_status s = check_status(c);
     if (s != CGD_OK) return s;
     hipStream_t st = c->stream;
-    HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg, c->schur_maxA,
-                              c->d_pool, c->d_eig, c->d_pool, st));
+    auto mark = [&](int stage, int which) -> hipError_t {
+        if (!c->timing) return hipSuccess;
+        c->stage_ran[stage] = true;
+        return hipEventRecord(c->ev[stage][which], st);
+    };
+    for (int i = 0; i < CGD_NSTAGES; ++i) c->stage_ran[i] = false;
+    if (c->schur_nwg > 0) {
+        HIP_OK(mark(CGD_STAGE_SCHUR, 0));
+        HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg,
+                                  c->schur_maxA, c->d_pool, c->d_eig, c->d_pool, st));
+        HIP_OK(mark(CGD_STAGE_SCHUR, 1));
+    }
     for (auto &k : c->classes) {
         if (k.nitems == 0) continue;
         LuLaunch a{k.d_jobs, k.d_prefix, (int)k.jobs.size(), k.nitems, c->d_blocks, c->d_inst,
                    c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        HIP_OK(mark(CGD_STAGE_LU_REG0 + k.cls, 0));
         HIP_OK(launch_lu_reg(k.cls, a, st));
+        HIP_OK(mark(CGD_STAGE_LU_REG0 + k.cls, 1));
     }
     if (c->big.nitems > 0) {
         LuLaunch a{c->big.d_jobs, c->big.d_prefix, (int)c->big.jobs.size(), c->big.nitems, c->d_blocks, c->d_inst,
                    c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        HIP_OK(mark(CGD_STAGE_LU_BIG, 0));
         HIP_OK(launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st));
+        HIP_OK(mark(CGD_STAGE_LU_BIG, 1));
     }
+    HIP_OK(mark(CGD_STAGE_COMBINE, 0));
     HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA, st));
+    HIP_OK(mark(CGD_STAGE_COMBINE, 1));
+    HIP_OK(mark(CGD_STAGE_DFT, 0));
     for (size_t si = 0; si < c->stages.size(); ++si) {
         DftStage &S = c->stages[si];
         const double2 *in = (si % 2 == 0) ? c->d_gA : c->d_gB;
@@ -688,6 +732,7 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
         HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, d_probs, d_err_bound,
                                 c->d_status, st));
     }
+    HIP_OK(mark(CGD_STAGE_DFT, 1));
     HIP_OK(hipMemcpyAsync(c->h_status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_OK(hipEventRecord(c->ev_status, st));
     c->status_pending = true;
@@ -707,6 +752,38 @@ cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
     if (!c->evaluated) return fail(CGD_ERR_STATE, "cgd_grad before cgd_eval");
     return fail(CGD_ERR_ARG, "cgd_grad: not available in this build");
+}
+
+cgd_status cgd_set_timing(cgd_ctx *c, int32_t enable) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (enable && !c->ev[0][0])
+        for (int i = 0; i < CGD_NSTAGES; ++i)
+            for (int j = 0; j < 2; ++j) HIP_OK(hipEventCreate(&c->ev[i][j]));
+    c->timing = enable != 0;
+    return CGD_OK;
+}
+
+cgd_status cgd_stage_times(cgd_ctx *c, double *ms) {
+    if (!c || !ms) return fail(CGD_ERR_ARG, "NULL argument");
+    if (!c->evaluated) return fail(CGD_ERR_STATE, "no evaluation yet");
+    for (int i = 0; i < CGD_NSTAGES; ++i) {
+        ms[i] = -1.0;
+        if (!c->timing || !c->stage_ran[i]) continue;
+        HIP_OK(hipEventSynchronize(c->ev[i][1]));
+        float t = 0;
+        HIP_OK(hipEventElapsedTime(&t, c->ev[i][0], c->ev[i][1]));
+        ms[i] = t;
+    }
+    return CGD_OK;
+}
+
+cgd_status cgd_stage_work(const cgd_ctx *c, double *flops, double *bytes) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    for (int i = 0; i < CGD_NSTAGES; ++i) {
+        if (flops) flops[i] = c->work_flops[i];
+        if (bytes) bytes[i] = c->work_bytes[i];
+    }
+    return CGD_OK;
 }
 
 void cgd_destroy(cgd_ctx *ctx) {
