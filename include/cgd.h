@@ -110,8 +110,10 @@ cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_
 
 /* Evaluate the wrapped distributions of all instances into d_probs (device,
  * n_probs_total doubles).  d_err_bound (device, n_inst doubles, or NULL)
- * receives, per instance, the largest |imaginary part| left by the inverse
- * DFT (a rounding witness; +inf after a numeric failure).  A numeric failure
+ * receives, per instance, a bound on the absolute error added by the mixed
+ * path to every probability: (1/prod G) sum over the points kept in FP32 of
+ * c_k |G_k| tau, with tau the assumed relative error of an FP32 value of G
+ * (0 on the FP64 path; +inf after a numeric failure).  A numeric failure
  * detected on the device is reported by the next call as CGD_ERR_NUMERIC. */
 cgd_status cgd_eval(cgd_ctx *ctx, double *d_probs, double *d_err_bound);
 
@@ -140,6 +142,8 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  *   CGD_STAGE_LU_BIG     blocked factorisations, orders 145..480
  *   CGD_STAGE_COMBINE    log G per point and G = exp(log G)
  *   CGD_STAGE_DFT        all axis passes of the inverse DFT
+ *   CGD_STAGE_FIX        mixed path: selection of the points whose FP32 value can
+ *                        matter, their FP64 re-factorisation and the second combine
  * With timing enabled, cgd_eval records a HIP event pair on the context's
  * stream around every stage; cgd_stage_times waits for the last evaluation
  * and returns each stage's duration in ms (-1 for stages with no work).
@@ -154,11 +158,18 @@ enum {
     CGD_STAGE_LU_BIG = 6,
     CGD_STAGE_COMBINE = 7,
     CGD_STAGE_DFT = 8,
-    CGD_NSTAGES = 9
+    CGD_STAGE_FIX = 9,
+    CGD_NSTAGES = 10
 };
 cgd_status cgd_set_timing(cgd_ctx *ctx, int32_t enable);
 cgd_status cgd_stage_times(cgd_ctx *ctx, double *ms /* CGD_NSTAGES */);
 cgd_status cgd_stage_work(const cgd_ctx *ctx, double *flops /* CGD_NSTAGES */, double *bytes /* CGD_NSTAGES */);
+
+/* Mixed path: number of (internal block, grid point) factorisations that the
+ * last cgd_eval repeated in FP64, and the total number of factorisations per
+ * evaluation.  Waits for the last evaluation.  CGD_ERR_STATE on the FP64 path
+ * or before the first evaluation. */
+cgd_status cgd_mixed_stats(cgd_ctx *ctx, int64_t *n_refactored, int64_t *n_total);
 
 void cgd_destroy(cgd_ctx *ctx);
 

@@ -22,7 +22,7 @@ STATUS_NAMES = ["CGD_OK", "CGD_ERR_ARG", "CGD_ERR_NONPHYSICAL", "CGD_ERR_NUMERIC
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_DENSE_INTERNAL = 1
 FLAG_NO_SCHUR = 2
-STAGES = ["schur", "lu_reg32", "lu_reg64", "lu_reg96", "lu_reg128", "lu_reg144", "lu_big", "combine", "dft"]
+STAGES = ["schur", "lu_reg32", "lu_reg64", "lu_reg96", "lu_reg128", "lu_reg144", "lu_big", "combine", "dft", "fix"]
 
 
 class CgdError(RuntimeError):
@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
     L.cgd_stage_times.argtypes = [vp, vp]
     L.cgd_stage_work.restype = i32
     L.cgd_stage_work.argtypes = [vp, vp, vp]
+    L.cgd_mixed_stats.restype = i32
+    L.cgd_mixed_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.cgd_destroy.restype = None
     L.cgd_destroy.argtypes = [vp]
     L.cgd_last_error.restype = ctypes.c_char_p
@@ -173,6 +175,12 @@ class Context:
         b = np.zeros(len(STAGES))
         _check(lib().cgd_stage_work(self._h, f.ctypes.data, b.ctypes.data))
         return dict(zip(STAGES, f)), dict(zip(STAGES, b))
+
+    def mixed_stats(self):
+        """(factorisations repeated in FP64 by the last mixed evaluation, total per evaluation)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().cgd_mixed_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -17,6 +17,11 @@ using namespace cgd;
 
 namespace {
 
+// Mixed path: assumed bound on the relative error of an FP32 generating-function
+// value, in units of (matrix order + 1) * 2^-24 (calibrated against FP64 on the
+// benchmark workloads with a safety factor; see the mixed-path tests).
+constexpr double kTauScale = 16.0;
+
 thread_local std::string g_err;
 
 cgd_status fail(cgd_status s, const std::string &msg) {
@@ -347,6 +352,12 @@ struct cgd_ctx {
     int32_t *d_rb = nullptr;
     double *d_eig = nullptr;
     double2 *d_contrib = nullptr, *d_logg = nullptr, *d_gA = nullptr, *d_gB = nullptr, *d_work = nullptr;
+    // mixed path
+    float2 *d_pool32 = nullptr;
+    double2 *d_logg32 = nullptr;
+    int2 *d_list[kRegClasses] = {};
+    int2 **d_list_ptrs = nullptr;
+    int *d_counts = nullptr;
     int *d_status = nullptr;
     int *h_status = nullptr;
     hipEvent_t ev_status = nullptr;
@@ -366,7 +377,8 @@ void free_ctx(cgd_ctx *c) {
     auto fr = [](void *p) { if (p) (void)hipFree(p); };
     fr(c->d_inst); fr(c->d_blocks); fr(c->d_schur); fr(c->d_schur_prefix); fr(c->d_inst_pt_prefix);
     fr(c->d_pool); fr(c->d_rb); fr(c->d_eig); fr(c->d_contrib); fr(c->d_logg); fr(c->d_gA); fr(c->d_gB);
-    fr(c->d_work); fr(c->d_status);
+    fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list_ptrs); fr(c->d_counts);
+    for (int k = 0; k < kRegClasses; ++k) fr(c->d_list[k]);
     for (auto &k : c->classes) { fr(k.d_jobs); fr(k.d_prefix); }
     fr(c->big.d_jobs); fr(c->big.d_prefix);
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
@@ -457,6 +469,9 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.nprobs = nprob;
         d.logpr0_re = h.logpr0;
         d.logpr0_im = 0.0;
+        d.first_block = -1;
+        d.theta = INFINITY;
+        d.tau = 0.0;
         c->inst_pt_prefix[i] = pt;
         c->prob_offsets[i] = po;
         pt += np;
@@ -480,11 +495,20 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         return off;
     };
     c->blocks.resize(hblocks.size());
-    std::vector<int64_t> c_region(hblocks.size(), -1);
     for (size_t b = 0; b < hblocks.size(); ++b) {
         const HostBlock &h = hblocks[b];
         BlockDev &d = c->blocks[b];
         std::memset(&d, 0, sizeof(d));
+        InstDev &I0 = c->inst[h.inst];
+        if (I0.first_block < 0) I0.first_block = (int32_t)b;
+        d.cls = kRegClasses;
+        for (int k = 0; k < kRegClasses; ++k)
+            if (h.nb <= reg_class_limit(k)) { d.cls = k; break; }
+        if (c->prec == CGD_PREC_MIXED && d.cls < kRegClasses) {
+            // relative error of an FP32 value of G: kTauScale (n + 1) 2^-24 per block, summed
+            I0.tau += kTauScale * (h.nb + 1) * 5.9604644775390625e-08;
+            I0.theta = c->tol / I0.tau;
+        }
         d.inst = h.inst;
         d.blk = h.blk;
         d.nb = h.nb;
@@ -541,9 +565,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     c->big.cls = -1;
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         const BlockDev &d = c->blocks[b];
-        LuClass *lc = nullptr;
-        for (int k = 0; k < kRegClasses; ++k)
-            if (d.nb <= reg_class_limit(k)) { lc = &c->classes[k]; break; }
+        LuClass *lc = d.cls < kRegClasses ? &c->classes[d.cls] : nullptr;
         if (!lc) {
             if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
             lc = &c->big;
@@ -645,6 +667,23 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     if (c->big.nitems > 0) {
         HIP_OK(hipMalloc((void **)&c->d_work, sizeof(double2) * (size_t)c->big_nwg * c->big_ldw * c->big_ldw));
     }
+    if (c->prec == CGD_PREC_MIXED) {
+        std::vector<float2> p32(pool.size());
+        for (size_t i = 0; i < pool.size(); ++i) {
+            p32[i].x = (float)pool[i].x;
+            p32[i].y = (float)pool[i].y;
+        }
+        if ((s = upload(&c->d_pool32, p32)) != CGD_OK) return s;
+        HIP_OK(hipMalloc((void **)&c->d_logg32, sizeof(double2) * np));
+        std::vector<int2 *> ptrs(kRegClasses, nullptr);
+        for (int k = 0; k < kRegClasses; ++k)
+            if (c->classes[k].nitems > 0) {
+                HIP_OK(hipMalloc((void **)&c->d_list[k], sizeof(int2) * c->classes[k].nitems));
+                ptrs[k] = c->d_list[k];
+            }
+        if ((s = upload(&c->d_list_ptrs, ptrs)) != CGD_OK) return s;
+        HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kRegClasses));
+    }
     HIP_OK(hipDeviceSynchronize());
     return CGD_OK;
 }
@@ -703,36 +742,60 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
     if (c->schur_nwg > 0) {
         HIP_OK(mark(CGD_STAGE_SCHUR, 0));
         HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg,
-                                  c->schur_maxA, c->d_pool, c->d_eig, c->d_pool, st));
+                                  c->schur_maxA, c->d_pool, c->d_eig, c->d_pool, c->d_pool32, st));
         HIP_OK(mark(CGD_STAGE_SCHUR, 1));
     }
+    const bool mixed = c->prec == CGD_PREC_MIXED;
     for (auto &k : c->classes) {
         if (k.nitems == 0) continue;
-        LuLaunch a{k.d_jobs, k.d_prefix, (int)k.jobs.size(), k.nitems, c->d_blocks, c->d_inst,
-                   c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        LuLaunch a{k.d_jobs, k.d_prefix, (int)k.jobs.size(), k.nitems, nullptr, nullptr, 0, c->d_blocks,
+                   c->d_inst, mixed ? (const void *)c->d_pool32 : (const void *)c->d_pool, c->d_rb, c->d_eig,
+                   c->d_contrib, c->d_status};
         HIP_OK(mark(CGD_STAGE_LU_REG0 + k.cls, 0));
-        HIP_OK(launch_lu_reg(k.cls, a, st));
+        HIP_OK(launch_lu_reg(k.cls, mixed, a, st));
         HIP_OK(mark(CGD_STAGE_LU_REG0 + k.cls, 1));
     }
     if (c->big.nitems > 0) {
-        LuLaunch a{c->big.d_jobs, c->big.d_prefix, (int)c->big.jobs.size(), c->big.nitems, c->d_blocks, c->d_inst,
-                   c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        LuLaunch a{c->big.d_jobs, c->big.d_prefix, (int)c->big.jobs.size(), c->big.nitems, nullptr, nullptr, 0,
+                   c->d_blocks, c->d_inst, c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
         HIP_OK(mark(CGD_STAGE_LU_BIG, 0));
         HIP_OK(launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st));
         HIP_OK(mark(CGD_STAGE_LU_BIG, 1));
     }
     HIP_OK(mark(CGD_STAGE_COMBINE, 0));
-    HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA, st));
-    HIP_OK(mark(CGD_STAGE_COMBINE, 1));
+    if (mixed) {
+        // FP32 values -> select the points that matter -> FP64 re-factorisation of those
+        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg32,
+                              c->d_gA, st));
+        HIP_OK(mark(CGD_STAGE_COMBINE, 1));
+        HIP_OK(mark(CGD_STAGE_FIX, 0));
+        HIP_OK(launch_zero_ints(c->d_counts, kRegClasses, st));
+        HIP_OK(launch_select_points(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_blocks, c->d_logg32,
+                                    c->d_list_ptrs, c->d_counts, kRegClasses, st));
+        for (auto &k : c->classes) {
+            if (k.nitems == 0) continue;
+            LuLaunch a{nullptr, nullptr, 0, 0, c->d_list[k.cls], c->d_counts + k.cls, k.nitems, c->d_blocks,
+                       c->d_inst, c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+            HIP_OK(launch_lu_reg(k.cls, false, a, st));
+        }
+        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA,
+                              st));
+        HIP_OK(mark(CGD_STAGE_FIX, 1));
+    } else {
+        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA,
+                              st));
+        HIP_OK(mark(CGD_STAGE_COMBINE, 1));
+    }
     HIP_OK(mark(CGD_STAGE_DFT, 0));
     for (size_t si = 0; si < c->stages.size(); ++si) {
         DftStage &S = c->stages[si];
         const double2 *in = (si % 2 == 0) ? c->d_gA : c->d_gB;
         double2 *out = (si % 2 == 0) ? c->d_gB : c->d_gA;
-        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, d_probs, d_err_bound,
-                                c->d_status, st));
+        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, d_probs,
+                                mixed ? nullptr : d_err_bound, c->d_status, st));
     }
     HIP_OK(mark(CGD_STAGE_DFT, 1));
+    if (mixed) HIP_OK(launch_mixed_err(c->d_inst, c->n_inst, c->d_logg32, d_err_bound, c->d_status, st));
     HIP_OK(hipMemcpyAsync(c->h_status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_OK(hipEventRecord(c->ev_status, st));
     c->status_pending = true;
@@ -774,6 +837,23 @@ cgd_status cgd_stage_times(cgd_ctx *c, double *ms) {
         HIP_OK(hipEventElapsedTime(&t, c->ev[i][0], c->ev[i][1]));
         ms[i] = t;
     }
+    return CGD_OK;
+}
+
+cgd_status cgd_mixed_stats(cgd_ctx *c, int64_t *n_refactored, int64_t *n_total) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (c->prec != CGD_PREC_MIXED || !c->evaluated) return fail(CGD_ERR_STATE, "no mixed evaluation yet");
+    int h[kRegClasses];
+    if (c->stream) HIP_OK(hipStreamSynchronize(c->stream)); else HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost));
+    int64_t tot = 0, all = 0;
+    for (int k = 0; k < kRegClasses; ++k) {
+        tot += h[k];
+        all += c->classes[k].nitems;
+    }
+    all += c->big.nitems;
+    if (n_refactored) *n_refactored = tot;
+    if (n_total) *n_total = all;
     return CGD_OK;
 }
 

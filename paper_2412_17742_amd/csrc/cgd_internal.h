@@ -25,6 +25,10 @@ struct InstDev {
     int64_t prob_off;         // first output probability
     int64_t nprobs;           // prod (N_l + 1)
     double logpr0_re, logpr0_im;  // constant part of log G (vacuum probability, traced modes)
+    int32_t first_block;      // this instance's blocks are first_block .. first_block + nblocks - 1
+    int32_t pad2;
+    double theta;             // mixed path: points with |G| > theta are re-evaluated in FP64
+    double tau;               // mixed path: relative error bound assumed for an FP32 value of G
 };
 
 // One factorisation job family: an (instance, internal block) pair.  Every
@@ -43,6 +47,8 @@ struct BlockDev {
     int64_t hs_stride;        // complex stride per k of the eliminated bin (0: one matrix)
     int64_t rb_off;           // offset of nb row-bin indices (-1: factor 1)
     int64_t eig_off;          // offset of the eliminated bin's eigenvalues
+    int32_t cls;              // FP64 size class (register classes 0.., or kRegClassesMax for blocked)
+    int32_t pad;
 };
 
 // Build of the Schur matrices C(w_A) = H_BB + P diag(w_A / (1 - w_A lambda)) Q
@@ -70,9 +76,12 @@ struct LuLaunch {
     const int64_t *job_prefix;
     int njobs;
     int64_t nitems;
+    const int2 *list;          // explicit (block, point) items, or nullptr
+    const int *list_count;
+    int64_t list_capacity;
     const BlockDev *blocks;
     const InstDev *insts;
-    const double2 *Hpool;
+    const void *pool;          // double2 or float2 matrices
     const int32_t *rbpool;
     const double *eigpool;
     double2 *contrib;
@@ -82,11 +91,19 @@ struct LuLaunch {
 // launchers (cgd_kernels.hip)
 int reg_class_limit(int cls);          // max matrix order of register class cls (0 = none)
 constexpr int kRegClasses = 5;
-hipError_t launch_lu_reg(int cls, const LuLaunch &a, hipStream_t st);
+hipError_t launch_lu_reg(int cls, bool fp32, const LuLaunch &a, hipStream_t st);
 size_t lu_big_lds_bytes(int ldw);
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st);
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
-                              const double2 *pool_in, const double *eigpool, double2 *pool_out, hipStream_t st);
+                              const double2 *pool_in, const double *eigpool, double2 *pool_out, float2 *pool32_out,
+                              hipStream_t st);
+// mixed path
+hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
+hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                                const BlockDev *blocks, const double2 *logg, int2 *const *lists, int *counts,
+                                int n_lists, hipStream_t st);
+hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, double *err, const int *status,
+                            hipStream_t st);
 int schur_rows_per_wg();
 hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
                           const double2 *contrib, double2 *logg, double2 *gval, hipStream_t st);

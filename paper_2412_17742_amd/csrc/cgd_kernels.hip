@@ -103,7 +103,7 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2 *s_red) {
 // ---------------------------------------------------------------------------
 // Kernel A: register-resident unpivoted LU, one workgroup per (block, point).
 //
-// The (padded) NR x NR matrix is distributed cyclically over a PR x PC thread
+// The (padded) N x N matrix is distributed cyclically over a PR x PC thread
 // grid: element (i, j) lives in thread (i % PR, j % PC) at register slot
 // (i / PR, j / PC).  Step k broadcasts row k and column k through LDS
 // (double-buffered, one barrier per step) and every thread applies the
@@ -111,142 +111,192 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2 *s_red) {
 // unrolled loop over register rows r (k in [r PR, (r+1) PR)) so that every
 // register index is a compile-time constant and the update only touches the
 // register rows >= r and columns >= (r PR)/PC that can still be active.
+//
+// T = double: the FP64 path.  T = float: the first pass of the mixed path
+// (matrix and elimination in complex FP32, logarithms of the pivots and
+// their sum in FP64).  The workgroup loops over its items, either the
+// contiguous range of a size class (job prefix sums) or an explicit list of
+// (block, point) pairs built on the device.
 // ---------------------------------------------------------------------------
-template <int PR, int PC, int TR, int TC>
-__global__ void __launch_bounds__(PR *PC)
-lu_reg_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ job_prefix, int njobs,
-           const BlockDev *__restrict__ blocks, const InstDev *__restrict__ insts,
-           const double2 *__restrict__ Hpool, const int32_t *__restrict__ rbpool,
-           const double *__restrict__ eigpool, double2 *__restrict__ contrib,
-           int *__restrict__ status)
+template <typename T> struct cx2 { T x, y; };
+template <typename T> __device__ __forceinline__ cx2<T> mk2(T a, T b) { cx2<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ cx2<T> mul2(cx2<T> a, cx2<T> b) {
+    return mk2<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ cx2<T> fnms2(cx2<T> a, cx2<T> l, cx2<T> u) {
+    a.x = fma(-l.x, u.x, a.x);
+    a.x = fma(l.y, u.y, a.x);
+    a.y = fma(-l.x, u.y, a.y);
+    a.y = fma(-l.y, u.x, a.y);
+    return a;
+}
+template <typename T> __device__ __forceinline__ cx2<T> inv2(cx2<T> d) {
+    const T s = T(1) / (d.x * d.x + d.y * d.y);
+    return mk2<T>(d.x * s, -d.y * s);
+}
+template <typename T> struct PoolT;
+template <> struct PoolT<double> { typedef double2 type; };
+template <> struct PoolT<float> { typedef float2 type; };
+
+struct LuArgs {
+    const int32_t *job_block;
+    const int64_t *job_prefix;
+    int njobs;
+    int64_t nitems;
+    const int2 *list;         // explicit (block, point) items, or nullptr
+    const int *list_count;
+    const BlockDev *blocks;
+    const InstDev *insts;
+    const void *pool;         // double2 (FP64) or float2 (FP32) matrices
+    const int32_t *rbpool;
+    const double *eigpool;
+    double2 *contrib;
+    int *status;
+};
+
+template <typename T, int PR, int PC, int TR, int TC>
+__global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 {
+    typedef cx2<T> C;
+    typedef typename PoolT<T>::type PT;
     constexpr int NT = PR * PC;
     constexpr int N = PR * TR;
     static_assert(PR * TR == PC * TC, "square padding");
     static_assert(PC % PR == 0, "column owner must be uniform over a register row");
-    __shared__ double2 s_u[2][N];
-    __shared__ double2 s_l[2][N];
-    __shared__ double2 s_d[N];
-    __shared__ double2 s_piv[N];
+    __shared__ C s_u[2][N];
+    __shared__ C s_l[2][N];
+    __shared__ C s_d[N];
+    __shared__ C s_piv[N];
     __shared__ double2 s_w[kMaxBins];
     __shared__ double2 s_red[NT / 64 + 1];
     __shared__ int s_bad;
 
     const int tid = threadIdx.x;
     const int tx = tid % PC, ty = tid / PC;
-    const int64_t item = blockIdx.x;
-    const int job = find_job(job_prefix, njobs, item);
-    const BlockDev B = blocks[job_block[job]];
-    const InstDev &I = insts[B.inst];
-    const int64_t pt = item - job_prefix[job];
-    const int nb = B.nb;
-
-    if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    for (int i = tid; i < nb; i += NT) {
-        const int b = rbpool[B.rb_off + i];
-        s_d[i] = b < 0 ? cmk(1.0, 0.0) : s_w[b];
-    }
-    __syncthreads();
-
-    const double2 *__restrict__ Hs = Hpool + B.h_off;
-    if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
-
-    double2 a[TR][TC];
-    #pragma unroll
-    for (int r = 0; r < TR; ++r) {
-        const int i = r * PR + ty;
-        #pragma unroll
-        for (int c = 0; c < TC; ++c) {
-            const int j = c * PC + tx;
-            double2 v = cmk(i == j ? 1.0 : 0.0, 0.0);
-            if (i < nb && j < nb) {
-                const double2 h = Hs[(int64_t)i * nb + j];
-                const double2 d = s_d[i];
-                v.x -= d.x * h.x - d.y * h.y;
-                v.y -= d.x * h.y + d.y * h.x;
-            }
-            a[r][c] = v;
+    {
+        const int64_t item = blockIdx.x;
+        if (A.list && item >= (int64_t)*A.list_count) return;
+        int bi;
+        int64_t pt;
+        if (A.list) {
+            const int2 e = A.list[item];
+            bi = e.x;
+            pt = e.y;
+        } else {
+            const int job = find_job(A.job_prefix, A.njobs, item);
+            bi = A.job_block[job];
+            pt = item - A.job_prefix[job];
         }
-    }
+        const BlockDev B = A.blocks[bi];
+        const InstDev &I = A.insts[B.inst];
+        const int nb = B.nb;
 
-    #pragma unroll
-    for (int r = 0; r < TR; ++r) {
-        const int cown = (r * PR) / PC;
-        int kend = nb - r * PR;
-        kend = kend < 0 ? 0 : (kend > PR ? PR : kend);
-        for (int kk = 0; kk < kend; ++kk) {
-            const int k = r * PR + kk;
-            const int buf = k & 1;
-            if (ty == kk) {
+        if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+        if (tid == 0) s_bad = 0;
+        __syncthreads();
+        for (int i = tid; i < nb; i += NT) {
+            const int b = A.rbpool[B.rb_off + i];
+            s_d[i] = b < 0 ? mk2<T>(T(1), T(0)) : mk2<T>((T)s_w[b].x, (T)s_w[b].y);
+        }
+        __syncthreads();
+
+        const PT *__restrict__ Hs = (const PT *)A.pool + B.h_off;
+        if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
+
+        C a[TR][TC];
+        #pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            const int i = r * PR + ty;
+            #pragma unroll
+            for (int c = 0; c < TC; ++c) {
+                const int j = c * PC + tx;
+                C v = mk2<T>(i == j ? T(1) : T(0), T(0));
+                if (i < nb && j < nb) {
+                    const PT h = Hs[(int64_t)i * nb + j];
+                    const C d = s_d[i];
+                    v.x -= d.x * h.x - d.y * h.y;
+                    v.y -= d.x * h.y + d.y * h.x;
+                }
+                a[r][c] = v;
+            }
+        }
+
+        #pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            const int cown = (r * PR) / PC;
+            int kend = nb - r * PR;
+            kend = kend < 0 ? 0 : (kend > PR ? PR : kend);
+            for (int kk = 0; kk < kend; ++kk) {
+                const int k = r * PR + kk;
+                const int buf = k & 1;
+                if (ty == kk) {
+                    #pragma unroll
+                    for (int c = cown; c < TC; ++c) {
+                        const int j = c * PC + tx;
+                        if (j >= k) s_u[buf][j] = a[r][c];
+                    }
+                }
+                if (tx == k % PC) {
+                    #pragma unroll
+                    for (int r2 = r; r2 < TR; ++r2) {
+                        const int i = r2 * PR + ty;
+                        if (i > k) s_l[buf][i] = a[r2][cown];
+                    }
+                }
+                __syncthreads();
+                const C d = s_u[buf][k];
+                if (tid == 0) {
+                    s_piv[k] = d;
+                    if (!(d.x > T(0)) || !isfinite(d.y)) s_bad = 1;
+                }
+                const C dinv = inv2<T>(d);
+                C u[TC];
                 #pragma unroll
                 for (int c = cown; c < TC; ++c) {
                     const int j = c * PC + tx;
-                    if (j >= k) s_u[buf][j] = a[r][c];
+                    u[c] = (j > k && j < nb) ? s_u[buf][j] : mk2<T>(T(0), T(0));
                 }
-            }
-            if (tx == k % PC) {
                 #pragma unroll
                 for (int r2 = r; r2 < TR; ++r2) {
                     const int i = r2 * PR + ty;
-                    if (i > k) s_l[buf][i] = a[r2][cown];
+                    const C l = (i > k && i < nb) ? mul2<T>(s_l[buf][i], dinv) : mk2<T>(T(0), T(0));
+                    #pragma unroll
+                    for (int c = cown; c < TC; ++c) a[r2][c] = fnms2<T>(a[r2][c], l, u[c]);
                 }
             }
-            __syncthreads();
-            const double2 d = s_u[buf][k];
-            if (tid == 0) {
-                s_piv[k] = d;
-                if (!(d.x > 0.0) || !isfinite(d.y)) s_bad = 1;
-            }
-            const double2 dinv = cinv(d);
-            double2 u[TC];
-            #pragma unroll
-            for (int c = cown; c < TC; ++c) {
-                const int j = c * PC + tx;
-                u[c] = (j > k && j < nb) ? s_u[buf][j] : cmk(0.0, 0.0);
-            }
-            #pragma unroll
-            for (int r2 = r; r2 < TR; ++r2) {
-                const int i = r2 * PR + ty;
-                const double2 l = (i > k && i < nb) ? cmul(s_l[buf][i], dinv) : cmk(0.0, 0.0);
-                #pragma unroll
-                for (int c = cown; c < TC; ++c) a[r2][c] = cfnms(a[r2][c], l, u[c]);
-            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // epilogue: -1/2 [sum_i Log(pivot_i) + sum_i Log(1 - w_A lambda_i)] + E
-    const int nlog = nb - B.bordered;
-    double2 acc = cmk(0.0, 0.0);
-    for (int i = tid; i < nlog; i += NT) {
-        const double2 lg = clog(s_piv[i]);
-        acc.x += lg.x;
-        acc.y += lg.y;
-    }
-    if (B.n_eig > 0) {
-        const double2 wa = s_w[B.schur_axis];
-        const double *__restrict__ lam = eigpool + B.eig_off;
-        for (int i = tid; i < B.n_eig; i += NT) {
-            const double2 lg = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
+        // epilogue: -1/2 [sum_i Log(pivot_i) + sum_i Log(1 - w_A lambda_i)] + E, in FP64
+        const int nlog = nb - B.bordered;
+        double2 acc = cmk(0.0, 0.0);
+        for (int i = tid; i < nlog; i += NT) {
+            const double2 lg = clog(cmk((double)s_piv[i].x, (double)s_piv[i].y));
             acc.x += lg.x;
             acc.y += lg.y;
         }
-    }
-    acc = block_sum<NT>(acc, s_red);
-    if (tid == 0) {
-        double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
-        if (B.bordered) {
-            const double2 p = s_piv[nb - 1];
-            res.x += 0.5 * (1.0 - p.x);
-            res.y += 0.5 * (0.0 - p.y);
+        if (B.n_eig > 0) {
+            const double2 wa = s_w[B.schur_axis];
+            const double *__restrict__ lam = A.eigpool + B.eig_off;
+            for (int i = tid; i < B.n_eig; i += NT) {
+                const double2 lg = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
+                acc.x += lg.x;
+                acc.y += lg.y;
+            }
         }
-        contrib[I.c_off + pt * I.nblocks + B.blk] = res;
-        if (s_bad) atomicOr(status, 1);
+        acc = block_sum<NT>(acc, s_red);
+        if (tid == 0) {
+            double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
+            if (B.bordered) {
+                const C p = s_piv[nb - 1];
+                res.x += 0.5 * (1.0 - (double)p.x);
+                res.y += 0.5 * (0.0 - (double)p.y);
+            }
+            A.contrib[I.c_off + pt * I.nblocks + B.blk] = res;
+            if (s_bad) atomicOr(A.status, 1);
+        }
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // Kernel B: unpivoted LU for orders above the register-resident limit.  One
@@ -434,7 +484,7 @@ constexpr int kSchurRows = 8;
 __global__ void __launch_bounds__(256)
 schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ job_prefix, int njobs,
                 const double2 *__restrict__ pool_in, const double *__restrict__ eigpool,
-                double2 *__restrict__ pool_out)
+                double2 *__restrict__ pool_out, float2 *__restrict__ pool32_out)
 {
     extern __shared__ double2 s_dyn[];
     const int job = find_job(job_prefix, njobs, blockIdx.x);
@@ -483,7 +533,16 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
         #pragma unroll
         for (int rr = 0; rr < kSchurRows; ++rr) {
             const int r = r0 + rr;
-            if (r < J.nB) C[(int64_t)r * J.nB + col] = acc[rr];
+            if (r < J.nB) {
+                const int64_t o = (int64_t)r * J.nB + col;
+                C[o] = acc[rr];
+                if (pool32_out) {
+                    float2 f;
+                    f.x = (float)acc[rr].x;
+                    f.y = (float)acc[rr].y;
+                    pool32_out[J.c_off + (int64_t)k * J.nB * J.nB + o] = f;
+                }
+            }
         }
     }
 }
@@ -560,14 +619,77 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
 }
 
 // ---------------------------------------------------------------------------
+// Mixed path.  After the FP32 pass, a point's value of G carries a relative
+// error of at most tau (per instance); it enters each probability as
+// c_k |G_k| tau / prod G, and sum_k c_k = prod G over the half grid.  So
+// re-evaluating in FP64 every point with |G_k| > theta = tol / tau bounds the
+// error of every probability by tol.  select_points appends the (block, point)
+// items of those points to one list per FP64 size class.
+// ---------------------------------------------------------------------------
+__global__ void zero_ints(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void select_points(const InstDev *__restrict__ insts, const int64_t *__restrict__ inst_pt_prefix,
+                              int n_inst, int64_t npts, const BlockDev *__restrict__ blocks,
+                              const double2 *__restrict__ logg, int2 *const *__restrict__ lists,
+                              int *__restrict__ counts, int n_lists)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const int i = find_job(inst_pt_prefix, n_inst, p);
+    const InstDev &I = insts[i];
+    if (!(logg[p].x > log(I.theta))) return;
+    const int64_t lp = p - I.pt_off;
+    for (int b = 0; b < I.nblocks; ++b) {
+        const int bi = I.first_block + b;
+        const int cls = blocks[bi].cls;
+        if (cls < 0 || cls >= n_lists || !lists[cls]) continue;
+        const int slot = atomicAdd(&counts[cls], 1);
+        lists[cls][slot] = make_int2(bi, (int)lp);
+    }
+}
+
+// Per instance: (1 / prod G) sum over the points left in FP32 of c_k |G_k| tau,
+// the bound on the error of every probability (deterministic order).
+__global__ void mixed_err(const InstDev *__restrict__ insts, const double2 *__restrict__ logg,
+                          double *__restrict__ err, const int *__restrict__ status)
+{
+    __shared__ double2 s_red[256 / 64 + 1];
+    const InstDev &I = insts[blockIdx.x];
+    int64_t stride = 1;
+    for (int l = 1; l < I.L; ++l) stride *= I.G[l];
+    const double lt = log(I.theta);
+    double acc = 0.0;
+    for (int64_t p = threadIdx.x; p < I.npts; p += blockDim.x) {
+        const double2 v = logg[I.pt_off + p];
+        if (v.x > lt) continue;
+        const int64_t k1 = p / stride;
+        const double ck = (k1 == 0 || 2 * k1 == I.G[0]) ? 1.0 : 2.0;
+        acc += ck * exp(v.x);
+    }
+    double2 t = block_sum<256>(cmk(acc, 0.0), s_red);
+    if (threadIdx.x == 0) {
+        double gprod = 1;
+        for (int l = 0; l < I.L; ++l) gprod *= I.G[l];
+        err[blockIdx.x] = (*status) ? INFINITY : t.x * I.tau / gprod;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
 
-template <int PR, int PC, int TR, int TC>
+template <typename T, int PR, int PC, int TR, int TC>
 static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
-    hipLaunchKernelGGL((lu_reg_f64<PR, PC, TR, TC>), dim3((unsigned)a.nitems), dim3(PR * PC), 0, st,
-                       a.job_block, a.job_prefix, a.njobs, a.blocks, a.insts, a.Hpool, a.rbpool, a.eigpool,
-                       a.contrib, a.status);
+    LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
+             a.rbpool, a.eigpool, a.contrib, a.status};
+    // one item per workgroup; for a device-built list the grid covers its capacity and
+    // workgroups past the list's length return at once
+    const int64_t grid = a.list ? a.list_capacity : a.nitems;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((lu_reg<T, PR, PC, TR, TC>), dim3((unsigned)grid), dim3(PR * PC), 0, st, A);
     return hipGetLastError();
 }
 
@@ -582,16 +704,21 @@ int reg_class_limit(int cls) {
     }
 }
 
-hipError_t launch_lu_reg(int cls, const LuLaunch &a, hipStream_t st) {
-    if (a.nitems <= 0) return hipSuccess;
+template <typename T>
+static hipError_t launch_reg_t(int cls, const LuLaunch &a, hipStream_t st) {
     switch (cls) {
-        case 0: return launch_reg<8, 8, 4, 4>(a, st);
-        case 1: return launch_reg<16, 16, 4, 4>(a, st);
-        case 2: return launch_reg<16, 32, 6, 3>(a, st);
-        case 3: return launch_reg<16, 32, 8, 4>(a, st);
-        case 4: return launch_reg<16, 48, 9, 3>(a, st);
+        case 0: return launch_reg<T, 8, 8, 4, 4>(a, st);
+        case 1: return launch_reg<T, 16, 16, 4, 4>(a, st);
+        case 2: return launch_reg<T, 16, 32, 6, 3>(a, st);
+        case 3: return launch_reg<T, 16, 32, 8, 4>(a, st);
+        case 4: return launch_reg<T, 16, 48, 9, 3>(a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_lu_reg(int cls, bool fp32, const LuLaunch &a, hipStream_t st) {
+    if (!a.list && a.nitems <= 0) return hipSuccess;
+    return fp32 ? launch_reg_t<float>(cls, a, st) : launch_reg_t<double>(cls, a, st);
 }
 
 size_t lu_big_lds_bytes(int ldw) {
@@ -604,20 +731,21 @@ hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hip
                                        (int)lu_big_lds_bytes(ldw));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(lu_big_f64, dim3(nwg), dim3(kBigThreads), lu_big_lds_bytes(ldw), st, a.job_block,
-                       a.job_prefix, a.njobs, a.nitems, a.blocks, a.insts, a.Hpool, a.rbpool, a.eigpool, work,
-                       ldw, a.contrib, a.status);
+                       a.job_prefix, a.njobs, a.nitems, a.blocks, a.insts, (const double2 *)a.pool, a.rbpool,
+                       a.eigpool, work, ldw, a.contrib, a.status);
     return hipGetLastError();
 }
 
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
-                              const double2 *pool_in, const double *eigpool, double2 *pool_out, hipStream_t st) {
+                              const double2 *pool_in, const double *eigpool, double2 *pool_out, float2 *pool32_out,
+                              hipStream_t st) {
     if (nwg <= 0) return hipSuccess;
     const size_t lds = sizeof(double2) * (size_t)maxA * (1 + kSchurRows);
     hipError_t e = hipFuncSetAttribute((const void *)schur_build_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(schur_build_f64, dim3((unsigned)nwg), dim3(256), lds, st, jobs, prefix, njobs, pool_in,
-                       eigpool, pool_out);
+                       eigpool, pool_out, pool32_out);
     return hipGetLastError();
 }
 
@@ -641,4 +769,28 @@ hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, in
 }
 
 
+}  // namespace cgd
+
+namespace cgd {
+hipError_t launch_zero_ints(int *p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_ints, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                                const BlockDev *blocks, const double2 *logg, int2 *const *lists, int *counts,
+                                int n_lists, hipStream_t st) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(select_points, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts,
+                       inst_pt_prefix, n_inst, npts, blocks, logg, lists, counts, n_lists);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, double *err, const int *status,
+                            hipStream_t st) {
+    if (n_inst <= 0 || !err) return hipSuccess;
+    hipLaunchKernelGGL(mixed_err, dim3(n_inst), dim3(256), 0, st, insts, logg, err, status);
+    return hipGetLastError();
+}
 }  // namespace cgd
