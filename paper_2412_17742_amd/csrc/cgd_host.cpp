@@ -305,8 +305,13 @@ cgd_status upload(T **dptr, const std::vector<T> &host) {
     return CGD_OK;
 }
 
+constexpr int kG64 = kRegClasses + 1;
+
+// timing slot of an LU launch: order buckets <=32, <=64, <=96, <=128, <=144, above
+int lu_stage(int cls) { return cls < 5 ? CGD_STAGE_LU_REG0 + cls : CGD_STAGE_LU_BIG; }
+
 struct LuClass {
-    int cls = 0;  // register class, or -1 for the blocked kernel
+    int cls = 0;  // class index within its group family
     std::vector<int32_t> jobs;
     std::vector<int64_t> prefix;
     int64_t nitems = 0;
@@ -336,8 +341,10 @@ struct cgd_ctx {
     std::vector<int64_t> schur_prefix;
     int64_t schur_nwg = 0;
     int schur_maxA = 0;
-    std::vector<LuClass> classes;
-    LuClass big;
+    // FP64 groups: register classes 0..kRegClasses-1, blocked kernel kRegClasses;
+    // mixed path: FP32 MFMA groups for the first pass
+    LuClass g64[kG64];
+    LuClass g32[kMfmaClasses];
     int big_ldw = 0, big_nwg = 0;
     std::vector<DftStage> stages;
     std::vector<int64_t> prob_offsets, inst_pt_prefix;
@@ -355,7 +362,8 @@ struct cgd_ctx {
     // mixed path
     float2 *d_pool32 = nullptr;
     double2 *d_logg32 = nullptr;
-    int2 *d_list[kRegClasses] = {};
+    int2 *d_list[kG64] = {};
+    int64_t list_cap[kG64] = {};
     int2 **d_list_ptrs = nullptr;
     int *d_counts = nullptr;
     int *d_status = nullptr;
@@ -378,9 +386,9 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_inst); fr(c->d_blocks); fr(c->d_schur); fr(c->d_schur_prefix); fr(c->d_inst_pt_prefix);
     fr(c->d_pool); fr(c->d_rb); fr(c->d_eig); fr(c->d_contrib); fr(c->d_logg); fr(c->d_gA); fr(c->d_gB);
     fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list_ptrs); fr(c->d_counts);
-    for (int k = 0; k < kRegClasses; ++k) fr(c->d_list[k]);
-    for (auto &k : c->classes) { fr(k.d_jobs); fr(k.d_prefix); }
-    fr(c->big.d_jobs); fr(c->big.d_prefix);
+    for (int k = 0; k < kG64; ++k) fr(c->d_list[k]);
+    for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
+    for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
     for (int i = 0; i < CGD_NSTAGES; ++i)
         for (int j = 0; j < 2; ++j)
@@ -504,7 +512,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.cls = kRegClasses;
         for (int k = 0; k < kRegClasses; ++k)
             if (h.nb <= reg_class_limit(k)) { d.cls = k; break; }
-        if (c->prec == CGD_PREC_MIXED && d.cls < kRegClasses) {
+        d.fp32 = (c->prec == CGD_PREC_MIXED && h.nb <= mfma_class_limit(kMfmaClasses - 1)) ? 1 : 0;
+        if (d.fp32) {
             // relative error of an FP32 value of G: kTauScale (n + 1) 2^-24 per block, summed
             I0.tau += kTauScale * (h.nb + 1) * 5.9604644775390625e-08;
             I0.theta = c->tol / I0.tau;
@@ -559,24 +568,32 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     if ((int64_t)c->schur_maxA * (1 + rows) * 16 > 150 * 1024)
         return fail(CGD_ERR_ARG, "eliminated bin too large for the Schur build");
 
-    // LU work lists per size class
-    c->classes.resize(kRegClasses);
-    for (int k = 0; k < kRegClasses; ++k) c->classes[k].cls = k;
-    c->big.cls = -1;
+    // LU work lists: FP64 groups (everything on the FP64 path; on the mixed path
+    // the blocks without an FP32 pass), FP32 MFMA groups (mixed first pass),
+    // and the capacity of the mixed second-pass lists per FP64 group
+    for (int k = 0; k < kG64; ++k) c->g64[k].cls = k;
+    for (int k = 0; k < kMfmaClasses; ++k) c->g32[k].cls = k;
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         const BlockDev &d = c->blocks[b];
-        LuClass *lc = d.cls < kRegClasses ? &c->classes[d.cls] : nullptr;
-        if (!lc) {
+        if (d.cls == kRegClasses) {
             if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
-            lc = &c->big;
             c->big_ldw = std::max(c->big_ldw, d.nb);
+        }
+        const int64_t np = c->inst[d.inst].npts;
+        LuClass *lc = &c->g64[d.cls];
+        if (d.fp32) {
+            int k32 = 0;
+            while (d.nb > mfma_class_limit(k32)) ++k32;
+            lc = &c->g32[k32];
+            c->list_cap[d.cls] += np;
         }
         lc->prefix.push_back(lc->nitems);
         lc->jobs.push_back((int32_t)b);
-        lc->nitems += c->inst[d.inst].npts;
+        lc->nitems += np;
     }
-    if (c->big.nitems > 0) {
-        c->big_nwg = (int)std::min<int64_t>(c->big.nitems, 1024);
+    {
+        const int64_t big_items = c->g64[kRegClasses].nitems + c->list_cap[kRegClasses];
+        if (big_items > 0) c->big_nwg = (int)std::min<int64_t>(big_items, 1024);
     }
 
     // DFT stages
@@ -619,15 +636,16 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         for (int m = 0; m < (int)n; ++m) f += 8.0 * m * m + 6.0 * m;
         return f;
     };
-    for (int k = 0; k < kRegClasses; ++k)
-        for (size_t j = 0; j < c->classes[k].jobs.size(); ++j) {
-            const BlockDev &d = c->blocks[c->classes[k].jobs[j]];
-            c->work_flops[CGD_STAGE_LU_REG0 + k] += lu_flops(d.nb) * c->inst[d.inst].npts;
+    for (int k = 0; k < kG64; ++k)
+        for (int32_t bj : c->g64[k].jobs) {
+            const BlockDev &d = c->blocks[bj];
+            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
         }
-    for (size_t j = 0; j < c->big.jobs.size(); ++j) {
-        const BlockDev &d = c->blocks[c->big.jobs[j]];
-        c->work_flops[CGD_STAGE_LU_BIG] += lu_flops(d.nb) * c->inst[d.inst].npts;
-    }
+    for (int k = 0; k < kMfmaClasses; ++k)
+        for (int32_t bj : c->g32[k].jobs) {
+            const BlockDev &d = c->blocks[bj];
+            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
+        }
     for (const SchurDev &sj : c->schur) c->work_flops[CGD_STAGE_SCHUR] += 8.0 * sj.nA * (double)sj.nB * sj.nB * sj.nk;
     for (const DftStage &st : c->stages)
         for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
@@ -644,12 +662,13 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     if ((s = upload(&c->d_pool, pool)) != CGD_OK) return s;
     if ((s = upload(&c->d_rb, rbpool)) != CGD_OK) return s;
     if ((s = upload(&c->d_eig, eigpool)) != CGD_OK) return s;
-    for (auto &k : c->classes) {
-        if ((s = upload(&k.d_jobs, k.jobs)) != CGD_OK) return s;
-        if ((s = upload(&k.d_prefix, k.prefix)) != CGD_OK) return s;
+    for (auto *grp : {&c->g64[0], &c->g32[0]}) {
+        const int n = grp == &c->g64[0] ? kG64 : kMfmaClasses;
+        for (int k = 0; k < n; ++k) {
+            if ((s = upload(&grp[k].d_jobs, grp[k].jobs)) != CGD_OK) return s;
+            if ((s = upload(&grp[k].d_prefix, grp[k].prefix)) != CGD_OK) return s;
+        }
     }
-    if ((s = upload(&c->big.d_jobs, c->big.jobs)) != CGD_OK) return s;
-    if ((s = upload(&c->big.d_prefix, c->big.prefix)) != CGD_OK) return s;
     for (auto &st : c->stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
@@ -664,7 +683,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     HIP_OK(hipHostMalloc((void **)&c->h_status, sizeof(int), hipHostMallocDefault));
     *c->h_status = 0;
     HIP_OK(hipEventCreateWithFlags(&c->ev_status, hipEventDisableTiming));
-    if (c->big.nitems > 0) {
+    if (c->big_nwg > 0) {
         HIP_OK(hipMalloc((void **)&c->d_work, sizeof(double2) * (size_t)c->big_nwg * c->big_ldw * c->big_ldw));
     }
     if (c->prec == CGD_PREC_MIXED) {
@@ -675,14 +694,14 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         }
         if ((s = upload(&c->d_pool32, p32)) != CGD_OK) return s;
         HIP_OK(hipMalloc((void **)&c->d_logg32, sizeof(double2) * np));
-        std::vector<int2 *> ptrs(kRegClasses, nullptr);
-        for (int k = 0; k < kRegClasses; ++k)
-            if (c->classes[k].nitems > 0) {
-                HIP_OK(hipMalloc((void **)&c->d_list[k], sizeof(int2) * c->classes[k].nitems));
+        std::vector<int2 *> ptrs(kG64, nullptr);
+        for (int k = 0; k < kG64; ++k)
+            if (c->list_cap[k] > 0) {
+                HIP_OK(hipMalloc((void **)&c->d_list[k], sizeof(int2) * c->list_cap[k]));
                 ptrs[k] = c->d_list[k];
             }
         if ((s = upload(&c->d_list_ptrs, ptrs)) != CGD_OK) return s;
-        HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kRegClasses));
+        HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kG64));
     }
     HIP_OK(hipDeviceSynchronize());
     return CGD_OK;
@@ -746,21 +765,31 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
         HIP_OK(mark(CGD_STAGE_SCHUR, 1));
     }
     const bool mixed = c->prec == CGD_PREC_MIXED;
-    for (auto &k : c->classes) {
-        if (k.nitems == 0) continue;
-        LuLaunch a{k.d_jobs, k.d_prefix, (int)k.jobs.size(), k.nitems, nullptr, nullptr, 0, c->d_blocks,
-                   c->d_inst, mixed ? (const void *)c->d_pool32 : (const void *)c->d_pool, c->d_rb, c->d_eig,
-                   c->d_contrib, c->d_status};
-        HIP_OK(mark(CGD_STAGE_LU_REG0 + k.cls, 0));
-        HIP_OK(launch_lu_reg(k.cls, mixed, a, st));
-        HIP_OK(mark(CGD_STAGE_LU_REG0 + k.cls, 1));
-    }
-    if (c->big.nitems > 0) {
-        LuLaunch a{c->big.d_jobs, c->big.d_prefix, (int)c->big.jobs.size(), c->big.nitems, nullptr, nullptr, 0,
-                   c->d_blocks, c->d_inst, c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
-        HIP_OK(mark(CGD_STAGE_LU_BIG, 0));
-        HIP_OK(launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st));
-        HIP_OK(mark(CGD_STAGE_LU_BIG, 1));
+    // timing: a slot spans from its first launch to its last one in this evaluation
+    auto mark_begin = [&](int stage) -> hipError_t {
+        if (!c->timing || c->stage_ran[stage]) return hipSuccess;
+        return mark(stage, 0);
+    };
+    auto launch64 = [&](int k, const int2 *list, const int *count, int64_t cap) -> hipError_t {
+        const LuClass &g = c->g64[k];
+        LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, list, count, cap, c->d_blocks,
+                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+        return k < kRegClasses ? launch_lu_reg(k, false, a, st) : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
+    };
+    if (mixed)
+        for (auto &g : c->g32) {
+            if (g.nitems == 0) continue;
+            LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, nullptr, nullptr, 0, c->d_blocks,
+                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+            HIP_OK(mark_begin(lu_stage(g.cls)));
+            HIP_OK(launch_lu_mfma(g.cls, a, st));
+            HIP_OK(mark(lu_stage(g.cls), 1));
+        }
+    for (int k = 0; k < kG64; ++k) {
+        if (c->g64[k].nitems == 0) continue;
+        HIP_OK(mark_begin(lu_stage(k)));
+        HIP_OK(launch64(k, nullptr, nullptr, 0));
+        HIP_OK(mark(lu_stage(k), 1));
     }
     HIP_OK(mark(CGD_STAGE_COMBINE, 0));
     if (mixed) {
@@ -769,14 +798,12 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
                               c->d_gA, st));
         HIP_OK(mark(CGD_STAGE_COMBINE, 1));
         HIP_OK(mark(CGD_STAGE_FIX, 0));
-        HIP_OK(launch_zero_ints(c->d_counts, kRegClasses, st));
+        HIP_OK(launch_zero_ints(c->d_counts, kG64, st));
         HIP_OK(launch_select_points(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_blocks, c->d_logg32,
-                                    c->d_list_ptrs, c->d_counts, kRegClasses, st));
-        for (auto &k : c->classes) {
-            if (k.nitems == 0) continue;
-            LuLaunch a{nullptr, nullptr, 0, 0, c->d_list[k.cls], c->d_counts + k.cls, k.nitems, c->d_blocks,
-                       c->d_inst, c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
-            HIP_OK(launch_lu_reg(k.cls, false, a, st));
+                                    c->d_list_ptrs, c->d_counts, kG64, st));
+        for (int k = 0; k < kG64; ++k) {
+            if (c->list_cap[k] == 0) continue;
+            HIP_OK(launch64(k, c->d_list[k], c->d_counts + k, c->list_cap[k]));
         }
         HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA,
                               st));
@@ -843,15 +870,15 @@ cgd_status cgd_stage_times(cgd_ctx *c, double *ms) {
 cgd_status cgd_mixed_stats(cgd_ctx *c, int64_t *n_refactored, int64_t *n_total) {
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
     if (c->prec != CGD_PREC_MIXED || !c->evaluated) return fail(CGD_ERR_STATE, "no mixed evaluation yet");
-    int h[kRegClasses];
+    int h[kG64];
     if (c->stream) HIP_OK(hipStreamSynchronize(c->stream)); else HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost));
     int64_t tot = 0, all = 0;
-    for (int k = 0; k < kRegClasses; ++k) {
+    for (int k = 0; k < kG64; ++k) {
         tot += h[k];
-        all += c->classes[k].nitems;
+        all += c->g64[k].nitems;
     }
-    all += c->big.nitems;
+    for (int k = 0; k < kMfmaClasses; ++k) all += c->g32[k].nitems;
     if (n_refactored) *n_refactored = tot;
     if (n_total) *n_total = all;
     return CGD_OK;

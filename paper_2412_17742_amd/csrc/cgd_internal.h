@@ -47,8 +47,8 @@ struct BlockDev {
     int64_t hs_stride;        // complex stride per k of the eliminated bin (0: one matrix)
     int64_t rb_off;           // offset of nb row-bin indices (-1: factor 1)
     int64_t eig_off;          // offset of the eliminated bin's eigenvalues
-    int32_t cls;              // FP64 size class (register classes 0.., or kRegClassesMax for blocked)
-    int32_t pad;
+    int32_t cls;              // FP64 size class: register classes 0..kRegClasses-1, kRegClasses = blocked
+    int32_t fp32;             // mixed path: 1 if the first pass factorises this block in FP32
 };
 
 // Build of the Schur matrices C(w_A) = H_BB + P diag(w_A / (1 - w_A lambda)) Q
@@ -92,6 +92,9 @@ struct LuLaunch {
 int reg_class_limit(int cls);          // max matrix order of register class cls (0 = none)
 constexpr int kRegClasses = 5;
 hipError_t launch_lu_reg(int cls, bool fp32, const LuLaunch &a, hipStream_t st);
+constexpr int kMfmaClasses = 6;
+int mfma_class_limit(int cls);         // max matrix order of FP32 MFMA class cls
+hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st);
 size_t lu_big_lds_bytes(int ldw);
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st);
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,

@@ -299,6 +299,263 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// Kernel M: complex FP32 unpivoted LU on MFMA (first pass of the mixed path).
+//
+// The padded 16 NTILE x 16 NTILE matrix is split into 16 x 16 tiles; tile
+// (I, J) is held by wave (I mod WR, J mod WC) as two MFMA accumulators (real
+// and imaginary part) in the 16x16x4 f32 layout: lane l, register v holds
+// element (4 (l/16) + v, l mod 16) of the tile.  The elimination proceeds in
+// panels of 4 columns k..k+3, each a block step
+//     A22 <- A22 - X (D^-1 Y),   X = A[k+4:, k:k+4], D = A[k:k+4, k:k+4], Y = A[k:k+4, k+4:],
+// which is the Schur complement after four more pivots:
+//   1. the waves holding tile column k/16 write X (and D) and the waves
+//      holding tile row k/16 write the panel rows (D and Y) to LDS; barrier;
+//   2. the waves holding tile row k/16 factorise D = L_D U_D (every lane, from
+//      LDS) and solve W = D^-1 Y, one column per lane; the wave holding the
+//      diagonal tile records the pivots of U_D; barrier;
+//   3. every tile at or right/below the panel is updated, A -= X W, with four
+//      real 16x16x4 MFMAs (complex product); lane l supplies X[row, l/16] and
+//      W[l/16, col] in the MFMA operand layouts.
+// Rows and columns already eliminated receive harmless updates (their
+// operands are zero).  Pivots go to LDS; the epilogue (FP64) is the same as in
+// the register kernel.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ float2 fmul(float2 a, float2 b) { return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ float2 fsub_mul(float2 c, float2 a, float2 b) {  // c - a b
+    return f2(c.x - (a.x * b.x - a.y * b.y), c.y - (a.x * b.y + a.y * b.x));
+}
+__device__ __forceinline__ float2 finv(float2 d) {  // 1/d with the hardware reciprocal (1 ulp)
+    const float s = __builtin_amdgcn_rcpf(d.x * d.x + d.y * d.y);
+    return f2(d.x * s, -d.y * s);
+}
+
+template <int NTILE, int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
+{
+    constexpr int NW = WR * WC;
+    constexpr int NT = 64 * NW;
+    constexpr int N = 16 * NTILE;
+    constexpr int TRW = (NTILE + WR - 1) / WR;
+    constexpr int TCW = (NTILE + WC - 1) / WC;
+    static_assert(TCW <= 4, "one tile column per lane group in step 2");
+    __shared__ float2 s_X[N][4];   // panel columns (rows >= k)
+    __shared__ float2 s_Y[4][N];   // panel rows (columns >= k)
+    __shared__ float2 s_W[4][N];   // D^-1 Y
+    __shared__ float2 s_d[N];
+    __shared__ float2 s_piv[N];
+    __shared__ double2 s_w[kMaxBins];
+    __shared__ double2 s_red[NW + 1];
+    __shared__ int s_bad;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = wave / WC, wc = wave % WC;
+    const int lg = lane >> 4, lc = lane & 15;
+
+    const int64_t item = blockIdx.x;
+    if (A.list && item >= (int64_t)*A.list_count) return;
+    int bi;
+    int64_t pt;
+    if (A.list) {
+        const int2 e = A.list[item];
+        bi = e.x;
+        pt = e.y;
+    } else {
+        const int job = find_job(A.job_prefix, A.njobs, item);
+        bi = A.job_block[job];
+        pt = item - A.job_prefix[job];
+    }
+    const BlockDev B = A.blocks[bi];
+    const InstDev &I = A.insts[B.inst];
+    const int nb = B.nb;
+
+    if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int i = tid; i < nb; i += NT) {
+        const int b = A.rbpool[B.rb_off + i];
+        s_d[i] = b < 0 ? f2(1.0f, 0.0f) : f2((float)s_w[b].x, (float)s_w[b].y);
+    }
+    __syncthreads();
+
+    const float2 *__restrict__ Hs = (const float2 *)A.pool + B.h_off;
+    if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
+
+    f32x4 ar[TRW][TCW], ai[TRW][TCW];
+    #pragma unroll
+    for (int ti = 0; ti < TRW; ++ti)
+        #pragma unroll
+        for (int tj = 0; tj < TCW; ++tj) {
+            const int It = wr + ti * WR, Jt = wc + tj * WC;
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = It * 16 + 4 * lg + v, j = Jt * 16 + lc;
+                float re = (i == j) ? 1.0f : 0.0f, im = 0.0f;
+                if (It < NTILE && Jt < NTILE && i < nb && j < nb) {
+                    const float2 h = Hs[(int64_t)i * nb + j];
+                    const float2 d = s_d[i];
+                    re -= d.x * h.x - d.y * h.y;
+                    im -= d.x * h.y + d.y * h.x;
+                }
+                ar[ti][tj][v] = re;
+                ai[ti][tj][v] = im;
+            }
+        }
+
+    const int npan = (nb + 3) >> 2;
+    #pragma unroll
+    for (int J = 0; J < NTILE; ++J) {
+        if (J * 16 >= nb) break;
+        const int tjJ = J / WC, tiJ = J / WR;
+        const bool own_col = (wc == J % WC), own_row = (wr == J % WR);
+        for (int q = 0; q < 16; q += 4) {
+            const int k = J * 16 + q;
+            if ((k >> 2) >= npan) break;
+            // 1. publish the panel
+            if (own_col && lc >= q && lc < q + 4) {
+                #pragma unroll
+                for (int ti = 0; ti < TRW; ++ti) {
+                    const int It = wr + ti * WR;
+                    if (It >= J && It < NTILE) {
+                        #pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            s_X[It * 16 + 4 * lg + v][lc - q] = f2(ar[ti][tjJ][v], ai[ti][tjJ][v]);
+                    }
+                }
+            }
+            if (own_row && lg == (q >> 2)) {
+                #pragma unroll
+                for (int tj = 0; tj < TCW; ++tj) {
+                    const int Jt = wc + tj * WC;
+                    if (Jt >= J && Jt < NTILE) {
+                        #pragma unroll
+                        for (int v = 0; v < 4; ++v) s_Y[v][Jt * 16 + lc] = f2(ar[tiJ][tj][v], ai[tiJ][tj][v]);
+                    }
+                }
+            }
+            __syncthreads();
+            // 2. D = L_D U_D and W = D^-1 Y (waves of tile row k/16, one column per lane)
+            if (own_row) {
+                const float2 d00 = s_Y[0][k], d01 = s_Y[0][k + 1], d02 = s_Y[0][k + 2], d03 = s_Y[0][k + 3];
+                const float2 d10 = s_Y[1][k], d11 = s_Y[1][k + 1], d12 = s_Y[1][k + 2], d13 = s_Y[1][k + 3];
+                const float2 d20 = s_Y[2][k], d21 = s_Y[2][k + 1], d22 = s_Y[2][k + 2], d23 = s_Y[2][k + 3];
+                const float2 d30 = s_Y[3][k], d31 = s_Y[3][k + 1], d32 = s_Y[3][k + 2], d33 = s_Y[3][k + 3];
+                const float2 r0 = finv(d00);
+                const float2 l10 = fmul(d10, r0), l20 = fmul(d20, r0), l30 = fmul(d30, r0);
+                const float2 u11 = fsub_mul(d11, l10, d01), u12 = fsub_mul(d12, l10, d02), u13 = fsub_mul(d13, l10, d03);
+                const float2 r1 = finv(u11);
+                const float2 l21 = fmul(fsub_mul(d21, l20, d01), r1), l31 = fmul(fsub_mul(d31, l30, d01), r1);
+                const float2 u22 = fsub_mul(fsub_mul(d22, l20, d02), l21, u12);
+                const float2 u23 = fsub_mul(fsub_mul(d23, l20, d03), l21, u13);
+                const float2 r2 = finv(u22);
+                const float2 l32 = fmul(fsub_mul(fsub_mul(d32, l30, d02), l31, u12), r2);
+                const float2 u33 = fsub_mul(fsub_mul(fsub_mul(d33, l30, d03), l31, u13), l32, u23);
+                const float2 r3 = finv(u33);
+                if (wc == J % WC && lane == 0) {
+                    s_piv[k] = d00;
+                    if (k + 1 < nb) s_piv[k + 1] = u11;
+                    if (k + 2 < nb) s_piv[k + 2] = u22;
+                    if (k + 3 < nb) s_piv[k + 3] = u33;
+                    const bool bad = !(d00.x > 0.f) || (k + 1 < nb && !(u11.x > 0.f)) ||
+                                     (k + 2 < nb && !(u22.x > 0.f)) || (k + 3 < nb && !(u33.x > 0.f)) ||
+                                     !isfinite(u33.x + u22.x + u11.x + d00.x);
+                    if (bad) s_bad = 1;
+                }
+                if (lg < TCW) {
+                    const int Jt = wc + lg * WC;
+                    if (Jt >= J && Jt < NTILE) {
+                        const int j = Jt * 16 + lc;
+                        float2 w0 = f2(0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
+                        if (j > k + 3) {
+                            const float2 y0 = s_Y[0][j], y1 = s_Y[1][j], y2 = s_Y[2][j], y3 = s_Y[3][j];
+                            const float2 z1 = fsub_mul(y1, l10, y0);
+                            const float2 z2 = fsub_mul(fsub_mul(y2, l20, y0), l21, z1);
+                            const float2 z3 = fsub_mul(fsub_mul(fsub_mul(y3, l30, y0), l31, z1), l32, z2);
+                            w3 = fmul(z3, r3);
+                            w2 = fmul(fsub_mul(z2, u23, w3), r2);
+                            w1 = fmul(fsub_mul(fsub_mul(z1, u12, w2), u13, w3), r1);
+                            w0 = fmul(fsub_mul(fsub_mul(fsub_mul(y0, d01, w1), d02, w2), d03, w3), r0);
+                        }
+                        s_W[0][j] = w0;
+                        s_W[1][j] = w1;
+                        s_W[2][j] = w2;
+                        s_W[3][j] = w3;
+                    }
+                }
+            }
+            __syncthreads();
+            // 3. A -= X W on MFMA: A operand -X[row, l/16], B operand W[l/16, col]
+            float anr[TRW], ani[TRW], api[TRW];
+            #pragma unroll
+            for (int ti = 0; ti < TRW; ++ti) {
+                const int It = wr + ti * WR;
+                const int i = It * 16 + lc;
+                float2 x = f2(0.f, 0.f);
+                if (It >= J && It < NTILE && i > k + 3) x = s_X[i][lg];
+                anr[ti] = -x.x;
+                ani[ti] = -x.y;
+                api[ti] = x.y;
+            }
+            float bwr[TCW], bwi[TCW];
+            #pragma unroll
+            for (int tj = 0; tj < TCW; ++tj) {
+                const int Jt = wc + tj * WC;
+                float2 w = f2(0.f, 0.f);
+                if (Jt >= J && Jt < NTILE) w = s_W[lg][Jt * 16 + lc];
+                bwr[tj] = w.x;
+                bwi[tj] = w.y;
+            }
+            #pragma unroll
+            for (int ti = 0; ti < TRW; ++ti) {
+                const int It = wr + ti * WR;
+                if (It < J || It >= NTILE) continue;
+                #pragma unroll
+                for (int tj = 0; tj < TCW; ++tj) {
+                    const int Jt = wc + tj * WC;
+                    if (Jt < J || Jt >= NTILE) continue;
+                    ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwr[tj], ar[ti][tj], 0, 0, 0);
+                    ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(api[ti], bwi[tj], ar[ti][tj], 0, 0, 0);
+                    ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwi[tj], ai[ti][tj], 0, 0, 0);
+                    ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ani[ti], bwr[tj], ai[ti][tj], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    const int nlog = nb - B.bordered;
+    double2 acc = cmk(0.0, 0.0);
+    for (int i = tid; i < nlog; i += NT) {
+        const double2 lgv = clog(cmk((double)s_piv[i].x, (double)s_piv[i].y));
+        acc.x += lgv.x;
+        acc.y += lgv.y;
+    }
+    if (B.n_eig > 0) {
+        const double2 wa = s_w[B.schur_axis];
+        const double *__restrict__ lam = A.eigpool + B.eig_off;
+        for (int i = tid; i < B.n_eig; i += NT) {
+            const double2 lgv = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
+            acc.x += lgv.x;
+            acc.y += lgv.y;
+        }
+    }
+    acc = block_sum<NT>(acc, s_red);
+    if (tid == 0) {
+        double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
+        if (B.bordered) {
+            const float2 pb = s_piv[nb - 1];
+            res.x += 0.5 * (1.0 - (double)pb.x);
+            res.y += 0.5 * (0.0 - (double)pb.y);
+        }
+        A.contrib[I.c_off + pt * I.nblocks + B.blk] = res;
+        if (s_bad) atomicOr(A.status, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Kernel B: unpivoted LU for orders above the register-resident limit.  One
 // workgroup per (block, point), persistent over the work list; the matrix
 // lives in a per-workgroup global workspace (L2/MALL resident) and is
@@ -312,7 +569,8 @@ constexpr int kBigThreads = 256;
 
 __global__ void __launch_bounds__(kBigThreads)
 lu_big_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ job_prefix, int njobs,
-           int64_t nitems, const BlockDev *__restrict__ blocks, const InstDev *__restrict__ insts,
+           int64_t nitems_range, const int2 *__restrict__ list, const int *__restrict__ list_count,
+           const BlockDev *__restrict__ blocks, const InstDev *__restrict__ insts,
            const double2 *__restrict__ Hpool, const int32_t *__restrict__ rbpool,
            const double *__restrict__ eigpool, double2 *__restrict__ work, int ldw,
            double2 *__restrict__ contrib, int *__restrict__ status)
@@ -329,12 +587,22 @@ lu_big_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ jo
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
     double2 *__restrict__ W = work + (size_t)blockIdx.x * ldw * ldw;
+    const int64_t nitems = list ? (int64_t)*list_count : nitems_range;
 
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const int job = find_job(job_prefix, njobs, item);
-        const BlockDev B = blocks[job_block[job]];
+        int bi;
+        int64_t pt;
+        if (list) {
+            const int2 e = list[item];
+            bi = e.x;
+            pt = e.y;
+        } else {
+            const int job = find_job(job_prefix, njobs, item);
+            bi = job_block[job];
+            pt = item - job_prefix[job];
+        }
+        const BlockDev B = blocks[bi];
         const InstDev &I = insts[B.inst];
-        const int64_t pt = item - job_prefix[job];
         const int nb = B.nb;
         __syncthreads();
         if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
@@ -645,7 +913,7 @@ __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *
     for (int b = 0; b < I.nblocks; ++b) {
         const int bi = I.first_block + b;
         const int cls = blocks[bi].cls;
-        if (cls < 0 || cls >= n_lists || !lists[cls]) continue;
+        if (!blocks[bi].fp32 || cls < 0 || cls >= n_lists || !lists[cls]) continue;
         const int slot = atomicAdd(&counts[cls], 1);
         lists[cls][slot] = make_int2(bi, (int)lp);
     }
@@ -716,6 +984,41 @@ static hipError_t launch_reg_t(int cls, const LuLaunch &a, hipStream_t st) {
     }
 }
 
+template <int NTILE, int WR, int WC>
+static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
+    LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
+             a.rbpool, a.eigpool, a.contrib, a.status};
+    const int64_t grid = a.list ? a.list_capacity : a.nitems;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC>), dim3((unsigned)grid), dim3(64 * WR * WC), 0, st, A);
+    return hipGetLastError();
+}
+
+int mfma_class_limit(int cls) {
+    switch (cls) {
+        case 0: return 32;
+        case 1: return 64;
+        case 2: return 96;
+        case 3: return 128;
+        case 4: return 144;
+        case 5: return 192;
+        default: return 0;
+    }
+}
+
+hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st) {
+    if (!a.list && a.nitems <= 0) return hipSuccess;
+    switch (cls) {
+        case 0: return launch_mfma<2, 1, 2>(a, st);
+        case 1: return launch_mfma<4, 2, 2>(a, st);
+        case 2: return launch_mfma<6, 2, 4>(a, st);
+        case 3: return launch_mfma<8, 2, 4>(a, st);
+        case 4: return launch_mfma<9, 3, 4>(a, st);
+        case 5: return launch_mfma<12, 3, 4>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_lu_reg(int cls, bool fp32, const LuLaunch &a, hipStream_t st) {
     if (!a.list && a.nitems <= 0) return hipSuccess;
     return fp32 ? launch_reg_t<float>(cls, a, st) : launch_reg_t<double>(cls, a, st);
@@ -726,13 +1029,13 @@ size_t lu_big_lds_bytes(int ldw) {
 }
 
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st) {
-    if (a.nitems <= 0) return hipSuccess;
+    if (!a.list && a.nitems <= 0) return hipSuccess;
     hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lu_big_lds_bytes(ldw));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(lu_big_f64, dim3(nwg), dim3(kBigThreads), lu_big_lds_bytes(ldw), st, a.job_block,
-                       a.job_prefix, a.njobs, a.nitems, a.blocks, a.insts, (const double2 *)a.pool, a.rbpool,
-                       a.eigpool, work, ldw, a.contrib, a.status);
+                       a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts,
+                       (const double2 *)a.pool, a.rbpool, a.eigpool, work, ldw, a.contrib, a.status);
     return hipGetLastError();
 }
 
