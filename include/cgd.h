@@ -69,6 +69,8 @@ typedef enum {
                                       give the same determinant; for testing/measurement) */
 #define CGD_FLAG_NO_SCHUR 2u       /* evaluate every grid point with a full factorisation
                                       instead of reusing the first bin's eigenbasis */
+#define CGD_FLAG_GRAD 4u           /* prepare cgd_grad (keeps each internal block's full
+                                      matrix on the device); needs 2M(+1) <= 96 per block */
 
 /* One instance (a Gaussian state plus its binning).  Sec. VI A (set partition
  * Lambda, coarse pattern b), Sec. VI B (internal modes). */
@@ -125,14 +127,18 @@ cgd_status cgd_eval(cgd_ctx *ctx, double *d_probs, double *d_err_bound);
 int64_t    cgd_points(const cgd_ctx *ctx);
 cgd_status cgd_grid_values(cgd_ctx *ctx, double *d_logg);
 
-/* Gradient of a real loss with respect to the inputs, given dLoss/dP.
- * Requires a preceding cgd_eval on the same context (CGD_ERR_STATE otherwise)
- * and the FP64 precision.  Outputs (device, may be NULL each):
+/* Gradient of a real loss with respect to the inputs, given dLoss/dP (device,
+ * n_probs_total doubles, same layout as the probabilities).  Requires a
+ * context created with CGD_FLAG_GRAD and a preceding cgd_eval (CGD_ERR_STATE
+ * otherwise).  Outputs (device, may be NULL each; instances concatenated):
  *   d_dr      sum_i M_i doubles               dLoss/dr
  *   d_dT      sum_i M_i*M_i complex            dLoss/dRe T + i dLoss/dIm T
  *   d_dalpha  sum_i M_i complex                dLoss/dRe alpha + i dLoss/dIm alpha
- * d log det S = tr(S^-1 dS) with the factorisations of the evaluation
- * recomputed per grid point. */
+ * Per grid point and internal block, S' (bordered) is inverted in FP64 on the
+ * GPU (d log det S = tr(S^-1 dS)); the sums over the grid are reduced in a
+ * fixed order (bitwise reproducible); the chain rule from H = I - Sigma^-1,
+ * gamma and log Pr(0) to (r, T, alpha) runs on the host in FP64.  The call
+ * waits for the device (the host chain rule needs the reduced sums). */
 cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *d_dT,
                     double *d_dalpha);
 

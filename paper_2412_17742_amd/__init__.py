@@ -22,7 +22,18 @@ STATUS_NAMES = ["CGD_OK", "CGD_ERR_ARG", "CGD_ERR_NONPHYSICAL", "CGD_ERR_NUMERIC
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_DENSE_INTERNAL = 1
 FLAG_NO_SCHUR = 2
-STAGES = ["schur", "lu_reg32", "lu_reg64", "lu_reg96", "lu_reg128", "lu_reg144", "lu_big", "combine", "dft", "fix"]
+FLAG_GRAD = 4
+# launch stages of one evaluation (per-stage timing); LU stages are order buckets
+STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144", "combine", "dft", "fix"]
+# the kernels behind each LU bucket: (FP64 path, FP32 first pass of the mixed path)
+LU_KERNELS = {
+    "lu_le32": ("lu_reg<double,8,8,4,4>", "lu_mfma_f32<2,1,2>"),
+    "lu_le64": ("lu_reg<double,16,16,4,4>", "lu_mfma_f32<4,2,2>"),
+    "lu_le96": ("lu_reg<double,16,32,6,3>", "lu_mfma_f32<6,2,4>"),
+    "lu_le128": ("lu_reg<double,16,32,8,4>", "lu_mfma_f32<8,2,4>"),
+    "lu_le144": ("lu_reg<double,16,48,9,3>", "lu_mfma_f32<9,3,4>"),
+    "lu_gt144": ("lu_big_f64", "lu_mfma_f32<12,3,4> (orders <= 192)"),
+}
 
 
 class CgdError(RuntimeError):
@@ -134,6 +145,7 @@ class Context:
         self.n_grid = ng.value
         self.n_points = L.cgd_points(self._h)
         self.shapes = [tuple(int(c) + 1 for c in x["cutoff"]) for x in instances]
+        self._M = [np.asarray(x["T"]).shape[0] for x in instances]
 
     def eval(self, probs=None, err=None):
         """Wrapped distributions of all instances, concatenated (device float64)."""
@@ -159,6 +171,21 @@ class Context:
         out = torch.empty(2 * self.n_points, dtype=torch.float64, device="cuda")
         _check(lib().cgd_grid_values(self._h, ctypes.c_void_p(out.data_ptr())))
         return torch.view_as_complex(out.view(-1, 2))
+
+    def grad(self, dprobs):
+        """Gradient of L with dL/dP = dprobs (device float64, n_probs): returns
+        (dL/dr, dL/dRe T + i dL/dIm T, dL/dRe alpha + i dL/dIm alpha) as device
+        tensors (instances concatenated; T flattened row-major)."""
+        import torch
+        assert dprobs.dtype == torch.float64 and dprobs.is_cuda and dprobs.is_contiguous()
+        nM = int(sum(self._M))
+        nT = int(sum(m * m for m in self._M))
+        dr = torch.zeros(nM, dtype=torch.float64, device="cuda")
+        dT = torch.zeros(2 * nT, dtype=torch.float64, device="cuda")
+        da = torch.zeros(2 * nM, dtype=torch.float64, device="cuda")
+        _check(lib().cgd_grad(self._h, ctypes.c_void_p(dprobs.data_ptr()), ctypes.c_void_p(dr.data_ptr()),
+                              ctypes.c_void_p(dT.data_ptr()), ctypes.c_void_p(da.data_ptr())))
+        return dr, torch.view_as_complex(dT.view(-1, 2)), torch.view_as_complex(da.view(-1, 2))
 
     def set_timing(self, enable: bool = True):
         _check(lib().cgd_set_timing(self._h, int(enable)))
@@ -207,3 +234,60 @@ def binned_distribution(instances, precision: str = "fp64", tol: float = 1e-9, f
         import torch
         torch.cuda.current_stream().synchronize()
         return [p.clone() for p in ctx.split(probs)]
+
+
+class _Distribution:
+    """torch.autograd.Function over a batch of instances that share their
+    binning: forward = cgd_eval, backward = cgd_grad."""
+
+    @staticmethod
+    def make():
+        import torch
+
+        class Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, r, T, alpha, spec):
+                B, M = r.shape
+                insts = []
+                for b in range(B):
+                    insts.append(dict(
+                        T=T[b].detach().cpu().numpy(), r=r[b].detach().cpu().numpy(),
+                        alpha=None if alpha is None else alpha[b].detach().cpu().numpy(),
+                        schmidt=spec.get("schmidt"), bin_of=spec["bin_of"], cutoff=spec["cutoff"],
+                        grid=spec.get("grid"), resolve_internal=spec.get("resolve_internal", 0)))
+                c = Context(insts, flags=FLAG_GRAD)
+                P = c.eval().clone()
+                ctx.c = c
+                ctx.B, ctx.M = B, M
+                ctx.has_alpha = alpha is not None
+                ctx.devices = (r.device, T.device, None if alpha is None else alpha.device)
+                shape = tuple(int(x) + 1 for x in spec["cutoff"])
+                return P.view(B, *shape)
+
+            @staticmethod
+            def backward(ctx, gP):
+                dr, dT, da = ctx.c.grad(gP.contiguous().view(-1).to(torch.float64))
+                ctx.c.close()
+                B, M = ctx.B, ctx.M
+                dr = dr.view(B, M).to(ctx.devices[0])
+                dT = dT.view(B, M, M).to(ctx.devices[1])
+                da = da.view(B, M).to(ctx.devices[2]) if ctx.has_alpha else None
+                return dr, dT, da, None
+
+        return Fn
+
+
+_fn = None
+
+
+def distribution(r, T, alpha, spec):
+    """Differentiable binned distributions of a batch of states with one binning.
+
+    r: (B, M) float64, T: (B, M, M) complex128, alpha: (B, M) complex128 or None
+    (torch tensors, any device); spec: dict with schmidt, bin_of, cutoff and
+    optionally grid and resolve_internal.  Returns a (B, N_1+1, ..., N_L+1)
+    float64 CUDA tensor; backward runs the library's adjoint."""
+    global _fn
+    if _fn is None:
+        _fn = _Distribution.make()
+    return _fn.apply(r, T, alpha, spec)

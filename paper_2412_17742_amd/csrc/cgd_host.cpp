@@ -20,7 +20,7 @@ namespace {
 // Mixed path: assumed bound on the relative error of an FP32 generating-function
 // value, in units of (matrix order + 1) * 2^-24 (calibrated against FP64 on the
 // benchmark workloads with a safety factor; see the mixed-path tests).
-constexpr double kTauScale = 16.0;
+constexpr double kTauScale = 2.0;
 
 thread_local std::string g_err;
 
@@ -46,6 +46,26 @@ struct HostBlock {
     int schur_axis = -1;        // eliminated bin
     std::vector<double> eig;    // its eigenvalues
     CMat P, Q;                  // H_BA V and V^H H_AB
+};
+
+// Gradient data of one internal block: the full (bordered) matrix before any
+// reduction, and what the chain rule needs.
+struct GradHost {
+    int inst = 0, k = 0;
+    int n2 = 0, bordered = 0;
+    CMat Sinv;                  // Sigma^-1 (2M x 2M)
+    std::vector<cplx> v;        // Sigma^-1 zbar
+    CMat Hf;                    // bordered H (order n2 + bordered)
+    std::vector<int32_t> rb;    // row bins of Hf
+};
+
+// Copy of one instance's inputs (the chain rule needs them after create).
+struct HostInstCopy {
+    int M = 0, K = 1;
+    std::vector<cplx> T, alpha_v;
+    const cplx *alpha = nullptr;
+    std::vector<double> r, schmidt;
+    std::vector<std::vector<double>> rk;
 };
 
 struct HostInst {
@@ -127,7 +147,7 @@ cgd_status validate(const cgd_instance &in, int idx) {
 // eigenbasis.
 cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int> &kset, bool dense,
                           bool use_schur, const std::vector<std::vector<double>> &rk, HostInst &hi,
-                          std::vector<HostBlock> &out) {
+                          std::vector<HostBlock> &out, std::vector<GradHost> *grads) {
     const int M = in.M;
     const int nk = (int)kset.size();
     const int m = M * nk;  // modes in this block
@@ -208,6 +228,19 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
             Hf(n2, i) = -v[i < m ? i + m : i - m]; // gamma = X Sigma^-1 zbar
         }
         Hf(n2, n2) = 0.0;
+    }
+
+    if (grads) {
+        GradHost g;
+        g.inst = idx;
+        g.k = kset[0];
+        g.n2 = n2;
+        g.bordered = displaced ? 1 : 0;
+        g.Sinv = Sinv;
+        g.v = v;
+        g.Hf = Hf;
+        g.rb = rb;
+        grads->push_back(std::move(g));
     }
 
     // integrate out unmeasured modes: det S = det(I - H_UU) det(I - D_R H_red),
@@ -371,6 +404,20 @@ struct cgd_ctx {
     hipEvent_t ev_status = nullptr;
     bool status_pending = false;
     bool poisoned = false;
+    // gradient
+    std::vector<GradHost> grads;
+    std::vector<HostInstCopy> hinst_copy;
+    std::vector<GradBlockDev> gblocks;
+    LuClass gadj[kAdjClasses];
+    int adj_chunk = 16;
+    int64_t part_stride = 0, adj_items = 0, z_total = 0, adj_total = 0;
+    std::vector<int64_t> z_elem_prefix, adj_off;
+    std::vector<DftStage> adj_stages;
+    GradBlockDev *d_gblocks = nullptr;
+    double2 *d_gpool = nullptr, *d_partial = nullptr, *d_z = nullptr, *d_adjA = nullptr, *d_adjB = nullptr,
+            *d_ghat = nullptr;
+    int32_t *d_grb = nullptr;
+    int64_t *d_z_prefix = nullptr, *d_adj_off = nullptr, *d_prob_prefix = nullptr;
     bool evaluated = false;
     bool timing = false;
     hipEvent_t ev[CGD_NSTAGES][2] = {};
@@ -390,6 +437,10 @@ void free_ctx(cgd_ctx *c) {
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
+    for (auto &s : c->adj_stages) { fr(s.d_desc); fr(s.d_prefix); }
+    for (auto &k : c->gadj) { fr(k.d_jobs); fr(k.d_prefix); }
+    fr(c->d_gblocks); fr(c->d_gpool); fr(c->d_partial); fr(c->d_z); fr(c->d_adjA); fr(c->d_adjB); fr(c->d_ghat);
+    fr(c->d_grb); fr(c->d_z_prefix); fr(c->d_adj_off); fr(c->d_prob_prefix);
     for (int i = 0; i < CGD_NSTAGES; ++i)
         for (int j = 0; j < 2; ++j)
             if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
@@ -412,11 +463,226 @@ cgd_status check_status(cgd_ctx *c) {
     return CGD_OK;
 }
 
+// Device structures of the adjoint: full bordered block matrices, work lists
+// (chunks of grid points), partial and reduced sums, adjoint-DFT passes.
+cgd_status build_grad(cgd_ctx *c, int n_inst) {
+    std::vector<double2> gpool;
+    std::vector<int32_t> grb;
+    for (int k = 0; k < kAdjClasses; ++k) c->gadj[k].cls = k;
+    c->gblocks.resize(c->grads.size());
+    std::vector<int> bcls(c->grads.size());
+    int64_t zoff = 0;
+    for (size_t b = 0; b < c->grads.size(); ++b) {
+        const GradHost &g = c->grads[b];
+        GradBlockDev &d = c->gblocks[b];
+        std::memset(&d, 0, sizeof(d));
+        d.inst = g.inst;
+        d.nb = g.Hf.r;
+        d.bordered = g.bordered;
+        int cls = -1;
+        for (int k = 0; k < kAdjClasses; ++k)
+            if (d.nb <= adj_class_limit(k)) { cls = k; break; }
+        if (cls < 0) return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD: block order above 96 is not supported");
+        bcls[b] = cls;
+        d.h_off = (int64_t)gpool.size();
+        for (const cplx &z : g.Hf.a) gpool.push_back(make_double2(z.real(), z.imag()));
+        d.rb_off = (int64_t)grb.size();
+        grb.insert(grb.end(), g.rb.begin(), g.rb.end());
+        const int64_t np = c->inst[g.inst].npts;
+        d.nchunks = (int32_t)((np + c->adj_chunk - 1) / c->adj_chunk);
+        const int n = d.nb - d.bordered;
+        d.z_off = zoff;
+        c->z_elem_prefix.push_back(zoff);
+        zoff += (int64_t)n * n + n + 1;
+        c->part_stride = std::max<int64_t>(c->part_stride, (int64_t)n * n + n + 1);
+    }
+    // work items (chunks of grid points) numbered class by class, so that each
+    // class launch covers one contiguous range
+    int64_t item = 0;
+    for (int k = 0; k < kAdjClasses; ++k)
+        for (size_t b = 0; b < c->grads.size(); ++b) {
+            if (bcls[b] != k) continue;
+            GradBlockDev &d = c->gblocks[b];
+            d.first_item = item;
+            c->gadj[k].jobs.push_back((int32_t)b);
+            c->gadj[k].prefix.push_back(item);
+            item += d.nchunks;
+        }
+    c->adj_items = item;
+    c->z_total = zoff;
+    // adjoint DFT passes: axis 0 first, (N_l + 1) -> H1 (axis 0) or G_l
+    c->adj_off.assign(n_inst, 0);
+    int64_t off = 0;
+    int Lmax = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        c->adj_off[i] = off;
+        off += std::max(c->inst[i].npts, c->inst[i].nprobs);
+        Lmax = std::max(Lmax, c->inst[i].L);
+    }
+    c->adj_total = off;
+    c->adj_stages.resize(Lmax);
+    for (int s2 = 0; s2 < Lmax; ++s2) {
+        DftStage &st = c->adj_stages[s2];
+        for (int i = 0; i < n_inst; ++i) {
+            const InstDev &I = c->inst[i];
+            if (I.L <= s2) continue;
+            const int a = s2;
+            int64_t dims[kMaxBins];
+            for (int l = 0; l < I.L; ++l) dims[l] = l < a ? (l == 0 ? I.H1 : I.G[l]) : (I.N[l] + 1);
+            DftStageDev d;
+            std::memset(&d, 0, sizeof(d));
+            d.inst = i;
+            d.K = I.N[a] + 1;
+            d.Bout = a == 0 ? I.H1 : I.G[a];
+            d.G = I.G[a];
+            d.final_stage = 0;
+            d.outer = 1;
+            for (int l = 0; l < a; ++l) d.outer *= dims[l];
+            d.inner = 1;
+            for (int l = a + 1; l < I.L; ++l) d.inner *= dims[l];
+            d.in_off = c->adj_off[i];
+            d.out_off = c->adj_off[i];
+            d.scale = 1.0;
+            st.prefix.push_back(st.total);
+            st.total += d.outer * d.Bout * d.inner;
+            st.desc.push_back(d);
+        }
+    }
+    cgd_status s;
+    if ((s = upload(&c->d_gblocks, c->gblocks)) != CGD_OK) return s;
+    if ((s = upload(&c->d_gpool, gpool)) != CGD_OK) return s;
+    if ((s = upload(&c->d_grb, grb)) != CGD_OK) return s;
+    if ((s = upload(&c->d_z_prefix, c->z_elem_prefix)) != CGD_OK) return s;
+    if ((s = upload(&c->d_adj_off, c->adj_off)) != CGD_OK) return s;
+    std::vector<int64_t> pp(c->prob_offsets.begin(), c->prob_offsets.begin() + n_inst);
+    if ((s = upload(&c->d_prob_prefix, pp)) != CGD_OK) return s;
+    for (auto &k : c->gadj) {
+        if ((s = upload(&k.d_jobs, k.jobs)) != CGD_OK) return s;
+        if ((s = upload(&k.d_prefix, k.prefix)) != CGD_OK) return s;
+    }
+    for (auto &st : c->adj_stages) {
+        if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
+        if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
+    }
+    HIP_OK(hipMalloc((void **)&c->d_partial, sizeof(double2) * std::max<int64_t>(1, c->adj_items * c->part_stride)));
+    HIP_OK(hipMalloc((void **)&c->d_z, sizeof(double2) * std::max<int64_t>(1, c->z_total)));
+    HIP_OK(hipMalloc((void **)&c->d_adjA, sizeof(double2) * std::max<int64_t>(1, c->adj_total)));
+    HIP_OK(hipMalloc((void **)&c->d_adjB, sizeof(double2) * std::max<int64_t>(1, c->adj_total)));
+    HIP_OK(hipMalloc((void **)&c->d_ghat, sizeof(double2) * std::max<int64_t>(1, c->npts)));
+    return CGD_OK;
+}
+
+// Chain rule, host FP64: from dL = Re[tr(Z_H dH) + Z_g^T dgamma + Z_0 dlogPr0]
+// per internal block (H = I - Sigma^-1, gamma = X Sigma^-1 zbar,
+// logPr0 = -1/2 zbar^H Sigma^-1 zbar - 1/2 log det Sigma) to the inputs.  For
+// a complex input z with dL = Re(a dz + b conj(dz)) the reported gradient is
+// dL/dRe z + i dL/dIm z = conj(a) + b.
+void chain_rule(const cgd_ctx *c, const cgd_instance *inst_unused, const std::vector<cplx> &zhost,
+                std::vector<double> &gr, std::vector<cplx> &gT, std::vector<cplx> &ga,
+                const std::vector<int64_t> &roff, const std::vector<int64_t> &toff) {
+    (void)inst_unused;
+    for (size_t b = 0; b < c->grads.size(); ++b) {
+        const GradHost &g = c->grads[b];
+        const GradBlockDev &d = c->gblocks[b];
+        const HostInstCopy &hc = c->hinst_copy[g.inst];
+        const int M = hc.M, n = g.n2;
+        const cplx *z = &zhost[d.z_off];
+        CMat ZH(n, n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) ZH(i, j) = z[(int64_t)i * n + j];
+        std::vector<cplx> Zg(z + (int64_t)n * n, z + (int64_t)n * n + n);
+        const cplx Z0 = z[(int64_t)n * n + n];
+        const CMat &Si = g.Sinv;
+        // Gamma = Si ZH Si - v (Zg^T X Si) + Z0 (v v^H - Si) / 2
+        CMat Gm = matmul(matmul(Si, ZH), Si);
+        std::vector<cplx> xz(n);  // X Zg
+        for (int i = 0; i < n; ++i) xz[i] = Zg[i < M ? i + M : i - M];
+        std::vector<cplx> rho(n, cplx(0, 0));  // rho^T = Zg^T X Si  ->  rho = Si^T X Zg
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) rho[j] += xz[i] * Si(i, j);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                Gm(i, j) += -g.v[i] * rho[j] + 0.5 * Z0 * (g.v[i] * std::conj(g.v[j]) - Si(i, j));
+        // blocks of Gamma: dL = Re[tr(PhiN dN) + tr(G21 dM) + tr(G12 dM*)]
+        CMat PhiN(M, M), G21(M, M), G12(M, M);
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                PhiN(i, j) = Gm(j, i) + Gm(M + i, M + j);
+                G21(i, j) = Gm(M + i, j);
+                G12(i, j) = Gm(i, M + j);
+            }
+        // T and internal-mode squeezing of this block
+        CMat T(M, M);
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) T(i, j) = hc.T[(size_t)i * M + j];
+        const CMat Tt = transpose(T), Th = adjoint(T), Tc = conj(T);
+        std::vector<double> nn(M), mm(M), dn(M), dm(M), drk(M);
+        for (int j = 0; j < M; ++j) {
+            const double r = hc.rk[j][g.k];
+            nn[j] = std::sinh(r) * std::sinh(r);
+            mm[j] = std::sinh(r) * std::cosh(r);
+            dn[j] = std::sinh(2 * r);
+            dm[j] = std::cosh(2 * r);
+            const double ratio = hc.K == 1 ? 1.0 : hc.schmidt[g.k] / hc.schmidt[0];
+            const double sq = std::sqrt(ratio), th = std::tanh(hc.r[j]);
+            drk[j] = sq * (1.0 - th * th) / (1.0 - ratio * th * th);
+        }
+        auto diagl = [&](const std::vector<double> &w, const CMat &A) {  // diag(w) A
+            CMat R = A;
+            for (int i = 0; i < A.r; ++i)
+                for (int j = 0; j < A.c; ++j) R(i, j) *= w[i];
+            return R;
+        };
+        // coefficient of dT (tr(Xa dT)) and of dT* (tr(Xb dT*))
+        CMat Xa = diagl(nn, matmul(Th, transpose(PhiN)));
+        CMat t3 = diagl(mm, matmul(Tt, G21)), t4 = diagl(mm, matmul(Tt, transpose(G21)));
+        CMat Xb = diagl(nn, matmul(Tt, PhiN));
+        CMat t5 = diagl(mm, matmul(Th, G12)), t6 = diagl(mm, matmul(Th, transpose(G12)));
+        for (size_t e = 0; e < Xa.a.size(); ++e) {
+            Xa.a[e] += t3.a[e] + t4.a[e];
+            Xb.a[e] += t5.a[e] + t6.a[e];
+        }
+        CMat Cn = matmul(matmul(Tt, PhiN), Tc), Cm1 = matmul(matmul(Tt, G21), T), Cm2 = matmul(matmul(Th, G12), Tc);
+        const int64_t to = toff[g.inst], ro = roff[g.inst];
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) gT[to + (size_t)i * M + j] += std::conj(Xa(j, i)) + Xb(j, i);
+        for (int j = 0; j < M; ++j) {
+            const double dl = Cn(j, j).real() * dn[j] + (Cm1(j, j) + Cm2(j, j)).real() * dm[j];
+            gr[ro + j] += dl * drk[j];
+        }
+        // displacement: zbar = (beta, beta*), beta = T alpha on internal mode 0
+        if (g.k == 0 && hc.alpha) {
+            std::vector<cplx> ab(M), bb(M);
+            for (int i = 0; i < M; ++i) {
+                ab[i] = rho[i] - 0.5 * Z0 * (std::conj(g.v[i]) + g.v[M + i]);
+                bb[i] = rho[M + i] - 0.5 * Z0 * (std::conj(g.v[M + i]) + g.v[i]);
+            }
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < M; ++j) {
+                    const cplx al = hc.alpha[j];
+                    gT[to + (size_t)i * M + j] += std::conj(ab[i] * al) + bb[i] * std::conj(al);
+                }
+            for (int j = 0; j < M; ++j) {
+                cplx aa(0, 0), bs(0, 0);
+                for (int i = 0; i < M; ++i) {
+                    aa += T(i, j) * ab[i];            // (T^T a_beta)_j
+                    bs += std::conj(T(i, j)) * bb[i]; // (T^H b_beta)_j
+                }
+                ga[ro + j] += std::conj(aa) + bs;
+            }
+        }
+    }
+}
+
 cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     std::vector<HostInst> hinst(n_inst);
     std::vector<HostBlock> hblocks;
     const bool dense = c->flags & CGD_FLAG_DENSE_INTERNAL;
     const bool use_schur = !(c->flags & CGD_FLAG_NO_SCHUR);
+    const bool want_grad = c->flags & CGD_FLAG_GRAD;
+    if (want_grad && dense)
+        for (int i = 0; i < n_inst; ++i)
+            if (inst[i].K > 1) return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD works with internal-mode blocks (no CGD_FLAG_DENSE_INTERNAL)");
     for (int i = 0; i < n_inst; ++i) {
         const cgd_instance &in = inst[i];
         cgd_status s = validate(in, i);
@@ -436,14 +702,31 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 if (!(t < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(i) + ": Schmidt weights");
                 rk[j][k] = std::atanh(t);
             }
+        if (want_grad) {
+            HostInstCopy hc;
+            hc.M = in.M;
+            hc.K = in.K;
+            hc.T.resize((size_t)in.M * in.M);
+            for (size_t e = 0; e < hc.T.size(); ++e) hc.T[e] = cx(in.T, e);
+            hc.r.assign(in.r, in.r + in.M);
+            if (in.schmidt) hc.schmidt.assign(in.schmidt, in.schmidt + in.K);
+            if (in.alpha) {
+                hc.alpha_v.resize(in.M);
+                for (int j = 0; j < in.M; ++j) hc.alpha_v[j] = cx(in.alpha, j);
+            }
+            hc.rk = rk;
+            c->hinst_copy.push_back(std::move(hc));
+            c->hinst_copy.back().alpha = c->hinst_copy.back().alpha_v.empty() ? nullptr
+                                                                               : c->hinst_copy.back().alpha_v.data();
+        }
         if (dense || in.K == 1) {
             std::vector<int> ks(in.K);
             for (int k = 0; k < in.K; ++k) ks[k] = k;
-            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, hblocks);
+            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, hblocks, want_grad ? &c->grads : nullptr);
             if (s != CGD_OK) return s;
         } else {
             for (int k = 0; k < in.K; ++k) {
-                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, hblocks);
+                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, hblocks, want_grad ? &c->grads : nullptr);
                 if (s != CGD_OK) return s;
             }
         }
@@ -703,6 +986,10 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         if ((s = upload(&c->d_list_ptrs, ptrs)) != CGD_OK) return s;
         HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kG64));
     }
+    if (want_grad) {
+        cgd_status sg = build_grad(c, n_inst);
+        if (sg != CGD_OK) return sg;
+    }
     HIP_OK(hipDeviceSynchronize());
     return CGD_OK;
 }
@@ -718,7 +1005,7 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     if (!inst || n_inst <= 0) return fail(CGD_ERR_ARG, "need at least one instance");
     if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
     if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
-    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR)) return fail(CGD_ERR_ARG, "unknown flags");
+    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD)) return fail(CGD_ERR_ARG, "unknown flags");
     cgd_ctx *c = new (std::nothrow) cgd_ctx();
     if (!c) return fail(CGD_ERR_NOMEM, "host allocation");
     c->n_inst = n_inst;
@@ -838,10 +1125,55 @@ cgd_status cgd_grid_values(cgd_ctx *c, double *d_logg) {
 }
 
 cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_dT, double *d_dalpha) {
-    (void)d_dprobs; (void)d_dr; (void)d_dT; (void)d_dalpha;
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (!(c->flags & CGD_FLAG_GRAD)) return fail(CGD_ERR_STATE, "context created without CGD_FLAG_GRAD");
     if (!c->evaluated) return fail(CGD_ERR_STATE, "cgd_grad before cgd_eval");
-    return fail(CGD_ERR_ARG, "cgd_grad: not available in this build");
+    if (!d_dprobs) return fail(CGD_ERR_ARG, "d_dprobs is NULL");
+    cgd_status s = check_status(c);
+    if (s != CGD_OK) return s;
+    hipStream_t st = c->stream;
+    // adjoint DFT: Ghat_k = (1/prod G) sum_b dL/dP(b) w_k^-b on the half grid
+    HIP_OK(launch_adjoint_seed(c->d_inst, c->d_prob_prefix, c->n_inst, c->nprobs, d_dprobs, c->d_adj_off,
+                               c->d_adjA, st));
+    for (size_t si = 0; si < c->adj_stages.size(); ++si) {
+        DftStage &S = c->adj_stages[si];
+        const double2 *in = (si % 2 == 0) ? c->d_adjA : c->d_adjB;
+        double2 *out = (si % 2 == 0) ? c->d_adjB : c->d_adjA;
+        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, nullptr, nullptr,
+                                c->d_status, st));
+    }
+    HIP_OK(launch_adjoint_gather(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_adj_off, c->d_adjA,
+                                 c->d_adjB, c->d_ghat, st));
+    // per (block, chunk of points): Gauss-Jordan inverse and accumulation
+    for (auto &g : c->gadj) {
+        if (g.jobs.empty()) continue;
+        int nitems = 0;
+        for (int32_t bj : g.jobs) nitems += c->gblocks[bj].nchunks;
+        // job prefix holds absolute item indices; the launch covers this class's items
+        AdjArgs a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), c->adj_chunk, c->d_gblocks, c->d_inst, c->d_gpool,
+                  c->d_grb, c->d_logg, c->d_ghat, c->d_partial, c->part_stride};
+        HIP_OK(launch_adjoint(g.cls, a, nitems, g.prefix[0], st));
+    }
+    HIP_OK(launch_adjoint_reduce(c->d_gblocks, c->d_z_prefix, (int)c->gblocks.size(), c->z_total, c->d_partial,
+                                 c->part_stride, c->d_z, st));
+    std::vector<cplx> zh(c->z_total);
+    HIP_OK(hipMemcpyAsync(zh.data(), c->d_z, sizeof(double2) * c->z_total, hipMemcpyDeviceToHost, st));
+    if (st) HIP_OK(hipStreamSynchronize(st)); else HIP_OK(hipDeviceSynchronize());
+    // chain rule on the host (FP64), then upload
+    std::vector<int64_t> roff(c->n_inst + 1, 0), toff(c->n_inst + 1, 0);
+    for (int i = 0; i < c->n_inst; ++i) {
+        const int M = c->hinst_copy[i].M;
+        roff[i + 1] = roff[i] + M;
+        toff[i + 1] = toff[i] + (int64_t)M * M;
+    }
+    std::vector<double> gr(roff[c->n_inst], 0.0);
+    std::vector<cplx> gT(toff[c->n_inst], cplx(0, 0)), ga(roff[c->n_inst], cplx(0, 0));
+    chain_rule(c, nullptr, zh, gr, gT, ga, roff, toff);
+    if (d_dr) HIP_OK(hipMemcpyAsync(d_dr, gr.data(), sizeof(double) * gr.size(), hipMemcpyHostToDevice, st));
+    if (d_dT) HIP_OK(hipMemcpyAsync(d_dT, gT.data(), sizeof(cplx) * gT.size(), hipMemcpyHostToDevice, st));
+    if (d_dalpha) HIP_OK(hipMemcpyAsync(d_dalpha, ga.data(), sizeof(cplx) * ga.size(), hipMemcpyHostToDevice, st));
+    if (st) HIP_OK(hipStreamSynchronize(st)); else HIP_OK(hipDeviceSynchronize());
+    return check_status(c);
 }
 
 cgd_status cgd_set_timing(cgd_ctx *c, int32_t enable) {

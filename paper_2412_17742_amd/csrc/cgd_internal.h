@@ -63,6 +63,34 @@ struct SchurDev {
     int64_t p_off, q_off, hbb_off, eig_off, c_off;
 };
 
+// Gradient: one internal block with its full (bordered) matrix, no reduction.
+struct GradBlockDev {
+    int32_t inst;
+    int32_t nb;               // order including the border
+    int32_t bordered;
+    int32_t nchunks;          // chunks of grid points (work items) of this block
+    int64_t h_off;            // complex offset of the bordered H in the gradient pool
+    int64_t rb_off;           // row bins (nb entries)
+    int64_t first_item;       // first adjoint work item
+    int64_t z_off;            // output: n*n (Z_H) + n (Z_gamma) + 1 (Z_0), n = nb - bordered
+};
+
+struct AdjArgs {
+    const int32_t *job_block;  // gradient block per job
+    const int64_t *job_prefix; // first item of each job
+    int njobs;
+    int chunk;                 // grid points per item
+    const GradBlockDev *gblocks;
+    const InstDev *insts;
+    const double2 *pool;
+    const int32_t *rbpool;
+    const double2 *logg;
+    const double2 *ghat;
+    double2 *partial;
+    int64_t part_stride;
+    int item_base;             // absolute index of the launch's first item
+};
+
 // One axis pass of the separable inverse DFT for one instance.
 struct DftStageDev {
     int32_t inst, K, Bout, G;
@@ -100,6 +128,17 @@ hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hip
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
                               const double2 *pool_in, const double *eigpool, double2 *pool_out, float2 *pool32_out,
                               hipStream_t st);
+// adjoint
+int adj_class_limit(int cls);
+constexpr int kAdjClasses = 3;
+hipError_t launch_adjoint(int cls, const AdjArgs &a, int nitems, int64_t item_base, hipStream_t st);
+hipError_t launch_adjoint_reduce(const GradBlockDev *gblocks, const int64_t *elem_prefix, int ngb, int64_t total,
+                                 const double2 *partial, int64_t part_stride, double2 *zout, hipStream_t st);
+hipError_t launch_adjoint_gather(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                                 const int64_t *buf_off, const double2 *bufA, const double2 *bufB, double2 *ghat,
+                                 hipStream_t st);
+hipError_t launch_adjoint_seed(const InstDev *insts, const int64_t *prob_prefix, int n_inst, int64_t nprobs,
+                               const double *dprobs, const int64_t *buf_off, double2 *out, hipStream_t st);
 // mixed path
 hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
 hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,

@@ -247,7 +247,8 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
                 const C d = s_u[buf][k];
                 if (tid == 0) {
                     s_piv[k] = d;
-                    if (!(d.x > T(0)) || !isfinite(d.y)) s_bad = 1;
+                    // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
+                    if (!isfinite(d.x) || !isfinite(d.y) || (k < nb - B.bordered && !(d.x > T(0)))) s_bad = 1;
                 }
                 const C dinv = inv2<T>(d);
                 C u[TC];
@@ -459,9 +460,14 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                     if (k + 1 < nb) s_piv[k + 1] = u11;
                     if (k + 2 < nb) s_piv[k + 2] = u22;
                     if (k + 3 < nb) s_piv[k + 3] = u33;
-                    const bool bad = !(d00.x > 0.f) || (k + 1 < nb && !(u11.x > 0.f)) ||
-                                     (k + 2 < nb && !(u22.x > 0.f)) || (k + 3 < nb && !(u33.x > 0.f)) ||
-                                     !isfinite(u33.x + u22.x + u11.x + d00.x);
+                    // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
+                    const int nl = nb - B.bordered;
+                    const bool bad = (k < nl && !(d00.x > 0.f)) || (k + 1 < nl && !(u11.x > 0.f)) ||
+                                     (k + 2 < nl && !(u22.x > 0.f)) || (k + 3 < nl && !(u33.x > 0.f)) ||
+                                     !isfinite(d00.x + d00.y) ||
+                                     (k + 1 < nb && !isfinite(u11.x + u11.y)) ||
+                                     (k + 2 < nb && !isfinite(u22.x + u22.y)) ||
+                                     (k + 3 < nb && !isfinite(u33.x + u33.y));
                     if (bad) s_bad = 1;
                 }
                 if (lg < TCW) {
@@ -639,7 +645,8 @@ lu_big_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ jo
                 const double2 d = s_panel[kk * kPanel + kk];
                 if (tid == 0) {
                     s_piv[k0 + kk] = d;
-                    if (!(d.x > 0.0) || !isfinite(d.y)) s_bad = 1;
+                    // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
+                    if (!isfinite(d.x) || !isfinite(d.y) || (k0 + kk < nb - B.bordered && !(d.x > 0.0))) s_bad = 1;
                 }
                 const double2 dinv = cinv(d);
                 for (int i = kk + 1 + tid; i < mrows; i += kBigThreads) {
@@ -887,6 +894,252 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint.  For a real loss L of the probabilities, with Ghat_k the adjoint
+// DFT of dL/dP at grid point k and c_k the half-grid weight,
+//     dL = Re sum_k omega_k d log G_k,   omega_k = c_k G_k Ghat_k.
+// Per internal block, with S = I - D H and the bordered S' = [[S, D X gamma],
+// [gamma^T, 1]] (whose inverse is Q, p = 1/Q_nn):
+//     d log G = tr(W dH) + g^T d gamma + d log Pr(0),
+//     W = 1/2 (Q_11 + (p^2 - p) Q_{:,n} Q_{n,:}) D,   g = -p/2 (Q_{:,n} + X D Q_{n,:}^T)
+// (d log det S = tr(S^-1 dS); without displacement W = 1/2 S^-1 D, g = 0).
+// lu_adjoint inverts S' in registers by Gauss-Jordan elimination without
+// pivoting (same pivots as the LU, all in the right half-plane), over a chunk
+// of grid points of one block, and accumulates omega W, omega g and omega.
+// ---------------------------------------------------------------------------
+template <int PR, int PC, int TR, int TC>
+__global__ void __launch_bounds__(PR *PC)
+lu_adjoint(const AdjArgs A)
+{
+    constexpr int NT = PR * PC;
+    constexpr int N = PR * TR;
+    static_assert(PR * TR == PC * TC, "square padding");
+    static_assert(PC % PR == 0, "column owner must be uniform over a register row");
+    __shared__ double2 s_u[2][N];
+    __shared__ double2 s_l[2][N];
+    __shared__ double2 s_d[N];
+    __shared__ double2 s_qc[N];   // column n of Q (bordered)
+    __shared__ double2 s_qr[N];   // row n of Q
+    __shared__ double2 s_w[kMaxBins];
+    __shared__ double2 s_om;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % PC, ty = tid / PC;
+    const int item = A.item_base + (int)blockIdx.x;  // absolute item index
+    const int job = find_job(A.job_prefix, A.njobs, item);
+    const int gbi = A.job_block[job];
+    const GradBlockDev GB = A.gblocks[gbi];
+    const InstDev &I = A.insts[GB.inst];
+    const int nb = GB.nb;
+    const int n = nb - GB.bordered;  // order of S
+    const int64_t p0 = (int64_t)(item - A.job_prefix[job]) * A.chunk;
+    const int64_t p1 = p0 + A.chunk < I.npts ? p0 + A.chunk : I.npts;
+    const double2 *__restrict__ H = A.pool + GB.h_off;
+    int64_t stride0 = 1;
+    for (int l = 1; l < I.L; ++l) stride0 *= I.G[l];
+
+    double2 z[TR][TC];
+    double2 zg[TR];
+    #pragma unroll
+    for (int r = 0; r < TR; ++r) {
+        zg[r] = cmk(0.0, 0.0);
+        #pragma unroll
+        for (int c = 0; c < TC; ++c) z[r][c] = cmk(0.0, 0.0);
+    }
+    double2 z0 = cmk(0.0, 0.0);
+
+    for (int64_t pt = p0; pt < p1; ++pt) {
+        __syncthreads();
+        if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+        if (tid == 0) {
+            const double2 lg = A.logg[I.pt_off + pt];
+            const double2 gh = A.ghat[I.pt_off + pt];
+            const int64_t k1 = pt / stride0;
+            const double ck = (k1 == 0 || 2 * k1 == I.G[0]) ? 1.0 : 2.0;
+            double sn, cs;
+            sincos(lg.y, &sn, &cs);
+            const double m = ck * exp(lg.x);
+            const double2 g = cmk(m * cs, m * sn);
+            s_om = cmul(g, gh);
+        }
+        __syncthreads();
+        for (int i = tid; i < nb; i += NT) {
+            const int b = A.rbpool[GB.rb_off + i];
+            s_d[i] = b < 0 ? cmk(1.0, 0.0) : s_w[b];
+        }
+        __syncthreads();
+        const double2 om = s_om;
+
+        double2 a[TR][TC];
+        #pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            const int i = r * PR + ty;
+            #pragma unroll
+            for (int c = 0; c < TC; ++c) {
+                const int j = c * PC + tx;
+                double2 v = cmk(i == j ? 1.0 : 0.0, 0.0);
+                if (i < nb && j < nb) {
+                    const double2 h = H[(int64_t)i * nb + j];
+                    const double2 d = s_d[i];
+                    v.x -= d.x * h.x - d.y * h.y;
+                    v.y -= d.x * h.y + d.y * h.x;
+                }
+                a[r][c] = v;
+            }
+        }
+        // Gauss-Jordan inversion in place: a <- S'^-1
+        #pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            const int cown = (r * PR) / PC;
+            int kend = nb - r * PR;
+            kend = kend < 0 ? 0 : (kend > PR ? PR : kend);
+            for (int kk = 0; kk < kend; ++kk) {
+                const int k = r * PR + kk;
+                const int buf = k & 1;
+                if (ty == kk) {
+                    #pragma unroll
+                    for (int c = 0; c < TC; ++c) s_u[buf][c * PC + tx] = a[r][c];
+                }
+                if (tx == k % PC) {
+                    #pragma unroll
+                    for (int r2 = 0; r2 < TR; ++r2) s_l[buf][r2 * PR + ty] = a[r2][cown];
+                }
+                __syncthreads();
+                const double2 pinv = cinv(s_u[buf][k]);
+                double2 u[TC];
+                #pragma unroll
+                for (int c = 0; c < TC; ++c) u[c] = cmul(s_u[buf][c * PC + tx], pinv);  // a_kj / p
+                #pragma unroll
+                for (int r2 = 0; r2 < TR; ++r2) {
+                    const int i = r2 * PR + ty;
+                    const double2 l = s_l[buf][i];  // a_ik
+                    #pragma unroll
+                    for (int c = 0; c < TC; ++c) {
+                        const int j = c * PC + tx;
+                        double2 v = cfnms(a[r2][c], l, u[c]);                 // a_ij - a_ik a_kj / p
+                        if (r2 == r && i == k) v = u[c];                       // row k: a_kj / p
+                        if (c == cown && j == k) v = cmk(-(l.x * pinv.x - l.y * pinv.y),
+                                                         -(l.x * pinv.y + l.y * pinv.x));  // column k: -a_ik / p
+                        if (r2 == r && c == cown && i == k && j == k) v = pinv;  // pivot: 1 / p
+                        a[r2][c] = v;
+                    }
+                }
+            }
+        }
+        // accumulate omega W (and omega g, omega)
+        if (GB.bordered) {
+            __syncthreads();
+            #pragma unroll
+            for (int r = 0; r < TR; ++r)
+                #pragma unroll
+                for (int c = 0; c < TC; ++c) {
+                    const int i = r * PR + ty, j = c * PC + tx;
+                    if (j == n && i < nb) s_qc[i] = a[r][c];
+                    if (i == n && j < nb) s_qr[j] = a[r][c];
+                }
+            __syncthreads();
+        }
+        const double2 qnn = GB.bordered ? s_qc[n] : cmk(1.0, 0.0);
+        const double2 pb = cinv(qnn);
+        const double2 pp = cmk(pb.x * pb.x - pb.y * pb.y - pb.x, 2.0 * pb.x * pb.y - pb.y);  // p^2 - p
+        #pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            const int i = r * PR + ty;
+            #pragma unroll
+            for (int c = 0; c < TC; ++c) {
+                const int j = c * PC + tx;
+                if (i < n && j < n) {
+                    double2 q = a[r][c];
+                    if (GB.bordered) {
+                        const double2 t = cmul(pp, cmul(s_qc[i], s_qr[j]));
+                        q.x += t.x;
+                        q.y += t.y;
+                    }
+                    const double2 w = cmul(cmk(0.5 * q.x, 0.5 * q.y), s_d[j]);
+                    const double2 ow = cmul(om, w);
+                    z[r][c].x += ow.x;
+                    z[r][c].y += ow.y;
+                }
+            }
+            if (GB.bordered && tx == 0 && i < n) {
+                // g_i = -p/2 (Q_in + d_i' Q_ni'), i' the partner index in the other half
+                const int half = n / 2;
+                const int ip = i < half ? i + half : i - half;
+                const double2 t = cmul(s_d[ip], s_qr[ip]);
+                const double2 g = cmul(cmk(-0.5 * pb.x, -0.5 * pb.y), cmk(s_qc[i].x + t.x, s_qc[i].y + t.y));
+                const double2 og = cmul(om, g);
+                zg[r].x += og.x;
+                zg[r].y += og.y;
+            }
+        }
+        if (tid == 0) {
+            z0.x += om.x;
+            z0.y += om.y;
+        }
+    }
+    // write this chunk's partial sums: n x n, then n, then 1
+    double2 *__restrict__ out = A.partial + (int64_t)item * A.part_stride;
+    #pragma unroll
+    for (int r = 0; r < TR; ++r) {
+        const int i = r * PR + ty;
+        #pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            const int j = c * PC + tx;
+            if (i < n && j < n) out[(int64_t)i * n + j] = z[r][c];
+        }
+        if (tx == 0 && i < n) out[(int64_t)n * n + i] = zg[r];
+    }
+    if (tid == 0) out[(int64_t)n * n + n] = z0;
+}
+
+// Sum the chunk partials of every gradient block in a fixed order.
+__global__ void adjoint_reduce(const GradBlockDev *__restrict__ gblocks, const int64_t *__restrict__ elem_prefix,
+                               int ngb, int64_t total, const double2 *__restrict__ partial, int64_t part_stride,
+                               double2 *__restrict__ zout)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int b = find_job(elem_prefix, ngb, e);
+    const GradBlockDev GB = gblocks[b];
+    const int64_t le = e - elem_prefix[b];
+    double2 acc = cmk(0.0, 0.0);
+    for (int c = 0; c < GB.nchunks; ++c) {
+        const double2 v = partial[(int64_t)(GB.first_item + c) * part_stride + le];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    zout[GB.z_off + le] = acc;
+}
+
+// Move each instance's adjoint-DFT result (ping-pong buffer chosen by the
+// parity of its number of axes) to the point-indexed buffer.
+__global__ void adjoint_gather(const InstDev *__restrict__ insts, const int64_t *__restrict__ inst_pt_prefix,
+                               int n_inst, int64_t npts, const int64_t *__restrict__ buf_off,
+                               const double2 *__restrict__ bufA, const double2 *__restrict__ bufB,
+                               double2 *__restrict__ ghat)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const int i = find_job(inst_pt_prefix, n_inst, p);
+    const InstDev &I = insts[i];
+    const double2 *src = (I.L & 1) ? bufB : bufA;
+    ghat[p] = src[buf_off[i] + (p - I.pt_off)];
+}
+
+// Real dL/dP -> complex buffer scaled by 1/prod G (input of the adjoint DFT).
+__global__ void adjoint_seed(const InstDev *__restrict__ insts, const int64_t *__restrict__ prob_prefix, int n_inst,
+                             int64_t nprobs, const double *__restrict__ dprobs, const int64_t *__restrict__ buf_off,
+                             double2 *__restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nprobs) return;
+    const int i = find_job(prob_prefix, n_inst, q);
+    const InstDev &I = insts[i];
+    double gprod = 1;
+    for (int l = 0; l < I.L; ++l) gprod *= I.G[l];
+    out[buf_off[i] + (q - I.prob_off)] = cmk(dprobs[q] / gprod, 0.0);
+}
+
+// ---------------------------------------------------------------------------
 // Mixed path.  After the FP32 pass, a point's value of G carries a relative
 // error of at most tau (per instance); it enters each probability as
 // c_k |G_k| tau / prod G, and sum_k c_k = prod G over the half grid.  So
@@ -1094,6 +1347,60 @@ hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *log
                             hipStream_t st) {
     if (n_inst <= 0 || !err) return hipSuccess;
     hipLaunchKernelGGL(mixed_err, dim3(n_inst), dim3(256), 0, st, insts, logg, err, status);
+    return hipGetLastError();
+}
+}  // namespace cgd
+
+namespace cgd {
+template <int PR, int PC, int TR, int TC>
+static hipError_t launch_adj(const AdjArgs &a, int nitems, hipStream_t st) {
+    hipLaunchKernelGGL((lu_adjoint<PR, PC, TR, TC>), dim3(nitems), dim3(PR * PC), 0, st, a);
+    return hipGetLastError();
+}
+
+int adj_class_limit(int cls) {
+    switch (cls) {
+        case 0: return 32;
+        case 1: return 64;
+        case 2: return 96;
+        default: return 0;
+    }
+}
+
+hipError_t launch_adjoint(int cls, const AdjArgs &a0, int nitems, int64_t item_base, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    AdjArgs a = a0;
+    a.item_base = (int)item_base;
+    switch (cls) {
+        case 0: return launch_adj<8, 8, 4, 4>(a, nitems, st);
+        case 1: return launch_adj<16, 16, 4, 4>(a, nitems, st);
+        case 2: return launch_adj<16, 32, 6, 3>(a, nitems, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjoint_reduce(const GradBlockDev *gblocks, const int64_t *elem_prefix, int ngb, int64_t total,
+                                 const double2 *partial, int64_t part_stride, double2 *zout, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adjoint_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, gblocks,
+                       elem_prefix, ngb, total, partial, part_stride, zout);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gather(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                                 const int64_t *buf_off, const double2 *bufA, const double2 *bufB, double2 *ghat,
+                                 hipStream_t st) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adjoint_gather, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts, inst_pt_prefix,
+                       n_inst, npts, buf_off, bufA, bufB, ghat);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed(const InstDev *insts, const int64_t *prob_prefix, int n_inst, int64_t nprobs,
+                               const double *dprobs, const int64_t *buf_off, double2 *out, hipStream_t st) {
+    if (nprobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adjoint_seed, dim3((unsigned)((nprobs + 255) / 256)), dim3(256), 0, st, insts, prob_prefix,
+                       n_inst, nprobs, dprobs, buf_off, out);
     return hipGetLastError();
 }
 }  // namespace cgd

@@ -1,0 +1,109 @@
+"""Gradients from the adjoint kernels (through the C ABI) against the autograd
+oracle and central finite differences of the GPU forward."""
+import numpy as np
+import pytest
+
+import paper_2412_17742_amd as cgd
+import workloads as W
+from oracle import grad as og
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _gpu_grad(insts, dP_list):
+    import torch
+    with cgd.Context(insts, flags=cgd.FLAG_GRAD) as ctx:
+        P = ctx.eval()
+        dP = torch.tensor(np.concatenate([d.ravel() for d in dP_list]), dtype=torch.float64, device="cuda")
+        dr, dT, da = ctx.grad(dP)
+        torch.cuda.synchronize()
+        return dr.cpu().numpy(), dT.cpu().numpy(), da.cpu().numpy(), P.cpu().numpy()
+
+
+def _small_instances():
+    rng = W.rng_for(76)
+    out = []
+    M = 3
+    T = np.sqrt(0.7) * W.haar_unitary(M, rng)
+    alpha = 0.3 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    out.append(W.make_instance(T, rng.uniform(0.3, 0.6, M), alpha=alpha, schmidt=[0.7, 0.3],
+                               bin_of=[0, 1, -1], cutoff=[2, 3], grid=[5, 6]))
+    M = 4
+    T = np.sqrt(0.6) * W.haar_unitary(M, rng)
+    out.append(W.make_instance(T, rng.uniform(0.2, 0.7, M), bin_of=[0, 0, 1, 1], cutoff=[4, 4], grid=[8, 7]))
+    T = np.sqrt(0.8) * W.haar_unitary(M, rng)
+    alpha = 0.4 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    out.append(W.make_instance(T, rng.uniform(0.2, 0.5, M), alpha=alpha, bin_of=[0, 0, 0, 0], cutoff=[6], grid=[9]))
+    return out
+
+
+def test_adjoint_matches_autograd_oracle():
+    _say("adjoint vs autograd oracle (batched small instances)")
+    insts = _small_instances()
+    rng = np.random.default_rng(3)
+    dPs = [rng.standard_normal(tuple(int(c) + 1 for c in x["cutoff"])) for x in insts]
+    dr, dT, da, _ = _gpu_grad(insts, dPs)
+    ro = to = 0
+    for x, dP in zip(insts, dPs):
+        M = x["T"].shape[0]
+        gr, gT, ga, _ = og.gradients(x, dP)
+        assert np.abs(dr[ro:ro + M] - gr).max() < 1e-11, (dr[ro:ro + M], gr)
+        assert np.abs(dT[to:to + M * M].reshape(M, M) - gT).max() < 1e-11
+        if ga is not None:
+            assert np.abs(da[ro:ro + M] - ga).max() < 1e-11
+        else:
+            assert np.abs(da[ro:ro + M]).max() == 0.0
+        ro += M
+        to += M * M
+
+
+def test_config5_gradients_wrt_r_eta_theta_vs_finite_differences():
+    """Config 5 shape (M=32, K=4, 2 bins of 16, cutoff 12) on a few parameter
+    sets: d(loss)/d(r, eta, theta) through the autograd wrapper against central
+    differences (h = 1e-6) of the GPU forward."""
+    import torch
+    _say("config5 gradients vs central differences")
+    p = W.config5_params(2)
+    spec = dict(schmidt=p["schmidt"], bin_of=p["bin_of"], cutoff=p["cutoff"])
+    rng = np.random.default_rng(5)
+    wgt = torch.tensor(rng.standard_normal((2, 13, 13)), dtype=torch.float64, device="cuda")
+
+    def loss_of(r, eta, theta):
+        T = torch.stack([W.config5_transfer(eta[b], theta[b], p["phases"], p["M"]) for b in range(2)])
+        P = cgd.distribution(r, T, None, spec)
+        return (P * wgt).sum()
+
+    r = torch.tensor(np.stack([s["r"] for s in p["sets"]]), requires_grad=True)
+    eta = torch.tensor(np.stack([s["eta"] for s in p["sets"]]), requires_grad=True)
+    theta = torch.tensor(np.stack([s["theta"] for s in p["sets"]]), requires_grad=True)
+    L = loss_of(r, eta, theta)
+    L.backward()
+    h = 1e-6
+    checks = [("r", r, (0, 3)), ("r", r, (1, 30)), ("eta", eta, (0, 7)), ("eta", eta, (1, 16)),
+              ("theta", theta, (0, 0)), ("theta", theta, (1, 250)), ("theta", theta, (0, 495))]
+    for name, var, idx in checks:
+        with torch.no_grad():
+            base = [r.detach().clone(), eta.detach().clone(), theta.detach().clone()]
+            k = {"r": 0, "eta": 1, "theta": 2}[name]
+            plus = [b.clone() for b in base]
+            minus = [b.clone() for b in base]
+            plus[k][idx] += h
+            minus[k][idx] -= h
+            fd = (loss_of(*plus).item() - loss_of(*minus).item()) / (2 * h)
+        g = var.grad[idx].item()
+        _say(f"  d/d{name}{idx}: adjoint {g:.10e}  fd {fd:.10e}")
+        assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (name, idx, g, fd)
+
+
+def test_gradient_is_bitwise_reproducible():
+    import torch
+    insts = _small_instances()
+    dPs = [np.ones(tuple(int(c) + 1 for c in x["cutoff"])) for x in insts]
+    a = _gpu_grad(insts, dPs)
+    b = _gpu_grad(insts, dPs)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
