@@ -113,7 +113,22 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tol", type=float, default=1e-9, help="absolute error budget per probability (mixed path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 3 times (scale for HBM byte counters)")
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
+                    help="paths to time (the JSON line needs both for the mixed-vs-FP64 check)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 256 * 2 ** 20 // 8
+        src = torch.randn(n, device="cuda", dtype=torch.float64)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_call": n * 8, "calls": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU layout is "
               "described in DESIGN.md but not built", file=sys.stderr)
@@ -154,17 +169,24 @@ def main():
     # dominant kernel: the stage with the largest device time
     dom = max(stages, key=stages.get)
     dom_ms = stages[dom]
-    fp32_pass = best == "mixed" and dom.startswith("lu_reg")
     if dom == "dft":
         achieved = bytes_[dom] / (dom_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s")
+        kname = "dft_stage"
+    elif best == "mixed" and dom in cgd.LU_KERNELS:
+        # first pass of the mixed path: complex FP32 elimination on MFMA (16x16x4 f32)
+        achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s")
+        kname = cgd.LU_KERNELS[dom][1]
     else:
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
-        # FP64 and (non-packed) FP32 vector FMA share one rate: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+        # FP64 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
+        kname = cgd.LU_KERNELS.get(dom, (dom,))[0]
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = dom + (" (complex FP32)" if fp32_pass else " (complex FP64)")
+    roof["kernel"] = kname
+    roof["stage"] = dom
     roof["work_per_launch"] = flops[dom] if dom != "dft" else bytes_[dom]
 
     def summary(rec, name):

@@ -418,6 +418,10 @@ struct cgd_ctx {
             *d_ghat = nullptr;
     int32_t *d_grb = nullptr;
     int64_t *d_z_prefix = nullptr, *d_adj_off = nullptr, *d_prob_prefix = nullptr;
+    // HIP graph of the evaluation
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double *g_probs = nullptr, *g_err = nullptr;
     bool evaluated = false;
     bool timing = false;
     hipEvent_t ev[CGD_NSTAGES][2] = {};
@@ -444,6 +448,8 @@ void free_ctx(cgd_ctx *c) {
     for (int i = 0; i < CGD_NSTAGES; ++i)
         for (int j = 0; j < 2; ++j)
             if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->ev_status) (void)hipEventDestroy(c->ev_status);
     delete c;
@@ -986,6 +992,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         if ((s = upload(&c->d_list_ptrs, ptrs)) != CGD_OK) return s;
         HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kG64));
     }
+    HIP_OK(prepare_kernels(c->big_nwg > 0 ? c->big_ldw : 0, c->schur_maxA));
     if (want_grad) {
         cgd_status sg = build_grad(c, n_inst);
         if (sg != CGD_OK) return sg;
@@ -1033,12 +1040,9 @@ cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_
 
 int64_t cgd_points(const cgd_ctx *ctx) { return ctx ? ctx->npts : 0; }
 
-cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
-    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
-    if (!d_probs) return fail(CGD_ERR_ARG, "d_probs is NULL");
-    cgd_status s = check_status(c);
-    if (s != CGD_OK) return s;
-    hipStream_t st = c->stream;
+namespace {
+// Enqueue every launch of one evaluation on stream st.
+cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_err_bound) {
     auto mark = [&](int stage, int which) -> hipError_t {
         if (!c->timing) return hipSuccess;
         c->stage_ran[stage] = true;
@@ -1110,8 +1114,42 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
     }
     HIP_OK(mark(CGD_STAGE_DFT, 1));
     if (mixed) HIP_OK(launch_mixed_err(c->d_inst, c->n_inst, c->d_logg32, d_err_bound, c->d_status, st));
-    HIP_OK(hipMemcpyAsync(c->h_status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipEventRecord(c->ev_status, st));
+    return CGD_OK;
+}
+}  // namespace
+
+cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (!d_probs) return fail(CGD_ERR_ARG, "d_probs is NULL");
+    cgd_status s = check_status(c);
+    if (s != CGD_OK) return s;
+    if (c->timing) {
+        // per-stage events need the launches on the caller's stream, one by one
+        s = enqueue_eval(c, c->stream, d_probs, d_err_bound);
+        if (s != CGD_OK) return s;
+    } else {
+        // the launch sequence is captured once on a private stream into a HIP
+        // graph and replayed on the caller's stream; captured again when the
+        // output pointers change
+        if (!c->gexec || c->g_probs != d_probs || c->g_err != d_err_bound) {
+            if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+            if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            s = enqueue_eval(c, c->cap_stream, d_probs, d_err_bound);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+            if (s != CGD_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+            if (e != hipSuccess) return fail(CGD_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            const hipError_t e2 = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e2 != hipSuccess) return fail(CGD_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+            c->g_probs = d_probs;
+            c->g_err = d_err_bound;
+        }
+        HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+    }
+    HIP_OK(hipMemcpyAsync(c->h_status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipEventRecord(c->ev_status, c->stream));
     c->status_pending = true;
     c->evaluated = true;
     return CGD_OK;

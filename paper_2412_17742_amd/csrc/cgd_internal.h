@@ -124,6 +124,7 @@ constexpr int kMfmaClasses = 6;
 int mfma_class_limit(int cls);         // max matrix order of FP32 MFMA class cls
 hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st);
 size_t lu_big_lds_bytes(int ldw);
+hipError_t prepare_kernels(int big_ldw, int schur_maxA);
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st);
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
                               const double2 *pool_in, const double *eigpool, double2 *pool_out, float2 *pool32_out,

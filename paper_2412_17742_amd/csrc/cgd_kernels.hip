@@ -165,6 +165,7 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
     static_assert(PC % PR == 0, "column owner must be uniform over a register row");
     __shared__ C s_u[2][N];
     __shared__ C s_l[2][N];
+    __shared__ C s_inv[2];
     __shared__ C s_d[N];
     __shared__ C s_piv[N];
     __shared__ double2 s_w[kMaxBins];
@@ -234,6 +235,14 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
                     for (int c = cown; c < TC; ++c) {
                         const int j = c * PC + tx;
                         if (j >= k) s_u[buf][j] = a[r][c];
+                        if (j == k) {
+                            // the pivot's owner publishes its reciprocal and records it
+                            s_inv[buf] = inv2<T>(a[r][c]);
+                            const C d = a[r][c];
+                            s_piv[k] = d;
+                            // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
+                            if (!isfinite(d.x) || !isfinite(d.y) || (k < nb - B.bordered && !(d.x > T(0)))) s_bad = 1;
+                        }
                     }
                 }
                 if (tx == k % PC) {
@@ -244,13 +253,7 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
                     }
                 }
                 __syncthreads();
-                const C d = s_u[buf][k];
-                if (tid == 0) {
-                    s_piv[k] = d;
-                    // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
-                    if (!isfinite(d.x) || !isfinite(d.y) || (k < nb - B.bordered && !(d.x > T(0)))) s_bad = 1;
-                }
-                const C dinv = inv2<T>(d);
+                const C dinv = s_inv[buf];
                 C u[TC];
                 #pragma unroll
                 for (int c = cown; c < TC; ++c) {
@@ -310,13 +313,14 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 //     A22 <- A22 - X (D^-1 Y),   X = A[k+4:, k:k+4], D = A[k:k+4, k:k+4], Y = A[k:k+4, k+4:],
 // which is the Schur complement after four more pivots:
 //   1. the waves holding tile column k/16 write X (and D) and the waves
-//      holding tile row k/16 write the panel rows (D and Y) to LDS; barrier;
-//   2. the waves holding tile row k/16 factorise D = L_D U_D (every lane, from
-//      LDS) and solve W = D^-1 Y, one column per lane; the wave holding the
-//      diagonal tile records the pivots of U_D; barrier;
-//   3. every tile at or right/below the panel is updated, A -= X W, with four
-//      real 16x16x4 MFMAs (complex product); lane l supplies X[row, l/16] and
-//      W[l/16, col] in the MFMA operand layouts.
+//      holding tile row k/16 write the panel rows (D and Y) to LDS;
+//   2. the wave holding the diagonal tile reads D back, factorises it
+//      (D = L_D U_D, whose diagonal holds the four pivots) and writes D^-1;
+//      one barrier;
+//   3. every lane forms its operands, -X[row, l/16] and W[l/16, col] =
+//      sum_s D^-1[l/16, s] Y[s, col] (the MFMA operand layouts), and every
+//      tile at or right/below the panel is updated, A -= X W, with four real
+//      16x16x4 MFMAs (complex product).
 // Rows and columns already eliminated receive harmless updates (their
 // operands are zero).  Pivots go to LDS; the epilogue (FP64) is the same as in
 // the register kernel.
@@ -341,10 +345,9 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
     constexpr int N = 16 * NTILE;
     constexpr int TRW = (NTILE + WR - 1) / WR;
     constexpr int TCW = (NTILE + WC - 1) / WC;
-    static_assert(TCW <= 4, "one tile column per lane group in step 2");
-    __shared__ float2 s_X[N][4];   // panel columns (rows >= k)
-    __shared__ float2 s_Y[4][N];   // panel rows (columns >= k)
-    __shared__ float2 s_W[4][N];   // D^-1 Y
+    __shared__ float2 s_X2[2][N][4];   // panel columns (rows >= k), by panel parity
+    __shared__ float2 s_Y2[2][4][N];   // panel rows (columns >= k)
+    __shared__ float2 s_Di2[2][4][4];  // D^-1
     __shared__ float2 s_d[N];
     __shared__ float2 s_piv[N];
     __shared__ double2 s_w[kMaxBins];
@@ -415,6 +418,10 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
         for (int q = 0; q < 16; q += 4) {
             const int k = J * 16 + q;
             if ((k >> 2) >= npan) break;
+            // double-buffered by panel parity: one barrier per panel suffices
+            float2 (*s_X)[4] = s_X2[(k >> 2) & 1];
+            float2 (*s_Y)[N] = s_Y2[(k >> 2) & 1];
+            float2 (*s_Di)[4] = s_Di2[(k >> 2) & 1];
             // 1. publish the panel
             if (own_col && lc >= q && lc < q + 4) {
                 #pragma unroll
@@ -437,9 +444,12 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                     }
                 }
             }
-            __syncthreads();
-            // 2. D = L_D U_D and W = D^-1 Y (waves of tile row k/16, one column per lane)
-            if (own_row) {
+            // 2. the wave holding the diagonal tile inverts D (just written to s_Y by
+            //    its own lanes) and records the pivots of D = L_D U_D
+            if (own_row && own_col) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 const float2 d00 = s_Y[0][k], d01 = s_Y[0][k + 1], d02 = s_Y[0][k + 2], d03 = s_Y[0][k + 3];
                 const float2 d10 = s_Y[1][k], d11 = s_Y[1][k + 1], d12 = s_Y[1][k + 2], d13 = s_Y[1][k + 3];
                 const float2 d20 = s_Y[2][k], d21 = s_Y[2][k + 1], d22 = s_Y[2][k + 2], d23 = s_Y[2][k + 3];
@@ -455,7 +465,24 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                 const float2 l32 = fmul(fsub_mul(fsub_mul(d32, l30, d02), l31, u12), r2);
                 const float2 u33 = fsub_mul(fsub_mul(fsub_mul(d33, l30, d03), l31, u13), l32, u23);
                 const float2 r3 = finv(u33);
-                if (wc == J % WC && lane == 0) {
+                if (lane < 4) {
+                    // column c = lane of D^-1: solve L_D z = e_c, then U_D x = z
+                    const int cc = lane;
+                    const float2 e0 = f2(cc == 0 ? 1.f : 0.f, 0.f), e1 = f2(cc == 1 ? 1.f : 0.f, 0.f);
+                    const float2 e2 = f2(cc == 2 ? 1.f : 0.f, 0.f), e3 = f2(cc == 3 ? 1.f : 0.f, 0.f);
+                    const float2 z1 = fsub_mul(e1, l10, e0);
+                    const float2 z2 = fsub_mul(fsub_mul(e2, l20, e0), l21, z1);
+                    const float2 z3 = fsub_mul(fsub_mul(fsub_mul(e3, l30, e0), l31, z1), l32, z2);
+                    const float2 x3 = fmul(z3, r3);
+                    const float2 x2 = fmul(fsub_mul(z2, u23, x3), r2);
+                    const float2 x1 = fmul(fsub_mul(fsub_mul(z1, u12, x2), u13, x3), r1);
+                    const float2 x0 = fmul(fsub_mul(fsub_mul(fsub_mul(e0, d01, x1), d02, x2), d03, x3), r0);
+                    s_Di[0][cc] = x0;
+                    s_Di[1][cc] = x1;
+                    s_Di[2][cc] = x2;
+                    s_Di[3][cc] = x3;
+                }
+                if (lane == 0) {
                     s_piv[k] = d00;
                     if (k + 1 < nb) s_piv[k + 1] = u11;
                     if (k + 2 < nb) s_piv[k + 2] = u22;
@@ -469,27 +496,6 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                                      (k + 2 < nb && !isfinite(u22.x + u22.y)) ||
                                      (k + 3 < nb && !isfinite(u33.x + u33.y));
                     if (bad) s_bad = 1;
-                }
-                if (lg < TCW) {
-                    const int Jt = wc + lg * WC;
-                    if (Jt >= J && Jt < NTILE) {
-                        const int j = Jt * 16 + lc;
-                        float2 w0 = f2(0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
-                        if (j > k + 3) {
-                            const float2 y0 = s_Y[0][j], y1 = s_Y[1][j], y2 = s_Y[2][j], y3 = s_Y[3][j];
-                            const float2 z1 = fsub_mul(y1, l10, y0);
-                            const float2 z2 = fsub_mul(fsub_mul(y2, l20, y0), l21, z1);
-                            const float2 z3 = fsub_mul(fsub_mul(fsub_mul(y3, l30, y0), l31, z1), l32, z2);
-                            w3 = fmul(z3, r3);
-                            w2 = fmul(fsub_mul(z2, u23, w3), r2);
-                            w1 = fmul(fsub_mul(fsub_mul(z1, u12, w2), u13, w3), r1);
-                            w0 = fmul(fsub_mul(fsub_mul(fsub_mul(y0, d01, w1), d02, w2), d03, w3), r0);
-                        }
-                        s_W[0][j] = w0;
-                        s_W[1][j] = w1;
-                        s_W[2][j] = w2;
-                        s_W[3][j] = w3;
-                    }
                 }
             }
             __syncthreads();
@@ -505,27 +511,44 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                 ani[ti] = -x.y;
                 api[ti] = x.y;
             }
+            // B operand: row l/16 of W = D^-1 Y, formed per lane
+            const float2 di0 = s_Di[lg][0], di1 = s_Di[lg][1], di2 = s_Di[lg][2], di3 = s_Di[lg][3];
             float bwr[TCW], bwi[TCW];
             #pragma unroll
             for (int tj = 0; tj < TCW; ++tj) {
                 const int Jt = wc + tj * WC;
+                const int j = Jt * 16 + lc;
                 float2 w = f2(0.f, 0.f);
-                if (Jt >= J && Jt < NTILE) w = s_W[lg][Jt * 16 + lc];
+                if (Jt >= J && Jt < NTILE && j > k + 3) {
+                    w = fmul(di0, s_Y[0][j]);
+                    const float2 t1 = fmul(di1, s_Y[1][j]), t2 = fmul(di2, s_Y[2][j]), t3 = fmul(di3, s_Y[3][j]);
+                    w.x += t1.x + t2.x + t3.x;
+                    w.y += t1.y + t2.y + t3.y;
+                }
                 bwr[tj] = w.x;
                 bwi[tj] = w.y;
             }
+            // tiles of the next panel's tile row and column first: the next publish
+            // waits only for these, the other MFMAs drain during the barrier and
+            // the 4 x 4 solve of the next panel
+            const int Jn = (q == 12) ? J + 1 : J;
             #pragma unroll
-            for (int ti = 0; ti < TRW; ++ti) {
-                const int It = wr + ti * WR;
-                if (It < J || It >= NTILE) continue;
+            for (int pass = 0; pass < 2; ++pass) {
                 #pragma unroll
-                for (int tj = 0; tj < TCW; ++tj) {
-                    const int Jt = wc + tj * WC;
-                    if (Jt < J || Jt >= NTILE) continue;
-                    ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwr[tj], ar[ti][tj], 0, 0, 0);
-                    ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(api[ti], bwi[tj], ar[ti][tj], 0, 0, 0);
-                    ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwi[tj], ai[ti][tj], 0, 0, 0);
-                    ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ani[ti], bwr[tj], ai[ti][tj], 0, 0, 0);
+                for (int ti = 0; ti < TRW; ++ti) {
+                    const int It = wr + ti * WR;
+                    if (It < J || It >= NTILE) continue;
+                    #pragma unroll
+                    for (int tj = 0; tj < TCW; ++tj) {
+                        const int Jt = wc + tj * WC;
+                        if (Jt < J || Jt >= NTILE) continue;
+                        const bool first = (It == Jn) || (Jt == Jn);
+                        if (first != (pass == 0)) continue;
+                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwr[tj], ar[ti][tj], 0, 0, 0);
+                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(api[ti], bwi[tj], ar[ti][tj], 0, 0, 0);
+                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwi[tj], ai[ti][tj], 0, 0, 0);
+                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ani[ti], bwr[tj], ai[ti][tj], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -1283,9 +1306,6 @@ size_t lu_big_lds_bytes(int ldw) {
 
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st) {
     if (!a.list && a.nitems <= 0) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lu_big_lds_bytes(ldw));
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(lu_big_f64, dim3(nwg), dim3(kBigThreads), lu_big_lds_bytes(ldw), st, a.job_block,
                        a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts,
                        (const double2 *)a.pool, a.rbpool, a.eigpool, work, ldw, a.contrib, a.status);
@@ -1297,9 +1317,6 @@ hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int n
                               hipStream_t st) {
     if (nwg <= 0) return hipSuccess;
     const size_t lds = sizeof(double2) * (size_t)maxA * (1 + kSchurRows);
-    hipError_t e = hipFuncSetAttribute((const void *)schur_build_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(schur_build_f64, dim3((unsigned)nwg), dim3(256), lds, st, jobs, prefix, njobs, pool_in,
                        eigpool, pool_out, pool32_out);
     return hipGetLastError();
@@ -1402,5 +1419,24 @@ hipError_t launch_adjoint_seed(const InstDev *insts, const int64_t *prob_prefix,
     hipLaunchKernelGGL(adjoint_seed, dim3((unsigned)((nprobs + 255) / 256)), dim3(256), 0, st, insts, prob_prefix,
                        n_inst, nprobs, dprobs, buf_off, out);
     return hipGetLastError();
+}
+}  // namespace cgd
+
+namespace cgd {
+// Dynamic LDS limits of the kernels that need more than the default; called
+// once at context creation (not inside a captured launch sequence).
+hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
+    if (big_ldw > 0) {
+        const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lu_big_lds_bytes(big_ldw));
+        if (e != hipSuccess) return e;
+    }
+    if (schur_maxA > 0) {
+        const hipError_t e = hipFuncSetAttribute((const void *)schur_build_f64,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)(sizeof(double2) * (size_t)schur_maxA * (1 + kSchurRows)));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 }  // namespace cgd

@@ -238,3 +238,28 @@ def test_repeat_evaluations_are_bitwise_identical():
         b = ctx.eval().clone()
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager_evaluation(precision):
+    """cgd_eval replays a captured HIP graph; every replay, with unrelated
+    device work in between, must equal an eager (uncaptured) evaluation."""
+    import torch
+    _say("graph replays vs eager,", precision)
+    insts = [W.config2(grid=[5, 5, 5, 5]), W.config1(), _edge_instances()[3]]
+    insts[0]["cutoff"] = np.array([4, 4, 4, 4], np.int32)
+    with cgd.Context(insts, precision=precision) as ctx:
+        ctx.set_timing(True)
+        eager = ctx.eval().clone()
+        ctx.set_timing(False)
+        probs = torch.empty_like(eager)
+        x = torch.randn(512, 512, device="cuda", dtype=torch.float64)
+        for rep in range(4):
+            ctx.eval(probs)
+            x = x @ x.T / 512.0
+            torch.cuda.synchronize()
+            assert torch.equal(probs, eager), rep
+        other = torch.empty_like(eager)  # new output pointer: captured again
+        ctx.eval(other)
+        torch.cuda.synchronize()
+        assert torch.equal(other, eager)
