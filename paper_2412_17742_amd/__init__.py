@@ -32,7 +32,7 @@ LU_KERNELS = {
     "lu_le96": ("lu_reg<double,16,32,6,3>", "lu_mfma_f32<6,2,4>"),
     "lu_le128": ("lu_reg<double,16,32,8,4>", "lu_mfma_f32<8,2,4>"),
     "lu_le144": ("lu_reg<double,16,48,9,3>", "lu_mfma_f32<9,3,4>"),
-    "lu_gt144": ("lu_big_f64", "lu_mfma_f32<12,3,4> (orders <= 192)"),
+    "lu_gt144": ("lu_big_f64", "lu_mfma_f32<12,2,4> (orders <= 192)"),
 }
 
 

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "cgd_internal.h"
 
 namespace cgd {
@@ -211,13 +213,15 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
             #pragma unroll
             for (int c = 0; c < TC; ++c) {
                 const int j = c * PC + tx;
+                // clamped, unconditional loads: all of them are in flight at once
+                const bool in = i < nb && j < nb;
+                const int ic = in ? i : 0, jc = in ? j : 0;
+                PT h = Hs[(int64_t)ic * nb + jc];
+                if (!in) h.x = h.y = 0;
+                const C d = s_d[ic];
                 C v = mk2<T>(i == j ? T(1) : T(0), T(0));
-                if (i < nb && j < nb) {
-                    const PT h = Hs[(int64_t)i * nb + j];
-                    const C d = s_d[i];
-                    v.x -= d.x * h.x - d.y * h.y;
-                    v.y -= d.x * h.y + d.y * h.x;
-                }
+                v.x -= d.x * h.x - d.y * h.y;
+                v.y -= d.x * h.y + d.y * h.x;
                 a[r][c] = v;
             }
         }
@@ -308,51 +312,138 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 // The padded 16 NTILE x 16 NTILE matrix is split into 16 x 16 tiles; tile
 // (I, J) is held by wave (I mod WR, J mod WC) as two MFMA accumulators (real
 // and imaginary part) in the 16x16x4 f32 layout: lane l, register v holds
-// element (4 (l/16) + v, l mod 16) of the tile.  The elimination proceeds in
-// panels of 4 columns k..k+3, each a block step
-//     A22 <- A22 - X (D^-1 Y),   X = A[k+4:, k:k+4], D = A[k:k+4, k:k+4], Y = A[k:k+4, k+4:],
-// which is the Schur complement after four more pivots:
-//   1. the waves holding tile column k/16 write X (and D) and the waves
-//      holding tile row k/16 write the panel rows (D and Y) to LDS;
-//   2. the wave holding the diagonal tile reads D back, factorises it
-//      (D = L_D U_D, whose diagonal holds the four pivots) and writes D^-1;
-//      one barrier;
-//   3. every lane forms its operands, -X[row, l/16] and W[l/16, col] =
-//      sum_s D^-1[l/16, s] Y[s, col] (the MFMA operand layouts), and every
-//      tile at or right/below the panel is updated, A -= X W, with four real
-//      16x16x4 MFMAs (complex product).
-// Rows and columns already eliminated receive harmless updates (their
-// operands are zero).  Pivots go to LDS; the epilogue (FP64) is the same as in
-// the register kernel.
+// element (4 (l/16) + v, l mod 16) of the tile.  Elimination goes one tile
+// column at a time.  With D the diagonal tile, X the tiles below it and Y the
+// tiles to its right (all after the previous steps), the trailing matrix takes
+// the Schur complement update
+//     A22 <- A22 - X W,    W = D^-1 Y,
+// as 16 MFMAs per tile (K = 16, complex product as four real products).
+// det S is the product of det D over the steps, and the pivots of D's own
+// unpivoted elimination are the pivots of S.  One step J:
+//   1. every wave updates its tiles, those of tile row and column J+1 first;
+//      the owners then write X (negated, transposed) and Y of step J+1 to
+//      LDS, and the owner of tile (J+1, J+1) inverts it by Gauss-Jordan
+//      elimination in registers (row broadcast by lane-swap permutes, column
+//      broadcast by DPP row_newbcast), recording its pivots, while the other
+//      waves carry on with the rest of the update;
+//   2. barrier; the owners of tile row J+1 form W = D^-1 Y on MFMA and write
+//      it to LDS; barrier.
+// X and W are double-buffered by step parity.  Padding rows and columns hold
+// the identity and stay decoupled, so they add pivots equal to 1.  The
+// epilogue (FP64) is the same as in the register kernel.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
-__device__ __forceinline__ float2 fmul(float2 a, float2 b) { return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
-__device__ __forceinline__ float2 fsub_mul(float2 c, float2 a, float2 b) {  // c - a b
-    return f2(c.x - (a.x * b.x - a.y * b.y), c.y - (a.x * b.y + a.y * b.x));
+
+template <int K>
+__device__ __forceinline__ float row_bcast(float x) {  // lane K of each 16-lane row to the whole row
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x150 + K, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float2 finv(float2 d) {  // 1/d with the hardware reciprocal (1 ulp)
-    const float s = __builtin_amdgcn_rcpf(d.x * d.x + d.y * d.y);
-    return f2(d.x * s, -d.y * s);
+
+// 16-lane row G to all four rows: the 32-lane swap pairs rows (0,1) or
+// (2,3), the 16-lane swap then spreads the wanted one (VALU only).
+template <int G>
+__device__ __forceinline__ float group_to_all(float x) {
+    const unsigned u = __builtin_bit_cast(unsigned, x);
+    const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);  // rows (0 1 0 1), (2 3 2 3)
+    const unsigned y = (G < 2) ? h[0] : h[1];
+    const auto q = __builtin_amdgcn_permlane16_swap(y, y, false, false);
+    return __builtin_bit_cast(float, (G & 1) ? q[1] : q[0]);
 }
+
+__device__ __forceinline__ float uniform_read(float x, int src_lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src_lane));
+}
+
+// Gauss-Jordan inversion of the 16 x 16 tile held in the accumulator layout
+// (lane (g, c), register v: element (4g + v, c)).  Step k, with p = a[k][k]:
+// a[k][c] <- a[k][c]/p, a[r][k] <- -a[r][k]/p, a[k][k] <- 1/p and
+// a[r][c] <- a[r][c] - a[r][k] a[k][c]/p elsewhere.  After the 16 steps the
+// tile holds its inverse; p is the k-th pivot of the unpivoted LU.  Row k
+// reaches every lane by two lane-swap permutes and column k by DPP
+// row_newbcast, all in VALU; each step updates row k+1 first, so that its
+// broadcast overlaps the rest.
+template <int K>
+__device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int g, int c, float &rowr, float &rowi,
+                                        float &pr, float &pi) {
+    constexpr int KG = K >> 2, KV = K & 3;
+    constexpr int V1 = (K + 1) & 3, G1 = (K + 1) >> 2;
+    float colr[4], coli[4];
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        colr[v] = row_bcast<K>(ar[v]);
+        coli[v] = row_bcast<K>(ai[v]);
+    }
+    const float s = __builtin_amdgcn_rcpf(pr * pr + pi * pi);
+    const float rpr = pr * s, rpi = -pi * s;
+    const bool isk = (c == K);
+    const float tr = isk ? rpr : fmaf(rowr, rpr, -rowi * rpi);
+    const float ti = isk ? rpi : fmaf(rowr, rpi, rowi * rpr);
+    auto upd = [&](int v) {
+        const float br = isk ? 0.f : ar[v], bi = isk ? 0.f : ai[v];
+        ar[v] = fmaf(coli[v], ti, fmaf(-colr[v], tr, br));
+        ai[v] = fmaf(-coli[v], tr, fmaf(-colr[v], ti, bi));
+    };
+    if (K < 15) {
+        upd(V1);  // row K+1 (on group G1) first
+        rowr = group_to_all<G1>(ar[V1]);
+        rowi = group_to_all<G1>(ai[V1]);
+        pr = uniform_read(ar[V1], G1 * 16 + K + 1);
+        pi = uniform_read(ai[V1], G1 * 16 + K + 1);
+    }
+    #pragma unroll
+    for (int v = 0; v < 4; ++v)
+        if (K == 15 || v != V1) upd(v);
+    if (g == KG) {
+        ar[KV] = tr;
+        ai[KV] = ti;
+    }
+}
+
+// Runs the 16 steps; pivot k ends up in lane k of (pvr, pvi).
+template <int... K>
+__device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], int g, int c, float &pvr, float &pvi,
+                                       std::integer_sequence<int, K...>) {
+    const int lane = g * 16 + c;
+    float rowr = group_to_all<0>(ar[0]), rowi = group_to_all<0>(ai[0]);
+    float pr = uniform_read(ar[0], 0), pi = uniform_read(ai[0], 0);
+    pvr = pr;
+    pvi = pi;
+    auto keep = [&](int k) {
+        if (lane == k) {
+            pvr = pr;
+            pvi = pi;
+        }
+    };
+    ((gj_step<K>(ar, ai, g, c, rowr, rowi, pr, pi), keep(K + 1)), ...);
+}
+
+template <int NTILE, int WR, int WC>
+struct MfmaLds {
+    static constexpr int N = 16 * NTILE;
+    static constexpr int XS = N + 1;  // padded stride of the transposed X panel
+    float2 XT[2][16][XS];             // -X^T of the step's tile column, by step parity
+    float2 W[2][16][N];               // W = D^-1 Y, by step parity
+    float2 Y[16][N];                  // tile row of the next step (each wave its own tiles)
+    float2 DiT[16][17];               // (D^-1)^T
+    float2 d[N];
+    float2 piv[N];
+    double2 w[kMaxBins];
+    double2 red[WR * WC + 1];
+    int bad;
+};
 
 template <int NTILE, int WR, int WC>
 __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
 {
     constexpr int NW = WR * WC;
     constexpr int NT = 64 * NW;
-    constexpr int N = 16 * NTILE;
     constexpr int TRW = (NTILE + WR - 1) / WR;
     constexpr int TCW = (NTILE + WC - 1) / WC;
-    __shared__ float2 s_X2[2][N][4];   // panel columns (rows >= k), by panel parity
-    __shared__ float2 s_Y2[2][4][N];   // panel rows (columns >= k)
-    __shared__ float2 s_Di2[2][4][4];  // D^-1
-    __shared__ float2 s_d[N];
-    __shared__ float2 s_piv[N];
-    __shared__ double2 s_w[kMaxBins];
-    __shared__ double2 s_red[NW + 1];
-    __shared__ int s_bad;
+    using Lds = MfmaLds<NTILE, WR, WC>;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Lds &S = *reinterpret_cast<Lds *>(lds_raw);
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -375,13 +466,15 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
     const BlockDev B = A.blocks[bi];
     const InstDev &I = A.insts[B.inst];
     const int nb = B.nb;
+    const int nl = nb - B.bordered;  // pivots of S (the border's need not be in the right half-plane)
+    const int ntl = (nb + 15) >> 4;  // tiles in use
 
-    if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
-    if (tid == 0) s_bad = 0;
+    if (tid < I.L) point_w(I, pt, tid, S.w[tid]);
+    if (tid == 0) S.bad = 0;
     __syncthreads();
     for (int i = tid; i < nb; i += NT) {
         const int b = A.rbpool[B.rb_off + i];
-        s_d[i] = b < 0 ? f2(1.0f, 0.0f) : f2((float)s_w[b].x, (float)s_w[b].y);
+        S.d[i] = b < 0 ? f2(1.0f, 0.0f) : f2((float)S.w[b].x, (float)S.w[b].y);
     }
     __syncthreads();
 
@@ -396,174 +489,177 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
             const int It = wr + ti * WR, Jt = wc + tj * WC;
             #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                // clamped, unconditional loads: all of them are in flight at once
                 const int i = It * 16 + 4 * lg + v, j = Jt * 16 + lc;
-                float re = (i == j) ? 1.0f : 0.0f, im = 0.0f;
-                if (It < NTILE && Jt < NTILE && i < nb && j < nb) {
-                    const float2 h = Hs[(int64_t)i * nb + j];
-                    const float2 d = s_d[i];
-                    re -= d.x * h.x - d.y * h.y;
-                    im -= d.x * h.y + d.y * h.x;
-                }
-                ar[ti][tj][v] = re;
-                ai[ti][tj][v] = im;
+                const bool in = i < nb && j < nb;
+                const int ic = in ? i : 0, jc = in ? j : 0;
+                float2 h = Hs[(int64_t)ic * nb + jc];
+                const float2 d = S.d[ic];
+                if (!in) h = f2(0.f, 0.f);
+                ar[ti][tj][v] = ((i == j) ? 1.0f : 0.0f) - (d.x * h.x - d.y * h.y);
+                ai[ti][tj][v] = -(d.x * h.y + d.y * h.x);
             }
         }
 
-    const int npan = (nb + 3) >> 2;
-    #pragma unroll
-    for (int J = 0; J < NTILE; ++J) {
-        if (J * 16 >= nb) break;
-        const int tjJ = J / WC, tiJ = J / WR;
-        const bool own_col = (wc == J % WC), own_row = (wr == J % WR);
-        for (int q = 0; q < 16; q += 4) {
-            const int k = J * 16 + q;
-            if ((k >> 2) >= npan) break;
-            // double-buffered by panel parity: one barrier per panel suffices
-            float2 (*s_X)[4] = s_X2[(k >> 2) & 1];
-            float2 (*s_Y)[N] = s_Y2[(k >> 2) & 1];
-            float2 (*s_Di)[4] = s_Di2[(k >> 2) & 1];
-            // 1. publish the panel
-            if (own_col && lc >= q && lc < q + 4) {
-                #pragma unroll
-                for (int ti = 0; ti < TRW; ++ti) {
-                    const int It = wr + ti * WR;
-                    if (It >= J && It < NTILE) {
-                        #pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            s_X[It * 16 + 4 * lg + v][lc - q] = f2(ar[ti][tjJ][v], ai[ti][tjJ][v]);
-                    }
-                }
-            }
-            if (own_row && lg == (q >> 2)) {
-                #pragma unroll
-                for (int tj = 0; tj < TCW; ++tj) {
-                    const int Jt = wc + tj * WC;
-                    if (Jt >= J && Jt < NTILE) {
-                        #pragma unroll
-                        for (int v = 0; v < 4; ++v) s_Y[v][Jt * 16 + lc] = f2(ar[tiJ][tj][v], ai[tiJ][tj][v]);
-                    }
-                }
-            }
-            // 2. the wave holding the diagonal tile inverts D (just written to s_Y by
-            //    its own lanes) and records the pivots of D = L_D U_D
-            if (own_row && own_col) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const float2 d00 = s_Y[0][k], d01 = s_Y[0][k + 1], d02 = s_Y[0][k + 2], d03 = s_Y[0][k + 3];
-                const float2 d10 = s_Y[1][k], d11 = s_Y[1][k + 1], d12 = s_Y[1][k + 2], d13 = s_Y[1][k + 3];
-                const float2 d20 = s_Y[2][k], d21 = s_Y[2][k + 1], d22 = s_Y[2][k + 2], d23 = s_Y[2][k + 3];
-                const float2 d30 = s_Y[3][k], d31 = s_Y[3][k + 1], d32 = s_Y[3][k + 2], d33 = s_Y[3][k + 3];
-                const float2 r0 = finv(d00);
-                const float2 l10 = fmul(d10, r0), l20 = fmul(d20, r0), l30 = fmul(d30, r0);
-                const float2 u11 = fsub_mul(d11, l10, d01), u12 = fsub_mul(d12, l10, d02), u13 = fsub_mul(d13, l10, d03);
-                const float2 r1 = finv(u11);
-                const float2 l21 = fmul(fsub_mul(d21, l20, d01), r1), l31 = fmul(fsub_mul(d31, l30, d01), r1);
-                const float2 u22 = fsub_mul(fsub_mul(d22, l20, d02), l21, u12);
-                const float2 u23 = fsub_mul(fsub_mul(d23, l20, d03), l21, u13);
-                const float2 r2 = finv(u22);
-                const float2 l32 = fmul(fsub_mul(fsub_mul(d32, l30, d02), l31, u12), r2);
-                const float2 u33 = fsub_mul(fsub_mul(fsub_mul(d33, l30, d03), l31, u13), l32, u23);
-                const float2 r3 = finv(u33);
-                if (lane < 4) {
-                    // column c = lane of D^-1: solve L_D z = e_c, then U_D x = z
-                    const int cc = lane;
-                    const float2 e0 = f2(cc == 0 ? 1.f : 0.f, 0.f), e1 = f2(cc == 1 ? 1.f : 0.f, 0.f);
-                    const float2 e2 = f2(cc == 2 ? 1.f : 0.f, 0.f), e3 = f2(cc == 3 ? 1.f : 0.f, 0.f);
-                    const float2 z1 = fsub_mul(e1, l10, e0);
-                    const float2 z2 = fsub_mul(fsub_mul(e2, l20, e0), l21, z1);
-                    const float2 z3 = fsub_mul(fsub_mul(fsub_mul(e3, l30, e0), l31, z1), l32, z2);
-                    const float2 x3 = fmul(z3, r3);
-                    const float2 x2 = fmul(fsub_mul(z2, u23, x3), r2);
-                    const float2 x1 = fmul(fsub_mul(fsub_mul(z1, u12, x2), u13, x3), r1);
-                    const float2 x0 = fmul(fsub_mul(fsub_mul(fsub_mul(e0, d01, x1), d02, x2), d03, x3), r0);
-                    s_Di[0][cc] = x0;
-                    s_Di[1][cc] = x1;
-                    s_Di[2][cc] = x2;
-                    s_Di[3][cc] = x3;
-                }
-                if (lane == 0) {
-                    s_piv[k] = d00;
-                    if (k + 1 < nb) s_piv[k + 1] = u11;
-                    if (k + 2 < nb) s_piv[k + 2] = u22;
-                    if (k + 3 < nb) s_piv[k + 3] = u33;
-                    // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
-                    const int nl = nb - B.bordered;
-                    const bool bad = (k < nl && !(d00.x > 0.f)) || (k + 1 < nl && !(u11.x > 0.f)) ||
-                                     (k + 2 < nl && !(u22.x > 0.f)) || (k + 3 < nl && !(u33.x > 0.f)) ||
-                                     !isfinite(d00.x + d00.y) ||
-                                     (k + 1 < nb && !isfinite(u11.x + u11.y)) ||
-                                     (k + 2 < nb && !isfinite(u22.x + u22.y)) ||
-                                     (k + 3 < nb && !isfinite(u33.x + u33.y));
-                    if (bad) s_bad = 1;
-                }
-            }
-            __syncthreads();
-            // 3. A -= X W on MFMA: A operand -X[row, l/16], B operand W[l/16, col]
-            float anr[TRW], ani[TRW], api[TRW];
-            #pragma unroll
-            for (int ti = 0; ti < TRW; ++ti) {
-                const int It = wr + ti * WR;
-                const int i = It * 16 + lc;
-                float2 x = f2(0.f, 0.f);
-                if (It >= J && It < NTILE && i > k + 3) x = s_X[i][lg];
-                anr[ti] = -x.x;
-                ani[ti] = -x.y;
-                api[ti] = x.y;
-            }
-            // B operand: row l/16 of W = D^-1 Y, formed per lane
-            const float2 di0 = s_Di[lg][0], di1 = s_Di[lg][1], di2 = s_Di[lg][2], di3 = s_Di[lg][3];
-            float bwr[TCW], bwi[TCW];
+    // Publish what step Jn needs: -X^T (tiles below the diagonal), Y (tiles
+    // right of it), and D^-1 with the pivots (diagonal tile).  Tiles are
+    // addressed only with compile-time indices under wave-uniform branches (a
+    // runtime-indexed copy of the accumulators would go through scratch); the
+    // diagonal tile reaches the Gauss-Jordan registers through LDS.
+    auto publish = [&](int Jn) {
+        const int buf = Jn & 1;
+        const int sti = Jn / WR, stj = Jn / WC;
+        const bool own_r = (wr == Jn % WR), own_c = (wc == Jn % WC);
+        #pragma unroll
+        for (int ti = 0; ti < TRW; ++ti) {
+            const int It = wr + ti * WR;
             #pragma unroll
             for (int tj = 0; tj < TCW; ++tj) {
                 const int Jt = wc + tj * WC;
-                const int j = Jt * 16 + lc;
-                float2 w = f2(0.f, 0.f);
-                if (Jt >= J && Jt < NTILE && j > k + 3) {
-                    w = fmul(di0, s_Y[0][j]);
-                    const float2 t1 = fmul(di1, s_Y[1][j]), t2 = fmul(di2, s_Y[2][j]), t3 = fmul(di3, s_Y[3][j]);
-                    w.x += t1.x + t2.x + t3.x;
-                    w.y += t1.y + t2.y + t3.y;
-                }
-                bwr[tj] = w.x;
-                bwi[tj] = w.y;
-            }
-            // tiles of the next panel's tile row and column first: the next publish
-            // waits only for these, the other MFMAs drain during the barrier and
-            // the 4 x 4 solve of the next panel
-            const int Jn = (q == 12) ? J + 1 : J;
-            #pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-                #pragma unroll
-                for (int ti = 0; ti < TRW; ++ti) {
-                    const int It = wr + ti * WR;
-                    if (It < J || It >= NTILE) continue;
+                if (own_c && tj == stj && It > Jn && It < ntl) {
                     #pragma unroll
-                    for (int tj = 0; tj < TCW; ++tj) {
-                        const int Jt = wc + tj * WC;
-                        if (Jt < J || Jt >= NTILE) continue;
-                        const bool first = (It == Jn) || (Jt == Jn);
-                        if (first != (pass == 0)) continue;
-                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwr[tj], ar[ti][tj], 0, 0, 0);
-                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(api[ti], bwi[tj], ar[ti][tj], 0, 0, 0);
-                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(anr[ti], bwi[tj], ai[ti][tj], 0, 0, 0);
-                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ani[ti], bwr[tj], ai[ti][tj], 0, 0, 0);
-                    }
+                    for (int v = 0; v < 4; ++v)
+                        S.XT[buf][lc][It * 16 + 4 * lg + v] = f2(-ar[ti][tj][v], -ai[ti][tj][v]);
+                }
+                if (own_r && ti == sti && Jt > Jn && Jt < ntl) {
+                    #pragma unroll
+                    for (int v = 0; v < 4; ++v) S.Y[4 * lg + v][Jt * 16 + lc] = f2(ar[ti][tj][v], ai[ti][tj][v]);
+                }
+                if (own_r && own_c && ti == sti && tj == stj) {
+                    #pragma unroll
+                    for (int v = 0; v < 4; ++v) S.DiT[4 * lg + v][lc] = f2(ar[ti][tj][v], ai[ti][tj][v]);
                 }
             }
         }
-    }
-    __syncthreads();
+        if (own_r && own_c) {
+            // the tile went to DiT untransposed; this wave alone reads it back
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float gr[4], gi[4];
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float2 x = S.DiT[4 * lg + v][lc];
+                gr[v] = x.x;
+                gi[v] = x.y;
+            }
+            __builtin_amdgcn_wave_barrier();
+            float pvr, pvi;
+            gj_all(gr, gi, lg, lc, pvr, pvi, std::make_integer_sequence<int, 16>{});
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) S.DiT[lc][4 * lg + v] = f2(gr[v], gi[v]);
+            const int gk = Jn * 16 + lane;
+            if (lane < 16 && gk < nb) {
+                S.piv[gk] = f2(pvr, pvi);
+                if (!isfinite(pvr) || !isfinite(pvi) || (gk < nl && !(pvr > 0.f))) S.bad = 1;
+            }
+        }
+    };
 
-    const int nlog = nb - B.bordered;
+    // W = D^-1 Y for this wave's tiles of tile row Jn (after the barrier that
+    // publishes D^-1).
+    auto form_w = [&](int Jn) {
+        if (wr != Jn % WR) return;
+        const int buf = Jn & 1;
+        float dr[4], di[4], dn[4];
+        #pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float2 x = S.DiT[4 * s + lg][lc];  // A operand: D^-1[l%16][4s + l/16]
+            dr[s] = x.x;
+            di[s] = x.y;
+            dn[s] = -x.y;
+        }
+        #pragma unroll
+        for (int tj = 0; tj < TCW; ++tj) {
+            const int Jt = wc + tj * WC;
+            if (Jt > Jn && Jt < ntl) {
+                f32x4 wr_ = {0.f, 0.f, 0.f, 0.f}, wi_ = {0.f, 0.f, 0.f, 0.f};
+                #pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float2 y = S.Y[4 * s + lg][Jt * 16 + lc];  // B operand: Y[4s + l/16][l%16]
+                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], y.x, wr_, 0, 0, 0);
+                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dn[s], y.y, wr_, 0, 0, 0);
+                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], y.y, wi_, 0, 0, 0);
+                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(di[s], y.x, wi_, 0, 0, 0);
+                }
+                #pragma unroll
+                for (int v = 0; v < 4; ++v) S.W[buf][4 * lg + v][Jt * 16 + lc] = f2(wr_[v], wi_[v]);
+            }
+        }
+    };
+
+    if (ntl > 0) {
+        publish(0);
+        __syncthreads();
+        form_w(0);
+        __syncthreads();
+    }
+
+    #pragma unroll 1
+    for (int J = 0; J + 1 < ntl; ++J) {
+        const int buf = J & 1;
+        const int Jn = J + 1;
+        // A += (-X) W: real part (-Xr) Wr + Xi Wi, imaginary part (-Xr) Wi + (-Xi) Wr.
+        // Operands from LDS: A = -X[row, 16J + 4s + l/16] per tile row, B =
+        // W[4s + l/16, col] per pass (not held across the diagonal inversion).
+        auto update = [&](int pass) {
+            float wr_[TCW][4], wi_[TCW][4];
+            #pragma unroll
+            for (int tj = 0; tj < TCW; ++tj) {
+                const int Jt = wc + tj * WC;
+                #pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    float2 w = f2(0.f, 0.f);
+                    if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[buf][4 * s + lg][Jt * 16 + lc];
+                    wr_[tj][s] = w.x;
+                    wi_[tj][s] = w.y;
+                }
+            }
+            #pragma unroll
+            for (int ti = 0; ti < TRW; ++ti) {
+                const int It = wr + ti * WR;
+                if (It <= J || It >= ntl) continue;
+                if (pass == 1 && It == Jn) continue;  // tile row Jn went entirely in pass 0
+                float xr[4], xi[4], xn[4];
+                #pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float2 x = S.XT[buf][4 * s + lg][It * 16 + lc];
+                    xr[s] = x.x;
+                    xi[s] = x.y;
+                    xn[s] = -x.y;
+                }
+                #pragma unroll
+                for (int tj = 0; tj < TCW; ++tj) {
+                    const int Jt = wc + tj * WC;
+                    if (Jt <= J || Jt >= ntl) continue;
+                    const bool first = (It == Jn) || (Jt == Jn);
+                    if (first != (pass == 0)) continue;
+                    #pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[s], wr_[tj][s], ar[ti][tj], 0, 0, 0);
+                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[s], wi_[tj][s], ai[ti][tj], 0, 0, 0);
+                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xn[s], wi_[tj][s], ar[ti][tj], 0, 0, 0);
+                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[s], wr_[tj][s], ai[ti][tj], 0, 0, 0);
+                    }
+                }
+            }
+        };
+        update(0);
+        publish(Jn);
+        update(1);
+        __syncthreads();
+        form_w(Jn);
+        __syncthreads();
+    }
+
     double2 acc = cmk(0.0, 0.0);
-    for (int i = tid; i < nlog; i += NT) {
-        const double2 lgv = clog(cmk((double)s_piv[i].x, (double)s_piv[i].y));
+    for (int i = tid; i < nl; i += NT) {
+        const double2 lgv = clog(cmk((double)S.piv[i].x, (double)S.piv[i].y));
         acc.x += lgv.x;
         acc.y += lgv.y;
     }
     if (B.n_eig > 0) {
-        const double2 wa = s_w[B.schur_axis];
+        const double2 wa = S.w[B.schur_axis];
         const double *__restrict__ lam = A.eigpool + B.eig_off;
         for (int i = tid; i < B.n_eig; i += NT) {
             const double2 lgv = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
@@ -571,16 +667,16 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
             acc.y += lgv.y;
         }
     }
-    acc = block_sum<NT>(acc, s_red);
+    acc = block_sum<NT>(acc, S.red);
     if (tid == 0) {
         double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
         if (B.bordered) {
-            const float2 pb = s_piv[nb - 1];
+            const float2 pb = S.piv[nb - 1];
             res.x += 0.5 * (1.0 - (double)pb.x);
             res.y += 0.5 * (0.0 - (double)pb.y);
         }
         A.contrib[I.c_off + pt * I.nblocks + B.blk] = res;
-        if (s_bad) atomicOr(A.status, 1);
+        if (S.bad) atomicOr(A.status, 1);
     }
 }
 
@@ -1266,8 +1362,15 @@ static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
              a.rbpool, a.eigpool, a.contrib, a.status};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC>), dim3((unsigned)grid), dim3(64 * WR * WC), 0, st, A);
+    hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC>), dim3((unsigned)grid), dim3(64 * WR * WC),
+                       sizeof(MfmaLds<NTILE, WR, WC>), st, A);
     return hipGetLastError();
+}
+
+template <int NTILE, int WR, int WC>
+static hipError_t prepare_mfma() {
+    return hipFuncSetAttribute((const void *)lu_mfma_f32<NTILE, WR, WC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sizeof(MfmaLds<NTILE, WR, WC>));
 }
 
 int mfma_class_limit(int cls) {
@@ -1290,7 +1393,7 @@ hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st) {
         case 2: return launch_mfma<6, 2, 4>(a, st);
         case 3: return launch_mfma<8, 2, 4>(a, st);
         case 4: return launch_mfma<9, 3, 4>(a, st);
-        case 5: return launch_mfma<12, 3, 4>(a, st);
+        case 5: return launch_mfma<12, 2, 4>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1426,6 +1529,9 @@ namespace cgd {
 // Dynamic LDS limits of the kernels that need more than the default; called
 // once at context creation (not inside a captured launch sequence).
 hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
+    for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<4, 2, 2>(), prepare_mfma<6, 2, 4>(),
+                         prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(), prepare_mfma<12, 2, 4>()})
+        if (e != hipSuccess) return e;
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lu_big_lds_bytes(big_ldw));
