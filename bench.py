@@ -17,6 +17,8 @@ CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -34,16 +36,35 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
-    "cfg4a": ("GBS scale: M=144 squeezed inputs (r~U[0.4,1.2]) on sqrt(0.3)*Haar, K=1, "
+    "gbs144_2bins": ("GBS scale: M=144 squeezed inputs (r~U[0.4,1.2]) on sqrt(0.3)*Haar, K=1, "
               "2 bins of 72 modes, cutoff 120, grid 121x121 (288x288 complex per point)",
-              lambda: [W.config4("a")]),
-    "cfg4b": ("GBS scale: M=144, K=1, 3 bins of 48 modes, cutoff 40, grid 41^3",
-              lambda: [W.config4("b")]),
-    "cfg2": ("M=16, K=3 Schmidt modes, displaced, 4 bins of 4, cutoff 10, grid 11^4 (96x96 complex per point)",
-             lambda: [W.config2()]),
-    "cfg3": ("512 uneven instances: M~U{8..64}, K~U{1..4}, L~U{1..4}, cutoffs~U{4..12}", W.config3),
-    "cfg5": ("64 parameter sets: M=32, K=4, 2 bins of 16, cutoff 12 (256x256 complex per point)", W.config5),
+              lambda: [W.gbs_m144(2)]),
+    "gbs144_3bins": ("GBS scale: M=144, K=1, 3 bins of 48 modes, cutoff 40, grid 41^3",
+              lambda: [W.gbs_m144(3)]),
+    "lossy16_k3": ("M=16, K=3 Schmidt modes, displaced, 4 bins of 4, cutoff 10, grid 11^4 (96x96 complex per point)",
+             lambda: [W.lossy_m16_k3()]),
+    "uneven512": ("512 uneven instances: M~U{8..64}, K~U{1..4}, L~U{1..4}, cutoffs~U{4..12}", W.uneven_batch),
+    "mesh32_k4": ("64 parameter sets: M=32, K=4, 2 bins of 16, cutoff 12 (256x256 complex per point)", W.mesh_batch),
 }
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 summaries
+    under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain copy), or None when no summary was taken on the current
+    kernel sources."""
+    src = os.path.join(ROOT, "paper_2412_17742_amd", "csrc", "cgd_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record:"):
+                    continue
+                rec = json.loads(line.split(":", 1)[1])
+                if rec["kernel"] == kernel and rec["workload"] == workload and rec["kernels_sha256"] == sha:
+                    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    return None
 
 
 def cpu_baseline(instances, seconds: float):
@@ -109,7 +130,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg4a", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gbs144_2bins", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tol", type=float, default=1e-9, help="absolute error budget per probability (mixed path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -184,10 +205,10 @@ def main():
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
         kname = cgd.LU_KERNELS.get(dom, (dom,))[0]
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
     roof["kernel"] = kname
     roof["stage"] = dom
     roof["work_per_launch"] = flops[dom] if dom != "dft" else bytes_[dom]
+    roof["traffic"] = recorded_traffic(kname, args.workload)  # HBM bytes per launch, None if not measured
 
     def summary(rec, name):
         out = dict(grid_dets_per_s=n_points / (rec["ms"] * 1e-3), probs_per_s=n_probs / (rec["ms"] * 1e-3),

@@ -47,7 +47,7 @@ def _create(inst, **kw):
     (lambda x: x.update(schmidt=np.array([0.3, 0.7])), cgd.CGD_ERR_NONPHYSICAL),
 ])
 def test_create_rejects_invalid_instances(mutate, status):
-    inst = W.config1()
+    inst = W.plain_m4()
     mutate(inst)
     st, h, msg = _create(inst)
     assert st == status, msg
@@ -60,7 +60,7 @@ def test_create_rejects_bad_call_arguments():
     h = ctypes.c_void_p()
     assert L.cgd_create(ctypes.byref(h), None, 1, 0, 1e-9, 0, None) == cgd.CGD_ERR_ARG
     keep = []
-    arr = (cgd.CgdInstance * 1)(cgd._marshal(W.config1(), keep))
+    arr = (cgd.CgdInstance * 1)(cgd._marshal(W.plain_m4(), keep))
     assert L.cgd_create(ctypes.byref(h), arr, 1, 7, 1e-9, 0, None) == cgd.CGD_ERR_ARG
     assert L.cgd_create(ctypes.byref(h), arr, 1, cgd.PREC_MIXED, 0.0, 0, None) == cgd.CGD_ERR_ARG
     assert L.cgd_create(ctypes.byref(h), arr, 1, 0, 1e-9, 1 << 20, None) == cgd.CGD_ERR_ARG

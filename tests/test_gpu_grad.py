@@ -61,19 +61,19 @@ def test_adjoint_matches_autograd_oracle():
         to += M * M
 
 
-def test_config5_gradients_wrt_r_eta_theta_vs_finite_differences():
+def test_mesh_gradients_wrt_r_eta_theta_vs_finite_differences():
     """Config 5 shape (M=32, K=4, 2 bins of 16, cutoff 12) on a few parameter
     sets: d(loss)/d(r, eta, theta) through the autograd wrapper against central
     differences (h = 1e-6) of the GPU forward."""
     import torch
-    _say("config5 gradients vs central differences")
-    p = W.config5_params(2)
+    _say("mesh_batch gradients vs central differences")
+    p = W.mesh_params(2)
     spec = dict(schmidt=p["schmidt"], bin_of=p["bin_of"], cutoff=p["cutoff"])
     rng = np.random.default_rng(5)
     wgt = torch.tensor(rng.standard_normal((2, 13, 13)), dtype=torch.float64, device="cuda")
 
     def loss_of(r, eta, theta):
-        T = torch.stack([W.config5_transfer(eta[b], theta[b], p["phases"], p["M"]) for b in range(2)])
+        T = torch.stack([W.mesh_transfer(eta[b], theta[b], p["phases"], p["M"]) for b in range(2)])
         P = cgd.distribution(r, T, None, spec)
         return (P * wgt).sum()
 

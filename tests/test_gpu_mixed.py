@@ -33,11 +33,11 @@ def _per_instance_maxdiff(a, b, offs):
 
 
 CASES = {
-    "cfg1": lambda: [W.config1()],
-    "cfg2": lambda: [W.config2()],
-    "cfg4a": lambda: [W.config4("a")],
-    "cfg5": lambda: W.config5(16),
-    "cfg3": lambda: W.config3(96),
+    "plain4": lambda: [W.plain_m4()],
+    "lossy16_k3": lambda: [W.lossy_m16_k3()],
+    "gbs144_2bins": lambda: [W.gbs_m144(2)],
+    "mesh32_k4": lambda: W.mesh_batch(16),
+    "uneven512": lambda: W.uneven_batch(96),
 }
 
 
@@ -71,8 +71,8 @@ def test_mixed_matches_fp64_within_1e9(name):
 
 def test_mixed_with_blocked_kernel_and_elimination_off():
     # orders above the register limit stay FP64 in both passes
-    _say("mixed cfg4b / no-Schur cfg2")
-    for insts, flags in (([W.config4("b")], 0), ([W.config2()], cgd.FLAG_NO_SCHUR | cgd.FLAG_DENSE_INTERNAL)):
+    _say("mixed gbs144_3bins / no-Schur lossy16_k3")
+    for insts, flags in (([W.gbs_m144(3)], 0), ([W.lossy_m16_k3()], cgd.FLAG_NO_SCHUR | cgd.FLAG_DENSE_INTERNAL)):
         p64, _, _, offs = _run(insts, "fp64", flags=flags)
         pm, errm, _, _ = _run(insts, "mixed", flags=flags)
         assert np.abs(pm - p64).max() <= TOL

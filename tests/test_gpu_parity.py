@@ -80,24 +80,24 @@ def check_grid_sample(inst, logg, idx, tol_g=TOL_FP64):
 
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("flags", FLAG_SETS)
-def test_config1_stated_grid(flags):
-    _say("config1 7x7 flags", flags)
-    inst = W.config1()
+def test_plain_m4_stated_grid(flags):
+    _say("plain_m4 7x7 flags", flags)
+    inst = W.plain_m4()
     (P,) = gpu_dists([inst], flags)
     assert np.abs(P - pgf.wrapped_distribution(inst)).max() <= TOL_FP64
 
 
-def test_config1_oversampled_matches_brute_force():
-    _say("config1 40x40 vs brute force")
-    inst = W.config1(grid=[40, 40])
+def test_plain_m4_oversampled_matches_brute_force():
+    _say("plain_m4 40x40 vs brute force")
+    inst = W.plain_m4(grid=[40, 40])
     (P,) = gpu_dists([inst])
-    assert np.abs(P - brute.box_probabilities(W.config1())).max() <= TOL_FP64
+    assert np.abs(P - brute.box_probabilities(W.plain_m4())).max() <= TOL_FP64
 
 
 @pytest.mark.parametrize("flags", FLAG_SETS)
-def test_config2_shape_small_grid(flags):
-    _say("config2 shape, 5^4 grid, flags", flags)
-    inst = W.config2(grid=[5, 5, 5, 5])
+def test_lossy_m16_k3_shape_small_grid(flags):
+    _say("lossy_m16_k3 shape, 5^4 grid, flags", flags)
+    inst = W.lossy_m16_k3(grid=[5, 5, 5, 5])
     inst["cutoff"] = np.array([4, 4, 4, 4], np.int32)
     (P,) = gpu_dists([inst], flags)
     ref = pgf.wrapped_distribution(inst)
@@ -106,9 +106,9 @@ def test_config2_shape_small_grid(flags):
 
 
 @pytest.mark.parametrize("flags", [0, cgd.FLAG_NO_SCHUR])
-def test_config2_full_grid_sampled_points(flags):
-    _say("config2 full 11^4, sampled points, flags", flags)
-    inst = W.config2()
+def test_lossy_m16_k3_full_grid_sampled_points(flags):
+    _say("lossy_m16_k3 full 11^4, sampled points, flags", flags)
+    inst = W.lossy_m16_k3()
     logg, _ = gpu_grid([inst], flags)
     rng = np.random.default_rng(7)
     idx = np.concatenate([[0, 1, len(logg) - 1], rng.choice(len(logg), 10, replace=False)])
@@ -164,7 +164,7 @@ def test_fock_heralding_fidelities_on_gpu():
             assert abs(F - F_paper) <= 0.5 * 10 ** (-case["decimals"]) + 1e-12
 
 
-def _config3_costs(insts):
+def _uneven_costs(insts):
     costs = []
     for x in insts:
         n = 2 * x["T"].shape[0] * W.n_internal(x)
@@ -172,11 +172,11 @@ def _config3_costs(insts):
     return np.array(costs)
 
 
-def test_config3_batch_cheapest_instances_full_parity():
-    _say("config3: full batch on the GPU, full parity on the cheapest instances")
-    insts = W.config3()
+def test_uneven_batch_cheapest_instances_full_parity():
+    _say("uneven_batch: full batch on the GPU, full parity on the cheapest instances")
+    insts = W.uneven_batch()
     got = gpu_dists(insts)
-    order = np.argsort(_config3_costs(insts))
+    order = np.argsort(_uneven_costs(insts))
     for i in order[:6]:
         _say("  instance", i)
         ref = pgf.wrapped_distribution(insts[i])
@@ -185,9 +185,9 @@ def test_config3_batch_cheapest_instances_full_parity():
         assert abs(P.sum() - 1.0) < 1e-11, i  # each box is its whole grid
 
 
-def test_config3_batch_sampled_points():
-    _say("config3: sampled grid values across the batch")
-    insts = W.config3()
+def test_uneven_batch_sampled_points():
+    _say("uneven_batch: sampled grid values across the batch")
+    insts = W.uneven_batch()
     logg, ctx = gpu_grid(insts)
     rng = np.random.default_rng(11)
     off = 0
@@ -202,10 +202,10 @@ def test_config3_batch_sampled_points():
     assert off == len(logg)
 
 
-@pytest.mark.parametrize("variant, flags", [("a", 0), ("b", 0), ("a", cgd.FLAG_NO_SCHUR)])
-def test_config4_sampled_points_and_sums(variant, flags):
-    _say("config4", variant, "flags", flags)
-    inst = W.config4(variant)
+@pytest.mark.parametrize("bins, flags", [(2, 0), (3, 0), (2, cgd.FLAG_NO_SCHUR)])
+def test_gbs_m144_sampled_points_and_sums(bins, flags):
+    _say("gbs m144,", bins, "bins, flags", flags)
+    inst = W.gbs_m144(bins)
     logg, _ = gpu_grid([inst], flags)
     rng = np.random.default_rng(13)
     idx = np.concatenate([[0, len(logg) - 1], rng.choice(len(logg), 4, replace=False)])
@@ -214,11 +214,11 @@ def test_config4_sampled_points_and_sums(variant, flags):
     assert abs(P.sum() - 1.0) < 1e-12
 
 
-def test_config4a_mean_photon_number_matches_trace_formula():
+def test_gbs_m144_mean_photon_number_matches_trace_formula():
     # the wrap beyond cutoff 120 is negligible here, so the per-bin mean of
     # the computed distribution is the exact one
-    _say("config4a means")
-    inst = W.config4("a")
+    _say("gbs m144 means")
+    inst = W.gbs_m144(2)
     (P,) = gpu_dists([inst])
     T, r = inst["T"], inst["r"]
     per_mode = (np.abs(T) ** 2) @ (np.sinh(r) ** 2)
@@ -231,9 +231,9 @@ def test_config4a_mean_photon_number_matches_trace_formula():
 def test_repeat_evaluations_are_bitwise_identical():
     _say("determinism")
     import torch
-    inst = W.config2(grid=[5, 5, 5, 5])
+    inst = W.lossy_m16_k3(grid=[5, 5, 5, 5])
     inst["cutoff"] = np.array([4, 4, 4, 4], np.int32)
-    with cgd.Context([inst, W.config1()]) as ctx:
+    with cgd.Context([inst, W.plain_m4()]) as ctx:
         a = ctx.eval().clone()
         b = ctx.eval().clone()
         torch.cuda.synchronize()
@@ -246,7 +246,7 @@ def test_graph_replays_match_eager_evaluation(precision):
     device work in between, must equal an eager (uncaptured) evaluation."""
     import torch
     _say("graph replays vs eager,", precision)
-    insts = [W.config2(grid=[5, 5, 5, 5]), W.config1(), _edge_instances()[3]]
+    insts = [W.lossy_m16_k3(grid=[5, 5, 5, 5]), W.plain_m4(), _edge_instances()[3]]
     insts[0]["cutoff"] = np.array([4, 4, 4, 4], np.int32)
     with cgd.Context(insts, precision=precision) as ctx:
         ctx.set_timing(True)

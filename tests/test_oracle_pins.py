@@ -180,8 +180,8 @@ def test_two_mode_squeezed_vacuum_diagonal_law():
 # Brute force vs generating function (whole chain)
 # ---------------------------------------------------------------------------
 
-def test_config1_brute_force_matches_oversampled_grid():
-    inst = W.config1()
+def test_plain_m4_brute_force_matches_oversampled_grid():
+    inst = W.plain_m4()
     exact = brute.box_probabilities(inst)
     wrapped = pgf.wrapped_distribution(inst, grid=[40, 40])
     assert np.abs(exact - wrapped).max() < 1e-15
@@ -224,7 +224,7 @@ def test_unmeasured_modes_two_routes():
 def test_normalisation_full_grid_box():
     # Eq. prob1: with the box equal to the whole grid, the wrapped
     # distribution sums to G(1) = 1
-    inst = W.config2(grid=[5, 5, 5, 5])
+    inst = W.lossy_m16_k3(grid=[5, 5, 5, 5])
     inst["cutoff"] = np.array([4, 4, 4, 4], np.int32)
     P, imag = pgf.wrapped_distribution(inst, return_imag=True)
     assert abs(P.sum() - 1.0) < 1e-13
@@ -276,7 +276,7 @@ def test_second_moments_per_bin():
 
 
 def test_conjugation_and_within_bin_permutation_invariance():
-    inst = W.config1(grid=[9, 9])
+    inst = W.plain_m4(grid=[9, 9])
     P = pgf.wrapped_distribution(inst)
     conj = dict(inst, T=inst["T"].conj())
     assert np.abs(pgf.wrapped_distribution(conj) - P).max() < 1e-15
@@ -288,7 +288,7 @@ def test_conjugation_and_within_bin_permutation_invariance():
 
 
 def test_hermitian_symmetry_and_real_axis():
-    S = st.assemble(W.config2())
+    S = st.assemble(W.lossy_m16_k3())
     rng = np.random.default_rng(5)
     for _ in range(3):
         w = np.exp(2j * np.pi * rng.random(4))

@@ -29,9 +29,9 @@ import numpy as np
 SEED_ROOT = (2412, 17742)
 
 
-def rng_for(cfg: int, inst: int = 0) -> np.random.Generator:
-    """Counter-style seeding: one independent PCG64 stream per (config, instance)."""
-    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([*SEED_ROOT, cfg, inst])))
+def rng_for(stream: int, inst: int = 0) -> np.random.Generator:
+    """Counter-style seeding: one independent PCG64 stream per (workload stream, instance)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([*SEED_ROOT, stream, inst])))
 
 
 def haar_unitary(m: int, rng: np.random.Generator) -> np.ndarray:
@@ -82,7 +82,7 @@ def n_internal(inst: dict) -> int:
 # build; see the design doc for the input recipe).
 # ---------------------------------------------------------------------------
 
-def config1(grid=None) -> dict:
+def plain_m4(grid=None) -> dict:
     """M=4 single-mode squeezed vacua (r=0.5) on sqrt(0.5)*Haar, K=1, no
     displacement, bins {0,1},{2,3}, cutoff 6 (grid 7x7 unless overridden)."""
     rng = rng_for(1)
@@ -91,7 +91,7 @@ def config1(grid=None) -> dict:
                          cutoff=[6, 6], grid=grid)
 
 
-def config2(grid=None) -> dict:
+def lossy_m16_k3(grid=None) -> dict:
     """M=16, K=3 (weights ~0.6^k), r~U[0.3,0.9], T=sqrt(0.4)*Haar, alpha~CN(0,0.1)
     on a seeded half of the inputs, 4 contiguous bins of 4, cutoff 10."""
     rng = rng_for(2)
@@ -106,7 +106,7 @@ def config2(grid=None) -> dict:
                          bin_of=contiguous_bins([4, 4, 4, 4]), cutoff=[10] * 4, grid=grid)
 
 
-def config3_instance(i: int) -> dict:
+def uneven_instance(i: int) -> dict:
     """One of the 512 uneven batching instances."""
     rng = rng_for(3, i)
     M = int(rng.integers(8, 65))
@@ -122,23 +122,25 @@ def config3_instance(i: int) -> dict:
                          bin_of=contiguous_bins(sizes), cutoff=cutoff)
 
 
-def config3(n: int = 512) -> list[dict]:
-    return [config3_instance(i) for i in range(n)]
+def uneven_batch(n: int = 512) -> list[dict]:
+    return [uneven_instance(i) for i in range(n)]
 
 
-def config4(variant: str = "a") -> dict:
+def gbs_m144(bins: int = 2) -> dict:
     """GBS scale: M=144, K=1, r~U[0.4,1.2], T=sqrt(0.3)*Haar, no displacement.
-    variant 'a': 2 bins of 72, cutoff 120; variant 'b': 3 bins of 48, cutoff 40."""
+    bins=2: 2 bins of 72, cutoff 120; bins=3: 3 bins of 48, cutoff 40."""
+    if bins not in (2, 3):
+        raise ValueError("gbs_m144 has 2 or 3 bins")
     rng = rng_for(4)
     M = 144
     r = rng.uniform(0.4, 1.2, M)
     U = haar_unitary(M, rng)
-    if variant == "a":
+    if bins == 2:
         return make_instance(np.sqrt(0.3) * U, r, bin_of=contiguous_bins([72, 72]), cutoff=[120, 120])
     return make_instance(np.sqrt(0.3) * U, r, bin_of=contiguous_bins([48, 48, 48]), cutoff=[40, 40, 40])
 
 
-# --- config 5: differentiable state-preparation parameters -----------------
+# --- workload 5: differentiable state-preparation parameters -----------------
 
 def mesh_layout(M: int):
     """Rectangular (Clements-style) mesh: M layers alternating even/odd
@@ -184,7 +186,7 @@ def mesh_unitary(theta, phases, M: int):
     return U
 
 
-def config5_params(n_sets: int = 64):
+def mesh_params(n_sets: int = 64):
     """Parameter sets for the differentiation workload: M=32, K=4 (weights
     ~0.5^k), r~U[0.3,1.0], loss~U[0.1,0.5] per mode (eta = 1-loss), 496 mesh
     angles, fixed phase screen shared by all sets."""
@@ -200,7 +202,7 @@ def config5_params(n_sets: int = 64):
                 bin_of=contiguous_bins([16, 16]), cutoff=np.array([12, 12], np.int32), sets=sets)
 
 
-def config5_transfer(eta, theta, phases, M=32):
+def mesh_transfer(eta, theta, phases, M=32):
     """T = diag(sqrt(eta)) U(theta); numpy or torch (differentiable)."""
     U = mesh_unitary(theta, phases, M)
     try:
@@ -212,11 +214,11 @@ def config5_transfer(eta, theta, phases, M=32):
     return np.sqrt(eta)[:, None] * U
 
 
-def config5(n_sets: int = 64) -> list[dict]:
-    p = config5_params(n_sets)
+def mesh_batch(n_sets: int = 64) -> list[dict]:
+    p = mesh_params(n_sets)
     out = []
     for s in p["sets"]:
-        T = config5_transfer(s["eta"], s["theta"], p["phases"], p["M"])
+        T = mesh_transfer(s["eta"], s["theta"], p["phases"], p["M"])
         out.append(make_instance(T, s["r"], schmidt=p["schmidt"], bin_of=p["bin_of"], cutoff=p["cutoff"]))
     return out
 
