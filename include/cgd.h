@@ -59,8 +59,9 @@ typedef enum {
 
 typedef enum {
     CGD_PREC_FP64 = 0,  /* complex128 factorisations everywhere                          */
-    CGD_PREC_MIXED = 1  /* complex64 factorisations with an FP64 log-det correction where
-                           the grid value is large enough to matter (see cgd_create tol) */
+    CGD_PREC_MIXED = 1  /* complex64 factorisations (MFMA) at every grid point, then a
+                           complex128 re-factorisation of the points whose FP32 value
+                           could move a probability by more than tol (see cgd_create) */
 } cgd_precision;
 
 /* cgd_create flags */
@@ -94,7 +95,10 @@ typedef struct {
  * needs.  n_inst instances are evaluated together by cgd_eval.
  *   prec        CGD_PREC_FP64 or CGD_PREC_MIXED
  *   tol         absolute error budget per probability for the mixed path (e.g.
- *               1e-9); ignored for FP64
+ *               1e-9): a point is re-factorised in FP64 when |G| tau > tol, tau
+ *               being the assumed relative error of its FP32 value (2 (n+1) 2^-24
+ *               summed over its blocks of order n), so the FP32 points left add
+ *               at most tol to any probability; ignored for FP64
  *   flags       0 or CGD_FLAG_* bits
  *   hip_stream  hipStream_t to enqueue on, or NULL for the null stream
  * Errors: CGD_ERR_ARG / CGD_ERR_NONPHYSICAL synchronously, before any launch.
@@ -145,7 +149,9 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
 /* Profiling.  The evaluation is a fixed sequence of launch stages:
  *   CGD_STAGE_SCHUR      Schur matrices of the bins left after eliminating one bin
  *   CGD_STAGE_LU_REG0..4 register-resident factorisations, orders <= 32, 64, 96, 128, 144
- *   CGD_STAGE_LU_BIG     blocked factorisations, orders 145..480
+ *                        (mixed path: the FP32 MFMA kernels of the same orders)
+ *   CGD_STAGE_LU_BIG     blocked FP64 factorisations, orders 145..480 (mixed path:
+ *                        the FP32 MFMA kernel for orders 145..192, FP64 above)
  *   CGD_STAGE_COMBINE    log G per point and G = exp(log G)
  *   CGD_STAGE_DFT        all axis passes of the inverse DFT
  *   CGD_STAGE_FIX        mixed path: selection of the points whose FP32 value can

@@ -69,8 +69,9 @@ def test_mixed_matches_fp64_within_1e9(name):
     assert d.max() <= TOL
 
 
-def test_mixed_with_blocked_kernel_and_elimination_off():
-    # orders above the register limit stay FP64 in both passes
+def test_mixed_order_192_class_and_elimination_off():
+    # order 192 (three bins of 48, one eliminated) takes the 8-wave MFMA class;
+    # the dense no-Schur lossy instance (order 97) the order-128 class
     _say("mixed gbs144_3bins / no-Schur lossy16_k3")
     for insts, flags in (([W.gbs_m144(3)], 0), ([W.lossy_m16_k3()], cgd.FLAG_NO_SCHUR | cgd.FLAG_DENSE_INTERNAL)):
         p64, _, _, offs = _run(insts, "fp64", flags=flags)
