@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 3 times (scale for HBM byte counters)")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="cgd_create flags (e.g. 8 = CGD_FLAG_HESSENBERG)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
                     help="paths to time (the JSON line needs both for the mixed-vs-FP64 check)")
     args = ap.parse_args()
@@ -164,7 +166,7 @@ def main():
     paths = {}
     for prec in ("fp64", "mixed"):
         t0 = time.perf_counter()
-        ctx = cgd.Context(instances, precision=prec, tol=args.tol)
+        ctx = cgd.Context(instances, precision=prec, tol=args.tol, flags=args.flags)
         create_s = time.perf_counter() - t0
         ms, wall_ms, probs = run(ctx, args.steps, args.warmup)
         stages = stage_profile(ctx, max(3, min(args.steps, 10)))
@@ -194,6 +196,11 @@ def main():
         achieved = bytes_[dom] / (dom_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s")
         kname = "dft_stage"
+    elif dom == "hess":
+        # Hessenberg route: FP64 reductions of the Schur matrices and O(n^2) factorisations
+        achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
+        kname = "hess_reduce_f64 + hess_det_f64"
     elif best == "mixed" and dom in cgd.LU_KERNELS:
         # first pass of the mixed path: complex FP32 elimination on MFMA (16x16x4 f32)
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
@@ -234,7 +241,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "instances": len(instances),
                    "evaluated_points": n_points, "grid_points": n_grid, "probabilities": n_probs,
-                   "precision": best, "tol": args.tol},
+                   "precision": best, "tol": args.tol, "flags": args.flags},
         "probs_per_s": n_probs / (ms * 1e-3),
         "grid_points_per_s": n_grid / (ms * 1e-3),
         "wall_ms_per_step": wall_ms,

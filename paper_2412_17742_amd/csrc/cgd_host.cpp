@@ -352,6 +352,16 @@ struct LuClass {
     int64_t *d_prefix = nullptr;
 };
 
+// Hessenberg-route jobs of one size class: reduction (one workgroup per k_A)
+// and factorisations (one workgroup per k_A and 16 values of k_B)
+struct HessClass {
+    std::vector<HessDev> jobs;
+    std::vector<int64_t> rprefix, dprefix;
+    int64_t rnwg = 0, dnwg = 0;
+    HessDev *d_jobs = nullptr;
+    int64_t *d_rprefix = nullptr, *d_dprefix = nullptr;
+};
+
 struct DftStage {
     std::vector<DftStageDev> desc;
     std::vector<int64_t> prefix;
@@ -379,6 +389,15 @@ struct cgd_ctx {
     LuClass g64[kG64];
     LuClass g32[kMfmaClasses];
     int big_ldw = 0, big_nwg = 0;
+    // Hessenberg route
+    std::vector<char> is_hess;
+    std::vector<HessDev> hess_all;
+    std::vector<int64_t> hess_sprefix;
+    int64_t hess_spts = 0, hess_ntab = 0, hess_nec = 0;
+    HessClass hcls[kHessClasses];
+    HessDev *d_hess_all = nullptr;
+    int64_t *d_hess_sprefix = nullptr;
+    double2 *d_eigc = nullptr, *d_htable = nullptr;
     std::vector<DftStage> stages;
     std::vector<int64_t> prob_offsets, inst_pt_prefix;
     int64_t nprobs = 0, npts = 0, ngrid = 0, ncontrib = 0;
@@ -442,6 +461,8 @@ void free_ctx(cgd_ctx *c) {
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
     for (auto &s : c->adj_stages) { fr(s.d_desc); fr(s.d_prefix); }
+    for (auto &h : c->hcls) { fr(h.d_jobs); fr(h.d_rprefix); fr(h.d_dprefix); }
+    fr(c->d_hess_all); fr(c->d_hess_sprefix); fr(c->d_eigc); fr(c->d_htable);
     for (auto &k : c->gadj) { fr(k.d_jobs); fr(k.d_prefix); }
     fr(c->d_gblocks); fr(c->d_gpool); fr(c->d_partial); fr(c->d_z); fr(c->d_adjA); fr(c->d_adjB); fr(c->d_ghat);
     fr(c->d_grb); fr(c->d_z_prefix); fr(c->d_adj_off); fr(c->d_prob_prefix);
@@ -792,16 +813,28 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         return off;
     };
     c->blocks.resize(hblocks.size());
+    c->is_hess.assign(hblocks.size(), 0);
     for (size_t b = 0; b < hblocks.size(); ++b) {
         const HostBlock &h = hblocks[b];
         BlockDev &d = c->blocks[b];
         std::memset(&d, 0, sizeof(d));
         InstDev &I0 = c->inst[h.inst];
         if (I0.first_block < 0) I0.first_block = (int32_t)b;
+        // Hessenberg route: the rows left after the eigenbasis elimination all in one bin
+        int hbin = -1;
+        bool hess = (c->flags & CGD_FLAG_HESSENBERG) && h.schur_axis >= 0 && !h.bordered && h.nb >= 1 &&
+                    h.nb <= hess_class_limit(kHessClasses - 1);
+        if (hess)
+            for (int32_t rb : h.rowbin) {
+                if (rb < 0 || (hbin >= 0 && rb != hbin)) { hess = false; break; }
+                hbin = rb;
+            }
+        if (hbin < 0 || hbin == h.schur_axis) hess = false;
+        c->is_hess[b] = hess;
         d.cls = kRegClasses;
         for (int k = 0; k < kRegClasses; ++k)
             if (h.nb <= reg_class_limit(k)) { d.cls = k; break; }
-        d.fp32 = (c->prec == CGD_PREC_MIXED && h.nb <= mfma_class_limit(kMfmaClasses - 1)) ? 1 : 0;
+        d.fp32 = (!hess && c->prec == CGD_PREC_MIXED && h.nb <= mfma_class_limit(kMfmaClasses - 1)) ? 1 : 0;
         if (d.fp32) {
             // relative error of an FP32 value of G: kTauScale (n + 1) 2^-24 per block, summed
             I0.tau += kTauScale * (h.nb + 1) * 5.9604644775390625e-08;
@@ -840,6 +873,29 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 c->schur.push_back(sj);
                 c->schur_maxA = std::max(c->schur_maxA, sj.nA);
             }
+            if (hess) {
+                HessDev hd;
+                std::memset(&hd, 0, sizeof(hd));
+                hd.inst = h.inst;
+                hd.blk = h.blk;
+                hd.n = h.nb;
+                hd.axA = h.schur_axis;
+                hd.axB = hbin;
+                hd.dA = sj.nk;
+                hd.dB = hbin == 0 ? I.H1 : I.G[hbin];
+                hd.GA = I.G[h.schur_axis];
+                hd.GB = I.G[hbin];
+                hd.n_eig = d.n_eig;
+                hd.cls = 0;
+                while (h.nb > hess_class_limit(hd.cls)) ++hd.cls;
+                hd.c_off = sj.c_off;
+                hd.eig_off = d.eig_off;
+                hd.t_off = c->hess_ntab;
+                c->hess_ntab += (int64_t)hd.dA * hd.dB;
+                hd.ec_off = c->hess_nec;
+                c->hess_nec += hd.dA;
+                c->hess_all.push_back(hd);
+            }
         } else {
             d.h_off = push_mat(h.H);
             d.hs_stride = 0;
@@ -862,8 +918,19 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     // and the capacity of the mixed second-pass lists per FP64 group
     for (int k = 0; k < kG64; ++k) c->g64[k].cls = k;
     for (int k = 0; k < kMfmaClasses; ++k) c->g32[k].cls = k;
+    for (const HessDev &hd : c->hess_all) {
+        HessClass &hc = c->hcls[hd.cls];
+        hc.rprefix.push_back(hc.rnwg);
+        hc.dprefix.push_back(hc.dnwg);
+        hc.jobs.push_back(hd);
+        hc.rnwg += hd.dA;
+        hc.dnwg += (int64_t)hd.dA * ((hd.dB + 15) / 16);
+        c->hess_sprefix.push_back(c->hess_spts);
+        c->hess_spts += c->inst[hd.inst].npts;
+    }
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         const BlockDev &d = c->blocks[b];
+        if (c->is_hess[b]) continue;
         if (d.cls == kRegClasses) {
             if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
             c->big_ldw = std::max(c->big_ldw, d.nb);
@@ -936,6 +1003,18 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
         }
     for (const SchurDev &sj : c->schur) c->work_flops[CGD_STAGE_SCHUR] += 8.0 * sj.nA * (double)sj.nB * sj.nB * sj.nk;
+    for (const HessDev &hd : c->hess_all) {
+        // reduction: column k with m = n - k - 1 rows below the diagonal costs
+        // 2 m (m + 1) complex multiply-adds for w and the left update and 2 n m for y
+        // and the right update; factorisation: 2 (n - k - 1) per step
+        double red = 0, fac = 0;
+        for (int k = 0; k + 2 < hd.n; ++k) {
+            const double m = hd.n - k - 1;
+            red += 2.0 * m * (m + 1) + 2.0 * hd.n * m;
+        }
+        for (int k = 0; k + 1 < hd.n; ++k) fac += 2.0 * (hd.n - k - 1);
+        c->work_flops[CGD_STAGE_HESS] += 8.0 * (red * hd.dA + fac * (double)hd.dA * hd.dB);
+    }
     for (const DftStage &st : c->stages)
         for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
     c->work_bytes[CGD_STAGE_DFT] = 16.0 * c->npts + 8.0 * c->nprobs;
@@ -961,6 +1040,17 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     for (auto &st : c->stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
+    }
+    if (!c->hess_all.empty()) {
+        for (auto &hc : c->hcls) {
+            if ((s = upload(&hc.d_jobs, hc.jobs)) != CGD_OK) return s;
+            if ((s = upload(&hc.d_rprefix, hc.rprefix)) != CGD_OK) return s;
+            if ((s = upload(&hc.d_dprefix, hc.dprefix)) != CGD_OK) return s;
+        }
+        if ((s = upload(&c->d_hess_all, c->hess_all)) != CGD_OK) return s;
+        if ((s = upload(&c->d_hess_sprefix, c->hess_sprefix)) != CGD_OK) return s;
+        HIP_OK(hipMalloc((void **)&c->d_eigc, sizeof(double2) * c->hess_nec));
+        HIP_OK(hipMalloc((void **)&c->d_htable, sizeof(double2) * c->hess_ntab));
     }
     const int64_t nc = std::max<int64_t>(c->ncontrib, 1), np = std::max<int64_t>(c->npts, 1);
     HIP_OK(hipMalloc((void **)&c->d_contrib, sizeof(double2) * nc));
@@ -1012,7 +1102,8 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     if (!inst || n_inst <= 0) return fail(CGD_ERR_ARG, "need at least one instance");
     if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
     if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
-    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD)) return fail(CGD_ERR_ARG, "unknown flags");
+    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD | CGD_FLAG_HESSENBERG))
+        return fail(CGD_ERR_ARG, "unknown flags");
     cgd_ctx *c = new (std::nothrow) cgd_ctx();
     if (!c) return fail(CGD_ERR_NOMEM, "host allocation");
     c->n_inst = n_inst;
@@ -1054,6 +1145,18 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg,
                                   c->schur_maxA, c->d_pool, c->d_eig, c->d_pool, c->d_pool32, st));
         HIP_OK(mark(CGD_STAGE_SCHUR, 1));
+    }
+    if (!c->hess_all.empty()) {
+        HIP_OK(mark(CGD_STAGE_HESS, 0));
+        for (auto &hc : c->hcls)
+            HIP_OK(launch_hess_reduce((int)(&hc - c->hcls), hc.d_jobs, hc.d_rprefix, (int)hc.jobs.size(), hc.rnwg,
+                                      c->d_pool, c->d_eig, c->d_eigc, st));
+        for (auto &hc : c->hcls)
+            HIP_OK(launch_hess_det((int)(&hc - c->hcls), hc.d_jobs, hc.d_dprefix, (int)hc.jobs.size(), hc.dnwg,
+                                   c->d_pool, c->d_eigc, c->d_htable, st));
+        HIP_OK(launch_hess_scatter(c->d_hess_all, c->d_hess_sprefix, (int)c->hess_all.size(), c->hess_spts,
+                                   c->d_inst, c->d_htable, c->d_contrib, st));
+        HIP_OK(mark(CGD_STAGE_HESS, 1));
     }
     const bool mixed = c->prec == CGD_PREC_MIXED;
     // timing: a slot spans from its first launch to its last one in this evaluation

@@ -63,6 +63,22 @@ struct SchurDev {
     int64_t p_off, q_off, hbb_off, eig_off, c_off;
 };
 
+// Hessenberg route: a block whose rows left after eliminating bin A (axis
+// axA) all lie in one bin (axis axB).  For each value k_A the Schur matrix
+// C(w_A) at c_off + k_A n^2 is reduced to Hessenberg form in place; every
+// pair (k_A, k_B) then costs one O(n^2) factorisation, stored at
+// t_off + k_A dB + k_B and copied to the points.
+struct HessDev {
+    int32_t inst, blk, n;
+    int32_t axA, axB;
+    int32_t dA, dB;           // number of k_A and k_B values (half grid on axis 0)
+    int32_t GB;               // grid extent of axis B
+    int32_t n_eig;
+    int32_t cls;              // size class (n <= 32, 64, 144)
+    int32_t GA;               // grid extent of axis A
+    int64_t c_off, eig_off, t_off, ec_off;
+};
+
 // Gradient: one internal block with its full (bordered) matrix, no reduction.
 struct GradBlockDev {
     int32_t inst;
@@ -147,6 +163,15 @@ hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_pre
                                 int n_lists, hipStream_t st);
 hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, double *err, const int *status,
                             hipStream_t st);
+// Hessenberg route
+constexpr int kHessClasses = 3;
+int hess_class_limit(int cls);          // max order of class cls: 32, 64, 144
+hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
+                              double2 *pool, const double *eigpool, double2 *eigc, hipStream_t st);
+hipError_t launch_hess_det(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
+                           const double2 *pool, const double2 *eigc, double2 *table, hipStream_t st);
+hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t total,
+                               const InstDev *insts, const double2 *table, double2 *contrib, hipStream_t st);
 int schur_rows_per_wg();
 hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
                           const double2 *contrib, double2 *logg, double2 *gval, hipStream_t st);

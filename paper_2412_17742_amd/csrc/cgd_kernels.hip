@@ -942,6 +942,402 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
 }
 
 // ---------------------------------------------------------------------------
+// Kernel H: blocks whose rows left after the eigenbasis elimination of bin A
+// all belong to one bin B.  Then D_B = w_B I, and for every value of w_A,
+//     det(I - w_B C(w_A)) = det(I - w_B Hh),   Hh = Q^H C(w_A) Q upper Hessenberg,
+// with Q a product of Householder reflections.  hess_reduce_f64 brings each
+// C(w_A) to that form (in place); hess_det_f64 factorises I - w_B Hh for
+// every w_B by unpivoted LU of a Hessenberg matrix (O(n^2)); hess_scatter
+// copies the per-(w_A, w_B) values to the evaluated points.  I - w_B C(w_A)
+// is the Schur complement of S after eliminating A, so it is accretive, and
+// so is any unitary similarity of it: every pivot has Re > 0 and the sum of
+// the principal logarithms of the pivots is the continuous branch.
+// ---------------------------------------------------------------------------
+constexpr int kHessThreads = 512;  // 16 x 32 grid: ty = tid / 32, tx = tid % 32
+constexpr int kHessDetThreads = 256;  // 4 waves x 4 points, 16 lanes per point
+
+template <int R, int SC>
+struct HessLds {
+    static constexpr int NMAX = (16 * R < 32 * SC) ? 16 * R : 32 * SC;
+    static constexpr int PYS = NMAX + 1;  // padded stride of the row-sum partials
+    double2 x[2][NMAX];                    // column k below the diagonal, by step parity
+    double nrm[2][16];                     // partial |x|^2 per thread row
+    double2 PW[16][NMAX];                  // partials of w_j = sum_i conj(v_i) a_ij, per thread row
+    double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column
+    double2 PS[kHessThreads];              // partials of s = v^H A v, per thread
+    double2 W[NMAX], Y[NMAX];
+    double2 S;
+    double2 red[kHessThreads / 64 + 1];
+};
+
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) b
+    return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Householder reduction to upper Hessenberg form of C(w_A), one workgroup per
+// (block, k_A); element (i, j) in thread (i mod 16, j mod 32), register
+// (i / 16, j / 32).  Column k: v = x - alpha e_1 with x = A[k+1:, k],
+// alpha = -(x_1/|x_1|) |x|, beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)); with
+// w = v^H A, y = A v and s = w v, the two-sided reflection is the rank-2
+// update A <- A - beta v w - beta (y - beta s v) v^H, so both sums come
+// from one pass over A.  Also writes sum_i Log(1 - w_A lambda_i) of the
+// eliminated bin.
+template <int R, int SC>
+__global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *__restrict__ jobs,
+                                                                 const int64_t *__restrict__ prefix, int njobs,
+                                                                 double2 *__restrict__ pool,
+                                                                 const double *__restrict__ eigpool,
+                                                                 double2 *__restrict__ eigc)
+{
+    using Lds = HessLds<R, SC>;
+    constexpr int NMAX = Lds::NMAX;
+    extern __shared__ __align__(16) unsigned char hess_raw[];
+    Lds &L = *reinterpret_cast<Lds *>(hess_raw);
+    const int job = find_job(prefix, njobs, blockIdx.x);
+    const HessDev J = jobs[job];
+    const int kA = (int)(blockIdx.x - prefix[job]);
+    const int n = J.n;
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    double2 *__restrict__ C = pool + J.c_off + (int64_t)kA * n * n;
+
+    double2 a[R][SC];
+    #pragma unroll
+    for (int r = 0; r < R; ++r)
+        #pragma unroll
+        for (int s = 0; s < SC; ++s) {
+            const int i = ty + 16 * r, j = tx + 32 * s;
+            const bool in = i < n && j < n;
+            const double2 h = C[in ? (int64_t)i * n + j : 0];
+            a[r][s] = in ? h : cmk(0.0, 0.0);
+        }
+
+    for (int k = 0; k + 2 < n; ++k) {
+        const int par = k & 1;
+        const int sk = k >> 5;
+        // A. column k below the diagonal and its partial squared norms
+        if (tx == (k & 31)) {
+            double acc = 0.0;
+            #pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                if (s != sk) continue;
+                #pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = ty + 16 * r;
+                    if (i > k && i < n) {
+                        L.x[par][i] = a[r][s];
+                        acc += a[r][s].x * a[r][s].x + a[r][s].y * a[r][s].y;
+                    }
+                }
+            }
+            L.nrm[par][ty] = acc;
+        }
+        __syncthreads();
+        // B. reflector, partial sums of w, y and s
+        double xn2 = 0.0;
+        #pragma unroll
+        for (int t = 0; t < 16; ++t) xn2 += L.nrm[par][t];
+        const double xn = sqrt(xn2);
+        const double2 x1 = L.x[par][k + 1];
+        const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
+        const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
+        const double2 v1 = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));  // x_1 - alpha
+        const double beta = xn > 0.0 ? 1.0 / (xn * (xn + ax1)) : 0.0;
+        auto vget = [&](int i) -> double2 {
+            if (i == k + 1) return v1;
+            return (i > k + 1 && i < n) ? L.x[par][i] : cmk(0.0, 0.0);
+        };
+        double2 vc[SC], pw[SC];
+        #pragma unroll
+        for (int s = 0; s < SC; ++s) {
+            vc[s] = vget(tx + 32 * s);
+            pw[s] = cmk(0.0, 0.0);
+        }
+        double2 ps = cmk(0.0, 0.0);
+        #pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = ty + 16 * r;
+            const double2 vi = vget(i);
+            double2 py = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                const double2 c = cconjmul(vi, a[r][s]);
+                pw[s].x += c.x;
+                pw[s].y += c.y;
+                const double2 d = cmul(a[r][s], vc[s]);
+                py.x += d.x;
+                py.y += d.y;
+            }
+            if (i < n) L.PY[tx][i] = py;
+            const double2 e = cconjmul(vi, py);
+            ps.x += e.x;
+            ps.y += e.y;
+        }
+        #pragma unroll
+        for (int s = 0; s < SC; ++s) {
+            const int j = tx + 32 * s;
+            if (j < n) L.PW[ty][j] = pw[s];
+        }
+        L.PS[tid] = ps;
+        __syncthreads();
+        // C. reductions, each in a fixed order
+        if (tid < n) {
+            double2 t = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                t.x += L.PW[q][tid].x;
+                t.y += L.PW[q][tid].y;
+            }
+            L.W[tid] = t;
+        } else if (tid >= 256 && tid - 256 < n) {
+            const int i = tid - 256;
+            double2 t = cmk(0.0, 0.0);
+            #pragma unroll 8
+            for (int q = 0; q < 32; ++q) {
+                t.x += L.PY[q][i].x;
+                t.y += L.PY[q][i].y;
+            }
+            L.Y[i] = t;
+        } else if (tid >= kHessThreads - 64) {
+            const int lane = tid & 63;
+            double2 t = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int q = 0; q < kHessThreads / 64; ++q) {
+                t.x += L.PS[lane + 64 * q].x;
+                t.y += L.PS[lane + 64 * q].y;
+            }
+            #pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                t.x += __shfl_xor(t.x, off, 64);
+                t.y += __shfl_xor(t.y, off, 64);
+            }
+            if (lane == 0) L.S = t;
+        }
+        __syncthreads();
+        // D. A <- A - beta v w - beta z v^H, z = y - beta s v
+        const double2 sv = L.S;
+        double2 wj[SC];
+        #pragma unroll
+        for (int s = 0; s < SC; ++s) {
+            const int j = tx + 32 * s;
+            wj[s] = j < n ? L.W[j] : cmk(0.0, 0.0);
+        }
+        #pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = ty + 16 * r;
+            const double2 vi = vget(i);
+            const double2 yi = i < n ? L.Y[i] : cmk(0.0, 0.0);
+            const double2 bsv = cmul(cmk(beta * sv.x, beta * sv.y), vi);
+            const double2 zi = cmk(beta * (yi.x - bsv.x), beta * (yi.y - bsv.y));  // beta z_i
+            const double2 bvi = cmk(beta * vi.x, beta * vi.y);
+            #pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                // a -= (beta v_i) w_j + (beta z_i) conj(v_j)
+                double2 t = a[r][s];
+                t = cfnms(t, bvi, wj[s]);
+                const double2 cv = cmk(vc[s].x, -vc[s].y);
+                t = cfnms(t, zi, cv);
+                a[r][s] = t;
+            }
+        }
+        if (tx == (k & 31)) {
+            #pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                if (s != sk) continue;
+                #pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = ty + 16 * r;
+                    if (i == k + 1) a[r][s] = cmk(-ph.x * xn, -ph.y * xn);  // alpha
+                    else if (i > k + 1) a[r][s] = cmk(0.0, 0.0);
+                }
+            }
+        }
+    }
+
+    #pragma unroll
+    for (int r = 0; r < R; ++r)
+        #pragma unroll
+        for (int s = 0; s < SC; ++s) {
+            const int i = ty + 16 * r, j = tx + 32 * s;
+            if (i < n && j < n) C[(int64_t)i * n + j] = a[r][s];
+        }
+
+    // sum_i Log(1 - w_A lambda_i)
+    double sn, cs;
+    sincospi(2.0 * (double)kA / (double)J.GA, &sn, &cs);
+    const double *__restrict__ lam = eigpool + J.eig_off;
+    double2 acc = cmk(0.0, 0.0);
+    for (int i = tid; i < J.n_eig; i += kHessThreads) {
+        const double2 lg = clog(cmk(1.0 - cs * lam[i], -sn * lam[i]));
+        acc.x += lg.x;
+        acc.y += lg.y;
+    }
+    acc = block_sum<kHessThreads>(acc, L.red);
+    if (tid == 0) eigc[J.ec_off + kA] = acc;
+}
+
+template <int K>
+__device__ __forceinline__ double dpp_bcast64(double x) {  // lane K of each 16-lane row
+    const int2 u = __builtin_bit_cast(int2, x);
+    int2 v;
+    v.x = __builtin_amdgcn_mov_dpp(u.x, 0x150 + K, 0xf, 0xf, true);
+    v.y = __builtin_amdgcn_mov_dpp(u.y, 0x150 + K, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, v);
+}
+
+// Per-point state of the Hessenberg factorisation (see hess_det_f64).
+template <int MB>
+struct HessDetState {
+    const double2 *__restrict__ Hh;
+    int n, e, m;                // order, lane within the point's 16 lanes, current block
+    double2 w;                  // w_B
+    double2 u[MB];              // row k of U: u_j in slot j / 16 of lane j % 16
+    double2 cur;                // slot m of u while block m runs
+    double argsum, logsum, magacc;
+    int npair;
+    double2 pend;
+    bool haspend;
+
+    __device__ __forceinline__ double2 hload(int row, int j) const {
+        const bool in = row < n && j < n;
+        const double2 h = Hh[in ? (int64_t)row * n + j : 0];
+        return in ? h : cmk(0.0, 0.0);
+    }
+    __device__ __forceinline__ double2 mrow(int row, int j, double2 h) const {  // (I - w Hh)[row][j]
+        const double2 t = cmul(w, h);
+        return cmk((row == j ? 1.0 : 0.0) - t.x, -t.y);
+    }
+    // one pivot; pivots are taken two at a time (see hess_det_f64)
+    __device__ __forceinline__ void take(double2 p) {
+        if (!haspend) {
+            pend = p;
+            haspend = true;
+            return;
+        }
+        const double2 q = cmul(pend, p);
+        argsum += atan2(q.y, q.x);
+        magacc *= q.x * q.x + q.y * q.y;
+        haspend = false;
+        if (++npair == 8) {
+            logsum += 0.5 * log(magacc);
+            magacc = 1.0;
+            npair = 0;
+        }
+    }
+    // step k = 16 m + E0: pivot u_k, multiplier M[k+1][k] / u_k, row k+1 of U
+    template <int E0>
+    __device__ __forceinline__ void step() {
+        const int k = 16 * m + E0;
+        if (k >= n - 1) return;
+        const double2 piv = cmk(dpp_bcast64<E0>(cur.x), dpp_bcast64<E0>(cur.y));
+        const double2 hm = hload(k + 1, e + 16 * m);
+        const double2 hsub = cmk(dpp_bcast64<E0>(hm.x), dpp_bcast64<E0>(hm.y));  // Hh[k+1][k]
+        const double2 t = cmul(w, hsub);
+        const double2 l = cmul(cmk(-t.x, -t.y), cinv(piv));
+        cur = cfnms(mrow(k + 1, e + 16 * m, hm), l, cur);
+        #pragma unroll
+        for (int q = 0; q < MB; ++q) {
+            if (q <= m || 16 * q >= n) continue;
+            const int j = e + 16 * q;
+            u[q] = cfnms(mrow(k + 1, j, hload(k + 1, j)), l, u[q]);
+        }
+        take(piv);
+    }
+    template <int... E>
+    __device__ __forceinline__ void block(std::integer_sequence<int, E...>) {
+        (step<E>(), ...);
+    }
+};
+
+// Per point: unpivoted LU of the upper Hessenberg matrix M = I - w_B Hh.
+// Row k+1 of U is M[k+1, :] - (M[k+1][k] / u_k) u with u = row k of U, so
+// only one row of U is live.  16 lanes per point (4 points per wave), lane e
+// holding u_j for j = e + 16 m; the slot of the current block of 16 steps is
+// kept in `cur` so that every register index is static.  The logarithms of
+// the pivots are taken two at a time: both lie in the right half-plane, so
+// the principal logarithm of their product is the sum of theirs.  Writes
+// -1/2 (sum Log pivots + sum_i Log(1 - w_A lambda_i)) per (k_A, k_B).
+template <int MB>
+__global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *__restrict__ jobs,
+                                                                const int64_t *__restrict__ prefix, int njobs,
+                                                                const double2 *__restrict__ pool,
+                                                                const double2 *__restrict__ eigc,
+                                                                double2 *__restrict__ table)
+{
+    const int job = find_job(prefix, njobs, blockIdx.x);
+    const HessDev J = jobs[job];
+    const int64_t local = blockIdx.x - prefix[job];
+    const int nch = (J.dB + 15) >> 4;
+    const int kA = (int)(local / nch), chunk = (int)(local % nch);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4;
+    const int kB = chunk * 16 + wave * 4 + g;
+    const bool valid = kB < J.dB;
+
+    HessDetState<MB> S;
+    S.Hh = pool + J.c_off + (int64_t)kA * J.n * J.n;
+    S.n = J.n;
+    S.e = lane & 15;
+    double sn, cs;
+    sincospi(2.0 * (double)(valid ? kB : 0) / (double)J.GB, &sn, &cs);
+    S.w = cmk(cs, sn);
+    #pragma unroll
+    for (int q = 0; q < MB; ++q) {
+        const int j = S.e + 16 * q;
+        S.u[q] = j < S.n ? S.mrow(0, j, S.hload(0, j)) : cmk(0.0, 0.0);
+    }
+    S.argsum = S.logsum = 0.0;
+    S.magacc = 1.0;
+    S.npair = 0;
+    S.pend = cmk(1.0, 0.0);
+    S.haspend = false;
+    S.cur = S.u[0];
+    for (S.m = 0; S.m < MB && 16 * S.m < S.n - 1; ++S.m) {
+        S.cur = S.u[0];
+        #pragma unroll
+        for (int q = 1; q < MB; ++q)
+            if (q == S.m) S.cur = S.u[q];
+        S.block(std::make_integer_sequence<int, 16>{});
+    }
+    // last pivot u_{n-1}: in `cur` if step n-2 ran in its block, else in its slot
+    const int ml = (S.n - 1) >> 4, el = (S.n - 1) & 15;
+    double2 last = S.cur;
+    if (el == 0) {
+        last = S.u[0];
+        #pragma unroll
+        for (int q = 1; q < MB; ++q)
+            if (q == ml) last = S.u[q];
+    }
+    last.x = __shfl(last.x, g * 16 + el, 64);
+    last.y = __shfl(last.y, g * 16 + el, 64);
+    S.take(last);
+    if (S.haspend) {
+        S.argsum += atan2(S.pend.y, S.pend.x);
+        S.magacc *= S.pend.x * S.pend.x + S.pend.y * S.pend.y;
+    }
+    S.logsum += 0.5 * log(S.magacc);
+    if (valid && S.e == 0) {
+        const double2 ec = eigc[J.ec_off + kA];
+        table[J.t_off + (int64_t)kA * J.dB + kB] = cmk(-0.5 * (S.logsum + ec.x), -0.5 * (S.argsum + ec.y));
+    }
+}
+
+// contrib of a Hessenberg block at every evaluated point of its instance
+__global__ void __launch_bounds__(256) hess_scatter(const HessDev *__restrict__ jobs,
+                                                    const int64_t *__restrict__ prefix, int njobs, int64_t total,
+                                                    const InstDev *__restrict__ insts,
+                                                    const double2 *__restrict__ table, double2 *__restrict__ contrib)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int job = find_job(prefix, njobs, t);
+    const HessDev J = jobs[job];
+    const InstDev &I = insts[J.inst];
+    const int64_t pt = t - prefix[job];
+    const int kA = point_k(I, pt, J.axA), kB = point_k(I, pt, J.axB);
+    contrib[I.c_off + pt * I.nblocks + J.blk] = table[J.t_off + (int64_t)kA * J.dB + kB];
+}
+
+// ---------------------------------------------------------------------------
 // log G(w) = log Pr(0) + (constant) + sum over internal blocks of each
 // block's contribution, then G = exp(log G).  One thread per evaluated point.
 // ---------------------------------------------------------------------------
@@ -1528,7 +1924,69 @@ hipError_t launch_adjoint_seed(const InstDev *insts, const int64_t *prob_prefix,
 namespace cgd {
 // Dynamic LDS limits of the kernels that need more than the default; called
 // once at context creation (not inside a captured launch sequence).
+int hess_class_limit(int cls) {
+    switch (cls) {
+        case 0: return 32;
+        case 1: return 64;
+        case 2: return 144;
+        default: return 0;
+    }
+}
+
+template <int R, int SC>
+static hipError_t launch_hr(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, double2 *pool,
+                            const double *eigpool, double2 *eigc, hipStream_t st) {
+    hipLaunchKernelGGL((hess_reduce_f64<R, SC>), dim3((unsigned)nwg), dim3(kHessThreads), sizeof(HessLds<R, SC>), st,
+                       jobs, prefix, njobs, pool, eigpool, eigc);
+    return hipGetLastError();
+}
+
+hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
+                              double2 *pool, const double *eigpool, double2 *eigc, hipStream_t st) {
+    if (nwg <= 0) return hipSuccess;
+    switch (cls) {
+        case 0: return launch_hr<2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 1: return launch_hr<4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 2: return launch_hr<9, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MB>
+static hipError_t launch_hd(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, const double2 *pool,
+                            const double2 *eigc, double2 *table, hipStream_t st) {
+    hipLaunchKernelGGL((hess_det_f64<MB>), dim3((unsigned)nwg), dim3(kHessDetThreads), 0, st, jobs, prefix, njobs,
+                       pool, eigc, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_hess_det(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
+                           const double2 *pool, const double2 *eigc, double2 *table, hipStream_t st) {
+    if (nwg <= 0) return hipSuccess;
+    switch (cls) {
+        case 0: return launch_hd<2>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
+        case 1: return launch_hd<4>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
+        case 2: return launch_hd<9>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t total,
+                               const InstDev *insts, const double2 *table, double2 *contrib, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hess_scatter, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, jobs, prefix, njobs,
+                       total, insts, table, contrib);
+    return hipGetLastError();
+}
+
 hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
+    for (hipError_t e : {hipFuncSetAttribute((const void *)hess_reduce_f64<2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)sizeof(HessLds<2, 1>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)sizeof(HessLds<4, 2>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<9, 5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)sizeof(HessLds<9, 5>))})
+        if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<4, 2, 2>(), prepare_mfma<6, 2, 4>(),
                          prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(), prepare_mfma<12, 2, 4>()})
         if (e != hipSuccess) return e;
