@@ -953,21 +953,23 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
 // so is any unitary similarity of it: every pivot has Re > 0 and the sum of
 // the principal logarithms of the pivots is the continuous branch.
 // ---------------------------------------------------------------------------
-constexpr int kHessThreads = 512;  // 16 x 32 grid: ty = tid / 32, tx = tid % 32
 constexpr int kHessDetThreads = 256;  // 4 waves x 4 points, 16 lanes per point
 
-template <int R, int SC>
+// TY x 32 thread grid (ty = tid / 32, tx = tid % 32); element (i, j) in thread
+// (i mod TY, j mod 32), register (i / TY, j / 32); orders n <= min(TY R, 32 SC)
+template <int TY, int R, int SC>
 struct HessLds {
-    static constexpr int NMAX = (16 * R < 32 * SC) ? 16 * R : 32 * SC;
+    static constexpr int NT = 32 * TY;
+    static constexpr int NMAX = (TY * R < 32 * SC) ? TY * R : 32 * SC;
     static constexpr int PYS = NMAX + 1;  // padded stride of the row-sum partials
     double2 x[2][NMAX];                    // column k below the diagonal, by step parity
-    double nrm[2][16];                     // partial |x|^2 per thread row
-    double2 PW[16][NMAX];                  // partials of w_j = sum_i conj(v_i) a_ij, per thread row
+    double nrm[2][TY];                     // partial |x|^2 per thread row
+    double2 PW[TY][NMAX];                  // partials of w_j = sum_i conj(v_i) a_ij, per thread row
     double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column
-    double2 PS[kHessThreads];              // partials of s = v^H A v, per thread
+    double2 PS[NT];                        // partials of s = v^H A v, per thread
     double2 W[NMAX], Y[NMAX];
     double2 S;
-    double2 red[kHessThreads / 64 + 1];
+    double2 red[NT / 64 + 1];
 };
 
 __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) b
@@ -975,22 +977,24 @@ __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) 
 }
 
 // Householder reduction to upper Hessenberg form of C(w_A), one workgroup per
-// (block, k_A); element (i, j) in thread (i mod 16, j mod 32), register
-// (i / 16, j / 32).  Column k: v = x - alpha e_1 with x = A[k+1:, k],
+// (block, k_A); element (i, j) in thread (i mod TY, j mod 32), register
+// (i / TY, j / 32).  Column k: v = x - alpha e_1 with x = A[k+1:, k],
 // alpha = -(x_1/|x_1|) |x|, beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)); with
 // w = v^H A, y = A v and s = w v, the two-sided reflection is the rank-2
 // update A <- A - beta v w - beta (y - beta s v) v^H, so both sums come
 // from one pass over A.  Also writes sum_i Log(1 - w_A lambda_i) of the
 // eliminated bin.
-template <int R, int SC>
-__global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *__restrict__ jobs,
+template <int TY, int R, int SC>
+__global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__restrict__ jobs,
                                                                  const int64_t *__restrict__ prefix, int njobs,
                                                                  double2 *__restrict__ pool,
                                                                  const double *__restrict__ eigpool,
                                                                  double2 *__restrict__ eigc)
 {
-    using Lds = HessLds<R, SC>;
+    using Lds = HessLds<TY, R, SC>;
     constexpr int NMAX = Lds::NMAX;
+    constexpr int NT = Lds::NT;
+    static_assert(NT >= 512 ? 256 + NMAX <= NT - 64 : NMAX <= NT - 64, "reduction threads overlap the last wave");
     extern __shared__ __align__(16) unsigned char hess_raw[];
     Lds &L = *reinterpret_cast<Lds *>(hess_raw);
     const int job = find_job(prefix, njobs, blockIdx.x);
@@ -1000,16 +1004,30 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     double2 *__restrict__ C = pool + J.c_off + (int64_t)kA * n * n;
 
+    // The matrix moves between HBM and registers through LDS (the row-sum
+    // partial buffer), CR register rows (CR TY matrix rows, contiguous in C)
+    // at a time: plain coalesced copies, and few live addresses.
+    constexpr int CR = (32 * Lds::PYS) / (NMAX * TY);
+    static_assert(CR >= 1, "staging buffer too small");
+    double2 *stage = &L.PY[0][0];
     double2 a[R][SC];
     #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int c0 = 0; c0 < R; c0 += CR) {
+        const int i0 = c0 * TY;
+        const int rows = max(0, min(CR * TY, n - i0));
+        for (int e = tid; e < rows * n; e += NT) stage[e] = C[(int64_t)i0 * n + e];
+        __syncthreads();
         #pragma unroll
-        for (int s = 0; s < SC; ++s) {
-            const int i = ty + 16 * r, j = tx + 32 * s;
-            const bool in = i < n && j < n;
-            const double2 h = C[in ? (int64_t)i * n + j : 0];
-            a[r][s] = in ? h : cmk(0.0, 0.0);
-        }
+        for (int r = c0; r < c0 + CR && r < R; ++r)
+            #pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                const int i = ty + TY * r, j = tx + 32 * s;
+                const bool in = i < n && j < n;
+                const double2 h = stage[in ? (i - i0) * n + j : 0];
+                a[r][s] = in ? h : cmk(0.0, 0.0);
+            }
+        __syncthreads();
+    }
 
     for (int k = 0; k + 2 < n; ++k) {
         const int par = k & 1;
@@ -1022,7 +1040,7 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
                 if (s != sk) continue;
                 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int i = ty + 16 * r;
+                    const int i = ty + TY * r;
                     if (i > k && i < n) {
                         L.x[par][i] = a[r][s];
                         acc += a[r][s].x * a[r][s].x + a[r][s].y * a[r][s].y;
@@ -1032,42 +1050,49 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
             L.nrm[par][ty] = acc;
         }
         __syncthreads();
-        // B. reflector, partial sums of w, y and s
+        // B. reflector, partial sums of w, y and s.  Only columns j > k and,
+        // for w, rows i > k carry nonzero terms (v vanishes elsewhere).
         double xn2 = 0.0;
         #pragma unroll
-        for (int t = 0; t < 16; ++t) xn2 += L.nrm[par][t];
+        for (int t = 0; t < TY; ++t) xn2 += L.nrm[par][t];
         const double xn = sqrt(xn2);
         const double2 x1 = L.x[par][k + 1];
         const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
         const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
         const double2 v1 = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));  // x_1 - alpha
         const double beta = xn > 0.0 ? 1.0 / (xn * (xn + ax1)) : 0.0;
+        // v_i: an LDS load at a clamped index, then value selects (a select
+        // between a pointer to v1 and one into LDS would put v1 in scratch)
         auto vget = [&](int i) -> double2 {
-            if (i == k + 1) return v1;
-            return (i > k + 1 && i < n) ? L.x[par][i] : cmk(0.0, 0.0);
+            const int ic = (i > k + 1 && i < n) ? i : k + 1;
+            const double2 xl = L.x[par][ic];
+            const bool one = i == k + 1, in = i > k + 1 && i < n;
+            return cmk(one ? v1.x : (in ? xl.x : 0.0), one ? v1.y : (in ? xl.y : 0.0));
         };
-        double2 vc[SC], pw[SC];
+        double2 pw[SC];
         #pragma unroll
-        for (int s = 0; s < SC; ++s) {
-            vc[s] = vget(tx + 32 * s);
-            pw[s] = cmk(0.0, 0.0);
-        }
+        for (int s = 0; s < SC; ++s) pw[s] = cmk(0.0, 0.0);
         double2 ps = cmk(0.0, 0.0);
         #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int i = ty + 16 * r;
+            const int i = ty + TY * r;
+            if (i >= n) continue;
             const double2 vi = vget(i);
             double2 py = cmk(0.0, 0.0);
             #pragma unroll
             for (int s = 0; s < SC; ++s) {
-                const double2 c = cconjmul(vi, a[r][s]);
-                pw[s].x += c.x;
-                pw[s].y += c.y;
-                const double2 d = cmul(a[r][s], vc[s]);
+                const int j = tx + 32 * s;
+                if (j <= k || j >= n) continue;
+                const double2 d = cmul(a[r][s], vget(j));
                 py.x += d.x;
                 py.y += d.y;
+                if (i > k) {
+                    const double2 c = cconjmul(vi, a[r][s]);
+                    pw[s].x += c.x;
+                    pw[s].y += c.y;
+                }
             }
-            if (i < n) L.PY[tx][i] = py;
+            L.PY[tx][i] = py;
             const double2 e = cconjmul(vi, py);
             ps.x += e.x;
             ps.y += e.y;
@@ -1083,13 +1108,15 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
         if (tid < n) {
             double2 t = cmk(0.0, 0.0);
             #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < TY; ++q) {
                 t.x += L.PW[q][tid].x;
                 t.y += L.PW[q][tid].y;
             }
             L.W[tid] = t;
-        } else if (tid >= 256 && tid - 256 < n) {
-            const int i = tid - 256;
+        }
+        // y: threads 256.. when there are enough, else the same threads as w
+        if (NT >= 512 ? (tid >= 256 && tid - 256 < n) : tid < n) {
+            const int i = NT >= 512 ? tid - 256 : tid;
             double2 t = cmk(0.0, 0.0);
             #pragma unroll 8
             for (int q = 0; q < 32; ++q) {
@@ -1097,11 +1124,12 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
                 t.y += L.PY[q][i].y;
             }
             L.Y[i] = t;
-        } else if (tid >= kHessThreads - 64) {
+        }
+        if (tid >= NT - 64) {
             const int lane = tid & 63;
             double2 t = cmk(0.0, 0.0);
             #pragma unroll
-            for (int q = 0; q < kHessThreads / 64; ++q) {
+            for (int q = 0; q < NT / 64; ++q) {
                 t.x += L.PS[lane + 64 * q].x;
                 t.y += L.PS[lane + 64 * q].y;
             }
@@ -1113,29 +1141,24 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
             if (lane == 0) L.S = t;
         }
         __syncthreads();
-        // D. A <- A - beta v w - beta z v^H, z = y - beta s v
+        // D. A <- A - beta v w - beta z v^H, z = y - beta s v, on columns j > k
         const double2 sv = L.S;
-        double2 wj[SC];
-        #pragma unroll
-        for (int s = 0; s < SC; ++s) {
-            const int j = tx + 32 * s;
-            wj[s] = j < n ? L.W[j] : cmk(0.0, 0.0);
-        }
         #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int i = ty + 16 * r;
+            const int i = ty + TY * r;
+            if (i >= n) continue;
             const double2 vi = vget(i);
-            const double2 yi = i < n ? L.Y[i] : cmk(0.0, 0.0);
+            const double2 yi = L.Y[i];
             const double2 bsv = cmul(cmk(beta * sv.x, beta * sv.y), vi);
             const double2 zi = cmk(beta * (yi.x - bsv.x), beta * (yi.y - bsv.y));  // beta z_i
             const double2 bvi = cmk(beta * vi.x, beta * vi.y);
             #pragma unroll
             for (int s = 0; s < SC; ++s) {
-                // a -= (beta v_i) w_j + (beta z_i) conj(v_j)
-                double2 t = a[r][s];
-                t = cfnms(t, bvi, wj[s]);
-                const double2 cv = cmk(vc[s].x, -vc[s].y);
-                t = cfnms(t, zi, cv);
+                const int j = tx + 32 * s;
+                if (j <= k || j >= n) continue;
+                const double2 vj = vget(j);
+                double2 t = cfnms(a[r][s], zi, cmk(vj.x, -vj.y));
+                if (i > k) t = cfnms(t, bvi, L.W[j]);
                 a[r][s] = t;
             }
         }
@@ -1145,7 +1168,7 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
                 if (s != sk) continue;
                 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int i = ty + 16 * r;
+                    const int i = ty + TY * r;
                     if (i == k + 1) a[r][s] = cmk(-ph.x * xn, -ph.y * xn);  // alpha
                     else if (i > k + 1) a[r][s] = cmk(0.0, 0.0);
                 }
@@ -1153,25 +1176,34 @@ __global__ void __launch_bounds__(kHessThreads) hess_reduce_f64(const HessDev *_
         }
     }
 
+    __syncthreads();
     #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int c0 = 0; c0 < R; c0 += CR) {
+        const int i0 = c0 * TY;
+        const int rows = max(0, min(CR * TY, n - i0));
         #pragma unroll
-        for (int s = 0; s < SC; ++s) {
-            const int i = ty + 16 * r, j = tx + 32 * s;
-            if (i < n && j < n) C[(int64_t)i * n + j] = a[r][s];
-        }
+        for (int r = c0; r < c0 + CR && r < R; ++r)
+            #pragma unroll
+            for (int s = 0; s < SC; ++s) {
+                const int i = ty + TY * r, j = tx + 32 * s;
+                if (i < n && j < n) stage[(i - i0) * n + j] = a[r][s];
+            }
+        __syncthreads();
+        for (int e = tid; e < rows * n; e += NT) C[(int64_t)i0 * n + e] = stage[e];
+        __syncthreads();
+    }
 
     // sum_i Log(1 - w_A lambda_i)
     double sn, cs;
     sincospi(2.0 * (double)kA / (double)J.GA, &sn, &cs);
     const double *__restrict__ lam = eigpool + J.eig_off;
     double2 acc = cmk(0.0, 0.0);
-    for (int i = tid; i < J.n_eig; i += kHessThreads) {
+    for (int i = tid; i < J.n_eig; i += NT) {
         const double2 lg = clog(cmk(1.0 - cs * lam[i], -sn * lam[i]));
         acc.x += lg.x;
         acc.y += lg.y;
     }
-    acc = block_sum<kHessThreads>(acc, L.red);
+    acc = block_sum<NT>(acc, L.red);
     if (tid == 0) eigc[J.ec_off + kA] = acc;
 }
 
@@ -1933,11 +1965,11 @@ int hess_class_limit(int cls) {
     }
 }
 
-template <int R, int SC>
+template <int TY, int R, int SC>
 static hipError_t launch_hr(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, double2 *pool,
                             const double *eigpool, double2 *eigc, hipStream_t st) {
-    hipLaunchKernelGGL((hess_reduce_f64<R, SC>), dim3((unsigned)nwg), dim3(kHessThreads), sizeof(HessLds<R, SC>), st,
-                       jobs, prefix, njobs, pool, eigpool, eigc);
+    hipLaunchKernelGGL((hess_reduce_f64<TY, R, SC>), dim3((unsigned)nwg), dim3(32 * TY), sizeof(HessLds<TY, R, SC>),
+                       st, jobs, prefix, njobs, pool, eigpool, eigc);
     return hipGetLastError();
 }
 
@@ -1945,9 +1977,9 @@ hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefi
                               double2 *pool, const double *eigpool, double2 *eigc, hipStream_t st) {
     if (nwg <= 0) return hipSuccess;
     switch (cls) {
-        case 0: return launch_hr<2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 1: return launch_hr<4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 2: return launch_hr<9, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 0: return launch_hr<16, 2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 1: return launch_hr<16, 4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 2: return launch_hr<8, 18, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1980,12 +2012,12 @@ hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int n
 }
 
 hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
-    for (hipError_t e : {hipFuncSetAttribute((const void *)hess_reduce_f64<2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)sizeof(HessLds<2, 1>)),
-                         hipFuncSetAttribute((const void *)hess_reduce_f64<4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)sizeof(HessLds<4, 2>)),
-                         hipFuncSetAttribute((const void *)hess_reduce_f64<9, 5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)sizeof(HessLds<9, 5>))})
+    for (hipError_t e : {hipFuncSetAttribute((const void *)hess_reduce_f64<16, 2, 1>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 2, 1>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 4, 2>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 4, 2>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<8, 18, 5>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<8, 18, 5>))})
         if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<4, 2, 2>(), prepare_mfma<6, 2, 4>(),
                          prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(), prepare_mfma<12, 2, 4>()})
