@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/cgd.h"
@@ -604,11 +606,12 @@ cgd_status build_grad(cgd_ctx *c, int n_inst) {
 // logPr0 = -1/2 zbar^H Sigma^-1 zbar - 1/2 log det Sigma) to the inputs.  For
 // a complex input z with dL = Re(a dz + b conj(dz)) the reported gradient is
 // dL/dRe z + i dL/dIm z = conj(a) + b.
-void chain_rule(const cgd_ctx *c, const cgd_instance *inst_unused, const std::vector<cplx> &zhost,
-                std::vector<double> &gr, std::vector<cplx> &gT, std::vector<cplx> &ga,
-                const std::vector<int64_t> &roff, const std::vector<int64_t> &toff) {
-    (void)inst_unused;
-    for (size_t b = 0; b < c->grads.size(); ++b) {
+// Contribution of internal block b to dL/dr (M), dL/dT (M*M) and dL/dalpha (M)
+// of its instance, written to gr, gT, ga (zero-initialised by the caller).
+void chain_rule_block(const cgd_ctx *c, size_t b, const std::vector<cplx> &zhost, std::vector<double> &gr,
+                      std::vector<cplx> &gT, std::vector<cplx> &ga) {
+    const int64_t to = 0, ro = 0;
+    {
         const GradHost &g = c->grads[b];
         const GradBlockDev &d = c->gblocks[b];
         const HostInstCopy &hc = c->hinst_copy[g.inst];
@@ -670,7 +673,6 @@ void chain_rule(const cgd_ctx *c, const cgd_instance *inst_unused, const std::ve
             Xb.a[e] += t5.a[e] + t6.a[e];
         }
         CMat Cn = matmul(matmul(Tt, PhiN), Tc), Cm1 = matmul(matmul(Tt, G21), T), Cm2 = matmul(matmul(Th, G12), Tc);
-        const int64_t to = toff[g.inst], ro = roff[g.inst];
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) gT[to + (size_t)i * M + j] += std::conj(Xa(j, i)) + Xb(j, i);
         for (int j = 0; j < M; ++j) {
@@ -698,6 +700,39 @@ void chain_rule(const cgd_ctx *c, const cgd_instance *inst_unused, const std::ve
                 ga[ro + j] += std::conj(aa) + bs;
             }
         }
+    }
+}
+
+// Chain rule over all blocks on up to 16 host threads; each block writes its own
+// buffers and the sums into gr, gT, ga are taken in block order (reproducible).
+void chain_rule(const cgd_ctx *c, const std::vector<cplx> &zhost, std::vector<double> &gr, std::vector<cplx> &gT,
+                std::vector<cplx> &ga, const std::vector<int64_t> &roff, const std::vector<int64_t> &toff) {
+    const size_t nb = c->grads.size();
+    std::vector<std::vector<double>> bgr(nb);
+    std::vector<std::vector<cplx>> bgT(nb), bga(nb);
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t b; (b = next.fetch_add(1)) < nb;) {
+            const int M = c->hinst_copy[c->grads[b].inst].M;
+            bgr[b].assign(M, 0.0);
+            bgT[b].assign((size_t)M * M, cplx(0, 0));
+            bga[b].assign(M, cplx(0, 0));
+            chain_rule_block(c, b, zhost, bgr[b], bgT[b], bga[b]);
+        }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nthr = std::min<size_t>({(size_t)16, (size_t)hw, nb});
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nthr; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    for (size_t b = 0; b < nb; ++b) {
+        const int inst = c->grads[b].inst;
+        for (size_t j = 0; j < bgr[b].size(); ++j) {
+            gr[roff[inst] + j] += bgr[b][j];
+            ga[roff[inst] + j] += bga[b][j];
+        }
+        for (size_t e = 0; e < bgT[b].size(); ++e) gT[toff[inst] + e] += bgT[b][e];
     }
 }
 
@@ -1309,7 +1344,7 @@ cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_
     }
     std::vector<double> gr(roff[c->n_inst], 0.0);
     std::vector<cplx> gT(toff[c->n_inst], cplx(0, 0)), ga(roff[c->n_inst], cplx(0, 0));
-    chain_rule(c, nullptr, zh, gr, gT, ga, roff, toff);
+    chain_rule(c, zh, gr, gT, ga, roff, toff);
     if (d_dr) HIP_OK(hipMemcpyAsync(d_dr, gr.data(), sizeof(double) * gr.size(), hipMemcpyHostToDevice, st));
     if (d_dT) HIP_OK(hipMemcpyAsync(d_dT, gT.data(), sizeof(cplx) * gT.size(), hipMemcpyHostToDevice, st));
     if (d_dalpha) HIP_OK(hipMemcpyAsync(d_dalpha, ga.data(), sizeof(cplx) * ga.size(), hipMemcpyHostToDevice, st));

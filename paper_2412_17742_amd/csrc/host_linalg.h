@@ -23,16 +23,23 @@ struct CMat {
     }
 };
 
+// complex products written out in real arithmetic (std::complex's operator*
+// carries a check for inf/nan on every product)
 inline CMat matmul(const CMat &A, const CMat &B) {
     CMat C(A.r, B.c);
-    for (int i = 0; i < A.r; ++i)
+    for (int i = 0; i < A.r; ++i) {
+        double *crow = reinterpret_cast<double *>(&C.a[(size_t)i * C.c]);
         for (int k = 0; k < A.c; ++k) {
-            const cplx aik = A(i, k);
-            if (aik == cplx(0, 0)) continue;
-            const cplx *brow = &B.a[(size_t)k * B.c];
-            cplx *crow = &C.a[(size_t)i * C.c];
-            for (int j = 0; j < B.c; ++j) crow[j] += aik * brow[j];
+            const double ar = A(i, k).real(), ai = A(i, k).imag();
+            if (ar == 0.0 && ai == 0.0) continue;
+            const double *brow = reinterpret_cast<const double *>(&B.a[(size_t)k * B.c]);
+            for (int j = 0; j < B.c; ++j) {
+                const double br = brow[2 * j], bi = brow[2 * j + 1];
+                crow[2 * j] += ar * br - ai * bi;
+                crow[2 * j + 1] += ar * bi + ai * br;
+            }
         }
+    }
     return C;
 }
 
