@@ -93,6 +93,26 @@ def cpu_baseline(instances, seconds: float):
                        f"plus a dense solve (numpy/LAPACK, FP64), {dt:.1f} s")
 
 
+def grad_timing(cgd, instances, steps, warmup, flags):
+    """Wall time of cgd_grad (adjoint DFT, per-point FP64 inverses, reductions,
+    host chain rule; the call waits for the device) after one evaluation."""
+    import torch
+    ctx = cgd.Context(instances, precision="fp64", flags=flags | cgd.FLAG_GRAD)
+    p = ctx.eval()
+    torch.cuda.synchronize()
+    dP = torch.ones_like(p)
+    for _ in range(warmup):
+        ctx.grad(dP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.grad(dP)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    ctx.close()
+    return dict(ms_per_grad=ms, unit="ms", what="dL/d(r, T, alpha) of all probabilities for dL/dP = 1")
+
+
 def run(ctx, steps, warmup):
     import torch
     probs = torch.empty(ctx.n_probs, dtype=torch.float64, device="cuda")
@@ -136,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 3 times (scale for HBM byte counters)")
+    ap.add_argument("--grad", action="store_true",
+                    help="also time cgd_grad (FP64 adjoint; blocks of order <= 96, e.g. --workload mesh32_k4)")
     ap.add_argument("--flags", type=int, default=0,
                     help="cgd_create flags (e.g. 8 = CGD_FLAG_HESSENBERG)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
@@ -249,6 +271,8 @@ def main():
         "mixed": summary(paths["mixed"], "mixed"),
         "roofline": roof,
     }
+    if args.grad:
+        out["grad"] = grad_timing(cgd, instances, args.steps, args.warmup, args.flags)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(instances, args.cpu_seconds)
     for rec in paths.values():

@@ -377,13 +377,15 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int g, i
     }
     const float s = __builtin_amdgcn_rcpf(pr * pr + pi * pi);
     const float rpr = pr * s, rpi = -pi * s;
+    // t = a[k][c] / p off column k.  On column k, t = 1 + 1/p, so that the
+    // common update a - a[r][k] t leaves -a[r][k] / p there with no zeroing of
+    // a (|1/p| > 1/2 for an accretive matrix, so nothing cancels badly).
     const bool isk = (c == K);
-    const float tr = isk ? rpr : fmaf(rowr, rpr, -rowi * rpi);
+    const float tr = isk ? 1.f + rpr : fmaf(rowr, rpr, -rowi * rpi);
     const float ti = isk ? rpi : fmaf(rowr, rpi, rowi * rpr);
     auto upd = [&](int v) {
-        const float br = isk ? 0.f : ar[v], bi = isk ? 0.f : ai[v];
-        ar[v] = fmaf(coli[v], ti, fmaf(-colr[v], tr, br));
-        ai[v] = fmaf(-coli[v], tr, fmaf(-colr[v], ti, bi));
+        ar[v] = fmaf(coli[v], ti, fmaf(-colr[v], tr, ar[v]));
+        ai[v] = fmaf(-coli[v], tr, fmaf(-colr[v], ti, ai[v]));
     };
     if (K < 15) {
         upd(V1);  // row K+1 (on group G1) first
@@ -395,8 +397,8 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int g, i
     #pragma unroll
     for (int v = 0; v < 4; ++v)
         if (K == 15 || v != V1) upd(v);
-    if (g == KG) {
-        ar[KV] = tr;
+    if (g == KG) {  // row k: a[k][c] / p, and 1/p at (k, k)
+        ar[KV] = isk ? rpr : tr;
         ai[KV] = ti;
     }
 }
