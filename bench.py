@@ -159,7 +159,7 @@ def main():
     ap.add_argument("--grad", action="store_true",
                     help="also time cgd_grad (FP64 adjoint; blocks of order <= 96, e.g. --workload mesh32_k4)")
     ap.add_argument("--flags", type=int, default=0,
-                    help="cgd_create flags (e.g. 8 = CGD_FLAG_HESSENBERG)")
+                    help="cgd_create flags (e.g. 8 = CGD_FLAG_HESSENBERG, 16 = CGD_FLAG_NO_HESSENBERG)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
                     help="paths to time (the JSON line needs both for the mixed-vs-FP64 check)")
     args = ap.parse_args()
@@ -218,11 +218,12 @@ def main():
         achieved = bytes_[dom] / (dom_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s")
         kname = "dft_stage"
-    elif dom == "hess":
-        # Hessenberg route: FP64 reductions of the Schur matrices and O(n^2) factorisations
+    elif dom in ("hess", "hess_det"):
+        # Hessenberg route: FP64 Householder reductions of the Schur matrices
+        # (one workgroup per value of w_A) and O(n^2) factorisations per point
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
-        kname = "hess_reduce_f64 + hess_det_f64"
+        kname = "hess_reduce_f64" if dom == "hess" else "hess_det_f64"
     elif best == "mixed" and dom in cgd.LU_KERNELS:
         # first pass of the mixed path: complex FP32 elimination on MFMA (16x16x4 f32)
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12

@@ -70,11 +70,15 @@ typedef enum {
                                       give the same determinant; for testing/measurement) */
 #define CGD_FLAG_NO_SCHUR 2u       /* evaluate every grid point with a full factorisation
                                       instead of reusing the first bin's eigenbasis */
-#define CGD_FLAG_HESSENBERG 8u     /* Hessenberg route: when the rows left after eliminating the
-                                      first bin all lie in one bin B (order <= 144, no
-                                      displacement border), reduce every Schur matrix C(w_A)
-                                      once to Hessenberg form so that each point costs O(n^2)
-                                      instead of a full factorisation (FP64 in both precisions) */
+#define CGD_FLAG_HESSENBERG 8u     /* Hessenberg route, forced: when the rows left after
+                                      eliminating the first bin all lie in one bin B (order
+                                      <= 144, no displacement border), reduce every Schur
+                                      matrix C(w_A) once to Hessenberg form so that each point
+                                      costs O(n^2) instead of a full factorisation (FP64 in
+                                      both precisions).  Without either Hessenberg flag the
+                                      library takes this route for those blocks when its
+                                      estimate of the time is lower (many points per w_A). */
+#define CGD_FLAG_NO_HESSENBERG 16u /* never take the Hessenberg route                        */
 #define CGD_FLAG_GRAD 4u           /* prepare cgd_grad (keeps each internal block's full
                                       matrix on the device); needs 2M(+1) <= 96 per block */
 
@@ -159,8 +163,9 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  *                        the FP32 MFMA kernel for orders 145..192, FP64 above)
  *   CGD_STAGE_COMBINE    log G per point and G = exp(log G)
  *   CGD_STAGE_DFT        all axis passes of the inverse DFT
- *   CGD_STAGE_HESS       Hessenberg route: reduction of each C(w_A), the O(n^2)
- *                        factorisation of every (w_A, w_B) pair, copy to the points
+ *   CGD_STAGE_HESS       Hessenberg route: reduction of each C(w_A)
+ *   CGD_STAGE_HESS_DET   Hessenberg route: the O(n^2) factorisation of every
+ *                        (w_A, w_B) pair, copy to the points
  *   CGD_STAGE_FIX        mixed path: selection of the points whose FP32 value can
  *                        matter, their FP64 re-factorisation and the second combine
  * With timing enabled, cgd_eval records a HIP event pair on the context's
@@ -169,8 +174,11 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  * cgd_stage_work returns each stage's algorithmic work per evaluation:
  * flops (complex LU of order n: 8 sum_m m^2 + 6 sum_m m, m = n-1..0, i.e.
  * about 8n^3/3 real flops; Schur build: 8 nA nB^2 per eliminated-bin value;
- * DFT: 8 flops per complex multiply-add) and bytes (DFT: each grid value
- * read once, each probability written once, 16 and 8 bytes). */
+ * Hessenberg reduction of order n: step k (m = n - k - 1 rows below the
+ * diagonal) 2 m (m + 1) + 2 n m complex multiply-adds; Hessenberg
+ * factorisation: 2 (n - k - 1) per pivot k; DFT: 8 flops per complex
+ * multiply-add) and bytes (DFT: each grid value read once, each
+ * probability written once, 16 and 8 bytes). */
 enum {
     CGD_STAGE_SCHUR = 0,
     CGD_STAGE_LU_REG0 = 1,
@@ -179,7 +187,8 @@ enum {
     CGD_STAGE_DFT = 8,
     CGD_STAGE_FIX = 9,
     CGD_STAGE_HESS = 10,
-    CGD_NSTAGES = 11
+    CGD_STAGE_HESS_DET = 11,
+    CGD_NSTAGES = 12
 };
 cgd_status cgd_set_timing(cgd_ctx *ctx, int32_t enable);
 cgd_status cgd_stage_times(cgd_ctx *ctx, double *ms /* CGD_NSTAGES */);

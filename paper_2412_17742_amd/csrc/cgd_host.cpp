@@ -356,6 +356,19 @@ struct LuClass {
 
 // Hessenberg-route jobs of one size class: reduction (one workgroup per k_A)
 // and factorisations (one workgroup per k_A and 16 values of k_B)
+// Blocks that can take the Hessenberg route: the first bin eliminated through
+// its eigenbasis, no displacement border, order within the reduction
+// kernels' limit, and every row left in one other bin.  Returns that bin, or -1.
+static int hess_bin(const HostBlock &h) {
+    if (h.schur_axis < 0 || h.bordered || h.nb < 1 || h.nb > hess_class_limit(kHessClasses - 1)) return -1;
+    int hbin = -1;
+    for (int32_t rb : h.rowbin) {
+        if (rb < 0 || (hbin >= 0 && rb != hbin)) return -1;
+        hbin = rb;
+    }
+    return hbin == h.schur_axis ? -1 : hbin;
+}
+
 struct HessClass {
     std::vector<HessDev> jobs;
     std::vector<int64_t> rprefix, dprefix;
@@ -476,6 +489,54 @@ void free_ctx(cgd_ctx *c) {
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->ev_status) (void)hipEventDestroy(c->ev_status);
     delete c;
+}
+
+// Route for the blocks hess_bin accepts (all of them, or none), unless a flag
+// forces it: the Hessenberg route replaces a factorisation per point by one
+// reduction per value of w_A plus an O(n^2) factorisation per (w_A, w_B).
+// Its reductions run one per compute unit and are latency bound, so with few
+// values of w_A, or few values of w_B per w_A, the factorisations per point
+// are faster.  Both sides are estimated from per-kernel times measured on
+// MI355X, in microseconds of one compute unit:
+//   reduction    (n - 2) steps of t_step (1.4, 2.0, 5.3 us for orders
+//                <= 32, 64, 144), one reduction per compute unit at a time;
+//   Hessenberg   10 (n / 144)^2 per (w_A, w_B);
+//   LU per point 148 (n / 144)^3 (FP64), 70 (n / 144)^3 (mixed, including
+//                the share of points factorised again in FP64).
+bool choose_hessenberg(const cgd_ctx *c, const std::vector<HostBlock> &hb, std::vector<int> &hbins) {
+    bool any = false;
+    for (size_t b = 0; b < hb.size(); ++b) {
+        hbins[b] = hess_bin(hb[b]);
+        any |= hbins[b] >= 0;
+    }
+    if (!any || (c->flags & CGD_FLAG_NO_HESSENBERG)) return false;
+    if (c->flags & CGD_FLAG_HESSENBERG) return true;
+    int ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    static constexpr double t_step[kHessClasses] = {1.4, 2.0, 5.3};
+    double red_n[kHessClasses] = {0.0, 0.0, 0.0};  // total reductions per class
+    double red_t[kHessClasses] = {0.0, 0.0, 0.0};  // longest reduction per class
+    double det_cu = 0.0, lu_cu = 0.0;
+    const double lu_scale = c->prec == CGD_PREC_MIXED ? 70.0 : 148.0;
+    for (size_t b = 0; b < hb.size(); ++b) {
+        if (hbins[b] < 0) continue;
+        const HostBlock &h = hb[b];
+        const InstDev &I = c->inst[h.inst];
+        const double nA = h.schur_axis == 0 ? I.H1 : I.G[h.schur_axis];
+        const double nB = hbins[b] == 0 ? I.H1 : I.G[hbins[b]];
+        int cls = 0;
+        while (h.nb > hess_class_limit(cls)) ++cls;
+        const double r = h.nb / 144.0;
+        red_n[cls] += nA;
+        red_t[cls] = std::max(red_t[cls], (h.nb - 2) * t_step[cls]);
+        det_cu += nA * nB * 10.0 * r * r;
+        lu_cu += (double)I.npts * lu_scale * r * r * r;
+    }
+    double t_hess = det_cu / ncu;
+    for (int k = 0; k < kHessClasses; ++k) t_hess += std::ceil(red_n[k] / ncu) * red_t[k];
+    return t_hess < lu_cu / ncu;
 }
 
 cgd_status check_status(cgd_ctx *c) {
@@ -849,22 +910,16 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     };
     c->blocks.resize(hblocks.size());
     c->is_hess.assign(hblocks.size(), 0);
+    std::vector<int> hbins(hblocks.size(), -1);
+    const bool use_hess = choose_hessenberg(c, hblocks, hbins);
     for (size_t b = 0; b < hblocks.size(); ++b) {
         const HostBlock &h = hblocks[b];
         BlockDev &d = c->blocks[b];
         std::memset(&d, 0, sizeof(d));
         InstDev &I0 = c->inst[h.inst];
         if (I0.first_block < 0) I0.first_block = (int32_t)b;
-        // Hessenberg route: the rows left after the eigenbasis elimination all in one bin
-        int hbin = -1;
-        bool hess = (c->flags & CGD_FLAG_HESSENBERG) && h.schur_axis >= 0 && !h.bordered && h.nb >= 1 &&
-                    h.nb <= hess_class_limit(kHessClasses - 1);
-        if (hess)
-            for (int32_t rb : h.rowbin) {
-                if (rb < 0 || (hbin >= 0 && rb != hbin)) { hess = false; break; }
-                hbin = rb;
-            }
-        if (hbin < 0 || hbin == h.schur_axis) hess = false;
+        const int hbin = hbins[b];
+        const bool hess = use_hess && hbin >= 0;
         c->is_hess[b] = hess;
         d.cls = kRegClasses;
         for (int k = 0; k < kRegClasses; ++k)
@@ -1048,7 +1103,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             red += 2.0 * m * (m + 1) + 2.0 * hd.n * m;
         }
         for (int k = 0; k + 1 < hd.n; ++k) fac += 2.0 * (hd.n - k - 1);
-        c->work_flops[CGD_STAGE_HESS] += 8.0 * (red * hd.dA + fac * (double)hd.dA * hd.dB);
+        c->work_flops[CGD_STAGE_HESS] += 8.0 * red * hd.dA;
+        c->work_flops[CGD_STAGE_HESS_DET] += 8.0 * fac * (double)hd.dA * hd.dB;
     }
     for (const DftStage &st : c->stages)
         for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
@@ -1137,8 +1193,11 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     if (!inst || n_inst <= 0) return fail(CGD_ERR_ARG, "need at least one instance");
     if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
     if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
-    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD | CGD_FLAG_HESSENBERG))
+    if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD | CGD_FLAG_HESSENBERG |
+                  CGD_FLAG_NO_HESSENBERG))
         return fail(CGD_ERR_ARG, "unknown flags");
+    if ((flags & CGD_FLAG_HESSENBERG) && (flags & CGD_FLAG_NO_HESSENBERG))
+        return fail(CGD_ERR_ARG, "CGD_FLAG_HESSENBERG and CGD_FLAG_NO_HESSENBERG together");
     cgd_ctx *c = new (std::nothrow) cgd_ctx();
     if (!c) return fail(CGD_ERR_NOMEM, "host allocation");
     c->n_inst = n_inst;
@@ -1186,12 +1245,14 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         for (auto &hc : c->hcls)
             HIP_OK(launch_hess_reduce((int)(&hc - c->hcls), hc.d_jobs, hc.d_rprefix, (int)hc.jobs.size(), hc.rnwg,
                                       c->d_pool, c->d_eig, c->d_eigc, st));
+        HIP_OK(mark(CGD_STAGE_HESS, 1));
+        HIP_OK(mark(CGD_STAGE_HESS_DET, 0));
         for (auto &hc : c->hcls)
             HIP_OK(launch_hess_det((int)(&hc - c->hcls), hc.d_jobs, hc.d_dprefix, (int)hc.jobs.size(), hc.dnwg,
                                    c->d_pool, c->d_eigc, c->d_htable, st));
         HIP_OK(launch_hess_scatter(c->d_hess_all, c->d_hess_sprefix, (int)c->hess_all.size(), c->hess_spts,
                                    c->d_inst, c->d_htable, c->d_contrib, st));
-        HIP_OK(mark(CGD_STAGE_HESS, 1));
+        HIP_OK(mark(CGD_STAGE_HESS_DET, 1));
     }
     const bool mixed = c->prec == CGD_PREC_MIXED;
     // timing: a slot spans from its first launch to its last one in this evaluation

@@ -42,6 +42,22 @@ __device__ __forceinline__ double2 cfnms(double2 a, double2 l, double2 u) {
     a.y = fma(-l.y, u.x, a.y);
     return a;
 }
+// a + l * u
+__device__ __forceinline__ double2 cfma(double2 l, double2 u, double2 a) {
+    a.x = fma(l.x, u.x, a.x);
+    a.x = fma(-l.y, u.y, a.x);
+    a.y = fma(l.x, u.y, a.y);
+    a.y = fma(l.y, u.x, a.y);
+    return a;
+}
+// a + conj(l) * u
+__device__ __forceinline__ double2 cfma_conj(double2 l, double2 u, double2 a) {
+    a.x = fma(l.x, u.x, a.x);
+    a.x = fma(l.y, u.y, a.x);
+    a.y = fma(l.x, u.y, a.y);
+    a.y = fma(-l.y, u.x, a.y);
+    return a;
+}
 __device__ __forceinline__ double2 cinv(double2 d) {
     const double s = 1.0 / (d.x * d.x + d.y * d.y);
     return cmk(d.x * s, -d.y * s);
@@ -958,34 +974,204 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
 constexpr int kHessDetThreads = 256;  // 4 waves x 4 points, 16 lanes per point
 
 // TY x 32 thread grid (ty = tid / 32, tx = tid % 32); element (i, j) in thread
-// (i mod TY, j mod 32), register (i / TY, j / 32); orders n <= min(TY R, 32 SC)
+// (i mod TY, j mod 32), register (i / TY, j / 32): RMAX = TY R rows and
+// CMAX = 32 SC columns are held, orders n <= min(RMAX, CMAX).
 template <int TY, int R, int SC>
 struct HessLds {
     static constexpr int NT = 32 * TY;
-    static constexpr int NMAX = (TY * R < 32 * SC) ? TY * R : 32 * SC;
-    static constexpr int PYS = NMAX + 1;  // padded stride of the row-sum partials
-    double2 x[2][NMAX];                    // column k below the diagonal, by step parity
+    static constexpr int RMAX = TY * R;
+    static constexpr int CMAX = 32 * SC;
+    static constexpr int NMAX = RMAX < CMAX ? RMAX : CMAX;
+    static constexpr int XMAX = RMAX > CMAX ? RMAX : CMAX;
+    static constexpr int PYS = RMAX + 1;  // padded stride of the row-sum partials
+    double2 x[2][XMAX];                    // v of step k (zero outside rows k+1..n-1), by step parity
+    double2 x1[2];                         // x_1 = A[k+1][k], by step parity
     double nrm[2][TY];                     // partial |x|^2 per thread row
-    double2 PW[TY][NMAX];                  // partials of w_j = sum_i conj(v_i) a_ij, per thread row
+    double2 PW[TY][CMAX];                  // partials of w_j = sum_i conj(v_i) a_ij, per thread row
     double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column
     double2 PS[NT];                        // partials of s = v^H A v, per thread
-    double2 W[NMAX], Y[NMAX];
+    double2 W[CMAX], Y[RMAX];
     double2 S;
     double2 red[NT / 64 + 1];
 };
 
-__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) b
-    return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+// Register column S holds column k: write x (zero at rows <= k and >= n)
+// and return this thread's share of |x|^2.
+template <int TY, int R, int SC, int S>
+__device__ __forceinline__ double hess_put_x(HessLds<TY, R, SC> &L, const double2 (&a)[R][SC], int k, int n,
+                                             int par, int ty) {
+    double acc = 0.0;
+    #pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = ty + TY * r;
+        const bool in = i > k && i < n;
+        const double2 xi = cmk(in ? a[r][S].x : 0.0, in ? a[r][S].y : 0.0);
+        L.x[par][i] = xi;
+        if (i == k + 1) L.x1[par] = xi;
+        acc = fma(xi.x, xi.x, fma(xi.y, xi.y, acc));
+    }
+    return acc;
+}
+
+// One Householder step k (column k) of hess_reduce_f64, R0 = k / TY.
+// Register rows r < R0 hold only rows < k, where v vanishes; register
+// columns s < S0 = k / 32 hold only columns < k, where v vanishes, so their
+// entries on or above the subdiagonal (rows i <= j + 1 <= k) do not change.  The
+// terms they would carry are left out at compile time.  Column k becomes
+// (alpha, O(eps |x|), ...) below the diagonal; what is left below the
+// subdiagonal never reaches the Hessenberg part (v vanishes on those rows and
+// columns in every later step) and is written out as zero.
+template <int TY, int R, int SC, int R0>
+__device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int k, int n, int tid) {
+    static_assert(32 % TY == 0 || TY % 32 == 0, "row and column blocks must nest");
+    constexpr int S0 = (R0 * TY) / 32;  // = k / 32, the register column of column k
+    constexpr int NT = 32 * TY, RMAX = TY * R, CMAX = 32 * SC;
+    const int par = k & 1, ty = tid >> 5, tx = tid & 31;
+
+    // A. x = column k below the diagonal, partial norms
+    if (tx == (k & 31)) L.nrm[par][ty] = hess_put_x<TY, R, SC, S0>(L, a, k, n, par, ty);
+    __syncthreads();
+    // reflector: v = x - alpha e_1, alpha = -(x_1/|x_1|) |x|,
+    // beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)); v_1 goes to LDS
+    double xn2 = 0.0;
+    #pragma unroll
+    for (int t = 0; t < TY; ++t) xn2 += L.nrm[par][t];
+    const double xn = sqrt(xn2);
+    const double2 x1 = L.x1[par];
+    const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
+    const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
+    const double beta = xn > 0.0 ? 1.0 / (xn * (xn + ax1)) : 0.0;
+    if (tid == 0) L.x[par][k + 1] = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));
+    __syncthreads();
+
+    // B. partial sums of y = A v (all rows), w = v^H A and s = v^H y
+    double2 ps = cmk(0.0, 0.0);
+    {
+        double2 vj[SC];
+        #pragma unroll
+        for (int s = S0; s < SC; ++s) vj[s] = L.x[par][tx + 32 * s];
+        #pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = ty + TY * r;
+            double2 py = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int s = S0; s < SC; ++s) py = cfma(a[r][s], vj[s], py);
+            L.PY[tx][i] = py;
+            if (r >= R0) ps = cfma_conj(L.x[par][i], py, ps);
+        }
+    }
+    {
+        double2 pw[SC];
+        #pragma unroll
+        for (int s = S0; s < SC; ++s) pw[s] = cmk(0.0, 0.0);
+        #pragma unroll
+        for (int r = R0; r < R; ++r) {
+            const double2 vi = L.x[par][ty + TY * r];
+            #pragma unroll
+            for (int s = S0; s < SC; ++s) pw[s] = cfma_conj(vi, a[r][s], pw[s]);
+        }
+        #pragma unroll
+        for (int s = S0; s < SC; ++s) L.PW[ty][tx + 32 * s] = pw[s];
+    }
+    L.PS[tid] = ps;
+    __syncthreads();
+
+    // C. reductions, each in a fixed order: w by threads 0.., y by threads
+    // 256.., s by the last wave
+    if (tid >= 32 * S0 && tid < CMAX) {
+        double2 t = cmk(0.0, 0.0);
+        #pragma unroll
+        for (int q = 0; q < TY; ++q) {
+            t.x += L.PW[q][tid].x;
+            t.y += L.PW[q][tid].y;
+        }
+        L.W[tid] = t;
+    }
+    if (tid >= 256 && tid - 256 < RMAX) {
+        const int i = tid - 256;
+        double2 t = cmk(0.0, 0.0);
+        #pragma unroll 8
+        for (int q = 0; q < 32; ++q) {
+            t.x += L.PY[q][i].x;
+            t.y += L.PY[q][i].y;
+        }
+        L.Y[i] = t;
+    }
+    if (tid >= NT - 64) {
+        const int lane = tid & 63;
+        double2 t = cmk(0.0, 0.0);
+        #pragma unroll
+        for (int q = 0; q < NT / 64; ++q) {
+            t.x += L.PS[lane + 64 * q].x;
+            t.y += L.PS[lane + 64 * q].y;
+        }
+        #pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            t.x += __shfl_xor(t.x, off, 64);
+            t.y += __shfl_xor(t.y, off, 64);
+        }
+        if (lane == 0) L.S = t;
+    }
+    __syncthreads();
+
+    // D. A <- A - beta z v^H - beta v w with z = y - beta s v, one rank-1
+    // term per pass
+    const double2 sv = L.S;
+    const double2 bs = cmk(beta * sv.x, beta * sv.y);
+    {
+        double2 cvj[SC];
+        #pragma unroll
+        for (int s = S0; s < SC; ++s) {
+            const double2 v = L.x[par][tx + 32 * s];
+            cvj[s] = cmk(v.x, -v.y);
+        }
+        #pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = ty + TY * r;
+            const double2 yi = L.Y[i];
+            double2 zi;  // beta z_i
+            if (r >= R0) {
+                const double2 bsv = cmul(bs, L.x[par][i]);
+                zi = cmk(beta * (yi.x - bsv.x), beta * (yi.y - bsv.y));
+            } else {
+                zi = cmk(beta * yi.x, beta * yi.y);
+            }
+            #pragma unroll
+            for (int s = S0; s < SC; ++s) a[r][s] = cfnms(a[r][s], zi, cvj[s]);
+        }
+    }
+    {
+        double2 wj[SC];
+        #pragma unroll
+        for (int s = S0; s < SC; ++s) wj[s] = L.W[tx + 32 * s];
+        #pragma unroll
+        for (int r = R0; r < R; ++r) {
+            const double2 vi = L.x[par][ty + TY * r];
+            const double2 bvi = cmk(beta * vi.x, beta * vi.y);
+            #pragma unroll
+            for (int s = S0; s < SC; ++s) a[r][s] = cfnms(a[r][s], bvi, wj[s]);
+        }
+    }
+}
+
+// Steps k with k / TY = R0, then R0 + 1, ..., R - 1: one loop per value, so
+// that each loop body is straight-line code.
+template <int TY, int R, int SC, int R0>
+__device__ __forceinline__ void hess_steps_from(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int n, int tid) {
+    const int k_lo = TY * R0, k_hi = min(TY * (R0 + 1), n - 2);
+    for (int k = k_lo; k < k_hi; ++k) hess_step<TY, R, SC, R0>(L, a, k, n, tid);
+    if constexpr (R0 + 1 < R) hess_steps_from<TY, R, SC, R0 + 1>(L, a, n, tid);
 }
 
 // Householder reduction to upper Hessenberg form of C(w_A), one workgroup per
-// (block, k_A); element (i, j) in thread (i mod TY, j mod 32), register
-// (i / TY, j / 32).  Column k: v = x - alpha e_1 with x = A[k+1:, k],
-// alpha = -(x_1/|x_1|) |x|, beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)); with
-// w = v^H A, y = A v and s = w v, the two-sided reflection is the rank-2
-// update A <- A - beta v w - beta (y - beta s v) v^H, so both sums come
-// from one pass over A.  Also writes sum_i Log(1 - w_A lambda_i) of the
-// eliminated bin.
+// (block, k_A).  Step k reflects column k: with v the Householder vector,
+// beta = 2 / |v|^2, w = v^H A, y = A v and s = w v, the two-sided
+// reflection is the rank-2 update A <- A - beta v w - beta (y - beta s v) v^H,
+// so both sums come from one pass over A.  Every element a thread holds goes
+// through the same straight-line code (v is zero outside rows k+1..n-1, in
+// LDS, padding included); only whole register rows and columns that carry no
+// terms are left out (hess_step).  Entries below the subdiagonal are written
+// as zero.  Also writes sum_i Log(1 - w_A lambda_i) of the eliminated bin.
 template <int TY, int R, int SC>
 __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__restrict__ jobs,
                                                                  const int64_t *__restrict__ prefix, int njobs,
@@ -994,9 +1180,10 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
                                                                  double2 *__restrict__ eigc)
 {
     using Lds = HessLds<TY, R, SC>;
-    constexpr int NMAX = Lds::NMAX;
+    constexpr int NMAX = Lds::NMAX, RMAX = Lds::RMAX, CMAX = Lds::CMAX, XMAX = Lds::XMAX;
     constexpr int NT = Lds::NT;
-    static_assert(NT >= 512 ? 256 + NMAX <= NT - 64 : NMAX <= NT - 64, "reduction threads overlap the last wave");
+    static_assert(NT >= 512, "reductions assume 512 threads or more");
+    static_assert(CMAX <= 256 && 256 + RMAX <= NT - 64, "reduction threads overlap");
     extern __shared__ __align__(16) unsigned char hess_raw[];
     Lds &L = *reinterpret_cast<Lds *>(hess_raw);
     const int job = find_job(prefix, njobs, blockIdx.x);
@@ -1005,6 +1192,9 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
     const int n = J.n;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     double2 *__restrict__ C = pool + J.c_off + (int64_t)kA * n * n;
+
+    // v is read at every index < XMAX; indices >= RMAX are never written
+    for (int e = tid; e < 2 * XMAX; e += NT) (&L.x[0][0])[e] = cmk(0.0, 0.0);
 
     // The matrix moves between HBM and registers through LDS (the row-sum
     // partial buffer), CR register rows (CR TY matrix rows, contiguous in C)
@@ -1031,152 +1221,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
         __syncthreads();
     }
 
-    for (int k = 0; k + 2 < n; ++k) {
-        const int par = k & 1;
-        const int sk = k >> 5;
-        // A. column k below the diagonal and its partial squared norms
-        if (tx == (k & 31)) {
-            double acc = 0.0;
-            #pragma unroll
-            for (int s = 0; s < SC; ++s) {
-                if (s != sk) continue;
-                #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int i = ty + TY * r;
-                    if (i > k && i < n) {
-                        L.x[par][i] = a[r][s];
-                        acc += a[r][s].x * a[r][s].x + a[r][s].y * a[r][s].y;
-                    }
-                }
-            }
-            L.nrm[par][ty] = acc;
-        }
-        __syncthreads();
-        // B. reflector, partial sums of w, y and s.  Only columns j > k and,
-        // for w, rows i > k carry nonzero terms (v vanishes elsewhere).
-        double xn2 = 0.0;
-        #pragma unroll
-        for (int t = 0; t < TY; ++t) xn2 += L.nrm[par][t];
-        const double xn = sqrt(xn2);
-        const double2 x1 = L.x[par][k + 1];
-        const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
-        const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
-        const double2 v1 = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));  // x_1 - alpha
-        const double beta = xn > 0.0 ? 1.0 / (xn * (xn + ax1)) : 0.0;
-        // v_i: an LDS load at a clamped index, then value selects (a select
-        // between a pointer to v1 and one into LDS would put v1 in scratch)
-        auto vget = [&](int i) -> double2 {
-            const int ic = (i > k + 1 && i < n) ? i : k + 1;
-            const double2 xl = L.x[par][ic];
-            const bool one = i == k + 1, in = i > k + 1 && i < n;
-            return cmk(one ? v1.x : (in ? xl.x : 0.0), one ? v1.y : (in ? xl.y : 0.0));
-        };
-        double2 pw[SC];
-        #pragma unroll
-        for (int s = 0; s < SC; ++s) pw[s] = cmk(0.0, 0.0);
-        double2 ps = cmk(0.0, 0.0);
-        #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = ty + TY * r;
-            if (i >= n) continue;
-            const double2 vi = vget(i);
-            double2 py = cmk(0.0, 0.0);
-            #pragma unroll
-            for (int s = 0; s < SC; ++s) {
-                const int j = tx + 32 * s;
-                if (j <= k || j >= n) continue;
-                const double2 d = cmul(a[r][s], vget(j));
-                py.x += d.x;
-                py.y += d.y;
-                if (i > k) {
-                    const double2 c = cconjmul(vi, a[r][s]);
-                    pw[s].x += c.x;
-                    pw[s].y += c.y;
-                }
-            }
-            L.PY[tx][i] = py;
-            const double2 e = cconjmul(vi, py);
-            ps.x += e.x;
-            ps.y += e.y;
-        }
-        #pragma unroll
-        for (int s = 0; s < SC; ++s) {
-            const int j = tx + 32 * s;
-            if (j < n) L.PW[ty][j] = pw[s];
-        }
-        L.PS[tid] = ps;
-        __syncthreads();
-        // C. reductions, each in a fixed order
-        if (tid < n) {
-            double2 t = cmk(0.0, 0.0);
-            #pragma unroll
-            for (int q = 0; q < TY; ++q) {
-                t.x += L.PW[q][tid].x;
-                t.y += L.PW[q][tid].y;
-            }
-            L.W[tid] = t;
-        }
-        // y: threads 256.. when there are enough, else the same threads as w
-        if (NT >= 512 ? (tid >= 256 && tid - 256 < n) : tid < n) {
-            const int i = NT >= 512 ? tid - 256 : tid;
-            double2 t = cmk(0.0, 0.0);
-            #pragma unroll 8
-            for (int q = 0; q < 32; ++q) {
-                t.x += L.PY[q][i].x;
-                t.y += L.PY[q][i].y;
-            }
-            L.Y[i] = t;
-        }
-        if (tid >= NT - 64) {
-            const int lane = tid & 63;
-            double2 t = cmk(0.0, 0.0);
-            #pragma unroll
-            for (int q = 0; q < NT / 64; ++q) {
-                t.x += L.PS[lane + 64 * q].x;
-                t.y += L.PS[lane + 64 * q].y;
-            }
-            #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                t.x += __shfl_xor(t.x, off, 64);
-                t.y += __shfl_xor(t.y, off, 64);
-            }
-            if (lane == 0) L.S = t;
-        }
-        __syncthreads();
-        // D. A <- A - beta v w - beta z v^H, z = y - beta s v, on columns j > k
-        const double2 sv = L.S;
-        #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = ty + TY * r;
-            if (i >= n) continue;
-            const double2 vi = vget(i);
-            const double2 yi = L.Y[i];
-            const double2 bsv = cmul(cmk(beta * sv.x, beta * sv.y), vi);
-            const double2 zi = cmk(beta * (yi.x - bsv.x), beta * (yi.y - bsv.y));  // beta z_i
-            const double2 bvi = cmk(beta * vi.x, beta * vi.y);
-            #pragma unroll
-            for (int s = 0; s < SC; ++s) {
-                const int j = tx + 32 * s;
-                if (j <= k || j >= n) continue;
-                const double2 vj = vget(j);
-                double2 t = cfnms(a[r][s], zi, cmk(vj.x, -vj.y));
-                if (i > k) t = cfnms(t, bvi, L.W[j]);
-                a[r][s] = t;
-            }
-        }
-        if (tx == (k & 31)) {
-            #pragma unroll
-            for (int s = 0; s < SC; ++s) {
-                if (s != sk) continue;
-                #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int i = ty + TY * r;
-                    if (i == k + 1) a[r][s] = cmk(-ph.x * xn, -ph.y * xn);  // alpha
-                    else if (i > k + 1) a[r][s] = cmk(0.0, 0.0);
-                }
-            }
-        }
-    }
+    hess_steps_from<TY, R, SC, 0>(L, a, n, tid);
 
     __syncthreads();
     #pragma unroll
@@ -1188,7 +1233,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
             #pragma unroll
             for (int s = 0; s < SC; ++s) {
                 const int i = ty + TY * r, j = tx + 32 * s;
-                if (i < n && j < n) stage[(i - i0) * n + j] = a[r][s];
+                if (i < n && j < n) stage[(i - i0) * n + j] = i > j + 1 ? cmk(0.0, 0.0) : a[r][s];
             }
         __syncthreads();
         for (int e = tid; e < rows * n; e += NT) C[(int64_t)i0 * n + e] = stage[e];
@@ -1706,18 +1751,38 @@ __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *
                               const double2 *__restrict__ logg, int2 *const *__restrict__ lists,
                               int *__restrict__ counts, int n_lists)
 {
+    // every lane takes part in the ballots below: no early return
+    const int lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npts) return;
-    const int i = find_job(inst_pt_prefix, n_inst, p);
-    const InstDev &I = insts[i];
-    if (!(logg[p].x > log(I.theta))) return;
-    const int64_t lp = p - I.pt_off;
-    for (int b = 0; b < I.nblocks; ++b) {
-        const int bi = I.first_block + b;
-        const int cls = blocks[bi].cls;
-        if (!blocks[bi].fp32 || cls < 0 || cls >= n_lists || !lists[cls]) continue;
-        const int slot = atomicAdd(&counts[cls], 1);
-        lists[cls][slot] = make_int2(bi, (int)lp);
+    int nb = 0, first = 0;
+    int64_t lp = 0;
+    if (p < npts) {
+        const int i = find_job(inst_pt_prefix, n_inst, p);
+        const InstDev &I = insts[i];
+        if (logg[p].x > log(I.theta)) {
+            nb = I.nblocks;
+            first = I.first_block;
+            lp = p - I.pt_off;
+        }
+    }
+    for (int b = 0; __any(b < nb); ++b) {
+        int cls = -1;
+        if (b < nb) {
+            const BlockDev &B = blocks[first + b];
+            if (B.fp32 && B.cls >= 0 && B.cls < n_lists && lists[B.cls]) cls = B.cls;
+        }
+        // one atomic per wave and list: lanes of the same list share it
+        unsigned long long pending = __ballot(cls >= 0);
+        while (pending) {
+            const int leader = __ffsll(pending) - 1;
+            const int c = __shfl(cls, leader);
+            const unsigned long long grp = __ballot(cls == c);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&counts[c], __popcll(grp));
+            base = __shfl(base, leader);
+            if (cls == c) lists[c][base + __popcll(grp & ((1ull << lane) - 1))] = make_int2(first + b, (int)lp);
+            pending &= ~grp;
+        }
     }
 }
 
@@ -1981,7 +2046,7 @@ hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefi
     switch (cls) {
         case 0: return launch_hr<16, 2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
         case 1: return launch_hr<16, 4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 2: return launch_hr<8, 18, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 2: return launch_hr<16, 9, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2018,8 +2083,8 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 2, 1>)),
                          hipFuncSetAttribute((const void *)hess_reduce_f64<16, 4, 2>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 4, 2>)),
-                         hipFuncSetAttribute((const void *)hess_reduce_f64<8, 18, 5>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<8, 18, 5>))})
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 9, 5>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 9, 5>))})
         if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<4, 2, 2>(), prepare_mfma<6, 2, 4>(),
                          prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(), prepare_mfma<12, 2, 4>()})

@@ -121,3 +121,16 @@ def test_agrees_with_full_route_on_mesh_batch(precision):
     b = gpu_dists(insts, 0, precision="fp64")
     for x, y in zip(a, b):
         assert np.abs(x - y).max() <= TOL
+
+
+def test_route_is_chosen_by_estimated_time():
+    # two bins of 72 modes, 121 x 121 grid: one reduction per w_A replaces 121
+    # factorisations of order 144, so the library takes the Hessenberg route;
+    # the mesh batch (order-32 blocks, 13 values of w_B per w_A) stays on the
+    # factorisation per point; either flag forces the choice
+    _say("automatic route choice")
+    gbs, mesh = [W.gbs_m144(2)], W.mesh_batch(64)
+    assert _route_taken(gbs, 0)
+    assert not _route_taken(gbs, cgd.FLAG_NO_HESSENBERG)
+    assert not _route_taken(mesh, 0)
+    assert _route_taken(mesh, H)

@@ -17,7 +17,9 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _run(instances, precision, tol=TOL, flags=0):
+def _run(instances, precision, tol=TOL, flags=cgd.FLAG_NO_HESSENBERG):
+    # the FP32 path is what is tested here: the Hessenberg route (FP64 in both
+    # precisions) is switched off unless a test asks for it
     import torch
     with cgd.Context(instances, precision=precision, tol=tol, flags=flags) as ctx:
         err = torch.full((ctx.n_inst,), -1.0, dtype=torch.float64, device="cuda")
@@ -74,7 +76,20 @@ def test_mixed_order_192_class_and_elimination_off():
     # the dense no-Schur lossy instance (order 97) the order-128 class
     _say("mixed gbs144_3bins / no-Schur lossy16_k3")
     for insts, flags in (([W.gbs_m144(3)], 0), ([W.lossy_m16_k3()], cgd.FLAG_NO_SCHUR | cgd.FLAG_DENSE_INTERNAL)):
+        flags |= cgd.FLAG_NO_HESSENBERG
         p64, _, _, offs = _run(insts, "fp64", flags=flags)
         pm, errm, _, _ = _run(insts, "mixed", flags=flags)
         assert np.abs(pm - p64).max() <= TOL
         assert np.all(errm <= TOL)
+
+
+def test_mixed_with_hessenberg_route_matches_fp64():
+    # the two-bin GBS instance takes the Hessenberg route by itself (FP64 in
+    # both precisions): no FP32 factorisation, a zero bound, and the FP64 values
+    _say("mixed, automatic route: gbs144_2bins")
+    insts = [W.gbs_m144(2)]
+    p64, _, _, _ = _run(insts, "fp64", flags=0)
+    pm, errm, (nfix, ntot), _ = _run(insts, "mixed", flags=0)
+    assert nfix == 0 and ntot == 0
+    assert np.all(errm == 0.0)
+    assert np.abs(pm - p64).max() <= 1e-14

@@ -202,7 +202,7 @@ def test_uneven_batch_sampled_points():
     assert off == len(logg)
 
 
-@pytest.mark.parametrize("bins, flags", [(2, 0), (3, 0), (2, cgd.FLAG_NO_SCHUR)])
+@pytest.mark.parametrize("bins, flags", [(2, 0), (2, cgd.FLAG_NO_HESSENBERG), (3, 0), (2, cgd.FLAG_NO_SCHUR)])
 def test_gbs_m144_sampled_points_and_sums(bins, flags):
     _say("gbs m144,", bins, "bins, flags", flags)
     inst = W.gbs_m144(bins)
