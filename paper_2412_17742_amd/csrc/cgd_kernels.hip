@@ -1267,6 +1267,7 @@ __device__ __forceinline__ double dpp_bcast64(double x) {  // lane K of each 16-
 template <int MB>
 struct HessDetState {
     const double2 *__restrict__ Hh;
+    const double2 *blk;         // LDS: rows 16 m + 1 .. 16 m + 16, columns 16 m .. (stride 16 MB)
     int n, e, m;                // order, lane within the point's 16 lanes, current block
     double2 w;                  // w_B
     double2 u[MB];              // row k of U: u_j in slot j / 16 of lane j % 16
@@ -1280,6 +1281,11 @@ struct HessDetState {
         const bool in = row < n && j < n;
         const double2 h = Hh[in ? (int64_t)row * n + j : 0];
         return in ? h : cmk(0.0, 0.0);
+    }
+    // Hh[16 m + E0 + 1][e + 16 q] from the staged block (zero outside the matrix)
+    template <int E0>
+    __device__ __forceinline__ double2 hblk(int q) const {
+        return blk[E0 * 16 * MB + e + 16 * (q - m)];
     }
     __device__ __forceinline__ double2 mrow(int row, int j, double2 h) const {  // (I - w Hh)[row][j]
         const double2 t = cmul(w, h);
@@ -1308,7 +1314,7 @@ struct HessDetState {
         const int k = 16 * m + E0;
         if (k >= n - 1) return;
         const double2 piv = cmk(dpp_bcast64<E0>(cur.x), dpp_bcast64<E0>(cur.y));
-        const double2 hm = hload(k + 1, e + 16 * m);
+        const double2 hm = hblk<E0>(m);
         const double2 hsub = cmk(dpp_bcast64<E0>(hm.x), dpp_bcast64<E0>(hm.y));  // Hh[k+1][k]
         const double2 t = cmul(w, hsub);
         const double2 l = cmul(cmk(-t.x, -t.y), cinv(piv));
@@ -1317,7 +1323,7 @@ struct HessDetState {
         for (int q = 0; q < MB; ++q) {
             if (q <= m || 16 * q >= n) continue;
             const int j = e + 16 * q;
-            u[q] = cfnms(mrow(k + 1, j, hload(k + 1, j)), l, u[q]);
+            u[q] = cfnms(mrow(k + 1, j, hblk<E0>(q)), l, u[q]);
         }
         take(piv);
     }
@@ -1331,9 +1337,12 @@ struct HessDetState {
 // Row k+1 of U is M[k+1, :] - (M[k+1][k] / u_k) u with u = row k of U, so
 // only one row of U is live.  16 lanes per point (4 points per wave), lane e
 // holding u_j for j = e + 16 m; the slot of the current block of 16 steps is
-// kept in `cur` so that every register index is static.  The logarithms of
-// the pivots are taken two at a time: both lie in the right half-plane, so
-// the principal logarithm of their product is the sum of theirs.  Writes
+// kept in `cur` so that every register index is static.  The 16 points of a
+// workgroup share one C(w_A): the 16 rows a block of steps reads are staged
+// in LDS (two buffers; the next block is loaded into registers while the
+// current one runs).  The logarithms of the pivots are taken two at a time:
+// both lie in the right half-plane, so the principal logarithm of their
+// product is the sum of theirs.  Writes
 // -1/2 (sum Log pivots + sum_i Log(1 - w_A lambda_i)) per (k_A, k_B).
 template <int MB>
 __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *__restrict__ jobs,
@@ -1342,6 +1351,8 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
                                                                 const double2 *__restrict__ eigc,
                                                                 double2 *__restrict__ table)
 {
+    static_assert(kHessDetThreads == 256, "staging maps 16 rows x 16 lanes");
+    extern __shared__ __align__(16) double2 hd_lds[];  // [2][16][16 MB]
     const int job = find_job(prefix, njobs, blockIdx.x);
     const HessDev J = jobs[job];
     const int64_t local = blockIdx.x - prefix[job];
@@ -1351,10 +1362,11 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     const int g = lane >> 4;
     const int kB = chunk * 16 + wave * 4 + g;
     const bool valid = kB < J.dB;
+    const int n = J.n;
 
     HessDetState<MB> S;
-    S.Hh = pool + J.c_off + (int64_t)kA * J.n * J.n;
-    S.n = J.n;
+    S.Hh = pool + J.c_off + (int64_t)kA * n * n;
+    S.n = n;
     S.e = lane & 15;
     double sn, cs;
     sincospi(2.0 * (double)(valid ? kB : 0) / (double)J.GB, &sn, &cs);
@@ -1362,7 +1374,7 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     #pragma unroll
     for (int q = 0; q < MB; ++q) {
         const int j = S.e + 16 * q;
-        S.u[q] = j < S.n ? S.mrow(0, j, S.hload(0, j)) : cmk(0.0, 0.0);
+        S.u[q] = j < n ? S.mrow(0, j, S.hload(0, j)) : cmk(0.0, 0.0);
     }
     S.argsum = S.logsum = 0.0;
     S.magacc = 1.0;
@@ -1370,15 +1382,44 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     S.pend = cmk(1.0, 0.0);
     S.haspend = false;
     S.cur = S.u[0];
-    for (S.m = 0; S.m < MB && 16 * S.m < S.n - 1; ++S.m) {
+
+    // staging: thread (E, c0) = (tid / 16, tid % 16) carries row 16 m + 1 + E,
+    // columns 16 m + c0 + 16 i, i < MB - m; zero outside the matrix
+    const int E = tid >> 4, c0 = tid & 15;
+    double2 pf[MB];
+    auto fetch = [&](int m) {
+        const int row = 16 * m + 1 + E;
+        #pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int col = 16 * m + c0 + 16 * i;
+            const bool in = i < MB - m && row < n && col < n;
+            const double2 h = S.Hh[in ? (int64_t)row * n + col : 0];
+            pf[i] = in ? h : cmk(0.0, 0.0);
+        }
+    };
+    auto stage = [&](int buf, int m) {
+        #pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (i < MB - m) hd_lds[(buf * 16 + E) * 16 * MB + c0 + 16 * i] = pf[i];
+    };
+    const int nblk = (n - 1 + 15) >> 4;  // blocks of steps k = 0 .. n - 2
+    fetch(0);
+    stage(0, 0);
+    __syncthreads();
+    for (int m = 0; m < nblk; ++m) {
+        if (m + 1 < nblk) fetch(m + 1);
+        S.m = m;
+        S.blk = hd_lds + (m & 1) * 16 * 16 * MB;
         S.cur = S.u[0];
         #pragma unroll
         for (int q = 1; q < MB; ++q)
-            if (q == S.m) S.cur = S.u[q];
+            if (q == m) S.cur = S.u[q];
         S.block(std::make_integer_sequence<int, 16>{});
+        if (m + 1 < nblk) stage((m + 1) & 1, m + 1);
+        __syncthreads();
     }
     // last pivot u_{n-1}: in `cur` if step n-2 ran in its block, else in its slot
-    const int ml = (S.n - 1) >> 4, el = (S.n - 1) & 15;
+    const int ml = (n - 1) >> 4, el = (n - 1) & 15;
     double2 last = S.cur;
     if (el == 0) {
         last = S.u[0];
@@ -2051,11 +2092,13 @@ hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefi
     }
 }
 
+static constexpr int hess_det_lds_bytes(int MB) { return 2 * 16 * 16 * MB * (int)sizeof(double2); }
+
 template <int MB>
 static hipError_t launch_hd(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, const double2 *pool,
                             const double2 *eigc, double2 *table, hipStream_t st) {
-    hipLaunchKernelGGL((hess_det_f64<MB>), dim3((unsigned)nwg), dim3(kHessDetThreads), 0, st, jobs, prefix, njobs,
-                       pool, eigc, table);
+    hipLaunchKernelGGL((hess_det_f64<MB>), dim3((unsigned)nwg), dim3(kHessDetThreads), hess_det_lds_bytes(MB), st,
+                       jobs, prefix, njobs, pool, eigc, table);
     return hipGetLastError();
 }
 
@@ -2084,7 +2127,9 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
                          hipFuncSetAttribute((const void *)hess_reduce_f64<16, 4, 2>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 4, 2>)),
                          hipFuncSetAttribute((const void *)hess_reduce_f64<16, 9, 5>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 9, 5>))})
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 9, 5>)),
+                         hipFuncSetAttribute((const void *)hess_det_f64<9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             hess_det_lds_bytes(9))})
         if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<4, 2, 2>(), prepare_mfma<6, 2, 4>(),
                          prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(), prepare_mfma<12, 2, 4>()})
