@@ -1001,30 +1001,29 @@ template <int TY, int R, int SC, int S>
 __device__ __forceinline__ double hess_put_x(HessLds<TY, R, SC> &L, const double2 (&a)[R][SC], int k, int n,
                                              int par, int ty) {
     double acc = 0.0;
+    double2 *xr = &L.x[par][ty];
     #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = ty + TY * r;
         const bool in = i > k && i < n;
         const double2 xi = cmk(in ? a[r][S].x : 0.0, in ? a[r][S].y : 0.0);
-        L.x[par][i] = xi;
+        xr[TY * r] = xi;
         if (i == k + 1) L.x1[par] = xi;
         acc = fma(xi.x, xi.x, fma(xi.y, xi.y, acc));
     }
     return acc;
 }
 
-// One Householder step k (column k) of hess_reduce_f64, R0 = k / TY.
-// Register rows r < R0 hold only rows < k, where v vanishes; register
-// columns s < S0 = k / 32 hold only columns < k, where v vanishes, so their
+// One Householder step k (column k) of hess_reduce_f64, R0 = k / TY and
+// S0 = k / 32.  Register rows r < R0 hold only rows < k, where v vanishes;
+// register columns s < S0 hold only columns < k, where v vanishes, so their
 // entries on or above the subdiagonal (rows i <= j + 1 <= k) do not change.  The
 // terms they would carry are left out at compile time.  Column k becomes
 // (alpha, O(eps |x|), ...) below the diagonal; what is left below the
 // subdiagonal never reaches the Hessenberg part (v vanishes on those rows and
 // columns in every later step) and is written out as zero.
-template <int TY, int R, int SC, int R0>
+template <int TY, int R, int SC, int R0, int S0>
 __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int k, int n, int tid) {
-    static_assert(32 % TY == 0 || TY % 32 == 0, "row and column blocks must nest");
-    constexpr int S0 = (R0 * TY) / 32;  // = k / 32, the register column of column k
     constexpr int NT = 32 * TY, RMAX = TY * R, CMAX = 32 * SC;
     const int par = k & 1, ty = tid >> 5, tx = tid & 31;
 
@@ -1044,20 +1043,24 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     if (tid == 0) L.x[par][k + 1] = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));
     __syncthreads();
 
+    // per-thread LDS bases; register rows and columns are constant offsets
+    const double2 *xr = &L.x[par][ty], *xc = &L.x[par][tx];
+    double2 *pyr = &L.PY[tx][ty], *pwr = &L.PW[ty][tx];
+    const double2 *yr = &L.Y[ty], *wc = &L.W[tx];
+
     // B. partial sums of y = A v (all rows), w = v^H A and s = v^H y
     double2 ps = cmk(0.0, 0.0);
     {
         double2 vj[SC];
         #pragma unroll
-        for (int s = S0; s < SC; ++s) vj[s] = L.x[par][tx + 32 * s];
+        for (int s = S0; s < SC; ++s) vj[s] = xc[32 * s];
         #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int i = ty + TY * r;
             double2 py = cmk(0.0, 0.0);
             #pragma unroll
             for (int s = S0; s < SC; ++s) py = cfma(a[r][s], vj[s], py);
-            L.PY[tx][i] = py;
-            if (r >= R0) ps = cfma_conj(L.x[par][i], py, ps);
+            pyr[TY * r] = py;
+            if (r >= R0) ps = cfma_conj(xr[TY * r], py, ps);
         }
     }
     {
@@ -1066,12 +1069,12 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
         for (int s = S0; s < SC; ++s) pw[s] = cmk(0.0, 0.0);
         #pragma unroll
         for (int r = R0; r < R; ++r) {
-            const double2 vi = L.x[par][ty + TY * r];
+            const double2 vi = xr[TY * r];
             #pragma unroll
             for (int s = S0; s < SC; ++s) pw[s] = cfma_conj(vi, a[r][s], pw[s]);
         }
         #pragma unroll
-        for (int s = S0; s < SC; ++s) L.PW[ty][tx + 32 * s] = pw[s];
+        for (int s = S0; s < SC; ++s) pwr[32 * s] = pw[s];
     }
     L.PS[tid] = ps;
     __syncthreads();
@@ -1079,21 +1082,23 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     // C. reductions, each in a fixed order: w by threads 0.., y by threads
     // 256.., s by the last wave
     if (tid >= 32 * S0 && tid < CMAX) {
+        const double2 *col = &L.PW[0][tid];
         double2 t = cmk(0.0, 0.0);
         #pragma unroll
         for (int q = 0; q < TY; ++q) {
-            t.x += L.PW[q][tid].x;
-            t.y += L.PW[q][tid].y;
+            t.x += col[q * CMAX].x;
+            t.y += col[q * CMAX].y;
         }
         L.W[tid] = t;
     }
     if (tid >= 256 && tid - 256 < RMAX) {
         const int i = tid - 256;
+        const double2 *col = &L.PY[0][i];
         double2 t = cmk(0.0, 0.0);
-        #pragma unroll 8
+        #pragma unroll
         for (int q = 0; q < 32; ++q) {
-            t.x += L.PY[q][i].x;
-            t.y += L.PY[q][i].y;
+            t.x += col[q * HessLds<TY, R, SC>::PYS].x;
+            t.y += col[q * HessLds<TY, R, SC>::PYS].y;
         }
         L.Y[i] = t;
     }
@@ -1122,16 +1127,15 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
         double2 cvj[SC];
         #pragma unroll
         for (int s = S0; s < SC; ++s) {
-            const double2 v = L.x[par][tx + 32 * s];
+            const double2 v = xc[32 * s];
             cvj[s] = cmk(v.x, -v.y);
         }
         #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int i = ty + TY * r;
-            const double2 yi = L.Y[i];
+            const double2 yi = yr[TY * r];
             double2 zi;  // beta z_i
             if (r >= R0) {
-                const double2 bsv = cmul(bs, L.x[par][i]);
+                const double2 bsv = cmul(bs, xr[TY * r]);
                 zi = cmk(beta * (yi.x - bsv.x), beta * (yi.y - bsv.y));
             } else {
                 zi = cmk(beta * yi.x, beta * yi.y);
@@ -1143,10 +1147,10 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     {
         double2 wj[SC];
         #pragma unroll
-        for (int s = S0; s < SC; ++s) wj[s] = L.W[tx + 32 * s];
+        for (int s = S0; s < SC; ++s) wj[s] = wc[32 * s];
         #pragma unroll
         for (int r = R0; r < R; ++r) {
-            const double2 vi = L.x[par][ty + TY * r];
+            const double2 vi = xr[TY * r];
             const double2 bvi = cmk(beta * vi.x, beta * vi.y);
             #pragma unroll
             for (int s = S0; s < SC; ++s) a[r][s] = cfnms(a[r][s], bvi, wj[s]);
@@ -1154,13 +1158,15 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     }
 }
 
-// Steps k with k / TY = R0, then R0 + 1, ..., R - 1: one loop per value, so
-// that each loop body is straight-line code.
-template <int TY, int R, int SC, int R0>
+// Steps k with (k / TY, k / 32) = (R0, S0), then the following values: one
+// loop per pair, so that each loop body is straight-line code.
+template <int TY, int R, int SC, int R0, int S0>
 __device__ __forceinline__ void hess_steps_from(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int n, int tid) {
-    const int k_lo = TY * R0, k_hi = min(TY * (R0 + 1), n - 2);
-    for (int k = k_lo; k < k_hi; ++k) hess_step<TY, R, SC, R0>(L, a, k, n, tid);
-    if constexpr (R0 + 1 < R) hess_steps_from<TY, R, SC, R0 + 1>(L, a, n, tid);
+    constexpr int RE = TY * (R0 + 1), SE = 32 * (S0 + 1);  // where R0, S0 change
+    const int k_lo = max(TY * R0, 32 * S0), k_hi = min(min(RE, SE), n - 2);
+    for (int k = k_lo; k < k_hi; ++k) hess_step<TY, R, SC, R0, S0>(L, a, k, n, tid);
+    constexpr int R1 = R0 + (RE <= SE ? 1 : 0), S1 = S0 + (SE <= RE ? 1 : 0);
+    if constexpr (R1 < R && S1 < SC) hess_steps_from<TY, R, SC, R1, S1>(L, a, n, tid);
 }
 
 // Householder reduction to upper Hessenberg form of C(w_A), one workgroup per
@@ -1221,7 +1227,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
         __syncthreads();
     }
 
-    hess_steps_from<TY, R, SC, 0>(L, a, n, tid);
+    hess_steps_from<TY, R, SC, 0, 0>(L, a, n, tid);
 
     __syncthreads();
     #pragma unroll
