@@ -1083,24 +1083,29 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     // 256.., s by the last wave
     if (tid >= 32 * S0 && tid < CMAX) {
         const double2 *col = &L.PW[0][tid];
-        double2 t = cmk(0.0, 0.0);
+        double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);  // two chains, fixed order
         #pragma unroll
-        for (int q = 0; q < TY; ++q) {
-            t.x += col[q * CMAX].x;
-            t.y += col[q * CMAX].y;
+        for (int q = 0; q < TY; q += 2) {
+            t0.x += col[q * CMAX].x;
+            t0.y += col[q * CMAX].y;
+            t1.x += col[(q + 1) * CMAX].x;
+            t1.y += col[(q + 1) * CMAX].y;
         }
-        L.W[tid] = t;
+        L.W[tid] = cmk(t0.x + t1.x, t0.y + t1.y);
     }
     if (tid >= 256 && tid - 256 < RMAX) {
         const int i = tid - 256;
         const double2 *col = &L.PY[0][i];
-        double2 t = cmk(0.0, 0.0);
+        constexpr int PYS = HessLds<TY, R, SC>::PYS;
+        double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
         #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            t.x += col[q * HessLds<TY, R, SC>::PYS].x;
-            t.y += col[q * HessLds<TY, R, SC>::PYS].y;
+        for (int q = 0; q < 32; q += 2) {
+            t0.x += col[q * PYS].x;
+            t0.y += col[q * PYS].y;
+            t1.x += col[(q + 1) * PYS].x;
+            t1.y += col[(q + 1) * PYS].y;
         }
-        L.Y[i] = t;
+        L.Y[i] = cmk(t0.x + t1.x, t0.y + t1.y);
     }
     if (tid >= NT - 64) {
         const int lane = tid & 63;
@@ -1269,6 +1274,18 @@ __device__ __forceinline__ double dpp_bcast64(double x) {  // lane K of each 16-
     return __builtin_bit_cast(double, v);
 }
 
+// Argument of x + iy to within 0.004 rad: atan(t) ~ t (pi/4 + 0.273 (1 - t))
+// on [0, 1], folded into the other octants.
+__device__ __forceinline__ float rough_arg(float x, float y) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    float r = t * fmaf(0.273f, 1.0f - t, 0.78539816f);
+    if (ay > ax) r = 1.57079633f - r;
+    if (x < 0.0f) r = 3.14159265f - r;
+    return y < 0.0f ? -r : r;
+}
+
 // Per-point state of the Hessenberg factorisation (see hess_det_f64).
 template <int MB>
 struct HessDetState {
@@ -1278,10 +1295,10 @@ struct HessDetState {
     double2 w;                  // w_B
     double2 u[MB];              // row k of U: u_j in slot j / 16 of lane j % 16
     double2 cur;                // slot m of u while block m runs
-    double argsum, logsum, magacc;
-    int npair;
-    double2 pend;
-    bool haspend;
+    double argsum, logsum;      // sum of Log(pivot) over the closed groups
+    double2 prod;               // product of the pivots of the open group
+    float aest;                 // rough sum of their arguments
+    int ngrp;                   // pivots in the open group
 
     __device__ __forceinline__ double2 hload(int row, int j) const {
         const bool in = row < n && j < n;
@@ -1297,22 +1314,23 @@ struct HessDetState {
         const double2 t = cmul(w, h);
         return cmk((row == j ? 1.0 : 0.0) - t.x, -t.y);
     }
-    // one pivot; pivots are taken two at a time (see hess_det_f64)
+    // Pivots are taken in groups of 16: the sum of their principal
+    // arguments is the argument of their product up to a multiple of 2 pi,
+    // which a rough running sum of the arguments (error < 0.004 rad each)
+    // fixes.  One exact atan2 and one log per group.
+    __device__ __forceinline__ void flush() {
+        const double th = atan2(prod.y, prod.x);
+        const double turns = rint(((double)aest - th) * 0.15915494309189535);  // 1 / (2 pi)
+        argsum += fma(turns, 6.283185307179586, th);
+        logsum += 0.5 * log(prod.x * prod.x + prod.y * prod.y);
+        prod = cmk(1.0, 0.0);
+        aest = 0.0f;
+        ngrp = 0;
+    }
     __device__ __forceinline__ void take(double2 p) {
-        if (!haspend) {
-            pend = p;
-            haspend = true;
-            return;
-        }
-        const double2 q = cmul(pend, p);
-        argsum += atan2(q.y, q.x);
-        magacc *= q.x * q.x + q.y * q.y;
-        haspend = false;
-        if (++npair == 8) {
-            logsum += 0.5 * log(magacc);
-            magacc = 1.0;
-            npair = 0;
-        }
+        prod = cmul(prod, p);
+        aest += rough_arg((float)p.x, (float)p.y);
+        if (++ngrp == 16) flush();
     }
     // step k = 16 m + E0: pivot u_k, multiplier M[k+1][k] / u_k, row k+1 of U
     template <int E0>
@@ -1346,9 +1364,8 @@ struct HessDetState {
 // kept in `cur` so that every register index is static.  The 16 points of a
 // workgroup share one C(w_A): the 16 rows a block of steps reads are staged
 // in LDS (two buffers; the next block is loaded into registers while the
-// current one runs).  The logarithms of the pivots are taken two at a time:
-// both lie in the right half-plane, so the principal logarithm of their
-// product is the sum of theirs.  Writes
+// current one runs).  The principal logarithms of the pivots are summed per
+// group of 16 (HessDetState::flush).  Writes
 // -1/2 (sum Log pivots + sum_i Log(1 - w_A lambda_i)) per (k_A, k_B).
 template <int MB>
 __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *__restrict__ jobs,
@@ -1383,10 +1400,9 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
         S.u[q] = j < n ? S.mrow(0, j, S.hload(0, j)) : cmk(0.0, 0.0);
     }
     S.argsum = S.logsum = 0.0;
-    S.magacc = 1.0;
-    S.npair = 0;
-    S.pend = cmk(1.0, 0.0);
-    S.haspend = false;
+    S.prod = cmk(1.0, 0.0);
+    S.aest = 0.0f;
+    S.ngrp = 0;
     S.cur = S.u[0];
 
     // staging: thread (E, c0) = (tid / 16, tid % 16) carries row 16 m + 1 + E,
@@ -1436,11 +1452,7 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     last.x = __shfl(last.x, g * 16 + el, 64);
     last.y = __shfl(last.y, g * 16 + el, 64);
     S.take(last);
-    if (S.haspend) {
-        S.argsum += atan2(S.pend.y, S.pend.x);
-        S.magacc *= S.pend.x * S.pend.x + S.pend.y * S.pend.y;
-    }
-    S.logsum += 0.5 * log(S.magacc);
+    if (S.ngrp > 0) S.flush();
     if (valid && S.e == 0) {
         const double2 ec = eigc[J.ec_off + kA];
         table[J.t_off + (int64_t)kA * J.dB + kB] = cmk(-0.5 * (S.logsum + ec.x), -0.5 * (S.argsum + ec.y));
