@@ -1290,11 +1290,10 @@ __device__ __forceinline__ float rough_arg(float x, float y) {
 template <int MB>
 struct HessDetState {
     const double2 *__restrict__ Hh;
-    const double2 *blk;         // LDS: rows 16 m + 1 .. 16 m + 16, columns 16 m .. (stride 16 MB)
-    int n, e, m;                // order, lane within the point's 16 lanes, current block
+    const double2 *blk;         // LDS: rows 16 M + 1 .. 16 M + 16, columns 16 M .. (stride 16 MB)
+    int n, e;                   // order, lane within the point's 16 lanes
     double2 w;                  // w_B
     double2 u[MB];              // row k of U: u_j in slot j / 16 of lane j % 16
-    double2 cur;                // slot m of u while block m runs
     double argsum, logsum;      // sum of Log(pivot) over the closed groups
     double2 prod;               // product of the pivots of the open group
     float aest;                 // rough sum of their arguments
@@ -1305,10 +1304,11 @@ struct HessDetState {
         const double2 h = Hh[in ? (int64_t)row * n + j : 0];
         return in ? h : cmk(0.0, 0.0);
     }
-    // Hh[16 m + E0 + 1][e + 16 q] from the staged block (zero outside the matrix)
-    template <int E0>
+    // Hh[16 M + E0 + 1][e + 16 q] from the staged block of block M (zero
+    // outside the matrix)
+    template <int M, int E0>
     __device__ __forceinline__ double2 hblk(int q) const {
-        return blk[E0 * 16 * MB + e + 16 * (q - m)];
+        return blk[E0 * 16 * MB + e + 16 * (q - M)];
     }
     __device__ __forceinline__ double2 mrow(int row, int j, double2 h) const {  // (I - w Hh)[row][j]
         const double2 t = cmul(w, h);
@@ -1332,36 +1332,77 @@ struct HessDetState {
         aest += rough_arg((float)p.x, (float)p.y);
         if (++ngrp == 16) flush();
     }
-    // step k = 16 m + E0: pivot u_k, multiplier M[k+1][k] / u_k, row k+1 of U
-    template <int E0>
+    // step k = 16 M + E0: pivot u_k, multiplier M[k+1][k] / u_k, row k+1 of U
+    // (slots q < M hold columns < k and are no longer needed)
+    template <int M, int E0>
     __device__ __forceinline__ void step() {
-        const int k = 16 * m + E0;
+        const int k = 16 * M + E0;
         if (k >= n - 1) return;
-        const double2 piv = cmk(dpp_bcast64<E0>(cur.x), dpp_bcast64<E0>(cur.y));
-        const double2 hm = hblk<E0>(m);
+        const double2 piv = cmk(dpp_bcast64<E0>(u[M].x), dpp_bcast64<E0>(u[M].y));
+        const double2 hm = hblk<M, E0>(M);
         const double2 hsub = cmk(dpp_bcast64<E0>(hm.x), dpp_bcast64<E0>(hm.y));  // Hh[k+1][k]
         const double2 t = cmul(w, hsub);
         const double2 l = cmul(cmk(-t.x, -t.y), cinv(piv));
-        cur = cfnms(mrow(k + 1, e + 16 * m, hm), l, cur);
+        u[M] = cfnms(mrow(k + 1, e + 16 * M, hm), l, u[M]);
         #pragma unroll
-        for (int q = 0; q < MB; ++q) {
-            if (q <= m || 16 * q >= n) continue;
+        for (int q = M + 1; q < MB; ++q) {
+            if (16 * q >= n) break;
             const int j = e + 16 * q;
-            u[q] = cfnms(mrow(k + 1, j, hblk<E0>(q)), l, u[q]);
+            u[q] = cfnms(mrow(k + 1, j, hblk<M, E0>(q)), l, u[q]);
         }
         take(piv);
     }
-    template <int... E>
+    template <int M, int... E>
     __device__ __forceinline__ void block(std::integer_sequence<int, E...>) {
-        (step<E>(), ...);
+        (step<M, E>(), ...);
     }
 };
+
+// Staging of block M (rows 16 M + 1 .. 16 M + 16, columns 16 M ..) for the
+// Hessenberg factorisation: thread (E, c0) loads row 16 M + 1 + E, columns
+// 16 M + c0 + 16 i, zero outside the matrix; then writes them to LDS buffer
+// M mod 2 (stride 16 MB).
+template <int MB, int M>
+__device__ __forceinline__ void hess_det_fetch(const double2 *__restrict__ Hh, int n, int E, int c0,
+                                               double2 (&pf)[MB]) {
+    const int row = 16 * M + 1 + E;
+    #pragma unroll
+    for (int i = 0; i < MB - M; ++i) {
+        const int col = 16 * M + c0 + 16 * i;
+        const bool in = row < n && col < n;
+        const double2 h = Hh[in ? (int64_t)row * n + col : 0];
+        pf[i] = in ? h : cmk(0.0, 0.0);
+    }
+}
+template <int MB, int M>
+__device__ __forceinline__ void hess_det_stage(double2 *lds, int E, int c0, const double2 (&pf)[MB]) {
+    #pragma unroll
+    for (int i = 0; i < MB - M; ++i) lds[((M & 1) * 16 + E) * 16 * MB + c0 + 16 * i] = pf[i];
+}
+
+// Blocks M, M + 1, .. of 16 pivot steps (nblk in all): the next block is
+// fetched into registers while this one runs and staged after it.
+template <int MB, int M>
+__device__ __forceinline__ void hess_det_blocks(HessDetState<MB> &S, double2 *lds, double2 (&pf)[MB], int nblk,
+                                                int E, int c0) {
+    if (M >= nblk) return;
+    if constexpr (M + 1 < MB) {
+        if (M + 1 < nblk) hess_det_fetch<MB, M + 1>(S.Hh, S.n, E, c0, pf);
+    }
+    S.blk = lds + (M & 1) * 16 * 16 * MB;
+    S.template block<M>(std::make_integer_sequence<int, 16>{});
+    if constexpr (M + 1 < MB) {
+        if (M + 1 < nblk) hess_det_stage<MB, M + 1>(lds, E, c0, pf);
+    }
+    __syncthreads();
+    if constexpr (M + 1 < MB) hess_det_blocks<MB, M + 1>(S, lds, pf, nblk, E, c0);
+}
 
 // Per point: unpivoted LU of the upper Hessenberg matrix M = I - w_B Hh.
 // Row k+1 of U is M[k+1, :] - (M[k+1][k] / u_k) u with u = row k of U, so
 // only one row of U is live.  16 lanes per point (4 points per wave), lane e
-// holding u_j for j = e + 16 m; the slot of the current block of 16 steps is
-// kept in `cur` so that every register index is static.  The 16 points of a
+// holding u_j for j = e + 16 m; block M of 16 steps is code of its own
+// (hess_det_blocks), so that every register index is static.  The 16 points of a
 // workgroup share one C(w_A): the 16 rows a block of steps reads are staged
 // in LDS (two buffers; the next block is loaded into registers while the
 // current one runs).  The principal logarithms of the pivots are summed per
@@ -1403,52 +1444,21 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     S.prod = cmk(1.0, 0.0);
     S.aest = 0.0f;
     S.ngrp = 0;
-    S.cur = S.u[0];
 
-    // staging: thread (E, c0) = (tid / 16, tid % 16) carries row 16 m + 1 + E,
-    // columns 16 m + c0 + 16 i, i < MB - m; zero outside the matrix
-    const int E = tid >> 4, c0 = tid & 15;
-    double2 pf[MB];
-    auto fetch = [&](int m) {
-        const int row = 16 * m + 1 + E;
-        #pragma unroll
-        for (int i = 0; i < MB; ++i) {
-            const int col = 16 * m + c0 + 16 * i;
-            const bool in = i < MB - m && row < n && col < n;
-            const double2 h = S.Hh[in ? (int64_t)row * n + col : 0];
-            pf[i] = in ? h : cmk(0.0, 0.0);
-        }
-    };
-    auto stage = [&](int buf, int m) {
-        #pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (i < MB - m) hd_lds[(buf * 16 + E) * 16 * MB + c0 + 16 * i] = pf[i];
-    };
+    // block M of 16 steps: rows 16 M + 1 + E of the staged block come from
+    // thread (E, c0) = (tid / 16, tid % 16), columns 16 M + c0 + 16 i
     const int nblk = (n - 1 + 15) >> 4;  // blocks of steps k = 0 .. n - 2
-    fetch(0);
-    stage(0, 0);
+    double2 pf[MB];
+    hess_det_fetch<MB, 0>(S.Hh, n, tid >> 4, tid & 15, pf);
+    hess_det_stage<MB, 0>(hd_lds, tid >> 4, tid & 15, pf);
     __syncthreads();
-    for (int m = 0; m < nblk; ++m) {
-        if (m + 1 < nblk) fetch(m + 1);
-        S.m = m;
-        S.blk = hd_lds + (m & 1) * 16 * 16 * MB;
-        S.cur = S.u[0];
-        #pragma unroll
-        for (int q = 1; q < MB; ++q)
-            if (q == m) S.cur = S.u[q];
-        S.block(std::make_integer_sequence<int, 16>{});
-        if (m + 1 < nblk) stage((m + 1) & 1, m + 1);
-        __syncthreads();
-    }
-    // last pivot u_{n-1}: in `cur` if step n-2 ran in its block, else in its slot
+    hess_det_blocks<MB, 0>(S, hd_lds, pf, nblk, tid >> 4, tid & 15);
+    // last pivot u_{n-1}: slot (n - 1) / 16, lane (n - 1) % 16
     const int ml = (n - 1) >> 4, el = (n - 1) & 15;
-    double2 last = S.cur;
-    if (el == 0) {
-        last = S.u[0];
-        #pragma unroll
-        for (int q = 1; q < MB; ++q)
-            if (q == ml) last = S.u[q];
-    }
+    double2 last = S.u[0];
+    #pragma unroll
+    for (int q = 1; q < MB; ++q)
+        if (q == ml) last = S.u[q];
     last.x = __shfl(last.x, g * 16 + el, 64);
     last.y = __shfl(last.y, g * 16 + el, 64);
     S.take(last);
