@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -414,6 +415,8 @@ struct cgd_ctx {
     int64_t *d_hess_sprefix = nullptr;
     double2 *d_eigc = nullptr, *d_htable = nullptr;
     std::vector<DftStage> stages;
+    std::map<int, int64_t> tw_of;      // grid extent G -> its twiddles in d_tw
+    double2 *d_tw = nullptr;           // exp(-2 pi i m / G), m < G, for every G in use
     std::vector<int64_t> prob_offsets, inst_pt_prefix;
     int64_t nprobs = 0, npts = 0, ngrid = 0, ncontrib = 0;
     // device
@@ -475,6 +478,7 @@ void free_ctx(cgd_ctx *c) {
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
+    fr(c->d_tw);
     for (auto &s : c->adj_stages) { fr(s.d_desc); fr(s.d_prefix); }
     for (auto &h : c->hcls) { fr(h.d_jobs); fr(h.d_rprefix); fr(h.d_dprefix); }
     fr(c->d_hess_all); fr(c->d_hess_sprefix); fr(c->d_eigc); fr(c->d_htable);
@@ -625,6 +629,7 @@ cgd_status build_grad(cgd_ctx *c, int n_inst) {
             d.K = I.N[a] + 1;
             d.Bout = a == 0 ? I.H1 : I.G[a];
             d.G = I.G[a];
+            d.tw_off = c->tw_of.at(d.G);
             d.final_stage = 0;
             d.outer = 1;
             for (int l = 0; l < a; ++l) d.outer *= dims[l];
@@ -1042,9 +1047,24 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         if (big_items > 0) c->big_nwg = (int)std::min<int64_t>(big_items, 1024);
     }
 
-    // DFT stages
+    // DFT stages; twiddles exp(-2 pi i m / G) for every grid extent in use
     int Lmax = 0;
     for (auto &d : c->inst) Lmax = std::max(Lmax, d.L);
+    {
+        std::vector<double2> tw;
+        for (const InstDev &I : c->inst)
+            for (int l = 0; l < I.L; ++l) {
+                const int G = I.G[l];
+                if (c->tw_of.count(G)) continue;
+                c->tw_of[G] = (int64_t)tw.size();
+                for (int m = 0; m < G; ++m) {
+                    const double a = -2.0 * M_PI * (double)m / (double)G;
+                    tw.push_back(make_double2(std::cos(a), std::sin(a)));
+                }
+            }
+        cgd_status s;
+        if ((s = upload(&c->d_tw, tw)) != CGD_OK) return s;
+    }
     c->stages.resize(Lmax);
     for (int s = 0; s < Lmax; ++s) {
         DftStage &st = c->stages[s];
@@ -1060,6 +1080,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             d.K = (int32_t)dims[a];
             d.Bout = I.N[a] + 1;
             d.G = I.G[a];
+            d.tw_off = c->tw_of.at(d.G);
             d.final_stage = a == 0;
             d.outer = 1;
             for (int l = 0; l < a; ++l) d.outer *= dims[l];
@@ -1308,7 +1329,7 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         DftStage &S = c->stages[si];
         const double2 *in = (si % 2 == 0) ? c->d_gA : c->d_gB;
         double2 *out = (si % 2 == 0) ? c->d_gB : c->d_gA;
-        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, d_probs,
+        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, c->d_tw, in, out, d_probs,
                                 mixed ? nullptr : d_err_bound, c->d_status, st));
     }
     HIP_OK(mark(CGD_STAGE_DFT, 1));
@@ -1376,8 +1397,8 @@ cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_
         DftStage &S = c->adj_stages[si];
         const double2 *in = (si % 2 == 0) ? c->d_adjA : c->d_adjB;
         double2 *out = (si % 2 == 0) ? c->d_adjB : c->d_adjA;
-        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, in, out, nullptr, nullptr,
-                                c->d_status, st));
+        HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, c->d_tw, in, out, nullptr,
+                                nullptr, c->d_status, st));
     }
     HIP_OK(launch_adjoint_gather(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_adj_off, c->d_adjA,
                                  c->d_adjB, c->d_ghat, st));

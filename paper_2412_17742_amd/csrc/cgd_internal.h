@@ -112,6 +112,7 @@ struct DftStageDev {
     int32_t inst, K, Bout, G;
     int32_t final_stage, pad;
     int64_t outer, inner, in_off, out_off;
+    int64_t tw_off;           // exp(-2 pi i m / G), m = 0 .. G-1, in the twiddle pool
     double scale;
 };
 
@@ -175,7 +176,7 @@ hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int n
 int schur_rows_per_wg();
 hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
                           const double2 *contrib, double2 *logg, double2 *gval, hipStream_t st);
-hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total,
+hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total, const double2 *tw,
                             const double2 *in, double2 *out, double *probs, double *err, const int *status,
                             hipStream_t st);
 

@@ -1520,8 +1520,9 @@ __global__ void combine_points(const InstDev *__restrict__ insts, const int64_t 
 // ---------------------------------------------------------------------------
 
 __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__restrict__ prefix, int n,
-                          int64_t total, const double2 *__restrict__ in, double2 *__restrict__ out,
-                          double *__restrict__ probs, double *__restrict__ err, const int *__restrict__ status)
+                          int64_t total, const double2 *__restrict__ twpool, const double2 *__restrict__ in,
+                          double2 *__restrict__ out, double *__restrict__ probs, double *__restrict__ err,
+                          const int *__restrict__ status)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
@@ -1532,21 +1533,23 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
     const int b = (int)((lq / S.inner) % S.Bout);
     const int64_t o = lq / (S.inner * S.Bout);
     const double2 *src = in + S.in_off + o * S.K * S.inner + i;
+    const double2 *tw = twpool + S.tw_off;
     double2 acc = cmk(0.0, 0.0);
+    int m = 0;  // k b mod G (b < G)
     for (int k = 0; k < S.K; ++k) {
-        const int m = (int)(((int64_t)k * b) % S.G);
-        double sn, cs;
-        sincospi(-2.0 * (double)m / (double)S.G, &sn, &cs);
+        const double2 t = tw[m];
         double2 v = src[(int64_t)k * S.inner];
         if (S.final_stage) {
             const double wk = (k == 0 || 2 * k == S.G) ? 1.0 : 2.0;
             v.x *= wk;
             v.y *= wk;
         }
-        acc.x = fma(v.x, cs, acc.x);
-        acc.x = fma(-v.y, sn, acc.x);
-        acc.y = fma(v.x, sn, acc.y);
-        acc.y = fma(v.y, cs, acc.y);
+        acc.x = fma(v.x, t.x, acc.x);
+        acc.x = fma(-v.y, t.y, acc.x);
+        acc.y = fma(v.x, t.y, acc.y);
+        acc.y = fma(v.y, t.x, acc.y);
+        m += b;
+        if (m >= S.G) m -= S.G;
     }
     if (S.final_stage) {
         probs[S.out_off + lq] = acc.x * S.scale;
@@ -1999,12 +2002,12 @@ hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, i
     return hipGetLastError();
 }
 
-hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total,
+hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total, const double2 *tw,
                             const double2 *in, double2 *out, double *probs, double *err, const int *status,
                             hipStream_t st) {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(dft_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, st_dev, prefix, n,
-                       total, in, out, probs, err, status);
+                       total, tw, in, out, probs, err, status);
     return hipGetLastError();
 }
 
