@@ -74,10 +74,14 @@ typedef enum {
                                       eliminating the first bin all lie in one bin B (order
                                       <= 144, no displacement border), reduce every Schur
                                       matrix C(w_A) once to Hessenberg form so that each point
-                                      costs O(n^2) instead of a full factorisation (FP64 in
-                                      both precisions).  Without either Hessenberg flag the
-                                      library takes this route for those blocks when its
-                                      estimate of the time is lower (many points per w_A). */
+                                      costs O(n^2) instead of a full factorisation.  When they
+                                      lie in two bins P and B (order <= 480, bin B <= 144),
+                                      the pair route first eliminates the rows of P for every
+                                      (w_A, w_P) by a partial LU and reduces what is left.
+                                      FP64 in both precisions.  Without either Hessenberg flag
+                                      the library takes these routes for those blocks when its
+                                      estimate of the time is lower (many points per
+                                      reduction). */
 #define CGD_FLAG_NO_HESSENBERG 16u /* never take the Hessenberg route                        */
 #define CGD_FLAG_GRAD 4u           /* prepare cgd_grad (keeps each internal block's full
                                       matrix on the device); needs 2M(+1) <= 96 per block */
@@ -166,6 +170,8 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  *   CGD_STAGE_HESS       Hessenberg route: reduction of each C(w_A)
  *   CGD_STAGE_HESS_DET   Hessenberg route: the O(n^2) factorisation of every
  *                        (w_A, w_B) pair, copy to the points
+ *   CGD_STAGE_PAIR       pair route: partial LU of every (w_A, w_P) pair, which
+ *                        leaves the matrix the Hessenberg stages reduce
  *   CGD_STAGE_FIX        mixed path: selection of the points whose FP32 value can
  *                        matter, their FP64 re-factorisation and the second combine
  * With timing enabled, cgd_eval records a HIP event pair on the context's
@@ -174,7 +180,8 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  * cgd_stage_work returns each stage's algorithmic work per evaluation:
  * flops (complex LU of order n: 8 sum_m m^2 + 6 sum_m m, m = n-1..0, i.e.
  * about 8n^3/3 real flops; Schur build: 8 nA nB^2 per eliminated-bin value;
- * Hessenberg reduction of order n: step k (m = n - k - 1 rows below the
+ * pair route: the nP pivots of a partial LU as for the LU; Hessenberg
+ * reduction of order n: step k (m = n - k - 1 rows below the
  * diagonal) 2 m (m + 1) + 2 n m complex multiply-adds; Hessenberg
  * factorisation: 2 (n - k - 1) per pivot k; DFT: 8 flops per complex
  * multiply-add) and bytes (DFT: each grid value read once, each
@@ -188,7 +195,8 @@ enum {
     CGD_STAGE_FIX = 9,
     CGD_STAGE_HESS = 10,
     CGD_STAGE_HESS_DET = 11,
-    CGD_NSTAGES = 12
+    CGD_STAGE_PAIR = 12,
+    CGD_NSTAGES = 13
 };
 cgd_status cgd_set_timing(cgd_ctx *ctx, int32_t enable);
 cgd_status cgd_stage_times(cgd_ctx *ctx, double *ms /* CGD_NSTAGES */);

@@ -27,7 +27,7 @@ FLAG_HESSENBERG = 8
 FLAG_NO_HESSENBERG = 16
 # launch stages of one evaluation (per-stage timing); LU stages are order buckets
 STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144", "combine", "dft", "fix",
-          "hess", "hess_det"]
+          "hess", "hess_det", "pair"]
 # the kernels behind each LU bucket: (FP64 path, FP32 first pass of the mixed path)
 LU_KERNELS = {
     "lu_le32": ("lu_reg<double,8,8,4,4>", "lu_mfma_f32<2,1,2>"),

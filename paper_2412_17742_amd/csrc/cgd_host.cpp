@@ -355,8 +355,6 @@ struct LuClass {
     int64_t *d_prefix = nullptr;
 };
 
-// Hessenberg-route jobs of one size class: reduction (one workgroup per k_A)
-// and factorisations (one workgroup per k_A and 16 values of k_B)
 // Blocks that can take the Hessenberg route: the first bin eliminated through
 // its eigenbasis, no displacement border, order within the reduction
 // kernels' limit, and every row left in one other bin.  Returns that bin, or -1.
@@ -370,6 +368,41 @@ static int hess_bin(const HostBlock &h) {
     return hbin == h.schur_axis ? -1 : hbin;
 }
 
+// Blocks that can take the pair route: as above, but the rows left lie in two
+// bins.  The bin with fewer values on the grid is eliminated per (w_A, w_P)
+// pair by a partial LU (fewer pairs); the other must fit a reduction class.
+constexpr int kPairMaxOrder = 480;
+// The pair route is switched off: its kernels ended in a GPU memory fault on
+// their first run and the cause is not found yet.
+constexpr bool kPairRoute = false;
+static bool pair_bins(const HostBlock &h, const InstDev &I, int &pbin, int &hbin) {
+    if (!kPairRoute) return false;
+    if (h.schur_axis < 0 || h.bordered || h.nb < 2 || h.nb > kPairMaxOrder) return false;
+    int b1 = -1, b2 = -1, n1 = 0, n2 = 0;
+    for (int32_t rb : h.rowbin) {
+        if (rb < 0 || rb == h.schur_axis) return false;
+        if (b1 < 0 || rb == b1) {
+            b1 = rb;
+            ++n1;
+        } else if (b2 < 0 || rb == b2) {
+            b2 = rb;
+            ++n2;
+        } else {
+            return false;
+        }
+    }
+    if (b2 < 0) return false;
+    auto nval = [&](int l) { return l == 0 ? I.H1 : I.G[l]; };
+    const int lim = hess_class_limit(kHessClasses - 1);
+    const bool first = nval(b1) <= nval(b2);
+    pbin = first ? b1 : b2;
+    hbin = first ? b2 : b1;
+    if ((first ? n2 : n1) > lim) std::swap(pbin, hbin);
+    return (pbin == b1 ? n2 : n1) <= lim;
+}
+
+// Hessenberg-route jobs of one size class: reduction (one workgroup per k_A)
+// and factorisations (one workgroup per k_A and 16 values of k_B)
 struct HessClass {
     std::vector<HessDev> jobs;
     std::vector<int64_t> rprefix, dprefix;
@@ -412,6 +445,16 @@ struct cgd_ctx {
     int64_t hess_spts = 0, hess_ntab = 0, hess_nec = 0;
     HessClass hcls[kHessClasses];
     HessDev *d_hess_all = nullptr;
+    // pair route: partial LU of each (w_A, w_P) pair before the reduction
+    std::vector<PairDev> pairs;
+    std::vector<int64_t> pair_prefix;
+    int64_t npairs = 0, s_region = 0;  // pairs; size of the S region after the uploaded pool
+    int64_t pool_host = 0;             // elements of the matrix pool written by the host
+    int pair_ldw = 0, pair_nwg = 0;
+    PairDev *d_pairs = nullptr;
+    int64_t *d_pair_prefix = nullptr;
+    int32_t *d_perm = nullptr;
+    double2 *d_pair_work = nullptr;
     int64_t *d_hess_sprefix = nullptr;
     double2 *d_eigc = nullptr, *d_htable = nullptr;
     std::vector<DftStage> stages;
@@ -482,6 +525,7 @@ void free_ctx(cgd_ctx *c) {
     for (auto &s : c->adj_stages) { fr(s.d_desc); fr(s.d_prefix); }
     for (auto &h : c->hcls) { fr(h.d_jobs); fr(h.d_rprefix); fr(h.d_dprefix); }
     fr(c->d_hess_all); fr(c->d_hess_sprefix); fr(c->d_eigc); fr(c->d_htable);
+    fr(c->d_pairs); fr(c->d_pair_prefix); fr(c->d_perm); fr(c->d_pair_work);
     for (auto &k : c->gadj) { fr(k.d_jobs); fr(k.d_prefix); }
     fr(c->d_gblocks); fr(c->d_gpool); fr(c->d_partial); fr(c->d_z); fr(c->d_adjA); fr(c->d_adjB); fr(c->d_ghat);
     fr(c->d_grb); fr(c->d_z_prefix); fr(c->d_adj_off); fr(c->d_prob_prefix);
@@ -495,22 +539,31 @@ void free_ctx(cgd_ctx *c) {
     delete c;
 }
 
-// Route for the blocks hess_bin accepts (all of them, or none), unless a flag
-// forces it: the Hessenberg route replaces a factorisation per point by one
-// reduction per value of w_A plus an O(n^2) factorisation per (w_A, w_B).
-// Its reductions run one per compute unit and are latency bound, so with few
-// values of w_A, or few values of w_B per w_A, the factorisations per point
-// are faster.  Both sides are estimated from per-kernel times measured on
-// MI355X, in microseconds of one compute unit:
-//   reduction    (n - 2) steps of t_step (1.4, 2.0, 5.3 us for orders
-//                <= 32, 64, 144), one reduction per compute unit at a time;
-//   Hessenberg   10 (n / 144)^2 per (w_A, w_B);
-//   LU per point 148 (n / 144)^3 (FP64), 70 (n / 144)^3 (mixed, including
-//                the share of points factorised again in FP64).
-bool choose_hessenberg(const cgd_ctx *c, const std::vector<HostBlock> &hb, std::vector<int> &hbins) {
+// Route for the blocks hess_bin or pair_bins accepts (all of them, or none),
+// unless a flag forces it: the Hessenberg route replaces a factorisation per
+// point by one reduction per value of w_A (pair route: per (w_A, w_P) pair,
+// after a partial LU) plus an O(n^2) factorisation per point.  The reductions
+// run one per compute unit and are latency bound, so with few values of w_A,
+// or few points per reduction, the factorisations per point are faster.  Both
+// sides are estimated from per-kernel times measured on MI355X, in
+// microseconds of one compute unit:
+//   reduction    (n - 2) steps of t_step (1.4, 2.0, 3.0, 5.3 us for orders
+//                <= 32, 64, 96, 144), one reduction per compute unit at a time;
+//   Hessenberg   3.7 (n / 144)^2 per point;
+//   partial LU   680 (n^3 - nB^3) / 192^3 per pair (blocked FP64 LU);
+//   LU per point orders <= 144: 148 (n / 144)^3 (FP64), 70 (n / 144)^3
+//                (mixed, including the share factorised again in FP64);
+//                above: 680 (n / 192)^3 (FP64), 130 (n / 192)^3 (mixed).
+bool choose_hessenberg(const cgd_ctx *c, const std::vector<HostBlock> &hb, std::vector<int> &hbins,
+                       std::vector<int> &pbins) {
     bool any = false;
     for (size_t b = 0; b < hb.size(); ++b) {
         hbins[b] = hess_bin(hb[b]);
+        pbins[b] = -1;
+        if (hbins[b] < 0 && !pair_bins(hb[b], c->inst[hb[b].inst], pbins[b], hbins[b])) {
+            hbins[b] = -1;
+            pbins[b] = -1;
+        }
         any |= hbins[b] >= 0;
     }
     if (!any || (c->flags & CGD_FLAG_NO_HESSENBERG)) return false;
@@ -519,26 +572,36 @@ bool choose_hessenberg(const cgd_ctx *c, const std::vector<HostBlock> &hb, std::
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
         ncu = 256;
-    static constexpr double t_step[kHessClasses] = {1.4, 2.0, 5.3};
-    double red_n[kHessClasses] = {0.0, 0.0, 0.0};  // total reductions per class
-    double red_t[kHessClasses] = {0.0, 0.0, 0.0};  // longest reduction per class
-    double det_cu = 0.0, lu_cu = 0.0;
-    const double lu_scale = c->prec == CGD_PREC_MIXED ? 70.0 : 148.0;
+    static constexpr double t_step[kHessClasses] = {1.4, 2.0, 3.0, 5.3};
+    double red_n[kHessClasses] = {};  // total reductions per class
+    double red_t[kHessClasses] = {};  // longest reduction per class
+    double det_cu = 0.0, plu_cu = 0.0, lu_cu = 0.0;
+    const bool mixed = c->prec == CGD_PREC_MIXED;
     for (size_t b = 0; b < hb.size(); ++b) {
         if (hbins[b] < 0) continue;
         const HostBlock &h = hb[b];
         const InstDev &I = c->inst[h.inst];
-        const double nA = h.schur_axis == 0 ? I.H1 : I.G[h.schur_axis];
-        const double nB = hbins[b] == 0 ? I.H1 : I.G[hbins[b]];
+        auto nval = [&](int l) { return (double)(l == 0 ? I.H1 : I.G[l]); };
+        double nred = nval(h.schur_axis);
+        int nH = h.nb;
+        if (pbins[b] >= 0) {
+            nH = 0;
+            for (int32_t rb : h.rowbin) nH += rb == hbins[b];
+            nred *= nval(pbins[b]);
+            const double n3 = (double)h.nb * h.nb * h.nb, h3 = (double)nH * nH * nH;
+            plu_cu += nred * 680.0 * (n3 - h3) / (192.0 * 192.0 * 192.0);
+        }
         int cls = 0;
-        while (h.nb > hess_class_limit(cls)) ++cls;
-        const double r = h.nb / 144.0;
-        red_n[cls] += nA;
-        red_t[cls] = std::max(red_t[cls], (h.nb - 2) * t_step[cls]);
-        det_cu += nA * nB * 10.0 * r * r;
-        lu_cu += (double)I.npts * lu_scale * r * r * r;
+        while (nH > hess_class_limit(cls)) ++cls;
+        const double r = nH / 144.0;
+        red_n[cls] += nred;
+        red_t[cls] = std::max(red_t[cls], (nH - 2) * t_step[cls]);
+        det_cu += nred * nval(hbins[b]) * 3.7 * r * r;
+        const double q = h.nb <= 144 ? h.nb / 144.0 : h.nb / 192.0;
+        const double per = h.nb <= 144 ? (mixed ? 70.0 : 148.0) : (mixed ? 130.0 : 680.0);
+        lu_cu += (double)I.npts * per * q * q * q;
     }
-    double t_hess = det_cu / ncu;
+    double t_hess = (det_cu + plu_cu) / ncu;
     for (int k = 0; k < kHessClasses; ++k) t_hess += std::ceil(red_n[k] / ncu) * red_t[k];
     return t_hess < lu_cu / ncu;
 }
@@ -915,8 +978,9 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     };
     c->blocks.resize(hblocks.size());
     c->is_hess.assign(hblocks.size(), 0);
-    std::vector<int> hbins(hblocks.size(), -1);
-    const bool use_hess = choose_hessenberg(c, hblocks, hbins);
+    std::vector<int> hbins(hblocks.size(), -1), pbins(hblocks.size(), -1);
+    const bool use_hess = choose_hessenberg(c, hblocks, hbins, pbins);
+    std::vector<int32_t> permpool;
     for (size_t b = 0; b < hblocks.size(); ++b) {
         const HostBlock &h = hblocks[b];
         BlockDev &d = c->blocks[b];
@@ -976,15 +1040,56 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 hd.n = h.nb;
                 hd.axA = h.schur_axis;
                 hd.axB = hbin;
+                hd.axP = -1;
+                hd.dP = 1;
                 hd.dA = sj.nk;
                 hd.dB = hbin == 0 ? I.H1 : I.G[hbin];
                 hd.GA = I.G[h.schur_axis];
                 hd.GB = I.G[hbin];
                 hd.n_eig = d.n_eig;
-                hd.cls = 0;
-                while (h.nb > hess_class_limit(hd.cls)) ++hd.cls;
                 hd.c_off = sj.c_off;
                 hd.eig_off = d.eig_off;
+                const int pbin = pbins[b];
+                if (pbin >= 0) {
+                    // pair route: rows of bin P first, S (rows of bin B) per pair after
+                    // the uploaded pool (offsets relative to its end until it is known)
+                    PairDev pd;
+                    std::memset(&pd, 0, sizeof(pd));
+                    pd.inst = h.inst;
+                    pd.n = h.nb;
+                    pd.perm_off = (int64_t)permpool.size();
+                    for (int i = 0; i < h.nb; ++i)
+                        if (h.rowbin[i] == pbin) permpool.push_back(i);
+                    pd.nP = (int32_t)(permpool.size() - pd.perm_off);
+                    for (int i = 0; i < h.nb; ++i)
+                        if (h.rowbin[i] == hbin) permpool.push_back(i);
+                    pd.axA = h.schur_axis;
+                    pd.axP = pbin;
+                    pd.dA = sj.nk;
+                    pd.dP = pbin == 0 ? I.H1 : I.G[pbin];
+                    pd.GA = I.G[h.schur_axis];
+                    pd.GP = I.G[pbin];
+                    pd.n_eig = d.n_eig;
+                    pd.c_off = sj.c_off;
+                    pd.hs_stride = (int64_t)h.nb * h.nb;
+                    pd.eig_off = d.eig_off;
+                    const int nH = h.nb - pd.nP;
+                    pd.s_off = c->s_region;
+                    c->s_region += (int64_t)pd.dA * pd.dP * nH * nH;
+                    pd.ec_off = c->hess_nec;
+                    c->pair_ldw = std::max(c->pair_ldw, h.nb);
+                    c->pair_prefix.push_back(c->npairs);
+                    c->npairs += (int64_t)pd.dA * pd.dP;
+                    c->pairs.push_back(pd);
+                    hd.n = nH;
+                    hd.axP = pbin;
+                    hd.dP = pd.dP;
+                    hd.dA = pd.dA * pd.dP;
+                    hd.n_eig = 0;
+                    hd.c_off = pd.s_off;  // relative for now
+                }
+                hd.cls = 0;
+                while (hd.n > hess_class_limit(hd.cls)) ++hd.cls;
                 hd.t_off = c->hess_ntab;
                 c->hess_ntab += (int64_t)hd.dA * hd.dB;
                 hd.ec_off = c->hess_nec;
@@ -996,6 +1101,11 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             d.hs_stride = 0;
         }
     }
+    // the S region of the pair route follows the uploaded pool
+    c->pool_host = (int64_t)pool.size();
+    for (PairDev &pd : c->pairs) pd.s_off += c->pool_host;
+    for (HessDev &hd : c->hess_all)
+        if (hd.axP >= 0) hd.c_off += c->pool_host;
     // schur work list: one workgroup per (job, k, row block)
     const int rows = schur_rows_per_wg();
     c->schur_prefix.clear();
@@ -1127,6 +1237,14 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         c->work_flops[CGD_STAGE_HESS] += 8.0 * red * hd.dA;
         c->work_flops[CGD_STAGE_HESS_DET] += 8.0 * fac * (double)hd.dA * hd.dB;
     }
+    for (const PairDev &pd : c->pairs) {
+        double f = 0;  // the nP pivots of a partial LU of order n
+        for (int k = 0; k < pd.nP; ++k) {
+            const double m = pd.n - k - 1;
+            f += 8.0 * m * m + 6.0 * m;
+        }
+        c->work_flops[CGD_STAGE_PAIR] += f * pd.dA * pd.dP;
+    }
     for (const DftStage &st : c->stages)
         for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
     c->work_bytes[CGD_STAGE_DFT] = 16.0 * c->npts + 8.0 * c->nprobs;
@@ -1139,7 +1257,21 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     if ((s = upload(&c->d_schur, c->schur)) != CGD_OK) return s;
     if ((s = upload(&c->d_schur_prefix, c->schur_prefix)) != CGD_OK) return s;
     if ((s = upload(&c->d_inst_pt_prefix, c->inst_pt_prefix)) != CGD_OK) return s;
-    if ((s = upload(&c->d_pool, pool)) != CGD_OK) return s;
+    HIP_OK(hipMalloc((void **)&c->d_pool, sizeof(double2) * std::max<int64_t>(1, c->pool_host + c->s_region)));
+    if (!pool.empty())
+        HIP_OK(hipMemcpy(c->d_pool, pool.data(), sizeof(double2) * pool.size(), hipMemcpyHostToDevice));
+    if (c->npairs > 0) {
+        if ((s = upload(&c->d_pairs, c->pairs)) != CGD_OK) return s;
+        if ((s = upload(&c->d_pair_prefix, c->pair_prefix)) != CGD_OK) return s;
+        if ((s = upload(&c->d_perm, permpool)) != CGD_OK) return s;
+        int ncu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        c->pair_nwg = (int)std::min<int64_t>(c->npairs, 2 * (int64_t)ncu);
+        HIP_OK(hipMalloc((void **)&c->d_pair_work,
+                         sizeof(double2) * (size_t)c->pair_nwg * c->pair_ldw * c->pair_ldw));
+    }
     if ((s = upload(&c->d_rb, rbpool)) != CGD_OK) return s;
     if ((s = upload(&c->d_eig, eigpool)) != CGD_OK) return s;
     for (auto *grp : {&c->g64[0], &c->g32[0]}) {
@@ -1194,7 +1326,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         if ((s = upload(&c->d_list_ptrs, ptrs)) != CGD_OK) return s;
         HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kG64));
     }
-    HIP_OK(prepare_kernels(c->big_nwg > 0 ? c->big_ldw : 0, c->schur_maxA));
+    HIP_OK(prepare_kernels(c->big_nwg > 0 ? c->big_ldw : 0, c->schur_maxA, c->npairs > 0 ? c->pair_ldw : 0));
     if (want_grad) {
         cgd_status sg = build_grad(c, n_inst);
         if (sg != CGD_OK) return sg;
@@ -1260,6 +1392,13 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg,
                                   c->schur_maxA, c->d_pool, c->d_eig, c->d_pool, c->d_pool32, st));
         HIP_OK(mark(CGD_STAGE_SCHUR, 1));
+    }
+    if (c->npairs > 0) {
+        HIP_OK(mark(CGD_STAGE_PAIR, 0));
+        HIP_OK(launch_pair_schur(c->d_pairs, c->d_pair_prefix, (int)c->pairs.size(), c->npairs, c->pair_nwg,
+                                 c->d_pool, c->d_perm, c->d_eig, c->d_pair_work, c->pair_ldw, c->d_eigc,
+                                 c->d_status, st));
+        HIP_OK(mark(CGD_STAGE_PAIR, 1));
     }
     if (!c->hess_all.empty()) {
         HIP_OK(mark(CGD_STAGE_HESS, 0));

@@ -74,9 +74,29 @@ struct HessDev {
     int32_t dA, dB;           // number of k_A and k_B values (half grid on axis 0)
     int32_t GB;               // grid extent of axis B
     int32_t n_eig;
-    int32_t cls;              // size class (n <= 32, 64, 144)
+    int32_t cls;              // size class (n <= 32, 64, 96, 144)
     int32_t GA;               // grid extent of axis A
+    int32_t axP, dP;          // pair route: the middle axis and its number of values (axP = -1: none);
+                              // the matrix index kA then runs over (k_A, k_P) pairs, kA_axis * dP + k_P
     int64_t c_off, eig_off, t_off, ec_off;
+};
+
+// Pair route: a block whose rows left after the eigenbasis elimination of
+// axis A lie in two bins, P and B.  For every (w_A, w_P) pair the rows of P
+// are eliminated by a partial LU of F = [[I - w_P C_PP, -w_P C_PB], [C_BP, C_BB]]
+// (C = C(w_A), bin-P rows first), which leaves S = C_BB + w_P C_BP
+// (I - w_P C_PP)^-1 C_PB, so that det(I - D C) = det(I - w_P C_PP) det(I - w_B S).
+struct PairDev {
+    int32_t inst, n, nP;      // order, rows of bin P (the pivots taken)
+    int32_t axA, axP;         // eliminated axis, partial-LU axis
+    int32_t dA, dP;           // number of values of k_A and k_P
+    int32_t GA, GP;           // their grid extents
+    int32_t n_eig;            // eigenvalues of the eliminated bin
+    int64_t c_off, hs_stride; // C(w_A) in the matrix pool, stride per value of k_A
+    int64_t perm_off;         // row order of F (int32 pool): bin P rows, then bin B rows
+    int64_t eig_off;
+    int64_t s_off;            // S, (n - nP)^2 per pair, in the matrix pool
+    int64_t ec_off;           // per pair: sum Log(1 - w_A lambda_i) + log det(I - w_P C_PP)
 };
 
 // Gradient: one internal block with its full (bordered) matrix, no reduction.
@@ -141,7 +161,7 @@ constexpr int kMfmaClasses = 6;
 int mfma_class_limit(int cls);         // max matrix order of FP32 MFMA class cls
 hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st);
 size_t lu_big_lds_bytes(int ldw);
-hipError_t prepare_kernels(int big_ldw, int schur_maxA);
+hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw);
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st);
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
                               const double2 *pool_in, const double *eigpool, double2 *pool_out, float2 *pool32_out,
@@ -165,12 +185,16 @@ hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_pre
 hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, double *err, const int *status,
                             hipStream_t st);
 // Hessenberg route
-constexpr int kHessClasses = 3;
-int hess_class_limit(int cls);          // max order of class cls: 32, 64, 144
+constexpr int kHessClasses = 4;
+int hess_class_limit(int cls);          // max order of class cls: 32, 64, 96, 144
 hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
                               double2 *pool, const double *eigpool, double2 *eigc, hipStream_t st);
 hipError_t launch_hess_det(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
                            const double2 *pool, const double2 *eigc, double2 *table, hipStream_t st);
+hipError_t launch_pair_schur(const PairDev *jobs, const int64_t *prefix, int njobs, int64_t npairs, int nwg,
+                             double2 *pool, const int32_t *permpool, const double *eigpool, double2 *work, int ldw,
+                             double2 *eigc, int *status, hipStream_t st);
+size_t pair_schur_lds_bytes(int ldw);
 hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t total,
                                const InstDev *insts, const double2 *table, double2 *contrib, hipStream_t st);
 int schur_rows_per_wg();

@@ -710,6 +710,103 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
 constexpr int kPanel = 16;
 constexpr int kBigThreads = 256;
 
+// Right-looking blocked unpivoted LU of W (order nb, leading dimension ldw,
+// in global memory) for the pivots k < kstop, the steps of lu_big_f64: each
+// panel of kPanel columns is factorised in LDS, the U row block is solved in
+// place, and the trailing matrix (all rows and columns >= the panel's end) is
+// updated in 64 x 64 tiles with 4 x 4 register blocks per thread against an
+// LDS-staged U tile.  Pivots go to s_piv; *s_bad is set for a non-finite
+// pivot, or one with Re <= 0 among the first check_lim.  With kstop < nb,
+// W[kstop:, kstop:] ends as the Schur complement of the leading block.
+__device__ __forceinline__ void big_lu_steps(double2 *__restrict__ W, int ldw, int nb, int kstop, int check_lim,
+                                             double2 *s_panel, double2 *s_utile, double2 *s_piv, int *s_bad)
+{
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    for (int k0 = 0; k0 < kstop; k0 += kPanel) {
+        const int kb = min(kPanel, kstop - k0);
+        const int mrows = nb - k0;
+        // panel -> LDS
+        for (int e = tid; e < mrows * kPanel; e += kBigThreads) {
+            const int i = e / kPanel, t = e % kPanel;
+            s_panel[e] = t < kb ? W[(size_t)(k0 + i) * ldw + k0 + t] : cmk(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kb; ++kk) {
+            const double2 d = s_panel[kk * kPanel + kk];
+            if (tid == 0) {
+                s_piv[k0 + kk] = d;
+                if (!isfinite(d.x) || !isfinite(d.y) || (k0 + kk < check_lim && !(d.x > 0.0))) *s_bad = 1;
+            }
+            const double2 dinv = cinv(d);
+            for (int i = kk + 1 + tid; i < mrows; i += kBigThreads) {
+                const double2 l = cmul(s_panel[i * kPanel + kk], dinv);
+                s_panel[i * kPanel + kk] = l;
+                for (int t = kk + 1; t < kb; ++t)
+                    s_panel[i * kPanel + t] = cfnms(s_panel[i * kPanel + t], l, s_panel[kk * kPanel + t]);
+            }
+            __syncthreads();
+        }
+        const int j0 = k0 + kb;
+        if (j0 >= nb) break;
+        // U12 = L11^-1 A12 (unit lower triangular solve), in place in W
+        for (int j = j0 + tid; j < nb; j += kBigThreads) {
+            double2 x[kPanel];
+            #pragma unroll
+            for (int t = 0; t < kPanel; ++t) x[t] = t < kb ? W[(size_t)(k0 + t) * ldw + j] : cmk(0.0, 0.0);
+            #pragma unroll
+            for (int t = 1; t < kPanel; ++t) {
+                #pragma unroll
+                for (int s2 = 0; s2 < t; ++s2) x[t] = cfnms(x[t], s_panel[t * kPanel + s2], x[s2]);
+            }
+            #pragma unroll
+            for (int t = 0; t < kPanel; ++t)
+                if (t < kb) W[(size_t)(k0 + t) * ldw + j] = x[t];
+        }
+        __syncthreads();
+        // trailing update A22 -= L21 U12
+        for (int jt = j0; jt < nb; jt += 64) {
+            for (int e = tid; e < kPanel * 64; e += kBigThreads) {
+                const int t = e / 64, jj = jt + (e % 64);
+                s_utile[e] = (t < kb && jj < nb) ? W[(size_t)(k0 + t) * ldw + jj] : cmk(0.0, 0.0);
+            }
+            __syncthreads();
+            for (int it = j0; it < nb; it += 64) {
+                double2 acc[4][4];
+                #pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    #pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int i = it + ty + 16 * a, j = jt + tx + 16 * b;
+                        acc[a][b] = (i < nb && j < nb) ? W[(size_t)i * ldw + j] : cmk(0.0, 0.0);
+                    }
+                for (int t = 0; t < kb; ++t) {
+                    double2 l[4], u[4];
+                    #pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int i = it + ty + 16 * a;
+                        l[a] = i < nb ? s_panel[(i - k0) * kPanel + t] : cmk(0.0, 0.0);
+                    }
+                    #pragma unroll
+                    for (int b = 0; b < 4; ++b) u[b] = s_utile[t * 64 + tx + 16 * b];
+                    #pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        #pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = cfnms(acc[a][b], l[a], u[b]);
+                }
+                #pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    #pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int i = it + ty + 16 * a, j = jt + tx + 16 * b;
+                        if (i < nb && j < nb) W[(size_t)i * ldw + j] = acc[a][b];
+                    }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kBigThreads)
 lu_big_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ job_prefix, int njobs,
            int64_t nitems_range, const int2 *__restrict__ list, const int *__restrict__ list_count,
@@ -878,6 +975,88 @@ lu_big_f64(const int32_t *__restrict__ job_block, const int64_t *__restrict__ jo
                 res.y += 0.5 * (0.0 - p.y);
             }
             contrib[I.c_off + pt * I.nblocks + B.blk] = res;
+            if (s_bad) atomicOr(status, 1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair route (PairDev).  For every (k_A, k_P) pair, with C = C(w_A) and rows
+// and columns in the order perm (bin P first),
+//     F = E - D C,  E = diag(1 on bin-P rows, 0 on bin-B rows),
+//                   D = diag(w_P on bin-P rows, -1 on bin-B rows),
+// i.e. F = [[I - w_P C_PP, -w_P C_PB], [C_BP, C_BB]].  A partial unpivoted LU
+// over the nP pivots of bin P (big_lu_steps) leaves S = C_BB + w_P C_BP
+// (I - w_P C_PP)^-1 C_PB in the trailing block; S goes to the matrix pool for
+// the Hessenberg reduction, and sum Log(pivots) + sum_i Log(1 - w_A lambda_i)
+// goes to the pair's constant.  I - w_P C_PP is a principal block of the
+// accretive I - D C(w_A), so its pivots lie in the right half-plane and the
+// sum of their principal logarithms is the continuous branch.  One workgroup
+// per pair, persistent; F lives in a per-workgroup global workspace.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBigThreads)
+pair_schur_f64(const PairDev *__restrict__ jobs, const int64_t *__restrict__ prefix, int njobs, int64_t npairs,
+               double2 *__restrict__ pool, const int32_t *__restrict__ permpool, const double *__restrict__ eigpool,
+               double2 *__restrict__ work, int ldw, double2 *__restrict__ eigc, int *__restrict__ status)
+{
+    extern __shared__ double2 s_dyn[];
+    double2 *s_panel = s_dyn;                           // ldw x kPanel
+    double2 *s_utile = s_panel + (size_t)ldw * kPanel;  // kPanel x 64
+    double2 *s_piv = s_utile + kPanel * 64;             // ldw
+    int *s_perm = reinterpret_cast<int *>(s_piv + ldw); // ldw
+    __shared__ double2 s_red[kBigThreads / 64 + 1];
+    __shared__ int s_bad;
+
+    const int tid = threadIdx.x;
+    double2 *__restrict__ W = work + (size_t)blockIdx.x * ldw * ldw;
+    for (int64_t p = blockIdx.x; p < npairs; p += gridDim.x) {
+        const int job = find_job(prefix, njobs, p);
+        const PairDev J = jobs[job];
+        const int64_t lp = p - prefix[job];
+        const int kA = (int)(lp / J.dP), kP = (int)(lp % J.dP);
+        const int n = J.n, nP = J.nP, nH = J.n - J.nP;
+        double sn, cs;
+        sincospi(2.0 * (double)kP / (double)J.GP, &sn, &cs);
+        const double2 wP = cmk(cs, sn);
+        __syncthreads();  // the previous pair is done with s_perm, s_piv and W
+        for (int i = tid; i < n; i += kBigThreads) s_perm[i] = permpool[J.perm_off + i];
+        if (tid == 0) s_bad = 0;
+        __syncthreads();
+        const double2 *__restrict__ C = pool + J.c_off + (int64_t)kA * J.hs_stride;
+        for (int64_t e = tid; e < (int64_t)n * n; e += kBigThreads) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            const double2 h = C[(int64_t)s_perm[i] * n + s_perm[j]];
+            double2 v = h;
+            if (i < nP) {
+                const double2 t = cmul(wP, h);
+                v = cmk((i == j ? 1.0 : 0.0) - t.x, -t.y);
+            }
+            W[(size_t)i * ldw + j] = v;
+        }
+        __syncthreads();
+        big_lu_steps(W, ldw, n, nP, nP, s_panel, s_utile, s_piv, &s_bad);
+        __syncthreads();
+        double2 *__restrict__ S = pool + J.s_off + lp * nH * nH;
+        for (int64_t e = tid; e < (int64_t)nH * nH; e += kBigThreads) {
+            const int i = (int)(e / nH), j = (int)(e % nH);
+            S[e] = W[(size_t)(nP + i) * ldw + nP + j];
+        }
+        double2 acc = cmk(0.0, 0.0);
+        for (int i = tid; i < nP; i += kBigThreads) {
+            const double2 lg = clog(s_piv[i]);
+            acc.x += lg.x;
+            acc.y += lg.y;
+        }
+        sincospi(2.0 * (double)kA / (double)J.GA, &sn, &cs);
+        const double *__restrict__ lam = eigpool + J.eig_off;
+        for (int i = tid; i < J.n_eig; i += kBigThreads) {
+            const double2 lg = clog(cmk(1.0 - cs * lam[i], -sn * lam[i]));
+            acc.x += lg.x;
+            acc.y += lg.y;
+        }
+        acc = block_sum<kBigThreads>(acc, s_red);
+        if (tid == 0) {
+            eigc[J.ec_off + lp] = acc;
             if (s_bad) atomicOr(status, 1);
         }
     }
@@ -1251,7 +1430,9 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
         __syncthreads();
     }
 
-    // sum_i Log(1 - w_A lambda_i)
+    // sum_i Log(1 - w_A lambda_i); a pair job's constant comes with its
+    // Schur complement (pair_schur_f64)
+    if (J.axP >= 0) return;
     double sn, cs;
     sincospi(2.0 * (double)kA / (double)J.GA, &sn, &cs);
     const double *__restrict__ lam = eigpool + J.eig_off;
@@ -1481,7 +1662,9 @@ __global__ void __launch_bounds__(256) hess_scatter(const HessDev *__restrict__ 
     const HessDev J = jobs[job];
     const InstDev &I = insts[J.inst];
     const int64_t pt = t - prefix[job];
-    const int kA = point_k(I, pt, J.axA), kB = point_k(I, pt, J.axB);
+    int kA = point_k(I, pt, J.axA);
+    if (J.axP >= 0) kA = kA * J.dP + point_k(I, pt, J.axP);
+    const int kB = point_k(I, pt, J.axB);
     contrib[I.c_off + pt * I.nblocks + J.blk] = table[J.t_off + (int64_t)kA * J.dB + kB];
 }
 
@@ -1982,6 +2165,19 @@ hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hip
     return hipGetLastError();
 }
 
+size_t pair_schur_lds_bytes(int ldw) {
+    return sizeof(double2) * ((size_t)ldw * kPanel + kPanel * 64 + (size_t)ldw) + sizeof(int) * (size_t)ldw;
+}
+
+hipError_t launch_pair_schur(const PairDev *jobs, const int64_t *prefix, int njobs, int64_t npairs, int nwg,
+                             double2 *pool, const int32_t *permpool, const double *eigpool, double2 *work, int ldw,
+                             double2 *eigc, int *status, hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pair_schur_f64, dim3(nwg), dim3(kBigThreads), pair_schur_lds_bytes(ldw), st, jobs, prefix,
+                       njobs, npairs, pool, permpool, eigpool, work, ldw, eigc, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, int maxA,
                               const double2 *pool_in, const double *eigpool, double2 *pool_out, float2 *pool32_out,
                               hipStream_t st) {
@@ -2099,7 +2295,8 @@ int hess_class_limit(int cls) {
     switch (cls) {
         case 0: return 32;
         case 1: return 64;
-        case 2: return 144;
+        case 2: return 96;
+        case 3: return 144;
         default: return 0;
     }
 }
@@ -2118,7 +2315,8 @@ hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefi
     switch (cls) {
         case 0: return launch_hr<16, 2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
         case 1: return launch_hr<16, 4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 2: return launch_hr<16, 9, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 2: return launch_hr<16, 6, 3>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 3: return launch_hr<16, 9, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2139,7 +2337,8 @@ hipError_t launch_hess_det(int cls, const HessDev *jobs, const int64_t *prefix, 
     switch (cls) {
         case 0: return launch_hd<2>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
         case 1: return launch_hd<4>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
-        case 2: return launch_hd<9>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
+        case 2: return launch_hd<6>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
+        case 3: return launch_hd<9>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2152,11 +2351,13 @@ hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int n
     return hipGetLastError();
 }
 
-hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
+hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
     for (hipError_t e : {hipFuncSetAttribute((const void *)hess_reduce_f64<16, 2, 1>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 2, 1>)),
                          hipFuncSetAttribute((const void *)hess_reduce_f64<16, 4, 2>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 4, 2>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 6, 3>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 6, 3>)),
                          hipFuncSetAttribute((const void *)hess_reduce_f64<16, 9, 5>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 9, 5>)),
                          hipFuncSetAttribute((const void *)hess_det_f64<9>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2168,6 +2369,12 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA) {
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lu_big_lds_bytes(big_ldw));
+        if (e != hipSuccess) return e;
+    }
+    if (pair_ldw > 0) {
+        const hipError_t e = hipFuncSetAttribute((const void *)pair_schur_f64,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)pair_schur_lds_bytes(pair_ldw));
         if (e != hipSuccess) return e;
     }
     if (schur_maxA > 0) {

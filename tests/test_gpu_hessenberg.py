@@ -134,3 +134,74 @@ def test_route_is_chosen_by_estimated_time():
     assert not _route_taken(gbs, cgd.FLAG_NO_HESSENBERG)
     assert not _route_taken(mesh, 0)
     assert _route_taken(mesh, H)
+
+
+# --- pair route: rows left after the elimination in two bins -----------------
+# The route is switched off in the library: its first run on the GPU ended in
+# a memory fault whose cause is not found yet.
+PAIR_OFF = pytest.mark.skip(reason="pair route switched off (GPU memory fault on its first run, cause not found)")
+
+def _pair_taken(instances, flags):
+    with cgd.Context(instances, flags=flags) as ctx:
+        ctx.set_timing(True)
+        ctx.eval()
+        return ctx.stage_times()["pair"] >= 0
+
+
+def _three_bin_instance(sizes, seed, grid, schmidt=None, alpha=False):
+    rng = W.rng_for(950 + seed)
+    M = sum(sizes)
+    U = W.haar_unitary(M, rng)
+    r = rng.uniform(0.3, 0.8, M)
+    al = 0.3 * (rng.standard_normal(M) + 1j * rng.standard_normal(M)) if alpha else None
+    return W.make_instance(np.sqrt(0.5) * U, r, alpha=al, schmidt=schmidt, bin_of=W.contiguous_bins(list(sizes)),
+                           cutoff=[g - 1 for g in grid], grid=grid)
+
+
+@PAIR_OFF
+@pytest.mark.parametrize("sizes, grid", [((6, 5, 4), [5, 6, 7]), ((4, 6, 5), [6, 5, 4]), ((7, 3, 3), [4, 8, 3]),
+                                         ((5, 5, 5), [5, 5, 5])])
+def test_pair_route_three_bins_vs_oracle(sizes, grid):
+    _say("pair route, three bins", sizes, grid)
+    inst = _three_bin_instance(sizes, sum(sizes) + grid[1], grid)
+    assert _pair_taken([inst], H)
+    (P,) = gpu_dists([inst], H)
+    assert np.abs(P - pgf.wrapped_distribution(inst)).max() <= TOL
+
+
+@PAIR_OFF
+def test_pair_route_internal_modes_and_mixed_routes():
+    # K = 2: two blocks per point, both on the pair route; plus a displaced
+    # instance whose bordered block keeps the factorisation per point
+    _say("pair route with internal modes, batched with a displaced instance")
+    insts = [_three_bin_instance((5, 4, 4), 3, [5, 4, 6], schmidt=[0.7, 0.3]),
+             _three_bin_instance((4, 4, 3), 4, [4, 5, 4], schmidt=[0.6, 0.3, 0.1], alpha=True)]
+    got = gpu_dists(insts, H)
+    for inst, P in zip(insts, got):
+        assert np.abs(P - pgf.wrapped_distribution(inst)).max() <= TOL
+
+
+@PAIR_OFF
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pair_route_agrees_with_factorisation_per_point(precision):
+    _say("pair route vs factorisation per point,", precision)
+    insts = [_three_bin_instance((12, 10, 9), 7, [9, 11, 10]), _three_bin_instance((9, 9, 9), 8, [7, 7, 7])]
+    a = gpu_dists(insts, H, precision=precision)
+    b = gpu_dists(insts, cgd.FLAG_NO_HESSENBERG, precision="fp64")
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= TOL
+
+
+@PAIR_OFF
+def test_gbs_m144_three_bins_pair_route():
+    # three bins of 48 modes: eliminating the first leaves 192 rows in two bins;
+    # the library takes the pair route by itself
+    _say("gbs m144 three bins, pair route")
+    inst = W.gbs_m144(3)
+    assert _pair_taken([inst], 0)
+    logg, _ = gpu_grid([inst], 0)
+    rng = np.random.default_rng(23)
+    idx = np.concatenate([[0, 1, len(logg) - 1], rng.choice(len(logg), 5, replace=False)])
+    check_grid_sample(inst, logg, idx)
+    (P,) = gpu_dists([inst], 0)
+    assert abs(P.sum() - 1.0) < 1e-12
