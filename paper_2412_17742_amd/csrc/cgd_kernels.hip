@@ -1174,6 +1174,17 @@ struct HessLds {
     double2 red[NT / 64 + 1];
 };
 
+// x from lane (lane ^ 1) (CTRL 0xB1) or (lane ^ 2) (CTRL 0x4E) of the same
+// quad (DPP quad_perm)
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double x) {
+    const int2 u = __builtin_bit_cast(int2, x);
+    int2 v;
+    v.x = __builtin_amdgcn_mov_dpp(u.x, CTRL, 0xf, 0xf, true);
+    v.y = __builtin_amdgcn_mov_dpp(u.y, CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, v);
+}
+
 // Register column S holds column k: write x (zero at rows <= k and >= n)
 // and return this thread's share of |x|^2.
 template <int TY, int R, int SC, int S>
@@ -1258,33 +1269,43 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     L.PS[tid] = ps;
     __syncthreads();
 
-    // C. reductions, each in a fixed order: w by threads 0.., y by threads
-    // 256.., s by the last wave
-    if (tid >= 32 * S0 && tid < CMAX) {
-        const double2 *col = &L.PW[0][tid];
-        double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);  // two chains, fixed order
-        #pragma unroll
-        for (int q = 0; q < TY; q += 2) {
-            t0.x += col[q * CMAX].x;
-            t0.y += col[q * CMAX].y;
-            t1.x += col[(q + 1) * CMAX].x;
-            t1.y += col[(q + 1) * CMAX].y;
+    // C. reductions, each in a fixed order: w_j by lanes 2j, 2j+1 and y_i by
+    // lanes 2i, 2i+1 (each lane half of the partials, the pair combined by a
+    // lane swap), s by the last wave
+    {
+        const int h = tid & 1;
+        const int j = tid >> 1;
+        if (tid < 2 * CMAX && j >= 32 * S0) {
+            const double2 *col = &L.PW[h * (TY / 2)][j];
+            double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int q = 0; q < TY / 2; q += 2) {
+                t0.x += col[q * CMAX].x;
+                t0.y += col[q * CMAX].y;
+                t1.x += col[(q + 1) * CMAX].x;
+                t1.y += col[(q + 1) * CMAX].y;
+            }
+            double2 t = cmk(t0.x + t1.x, t0.y + t1.y);
+            t.x += quad_swap<0xB1>(t.x);  // lanes [1, 0, 3, 2]
+            t.y += quad_swap<0xB1>(t.y);
+            if (h == 0) L.W[j] = t;
         }
-        L.W[tid] = cmk(t0.x + t1.x, t0.y + t1.y);
-    }
-    if (tid >= 256 && tid - 256 < RMAX) {
-        const int i = tid - 256;
-        const double2 *col = &L.PY[0][i];
-        constexpr int PYS = HessLds<TY, R, SC>::PYS;
-        double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
-        #pragma unroll
-        for (int q = 0; q < 32; q += 2) {
-            t0.x += col[q * PYS].x;
-            t0.y += col[q * PYS].y;
-            t1.x += col[(q + 1) * PYS].x;
-            t1.y += col[(q + 1) * PYS].y;
+        if (tid < 2 * RMAX) {
+            constexpr int PYS = HessLds<TY, R, SC>::PYS;
+            const double2 *row = &L.PY[h * 16][j];
+            double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int q = 0; q < 16; q += 2) {
+                t0.x += row[q * PYS].x;
+                t0.y += row[q * PYS].y;
+                t1.x += row[(q + 1) * PYS].x;
+                t1.y += row[(q + 1) * PYS].y;
+            }
+            double2 t = cmk(t0.x + t1.x, t0.y + t1.y);
+            t.x += quad_swap<0xB1>(t.x);
+            t.y += quad_swap<0xB1>(t.y);
+            if (h == 0) L.Y[j] = t;
         }
-        L.Y[i] = cmk(t0.x + t1.x, t0.y + t1.y);
     }
     if (tid >= NT - 64) {
         const int lane = tid & 63;
@@ -1373,7 +1394,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
     constexpr int NMAX = Lds::NMAX, RMAX = Lds::RMAX, CMAX = Lds::CMAX, XMAX = Lds::XMAX;
     constexpr int NT = Lds::NT;
     static_assert(NT >= 512, "reductions assume 512 threads or more");
-    static_assert(CMAX <= 256 && 256 + RMAX <= NT - 64, "reduction threads overlap");
+    static_assert(2 * CMAX <= NT - 64 && 2 * RMAX <= NT - 64 && TY % 4 == 0, "reduction threads overlap");
     extern __shared__ __align__(16) unsigned char hess_raw[];
     Lds &L = *reinterpret_cast<Lds *>(hess_raw);
     const int job = find_job(prefix, njobs, blockIdx.x);
