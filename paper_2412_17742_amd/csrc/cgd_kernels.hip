@@ -1152,9 +1152,11 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
 // ---------------------------------------------------------------------------
 constexpr int kHessDetThreads = 256;  // 4 waves x 4 points, 16 lanes per point
 
-// TY x 32 thread grid (ty = tid / 32, tx = tid % 32); element (i, j) in thread
-// (i mod TY, j mod 32), register (i / TY, j / 32): RMAX = TY R rows and
-// CMAX = 32 SC columns are held, orders n <= min(RMAX, CMAX).
+// TY x 32 thread grid with TY = 16, ty = tid % 16 and tx = tid / 16: element
+// (i, j) in thread (i mod 16, j mod 32), register (i / 16, j / 32).  Matrix
+// column j is held by the 16 lanes of one DPP row (lanes 16 (tx mod 4) ..
+// 16 (tx mod 4) + 15 of wave tx / 4), so a column's sums need no LDS.  RMAX =
+// 16 R rows and CMAX = 32 SC columns are held, orders n <= min(RMAX, CMAX).
 template <int TY, int R, int SC>
 struct HessLds {
     static constexpr int NT = 32 * TY;
@@ -1162,11 +1164,11 @@ struct HessLds {
     static constexpr int CMAX = 32 * SC;
     static constexpr int NMAX = RMAX < CMAX ? RMAX : CMAX;
     static constexpr int XMAX = RMAX > CMAX ? RMAX : CMAX;
-    static constexpr int PYS = RMAX + 1;  // padded stride of the row-sum partials
+    static constexpr int PYS = RMAX + 1;  // padded strides of the partial sums
+    static constexpr int PWS = CMAX + 1;
     double2 x[2][XMAX];                    // v of step k (zero outside rows k+1..n-1), by step parity
-    double2 x1[2];                         // x_1 = A[k+1][k], by step parity
-    double nrm[2][TY];                     // partial |x|^2 per thread row
-    double2 PW[TY][CMAX];                  // partials of w_j = sum_i conj(v_i) a_ij, per thread row
+    double beta[2];                        // 2 / |v|^2 of step k, by step parity
+    double2 PW[TY][PWS];                   // partials of w_j = sum_i conj(v_i) a_ij, per thread row
     double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column
     double2 PS[NT];                        // partials of s = v^H A v, per thread
     double2 W[CMAX], Y[RMAX];
@@ -1175,7 +1177,8 @@ struct HessLds {
 };
 
 // x from lane (lane ^ 1) (CTRL 0xB1) or (lane ^ 2) (CTRL 0x4E) of the same
-// quad (DPP quad_perm)
+// quad (DPP quad_perm), or from the mirrored lane of the same half row
+// (0x141, lane 7 - i of each 8) or row (0x140, lane 15 - i of each 16)
 template <int CTRL>
 __device__ __forceinline__ double quad_swap(double x) {
     const int2 u = __builtin_bit_cast(int2, x);
@@ -1185,12 +1188,26 @@ __device__ __forceinline__ double quad_swap(double x) {
     return __builtin_bit_cast(double, v);
 }
 
-// Register column S holds column k: write x (zero at rows <= k and >= n)
-// and return this thread's share of |x|^2.
+// Sum over the 16 lanes of each DPP row; every lane of the row gets the same
+// value (each level adds two equal-order partial sums, and a + b = b + a).
+__device__ __forceinline__ double row16_sum(double x) {
+    x += quad_swap<0xB1>(x);
+    x += quad_swap<0x4E>(x);
+    x += quad_swap<0x141>(x);
+    x += quad_swap<0x140>(x);
+    return x;
+}
+
+// Reflector of step k, computed by the DPP row that holds column k (register
+// column S): x = column k below the diagonal goes to L.x[par] (zero at rows
+// <= k and >= n), then v_1 = x_1 - alpha with alpha = -(x_1/|x_1|) |x|
+// replaces x_1 there, and beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)) goes to
+// L.beta[par].  All 16 lanes of the row must be active.
 template <int TY, int R, int SC, int S>
-__device__ __forceinline__ double hess_put_x(HessLds<TY, R, SC> &L, const double2 (&a)[R][SC], int k, int n,
-                                             int par, int ty) {
+__device__ __forceinline__ void hess_reflector(HessLds<TY, R, SC> &L, const double2 (&a)[R][SC], int k, int n,
+                                               int par, int ty) {
     double acc = 0.0;
+    double2 x1 = cmk(0.0, 0.0);
     double2 *xr = &L.x[par][ty];
     #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1198,10 +1215,19 @@ __device__ __forceinline__ double hess_put_x(HessLds<TY, R, SC> &L, const double
         const bool in = i > k && i < n;
         const double2 xi = cmk(in ? a[r][S].x : 0.0, in ? a[r][S].y : 0.0);
         xr[TY * r] = xi;
-        if (i == k + 1) L.x1[par] = xi;
         acc = fma(xi.x, xi.x, fma(xi.y, xi.y, acc));
+        x1.x = i == k + 1 ? xi.x : x1.x;
+        x1.y = i == k + 1 ? xi.y : x1.y;
     }
-    return acc;
+    const double xn = sqrt(row16_sum(acc));
+    x1.x = row16_sum(x1.x);  // one nonzero term
+    x1.y = row16_sum(x1.y);
+    const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
+    if (ty == ((k + 1) & (TY - 1))) {
+        const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
+        L.x[par][k + 1] = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));
+        L.beta[par] = xn > 0.0 ? 1.0 / (xn * (xn + ax1)) : 0.0;
+    }
 }
 
 // One Householder step k (column k) of hess_reduce_f64, R0 = k / TY and
@@ -1215,23 +1241,12 @@ __device__ __forceinline__ double hess_put_x(HessLds<TY, R, SC> &L, const double
 template <int TY, int R, int SC, int R0, int S0>
 __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int k, int n, int tid) {
     constexpr int NT = 32 * TY, RMAX = TY * R, CMAX = 32 * SC;
-    const int par = k & 1, ty = tid >> 5, tx = tid & 31;
+    const int par = k & 1, ty = tid & (TY - 1), tx = tid / TY;
 
-    // A. x = column k below the diagonal, partial norms
-    if (tx == (k & 31)) L.nrm[par][ty] = hess_put_x<TY, R, SC, S0>(L, a, k, n, par, ty);
+    // A. reflector, by the DPP row that holds column k
+    if (tx == (k & 31)) hess_reflector<TY, R, SC, S0>(L, a, k, n, par, ty);
     __syncthreads();
-    // reflector: v = x - alpha e_1, alpha = -(x_1/|x_1|) |x|,
-    // beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)); v_1 goes to LDS
-    double xn2 = 0.0;
-    #pragma unroll
-    for (int t = 0; t < TY; ++t) xn2 += L.nrm[par][t];
-    const double xn = sqrt(xn2);
-    const double2 x1 = L.x1[par];
-    const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
-    const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
-    const double beta = xn > 0.0 ? 1.0 / (xn * (xn + ax1)) : 0.0;
-    if (tid == 0) L.x[par][k + 1] = cmk(ph.x * (ax1 + xn), ph.y * (ax1 + xn));
-    __syncthreads();
+    const double beta = L.beta[par];
 
     // per-thread LDS bases; register rows and columns are constant offsets
     const double2 *xr = &L.x[par][ty], *xc = &L.x[par][tx];
@@ -1276,14 +1291,15 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
         const int h = tid & 1;
         const int j = tid >> 1;
         if (tid < 2 * CMAX && j >= 32 * S0) {
+            constexpr int PWS = HessLds<TY, R, SC>::PWS;
             const double2 *col = &L.PW[h * (TY / 2)][j];
             double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
             #pragma unroll
             for (int q = 0; q < TY / 2; q += 2) {
-                t0.x += col[q * CMAX].x;
-                t0.y += col[q * CMAX].y;
-                t1.x += col[(q + 1) * CMAX].x;
-                t1.y += col[(q + 1) * CMAX].y;
+                t0.x += col[q * PWS].x;
+                t0.y += col[q * PWS].y;
+                t1.x += col[(q + 1) * PWS].x;
+                t1.y += col[(q + 1) * PWS].y;
             }
             double2 t = cmk(t0.x + t1.x, t0.y + t1.y);
             t.x += quad_swap<0xB1>(t.x);  // lanes [1, 0, 3, 2]
@@ -1394,14 +1410,15 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
     constexpr int NMAX = Lds::NMAX, RMAX = Lds::RMAX, CMAX = Lds::CMAX, XMAX = Lds::XMAX;
     constexpr int NT = Lds::NT;
     static_assert(NT >= 512, "reductions assume 512 threads or more");
-    static_assert(2 * CMAX <= NT - 64 && 2 * RMAX <= NT - 64 && TY % 4 == 0, "reduction threads overlap");
+    static_assert(2 * CMAX <= NT - 64 && 2 * RMAX <= NT - 64, "reduction threads overlap");
+    static_assert(TY == 16, "one matrix column per 16-lane DPP row");
     extern __shared__ __align__(16) unsigned char hess_raw[];
     Lds &L = *reinterpret_cast<Lds *>(hess_raw);
     const int job = find_job(prefix, njobs, blockIdx.x);
     const HessDev J = jobs[job];
     const int kA = (int)(blockIdx.x - prefix[job]);
     const int n = J.n;
-    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    const int tid = threadIdx.x, ty = tid & (TY - 1), tx = tid / TY;
     double2 *__restrict__ C = pool + J.c_off + (int64_t)kA * n * n;
 
     // v is read at every index < XMAX; indices >= RMAX are never written
