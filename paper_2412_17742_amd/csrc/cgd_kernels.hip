@@ -1155,7 +1155,7 @@ constexpr int kHessDetThreads = 256;  // 4 waves x 4 points, 16 lanes per point
 // TY x 32 thread grid with TY = 16, ty = tid % 16 and tx = tid / 16: element
 // (i, j) in thread (i mod 16, j mod 32), register (i / 16, j / 32).  Matrix
 // column j is held by the 16 lanes of one DPP row (lanes 16 (tx mod 4) ..
-// 16 (tx mod 4) + 15 of wave tx / 4), so a column's sums need no LDS.  RMAX =
+// 16 (tx mod 4) + 15 of wave tx / 4), so sums down a column run in DPP.  RMAX =
 // 16 R rows and CMAX = 32 SC columns are held, orders n <= min(RMAX, CMAX).
 template <int TY, int R, int SC>
 struct HessLds {
@@ -1168,7 +1168,7 @@ struct HessLds {
     static constexpr int PWS = CMAX + 1;
     double2 x[2][XMAX];                    // v of step k (zero outside rows k+1..n-1), by step parity
     double beta[2];                        // 2 / |v|^2 of step k, by step parity
-    double2 PW[TY][PWS];                   // partials of w_j = sum_i conj(v_i) a_ij, per thread row
+    double2 PW[TY / 4][PWS];               // partials of w_j = sum_i conj(v_i) a_ij, per 4 thread rows
     double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column
     double2 PS[NT];                        // partials of s = v^H A v, per thread
     double2 W[CMAX], Y[RMAX];
@@ -1196,6 +1196,16 @@ __device__ __forceinline__ double row16_sum(double x) {
     x += quad_swap<0x141>(x);
     x += quad_swap<0x140>(x);
     return x;
+}
+
+// x of lane LANE of the wave (wave-uniform result)
+template <int LANE>
+__device__ __forceinline__ double lane_read(double x) {
+    const int2 u = __builtin_bit_cast(int2, x);
+    int2 v;
+    v.x = __builtin_amdgcn_readlane(u.x, LANE);
+    v.y = __builtin_amdgcn_readlane(u.y, LANE);
+    return __builtin_bit_cast(double, v);
 }
 
 // Reflector of step k, computed by the DPP row that holds column k (register
@@ -1250,7 +1260,7 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
 
     // per-thread LDS bases; register rows and columns are constant offsets
     const double2 *xr = &L.x[par][ty], *xc = &L.x[par][tx];
-    double2 *pyr = &L.PY[tx][ty], *pwr = &L.PW[ty][tx];
+    double2 *pyr = &L.PY[tx][ty], *pwr = &L.PW[ty / 4][tx];
     const double2 *yr = &L.Y[ty], *wc = &L.W[tx];
 
     // B. partial sums of y = A v (all rows), w = v^H A and s = v^H y
@@ -1278,65 +1288,69 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
             #pragma unroll
             for (int s = S0; s < SC; ++s) pw[s] = cfma_conj(vi, a[r][s], pw[s]);
         }
+        // sums over each DPP quad (four thread rows of one column); the four
+        // lanes store the same value to the same place, which keeps the code
+        // free of branches
+        #pragma unroll
+        for (int s = S0; s < SC; ++s) {
+            pw[s].x += quad_swap<0xB1>(pw[s].x);
+            pw[s].y += quad_swap<0xB1>(pw[s].y);
+            pw[s].x += quad_swap<0x4E>(pw[s].x);
+            pw[s].y += quad_swap<0x4E>(pw[s].y);
+        }
         #pragma unroll
         for (int s = S0; s < SC; ++s) pwr[32 * s] = pw[s];
     }
     L.PS[tid] = ps;
     __syncthreads();
 
-    // C. reductions, each in a fixed order: w_j by lanes 2j, 2j+1 and y_i by
-    // lanes 2i, 2i+1 (each lane half of the partials, the pair combined by a
-    // lane swap), s by the last wave
+    // C. reductions, each in a fixed order: y_i by lanes 2i, 2i+1 (each lane
+    // half of the 32 partials in four chains, the pair combined by a lane
+    // swap), w_j by lane 2 RMAX + j (four partials), s by the last wave
     {
         const int h = tid & 1;
         const int j = tid >> 1;
-        if (tid < 2 * CMAX && j >= 32 * S0) {
-            constexpr int PWS = HessLds<TY, R, SC>::PWS;
-            const double2 *col = &L.PW[h * (TY / 2)][j];
-            double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
-            #pragma unroll
-            for (int q = 0; q < TY / 2; q += 2) {
-                t0.x += col[q * PWS].x;
-                t0.y += col[q * PWS].y;
-                t1.x += col[(q + 1) * PWS].x;
-                t1.y += col[(q + 1) * PWS].y;
-            }
-            double2 t = cmk(t0.x + t1.x, t0.y + t1.y);
-            t.x += quad_swap<0xB1>(t.x);  // lanes [1, 0, 3, 2]
-            t.y += quad_swap<0xB1>(t.y);
-            if (h == 0) L.W[j] = t;
-        }
         if (tid < 2 * RMAX) {
             constexpr int PYS = HessLds<TY, R, SC>::PYS;
             const double2 *row = &L.PY[h * 16][j];
-            double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
+            double2 u[4];
             #pragma unroll
-            for (int q = 0; q < 16; q += 2) {
-                t0.x += row[q * PYS].x;
-                t0.y += row[q * PYS].y;
-                t1.x += row[(q + 1) * PYS].x;
-                t1.y += row[(q + 1) * PYS].y;
-            }
-            double2 t = cmk(t0.x + t1.x, t0.y + t1.y);
-            t.x += quad_swap<0xB1>(t.x);
+            for (int c = 0; c < 4; ++c) u[c] = row[c * PYS];
+            #pragma unroll
+            for (int q = 4; q < 16; q += 4)
+                #pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    u[c].x += row[(q + c) * PYS].x;
+                    u[c].y += row[(q + c) * PYS].y;
+                }
+            double2 t = cmk((u[0].x + u[1].x) + (u[2].x + u[3].x), (u[0].y + u[1].y) + (u[2].y + u[3].y));
+            t.x += quad_swap<0xB1>(t.x);  // lanes [1, 0, 3, 2]
             t.y += quad_swap<0xB1>(t.y);
             if (h == 0) L.Y[j] = t;
+        }
+        const int jw = tid - 2 * RMAX;
+        if (jw >= 32 * S0 && jw < CMAX) {
+            constexpr int PWS = HessLds<TY, R, SC>::PWS;
+            const double2 *col = &L.PW[0][jw];
+            const double2 u0 = col[0], u1 = col[PWS], u2 = col[2 * PWS], u3 = col[3 * PWS];
+            L.W[jw] = cmk((u0.x + u1.x) + (u2.x + u3.x), (u0.y + u1.y) + (u2.y + u3.y));
         }
     }
     if (tid >= NT - 64) {
         const int lane = tid & 63;
-        double2 t = cmk(0.0, 0.0);
+        double2 t0 = cmk(0.0, 0.0), t1 = cmk(0.0, 0.0);
         #pragma unroll
-        for (int q = 0; q < NT / 64; ++q) {
-            t.x += L.PS[lane + 64 * q].x;
-            t.y += L.PS[lane + 64 * q].y;
+        for (int q = 0; q < NT / 64; q += 2) {
+            t0.x += L.PS[lane + 64 * q].x;
+            t0.y += L.PS[lane + 64 * q].y;
+            t1.x += L.PS[lane + 64 * (q + 1)].x;
+            t1.y += L.PS[lane + 64 * (q + 1)].y;
         }
-        #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            t.x += __shfl_xor(t.x, off, 64);
-            t.y += __shfl_xor(t.y, off, 64);
-        }
-        if (lane == 0) L.S = t;
+        // DPP row sums, then the four rows in a fixed order
+        const double tx0 = row16_sum(t0.x + t1.x), ty0 = row16_sum(t0.y + t1.y);
+        const double sx = (lane_read<0>(tx0) + lane_read<16>(tx0)) + (lane_read<32>(tx0) + lane_read<48>(tx0));
+        const double sy = (lane_read<0>(ty0) + lane_read<16>(ty0)) + (lane_read<32>(ty0) + lane_read<48>(ty0));
+        if (lane == 0) L.S = cmk(sx, sy);
     }
     __syncthreads();
 
@@ -1410,7 +1424,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
     constexpr int NMAX = Lds::NMAX, RMAX = Lds::RMAX, CMAX = Lds::CMAX, XMAX = Lds::XMAX;
     constexpr int NT = Lds::NT;
     static_assert(NT >= 512, "reductions assume 512 threads or more");
-    static_assert(2 * CMAX <= NT - 64 && 2 * RMAX <= NT - 64, "reduction threads overlap");
+    static_assert(2 * RMAX + CMAX <= NT - 64, "reduction threads overlap");
     static_assert(TY == 16, "one matrix column per 16-lane DPP row");
     extern __shared__ __align__(16) unsigned char hess_raw[];
     Lds &L = *reinterpret_cast<Lds *>(hess_raw);
