@@ -1771,9 +1771,8 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
     const double2 *tw = twpool + S.tw_off;
     double2 acc = cmk(0.0, 0.0);
     int m = 0;  // k b mod G (b < G)
-    for (int k = 0; k < S.K; ++k) {
-        const double2 t = tw[m];
-        double2 v = src[(int64_t)k * S.inner];
+    // one term in the order of k; the loads of eight terms go out together
+    auto term = [&](int k, double2 v, double2 t) {
         if (S.final_stage) {
             const double wk = (k == 0 || 2 * k == S.G) ? 1.0 : 2.0;
             v.x *= wk;
@@ -1783,6 +1782,22 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
         acc.x = fma(-v.y, t.y, acc.x);
         acc.y = fma(v.x, t.y, acc.y);
         acc.y = fma(v.y, t.x, acc.y);
+    };
+    int k = 0;
+    for (; k + 8 <= S.K; k += 8) {
+        double2 v[8], t[8];
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            t[u] = tw[m];
+            v[u] = src[(int64_t)(k + u) * S.inner];
+            m += b;
+            if (m >= S.G) m -= S.G;
+        }
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) term(k + u, v[u], t[u]);
+    }
+    for (; k < S.K; ++k) {
+        term(k, src[(int64_t)k * S.inner], tw[m]);
         m += b;
         if (m >= S.G) m -= S.G;
     }
