@@ -1759,8 +1759,10 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
                           double2 *__restrict__ out, double *__restrict__ probs, double *__restrict__ err,
                           const int *__restrict__ status)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
+    // four lanes (one DPP quad) per output, lane c taking the terms k = c mod 4
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const int c = (int)(threadIdx.x & 3);
+    if (q >= total) return;  // whole quads leave together
     const int e = find_job(prefix, n, q);
     const DftStageDev S = st[e];
     const int64_t lq = q - prefix[e];
@@ -1770,8 +1772,6 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
     const double2 *src = in + S.in_off + o * S.K * S.inner + i;
     const double2 *tw = twpool + S.tw_off;
     double2 acc = cmk(0.0, 0.0);
-    int m = 0;  // k b mod G (b < G)
-    // one term in the order of k; the loads of eight terms go out together
     auto term = [&](int k, double2 v, double2 t) {
         if (S.final_stage) {
             const double wk = (k == 0 || 2 * k == S.G) ? 1.0 : 2.0;
@@ -1783,24 +1783,31 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
         acc.y = fma(v.x, t.y, acc.y);
         acc.y = fma(v.y, t.x, acc.y);
     };
-    int k = 0;
-    for (; k + 8 <= S.K; k += 8) {
-        double2 v[8], t[8];
+    const int b4 = (int)((4 * (int64_t)b) % S.G);
+    int m = (int)(((int64_t)c * b) % S.G);  // k b mod G
+    int k = c;
+    for (; k + 12 < S.K; k += 16) {
+        double2 v[4], t[4];
         #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             t[u] = tw[m];
-            v[u] = src[(int64_t)(k + u) * S.inner];
-            m += b;
+            v[u] = src[(int64_t)(k + 4 * u) * S.inner];
+            m += b4;
             if (m >= S.G) m -= S.G;
         }
         #pragma unroll
-        for (int u = 0; u < 8; ++u) term(k + u, v[u], t[u]);
+        for (int u = 0; u < 4; ++u) term(k + 4 * u, v[u], t[u]);
     }
-    for (; k < S.K; ++k) {
+    for (; k < S.K; k += 4) {
         term(k, src[(int64_t)k * S.inner], tw[m]);
-        m += b;
+        m += b4;
         if (m >= S.G) m -= S.G;
     }
+    acc.x += quad_swap<0xB1>(acc.x);
+    acc.y += quad_swap<0xB1>(acc.y);
+    acc.x += quad_swap<0x4E>(acc.x);
+    acc.y += quad_swap<0x4E>(acc.y);
+    if (c != 0) return;
     if (S.final_stage) {
         probs[S.out_off + lq] = acc.x * S.scale;
         if (lq == 0 && err) err[S.inst] = (*status) ? INFINITY : 0.0;
@@ -2269,7 +2276,7 @@ hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, in
                             const double2 *in, double2 *out, double *probs, double *err, const int *status,
                             hipStream_t st) {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dft_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, st_dev, prefix, n,
+    hipLaunchKernelGGL(dft_stage, dim3((unsigned)((4 * total + 255) / 256)), dim3(256), 0, st, st_dev, prefix, n,
                        total, tw, in, out, probs, err, status);
     return hipGetLastError();
 }
