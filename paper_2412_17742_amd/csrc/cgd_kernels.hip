@@ -1068,9 +1068,10 @@ pair_schur_f64(const PairDev *__restrict__ jobs, const int64_t *__restrict__ pre
 //     C(w_A) = H_BB + P diag(f) Q,  f_i = w_A / (1 - w_A lambda_i),
 // so that I - D_B C(w_A) is the Schur complement of S(w) on the other bins and
 // det S = prod_i (1 - w_A lambda_i) det(I - D_B C(w_A)).
-// One workgroup per (job, k, 8-row block of C).
+// One workgroup per (job, k, 4-row block of C): many small workgroups, since
+// each thread walks the whole inner dimension.
 // ---------------------------------------------------------------------------
-constexpr int kSchurRows = 8;
+constexpr int kSchurRows = 4;
 
 __global__ void __launch_bounds__(256)
 schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ job_prefix, int njobs,
@@ -1110,8 +1111,8 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
             const int r = r0 + rr;
             acc[rr] = r < J.nB ? Hbb[(int64_t)r * J.nB + col] : cmk(0.0, 0.0);
         }
-        for (int i = 0; i < J.nA; ++i) {
-            const double2 q = Q[(int64_t)i * J.nB + col];
+        // terms in the order of i; the loads of four rows of Q go out together
+        auto terms = [&](int i, double2 q) {
             #pragma unroll
             for (int rr = 0; rr < kSchurRows; ++rr) {
                 const double2 pf = s_pf[rr * J.nA + i];
@@ -1120,7 +1121,16 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
                 acc[rr].y = fma(pf.x, q.y, acc[rr].y);
                 acc[rr].y = fma(pf.y, q.x, acc[rr].y);
             }
+        };
+        int i = 0;
+        for (; i + 4 <= J.nA; i += 4) {
+            double2 q[4];
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = Q[(int64_t)(i + u) * J.nB + col];
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) terms(i + u, q[u]);
         }
+        for (; i < J.nA; ++i) terms(i, Q[(int64_t)i * J.nB + col]);
         #pragma unroll
         for (int rr = 0; rr < kSchurRows; ++rr) {
             const int r = r0 + rr;
