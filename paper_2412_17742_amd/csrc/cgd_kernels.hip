@@ -1162,16 +1162,18 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
 // ---------------------------------------------------------------------------
 constexpr int kHessDetThreads = 256;  // 4 waves x 4 points, 16 lanes per point
 
-// TY x 32 thread grid with TY = 16, ty = tid % 16 and tx = tid / 16: element
-// (i, j) in thread (i mod 16, j mod 32), register (i / 16, j / 32).  Matrix
-// column j is held by the 16 lanes of one DPP row (lanes 16 (tx mod 4) ..
-// 16 (tx mod 4) + 15 of wave tx / 4), so sums down a column run in DPP.  RMAX =
-// 16 R rows and CMAX = 32 SC columns are held, orders n <= min(RMAX, CMAX).
-template <int TY, int R, int SC>
+// TY x TX thread grid (TY = 16 or 32), ty = tid % TY and tx = tid / TY:
+// element (i, j) in thread (i mod TY, j mod TX), register (i / TY, j / TX).
+// Matrix column j is held by TY consecutive lanes of one wave (one DPP row,
+// or two), so sums down a column run in DPP.  RMAX = TY R rows and CMAX =
+// TX SC columns are held, orders n <= min(RMAX, CMAX).  The y partials (one
+// per column thread) number TX per row and the w partials (one per DPP quad)
+// TY / 4 per column.
+template <int TY, int TX, int R, int SC>
 struct HessLds {
-    static constexpr int NT = 32 * TY;
+    static constexpr int NT = TX * TY;
     static constexpr int RMAX = TY * R;
-    static constexpr int CMAX = 32 * SC;
+    static constexpr int CMAX = TX * SC;
     static constexpr int NMAX = RMAX < CMAX ? RMAX : CMAX;
     static constexpr int XMAX = RMAX > CMAX ? RMAX : CMAX;
     static constexpr int PYS = RMAX + 1;  // padded strides of the partial sums
@@ -1179,7 +1181,8 @@ struct HessLds {
     double2 x[2][XMAX];                    // v of step k (zero outside rows k+1..n-1), by step parity
     double beta[2];                        // 2 / |v|^2 of step k, by step parity
     double2 PW[TY / 4][PWS];               // partials of w_j = sum_i conj(v_i) a_ij, per 4 thread rows
-    double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column
+    double2 PY[32][PYS];                   // partials of y_i = sum_j a_ij v_j, per thread column (TX <= 32
+                                           // rows used; 32 so that it can stage the matrix)
     double2 PS[NT];                        // partials of s = v^H A v, per thread
     double2 W[CMAX], Y[RMAX];
     double2 S;
@@ -1208,6 +1211,22 @@ __device__ __forceinline__ double row16_sum(double x) {
     return x;
 }
 
+// Sum over the TY lanes that hold one matrix column: one DPP row (TY = 16),
+// or two adjacent rows (TY = 32), whose row sums a 16-lane swap adds.
+template <int TY>
+__device__ __forceinline__ double col_sum(double x) {
+    x = row16_sum(x);
+    if constexpr (TY == 32) {
+        const int2 u = __builtin_bit_cast(int2, x);
+        const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u.x, (unsigned)u.x, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)u.y, (unsigned)u.y, false, false);
+        const double a = __builtin_bit_cast(double, make_uint2(lo[0], hi[0]));
+        const double b = __builtin_bit_cast(double, make_uint2(lo[1], hi[1]));
+        x = a + b;
+    }
+    return x;
+}
+
 // x of lane LANE of the wave (wave-uniform result)
 template <int LANE>
 __device__ __forceinline__ double lane_read(double x) {
@@ -1218,13 +1237,13 @@ __device__ __forceinline__ double lane_read(double x) {
     return __builtin_bit_cast(double, v);
 }
 
-// Reflector of step k, computed by the DPP row that holds column k (register
+// Reflector of step k, computed by the lanes that hold column k (register
 // column S): x = column k below the diagonal goes to L.x[par] (zero at rows
 // <= k and >= n), then v_1 = x_1 - alpha with alpha = -(x_1/|x_1|) |x|
 // replaces x_1 there, and beta = 2 / |v|^2 = 1 / (|x| (|x| + |x_1|)) goes to
-// L.beta[par].  All 16 lanes of the row must be active.
-template <int TY, int R, int SC, int S>
-__device__ __forceinline__ void hess_reflector(HessLds<TY, R, SC> &L, const double2 (&a)[R][SC], int k, int n,
+// L.beta[par].  All TY lanes of the column must be active.
+template <int TY, int TX, int R, int SC, int S>
+__device__ __forceinline__ void hess_reflector(HessLds<TY, TX, R, SC> &L, const double2 (&a)[R][SC], int k, int n,
                                                int par, int ty) {
     double acc = 0.0;
     double2 x1 = cmk(0.0, 0.0);
@@ -1239,9 +1258,9 @@ __device__ __forceinline__ void hess_reflector(HessLds<TY, R, SC> &L, const doub
         x1.x = i == k + 1 ? xi.x : x1.x;
         x1.y = i == k + 1 ? xi.y : x1.y;
     }
-    const double xn = sqrt(row16_sum(acc));
-    x1.x = row16_sum(x1.x);  // one nonzero term
-    x1.y = row16_sum(x1.y);
+    const double xn = sqrt(col_sum<TY>(acc));
+    x1.x = col_sum<TY>(x1.x);  // one nonzero term
+    x1.y = col_sum<TY>(x1.y);
     const double ax1 = sqrt(x1.x * x1.x + x1.y * x1.y);
     if (ty == ((k + 1) & (TY - 1))) {
         const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
@@ -1251,20 +1270,20 @@ __device__ __forceinline__ void hess_reflector(HessLds<TY, R, SC> &L, const doub
 }
 
 // One Householder step k (column k) of hess_reduce_f64, R0 = k / TY and
-// S0 = k / 32.  Register rows r < R0 hold only rows < k, where v vanishes;
+// S0 = k / TX.  Register rows r < R0 hold only rows < k, where v vanishes;
 // register columns s < S0 hold only columns < k, where v vanishes, so their
 // entries on or above the subdiagonal (rows i <= j + 1 <= k) do not change.  The
 // terms they would carry are left out at compile time.  Column k becomes
 // (alpha, O(eps |x|), ...) below the diagonal; what is left below the
 // subdiagonal never reaches the Hessenberg part (v vanishes on those rows and
 // columns in every later step) and is written out as zero.
-template <int TY, int R, int SC, int R0, int S0>
-__device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int k, int n, int tid) {
-    constexpr int NT = 32 * TY, RMAX = TY * R, CMAX = 32 * SC;
+template <int TY, int TX, int R, int SC, int R0, int S0>
+__device__ __forceinline__ void hess_step(HessLds<TY, TX, R, SC> &L, double2 (&a)[R][SC], int k, int n, int tid) {
+    constexpr int NT = TX * TY, RMAX = TY * R, CMAX = TX * SC;
     const int par = k & 1, ty = tid & (TY - 1), tx = tid / TY;
 
-    // A. reflector, by the DPP row that holds column k
-    if (tx == (k & 31)) hess_reflector<TY, R, SC, S0>(L, a, k, n, par, ty);
+    // A. reflector, by the lanes that hold column k
+    if (tx == k % TX) hess_reflector<TY, TX, R, SC, S0>(L, a, k, n, par, ty);
     __syncthreads();
     const double beta = L.beta[par];
 
@@ -1278,7 +1297,7 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     {
         double2 vj[SC];
         #pragma unroll
-        for (int s = S0; s < SC; ++s) vj[s] = xc[32 * s];
+        for (int s = S0; s < SC; ++s) vj[s] = xc[TX * s];
         #pragma unroll
         for (int r = 0; r < R; ++r) {
             double2 py = cmk(0.0, 0.0);
@@ -1309,41 +1328,41 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
             pw[s].y += quad_swap<0x4E>(pw[s].y);
         }
         #pragma unroll
-        for (int s = S0; s < SC; ++s) pwr[32 * s] = pw[s];
+        for (int s = S0; s < SC; ++s) pwr[TX * s] = pw[s];
     }
     L.PS[tid] = ps;
     __syncthreads();
 
-    // C. reductions, each in a fixed order: y_i by lanes 2i, 2i+1 (each lane
-    // half of the 32 partials in four chains, the pair combined by a lane
-    // swap), w_j by lane 2 RMAX + j (four partials), s by the last wave
+    // C. reductions, each in a fixed order: y_i by lane i (TX partials, four
+    // loads at a time), w_j by lane RMAX + j (TY / 4 partials), s by the last
+    // wave
     {
-        const int h = tid & 1;
-        const int j = tid >> 1;
-        if (tid < 2 * RMAX) {
-            constexpr int PYS = HessLds<TY, R, SC>::PYS;
-            const double2 *row = &L.PY[h * 16][j];
-            double2 u[4];
+        if (tid < RMAX) {
+            constexpr int PYS = HessLds<TY, TX, R, SC>::PYS;
+            const double2 *row = &L.PY[0][tid];
+            double2 t = cmk(0.0, 0.0);
             #pragma unroll
-            for (int c = 0; c < 4; ++c) u[c] = row[c * PYS];
-            #pragma unroll
-            for (int q = 4; q < 16; q += 4)
-                #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    u[c].x += row[(q + c) * PYS].x;
-                    u[c].y += row[(q + c) * PYS].y;
-                }
-            double2 t = cmk((u[0].x + u[1].x) + (u[2].x + u[3].x), (u[0].y + u[1].y) + (u[2].y + u[3].y));
-            t.x += quad_swap<0xB1>(t.x);  // lanes [1, 0, 3, 2]
-            t.y += quad_swap<0xB1>(t.y);
-            if (h == 0) L.Y[j] = t;
+            for (int q = 0; q < TX; q += 4) {
+                const double2 u0 = row[q * PYS], u1 = row[(q + 1) * PYS];
+                const double2 u2 = row[(q + 2) * PYS], u3 = row[(q + 3) * PYS];
+                t.x += (u0.x + u1.x) + (u2.x + u3.x);
+                t.y += (u0.y + u1.y) + (u2.y + u3.y);
+            }
+            L.Y[tid] = t;
         }
-        const int jw = tid - 2 * RMAX;
-        if (jw >= 32 * S0 && jw < CMAX) {
-            constexpr int PWS = HessLds<TY, R, SC>::PWS;
+        const int jw = tid - RMAX;
+        if (jw >= TX * S0 && jw < CMAX) {
+            constexpr int PWS = HessLds<TY, TX, R, SC>::PWS;
             const double2 *col = &L.PW[0][jw];
-            const double2 u0 = col[0], u1 = col[PWS], u2 = col[2 * PWS], u3 = col[3 * PWS];
-            L.W[jw] = cmk((u0.x + u1.x) + (u2.x + u3.x), (u0.y + u1.y) + (u2.y + u3.y));
+            double2 t = cmk(0.0, 0.0);
+            #pragma unroll
+            for (int q = 0; q < TY / 4; q += 4) {
+                const double2 u0 = col[q * PWS], u1 = col[(q + 1) * PWS];
+                const double2 u2 = col[(q + 2) * PWS], u3 = col[(q + 3) * PWS];
+                t.x += (u0.x + u1.x) + (u2.x + u3.x);
+                t.y += (u0.y + u1.y) + (u2.y + u3.y);
+            }
+            L.W[jw] = t;
         }
     }
     if (tid >= NT - 64) {
@@ -1372,7 +1391,7 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
         double2 cvj[SC];
         #pragma unroll
         for (int s = S0; s < SC; ++s) {
-            const double2 v = xc[32 * s];
+            const double2 v = xc[TX * s];
             cvj[s] = cmk(v.x, -v.y);
         }
         #pragma unroll
@@ -1392,7 +1411,7 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     {
         double2 wj[SC];
         #pragma unroll
-        for (int s = S0; s < SC; ++s) wj[s] = wc[32 * s];
+        for (int s = S0; s < SC; ++s) wj[s] = wc[TX * s];
         #pragma unroll
         for (int r = R0; r < R; ++r) {
             const double2 vi = xr[TY * r];
@@ -1403,15 +1422,15 @@ __device__ __forceinline__ void hess_step(HessLds<TY, R, SC> &L, double2 (&a)[R]
     }
 }
 
-// Steps k with (k / TY, k / 32) = (R0, S0), then the following values: one
+// Steps k with (k / TY, k / TX) = (R0, S0), then the following values: one
 // loop per pair, so that each loop body is straight-line code.
-template <int TY, int R, int SC, int R0, int S0>
-__device__ __forceinline__ void hess_steps_from(HessLds<TY, R, SC> &L, double2 (&a)[R][SC], int n, int tid) {
-    constexpr int RE = TY * (R0 + 1), SE = 32 * (S0 + 1);  // where R0, S0 change
-    const int k_lo = max(TY * R0, 32 * S0), k_hi = min(min(RE, SE), n - 2);
-    for (int k = k_lo; k < k_hi; ++k) hess_step<TY, R, SC, R0, S0>(L, a, k, n, tid);
+template <int TY, int TX, int R, int SC, int R0, int S0>
+__device__ __forceinline__ void hess_steps_from(HessLds<TY, TX, R, SC> &L, double2 (&a)[R][SC], int n, int tid) {
+    constexpr int RE = TY * (R0 + 1), SE = TX * (S0 + 1);  // where R0, S0 change
+    const int k_lo = max(TY * R0, TX * S0), k_hi = min(min(RE, SE), n - 2);
+    for (int k = k_lo; k < k_hi; ++k) hess_step<TY, TX, R, SC, R0, S0>(L, a, k, n, tid);
     constexpr int R1 = R0 + (RE <= SE ? 1 : 0), S1 = S0 + (SE <= RE ? 1 : 0);
-    if constexpr (R1 < R && S1 < SC) hess_steps_from<TY, R, SC, R1, S1>(L, a, n, tid);
+    if constexpr (R1 < R && S1 < SC) hess_steps_from<TY, TX, R, SC, R1, S1>(L, a, n, tid);
 }
 
 // Householder reduction to upper Hessenberg form of C(w_A), one workgroup per
@@ -1423,19 +1442,19 @@ __device__ __forceinline__ void hess_steps_from(HessLds<TY, R, SC> &L, double2 (
 // LDS, padding included); only whole register rows and columns that carry no
 // terms are left out (hess_step).  Entries below the subdiagonal are written
 // as zero.  Also writes sum_i Log(1 - w_A lambda_i) of the eliminated bin.
-template <int TY, int R, int SC>
-__global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__restrict__ jobs,
+template <int TY, int TX, int R, int SC>
+__global__ void __launch_bounds__(TX * TY) hess_reduce_f64(const HessDev *__restrict__ jobs,
                                                                  const int64_t *__restrict__ prefix, int njobs,
                                                                  double2 *__restrict__ pool,
                                                                  const double *__restrict__ eigpool,
                                                                  double2 *__restrict__ eigc)
 {
-    using Lds = HessLds<TY, R, SC>;
+    using Lds = HessLds<TY, TX, R, SC>;
     constexpr int NMAX = Lds::NMAX, RMAX = Lds::RMAX, CMAX = Lds::CMAX, XMAX = Lds::XMAX;
     constexpr int NT = Lds::NT;
     static_assert(NT >= 512, "reductions assume 512 threads or more");
-    static_assert(2 * RMAX + CMAX <= NT - 64, "reduction threads overlap");
-    static_assert(TY == 16, "one matrix column per 16-lane DPP row");
+    static_assert(RMAX + CMAX <= NT - 64 && TX % 4 == 0 && TX <= 32, "reduction threads overlap");
+    static_assert(TY == 16 || TY == 32, "one matrix column per one or two 16-lane DPP rows");
     extern __shared__ __align__(16) unsigned char hess_raw[];
     Lds &L = *reinterpret_cast<Lds *>(hess_raw);
     const int job = find_job(prefix, njobs, blockIdx.x);
@@ -1465,7 +1484,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
         for (int r = c0; r < c0 + CR && r < R; ++r)
             #pragma unroll
             for (int s = 0; s < SC; ++s) {
-                const int i = ty + TY * r, j = tx + 32 * s;
+                const int i = ty + TY * r, j = tx + TX * s;
                 const bool in = i < n && j < n;
                 const double2 h = stage[in ? (i - i0) * n + j : 0];
                 a[r][s] = in ? h : cmk(0.0, 0.0);
@@ -1473,7 +1492,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
         __syncthreads();
     }
 
-    hess_steps_from<TY, R, SC, 0, 0>(L, a, n, tid);
+    hess_steps_from<TY, TX, R, SC, 0, 0>(L, a, n, tid);
 
     __syncthreads();
     #pragma unroll
@@ -1484,7 +1503,7 @@ __global__ void __launch_bounds__(32 * TY) hess_reduce_f64(const HessDev *__rest
         for (int r = c0; r < c0 + CR && r < R; ++r)
             #pragma unroll
             for (int s = 0; s < SC; ++s) {
-                const int i = ty + TY * r, j = tx + 32 * s;
+                const int i = ty + TY * r, j = tx + TX * s;
                 if (i < n && j < n) stage[(i - i0) * n + j] = i > j + 1 ? cmk(0.0, 0.0) : a[r][s];
             }
         __syncthreads();
@@ -2385,10 +2404,10 @@ int hess_class_limit(int cls) {
     }
 }
 
-template <int TY, int R, int SC>
+template <int TY, int TX, int R, int SC>
 static hipError_t launch_hr(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, double2 *pool,
                             const double *eigpool, double2 *eigc, hipStream_t st) {
-    hipLaunchKernelGGL((hess_reduce_f64<TY, R, SC>), dim3((unsigned)nwg), dim3(32 * TY), sizeof(HessLds<TY, R, SC>),
+    hipLaunchKernelGGL((hess_reduce_f64<TY, TX, R, SC>), dim3((unsigned)nwg), dim3(TX * TY), sizeof(HessLds<TY, TX, R, SC>),
                        st, jobs, prefix, njobs, pool, eigpool, eigc);
     return hipGetLastError();
 }
@@ -2397,10 +2416,10 @@ hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefi
                               double2 *pool, const double *eigpool, double2 *eigc, hipStream_t st) {
     if (nwg <= 0) return hipSuccess;
     switch (cls) {
-        case 0: return launch_hr<16, 2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 1: return launch_hr<16, 4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 2: return launch_hr<16, 6, 3>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
-        case 3: return launch_hr<16, 9, 5>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 0: return launch_hr<16, 32, 2, 1>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 1: return launch_hr<16, 32, 4, 2>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 2: return launch_hr<16, 32, 6, 3>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
+        case 3: return launch_hr<32, 16, 5, 9>(jobs, prefix, njobs, nwg, pool, eigpool, eigc, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2436,14 +2455,14 @@ hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int n
 }
 
 hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
-    for (hipError_t e : {hipFuncSetAttribute((const void *)hess_reduce_f64<16, 2, 1>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 2, 1>)),
-                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 4, 2>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 4, 2>)),
-                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 6, 3>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 6, 3>)),
-                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 9, 5>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 9, 5>)),
+    for (hipError_t e : {hipFuncSetAttribute((const void *)hess_reduce_f64<16, 32, 2, 1>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 32, 2, 1>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 32, 4, 2>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 32, 4, 2>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<16, 32, 6, 3>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<16, 32, 6, 3>)),
+                         hipFuncSetAttribute((const void *)hess_reduce_f64<32, 16, 5, 9>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<32, 16, 5, 9>)),
                          hipFuncSetAttribute((const void *)hess_det_f64<9>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                              hess_det_lds_bytes(9))})
         if (e != hipSuccess) return e;
