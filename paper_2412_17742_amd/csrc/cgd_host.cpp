@@ -547,7 +547,7 @@ void free_ctx(cgd_ctx *c) {
 // or few points per reduction, the factorisations per point are faster.  Both
 // sides are estimated from per-kernel times measured on MI355X, in
 // microseconds of one compute unit:
-//   reduction    (n - 2) steps of t_step (1.4, 2.0, 3.0, 3.9 us for orders
+//   reduction    (n - 2) steps of t_step (1.4, 2.0, 3.0, 3.4 us for orders
 //                <= 32, 64, 96, 144), one reduction per compute unit at a time;
 //   Hessenberg   3.7 (n / 144)^2 per point;
 //   partial LU   680 (n^3 - nB^3) / 192^3 per pair (blocked FP64 LU);
@@ -572,7 +572,7 @@ bool choose_hessenberg(const cgd_ctx *c, const std::vector<HostBlock> &hb, std::
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
         ncu = 256;
-    static constexpr double t_step[kHessClasses] = {1.4, 2.0, 3.0, 3.9};
+    static constexpr double t_step[kHessClasses] = {1.4, 2.0, 3.0, 3.4};
     double red_n[kHessClasses] = {};  // total reductions per class
     double red_t[kHessClasses] = {};  // longest reduction per class
     double det_cu = 0.0, plu_cu = 0.0, lu_cu = 0.0;
