@@ -83,9 +83,11 @@ def test_fock_heralding_fidelities():
             assert abs(F - F_paper) <= 0.5 * 10 ** (-case["decimals"]) + 1e-12
 
 
-@pytest.mark.parametrize("mA, mB", [(16, 16), (18, 17), (32, 32), (34, 33), (72, 72)])
+@pytest.mark.parametrize("mA, mB", [(16, 16), (18, 17), (32, 32), (34, 33), (48, 48), (50, 49), (60, 59),
+                                    (72, 72)])
 def test_orders_at_class_edges(mA, mB):
-    # B has 2 mB rows: orders 32, 34, 64, 66, 144 after eliminating A
+    # B has 2 mB rows: orders 32, 34, 64, 66, 96, 98, 118, 144 after eliminating
+    # A (98 and 118 leave the order-144 class with partial row and column blocks)
     _say("orders at class edges:", 2 * mB)
     inst = _two_bin_instance(mA, mB, mB, grid=[3, 5])
     assert _route_taken([inst], H)
