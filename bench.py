@@ -46,6 +46,8 @@ WORKLOADS = {
     "uneven512": ("512 uneven instances: M~U{8..64}, K~U{1..4}, L~U{1..4}, cutoffs~U{4..12}", W.uneven_batch),
     "mesh32_k4": ("64 parameter sets: M=32, K=4, 2 bins of 16, cutoff 12 (256x256 complex per point)", W.mesh_batch),
 }
+# reported beside the main workload in the same JSON line
+EXTRA = ["gbs144_2bins", "gbs144_3bins", "lossy16_k3", "mesh32_k4"]
 
 
 def recorded_traffic(kernel: str, workload: str):
@@ -67,30 +69,40 @@ def recorded_traffic(kernel: str, workload: str):
     return None
 
 
-def cpu_baseline(instances, seconds: float):
+def cpu_baseline(instances, seconds: float, threads=None):
     """Oracle per-point evaluations (eigenvalue log-det + solve) on a bounded
-    sample of the workload's grid points, as grid dets/s."""
+    sample of the workload's grid points, as grid dets/s.  threads=None: the
+    BLAS threads numpy starts with (all host cores); otherwise limited to
+    that many."""
     from oracle import pgf
     from oracle import state as st
+    import contextlib
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
     except Exception:  # pragma: no cover
-        cores = os.cpu_count()
-    rng = np.random.default_rng(0)
-    states = [st.assemble(x) for x in instances]
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        i = int(rng.integers(len(instances)))
-        G = np.asarray(instances[i]["grid"], dtype=float)
-        k = np.array([rng.integers(int(g)) for g in G])
-        pgf.log_pgf(states[i], np.exp(2j * np.pi * k / G))
-        n += 1
-    dt = time.perf_counter() - t0
+        threadpool_info = threadpool_limits = None
+    limit = contextlib.nullcontext() if threads is None or threadpool_limits is None \
+        else threadpool_limits(limits=threads)
+    with limit:
+        if threadpool_info is not None:
+            cores = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        else:  # pragma: no cover
+            cores = threads or os.cpu_count()
+        rng = np.random.default_rng(0)
+        states = [st.assemble(x) for x in instances]
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            i = int(rng.integers(len(instances)))
+            G = np.asarray(instances[i]["grid"], dtype=float)
+            k = np.array([rng.integers(int(g)) for g in G])
+            pgf.log_pgf(states[i], np.exp(2j * np.pi * k / G))
+            n += 1
+        dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="grid dets/s", cores=int(cores), kind="oracle",
-                sample=f"{n} random grid points of the same workload, each by eigenvalues of D(w)XA "
-                       f"plus a dense solve (numpy/LAPACK, FP64), {dt:.1f} s")
+                sample=f"{n} random grid points (instance, then point, uniformly at random) of the same "
+                       f"workload, each by eigenvalues of D(w)XA plus a dense solve (numpy/LAPACK, FP64), "
+                       f"{dt:.1f} s on {int(cores)} BLAS thread(s)")
 
 
 def grad_timing(cgd, instances, steps, warmup, flags):
@@ -131,21 +143,65 @@ def run(ctx, steps, warmup):
     return s.elapsed_time(e) / steps, wall / steps * 1e3, probs
 
 
-def extra_workload(cgd, name, steps, warmup, tol):
-    """Grid dets/s of a second workload, both precisions (the faster one that
+def extra_workload(cgd, name, steps, warmup, tol, grad=False):
+    """Grid dets/s of another workload, both precisions (the faster one that
     stays within tol of FP64 counts), for the same JSON line."""
+    import torch
     desc, make = WORKLOADS[name]
     insts = make()
-    ms, probs = {}, {}
+    ms, probs, create_s, stats = {}, {}, {}, None
     for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
         with cgd.Context(insts, precision=prec, tol=tol) as ctx:
+            create_s[prec] = time.perf_counter() - t0
             ms[prec], _, p = run(ctx, steps, warmup)
             probs[prec] = p.clone()
             npts = ctx.n_points
-    ok = float((probs["mixed"] - probs["fp64"]).abs().max().item()) <= tol
+            if prec == "mixed":
+                err = torch.zeros(ctx.n_inst, dtype=torch.float64, device="cuda")
+                ctx.eval(probs[prec], err)
+                stats = ctx.mixed_stats()
+                err_bound = float(err.max().item())
+    maxdiff = float((probs["mixed"] - probs["fp64"]).abs().max().item())
+    ok = maxdiff <= tol
     best = "mixed" if ok and ms["mixed"] < ms["fp64"] else "fp64"
-    return {"workload": f"{name}: {desc}", "value": npts / (ms[best] * 1e-3), "unit": "grid dets/s",
-            "precision": best, "ms_per_step": ms[best], "fp64_ms": ms["fp64"], "mixed_ms": ms["mixed"]}
+    out = {"workload": f"{name}: {desc}", "value": npts / (ms[best] * 1e-3), "unit": "grid dets/s",
+           "precision": best, "ms_per_step": ms[best], "evaluated_points": npts,
+           "fp64_ms": ms["fp64"], "mixed_ms": ms["mixed"], "mixed_max_abs_diff_vs_fp64": maxdiff,
+           "mixed_err_bound": err_bound, "refactorised_fp64": stats[0], "factorisations": stats[1],
+           "create_s": create_s}
+    if grad:
+        out["grad"] = grad_timing(cgd, insts, max(2, steps // 4), 1, 0)
+    return out
+
+
+def _tuned_class(tuning, stage):
+    k = cgd_stages_lu().index(stage)
+    for c in tuning.get("classes", []):
+        if c["class"] == k:
+            return c
+    return None
+
+
+def cgd_stages_lu():
+    return ["lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144"]
+
+
+def lu_precision(tuning, stage):
+    """Precision the autotuner chose for an LU stage ('fp32+fp64' or 'fp64');
+    without a report, the FP32 pass runs for every eligible class."""
+    c = _tuned_class(tuning, stage)
+    if c is None:
+        return "fp32+fp64" if tuning.get("precision") == "mixed" else "fp64"
+    return c["precision"]
+
+
+def fp64_kernel_name(tuning, stage):
+    import paper_2412_17742_amd as cgd
+    c = _tuned_class(tuning, stage) if stage in cgd_stages_lu() else None
+    if c is not None and c["fp64_kernel"] == "lu_wave":
+        return f"lu_wave<double,{32 if c['class'] == 0 else 64}>"
+    return cgd.LU_KERNELS.get(stage, (stage,))[0]
 
 
 def stage_profile(ctx, steps):
@@ -167,12 +223,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="gbs144_2bins", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="uneven512", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tol", type=float, default=1e-9, help="absolute error budget per probability (mixed path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the second workload (lossy16_k3) reported beside the main one")
+                    help="skip the other workloads reported beside the main one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 3 times (scale for HBM byte counters)")
     ap.add_argument("--grad", action="store_true",
@@ -212,8 +268,10 @@ def main():
         ms, wall_ms, probs = run(ctx, args.steps, args.warmup)
         stages = stage_profile(ctx, max(3, min(args.steps, 10)))
         flops, bytes_ = ctx.stage_work()
+        tuning = ctx.tuning()
+        tuning["precision"] = prec
         rec = dict(ctx=ctx, ms=ms, wall_ms=wall_ms, probs=probs.clone(), stages=stages, flops=flops,
-                   bytes=bytes_, create_s=create_s)
+                   bytes=bytes_, create_s=create_s, tuning=tuning)
         if prec == "mixed":
             err = torch.zeros(ctx.n_inst, dtype=torch.float64, device="cuda")
             ctx.eval(rec["probs"], err)
@@ -243,7 +301,7 @@ def main():
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
         kname = "hess_reduce_f64" if dom == "hess" else "hess_det_f64"
-    elif best == "mixed" and dom in cgd.LU_KERNELS:
+    elif dom in cgd.LU_KERNELS and lu_precision(B["tuning"], dom) == "fp32+fp64":
         # first pass of the mixed path: complex FP32 elimination on MFMA (16x16x4 f32)
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
         roof = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s")
@@ -252,7 +310,7 @@ def main():
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
         # FP64 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
-        kname = cgd.LU_KERNELS.get(dom, (dom,))[0]
+        kname = fp64_kernel_name(B["tuning"], dom)
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = kname
     roof["stage"] = dom
@@ -261,7 +319,8 @@ def main():
 
     def summary(rec, name):
         out = dict(grid_dets_per_s=n_points / (rec["ms"] * 1e-3), probs_per_s=n_probs / (rec["ms"] * 1e-3),
-                   ms_per_step=rec["ms"], stage_ms=rec["stages"], create_s=rec["create_s"])
+                   ms_per_step=rec["ms"], stage_ms=rec["stages"], create_s=rec["create_s"],
+                   autotune=rec["tuning"].get("classes"))
         if name == "mixed":
             out.update(max_abs_diff_vs_fp64=maxdiff, err_bound=rec["err_bound"],
                        refactorised_fp64=rec["refactorised"], factorisations=rec["factorisations"],
@@ -293,12 +352,17 @@ def main():
     }
     if args.grad:
         out["grad"] = grad_timing(cgd, instances, args.steps, args.warmup, args.flags)
-    if not args.no_extra and args.workload != "lossy16_k3":
-        out["lossy16_k3"] = extra_workload(cgd, "lossy16_k3", args.steps, args.warmup, args.tol)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(instances, args.cpu_seconds)
     for rec in paths.values():
         rec["ctx"].close()
+    if not args.no_extra:
+        out["other_workloads"] = {}
+        for name in EXTRA:
+            if name != args.workload:
+                out["other_workloads"][name] = extra_workload(cgd, name, args.steps, args.warmup, args.tol,
+                                                              grad=name == "mesh32_k4")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(instances, args.cpu_seconds)
+        out["cpu_baseline"]["one_core"] = cpu_baseline(instances, args.cpu_seconds, threads=1)
     print(json.dumps(out), flush=True)
 
 

@@ -59,9 +59,10 @@ typedef enum {
 
 typedef enum {
     CGD_PREC_FP64 = 0,  /* complex128 factorisations everywhere                          */
-    CGD_PREC_MIXED = 1  /* complex64 factorisations (MFMA) at every grid point, then a
-                           complex128 re-factorisation of the points whose FP32 value
-                           could move a probability by more than tol (see cgd_create) */
+    CGD_PREC_MIXED = 1  /* complex64 factorisations at every grid point, then a complex128
+                           re-factorisation of the points with the largest |G| until the
+                           error bound of the points left in FP32 is within tol
+                           (see cgd_create) */
 } cgd_precision;
 
 /* cgd_create flags */
@@ -85,6 +86,9 @@ typedef enum {
 #define CGD_FLAG_NO_HESSENBERG 16u /* never take the Hessenberg route                        */
 #define CGD_FLAG_GRAD 4u           /* prepare cgd_grad (keeps each internal block's full
                                       matrix on the device); needs 2M(+1) <= 96 per block */
+#define CGD_FLAG_NO_AUTOTUNE 32u   /* skip the autotuner of cgd_create: default kernel shape
+                                      per size class, FP32 pass for every eligible class on
+                                      the mixed path (see cgd_tuning)                      */
 
 /* One instance (a Gaussian state plus its binning).  Sec. VI A (set partition
  * Lambda, coarse pattern b), Sec. VI B (internal modes). */
@@ -108,10 +112,14 @@ typedef struct {
  * needs.  n_inst instances are evaluated together by cgd_eval.
  *   prec        CGD_PREC_FP64 or CGD_PREC_MIXED
  *   tol         absolute error budget per probability for the mixed path (e.g.
- *               1e-9): a point is re-factorised in FP64 when |G| tau > tol, tau
- *               being the assumed relative error of its FP32 value (2 (n+1) 2^-24
- *               summed over its blocks of order n), so the FP32 points left add
- *               at most tol to any probability; ignored for FP64
+ *               1e-9).  A point's FP32 value of G is taken to carry a relative
+ *               error of at most tau (2 (n+1) 2^-24 summed over its blocks of
+ *               order n) and enters every probability as c_k |G_k| tau / prod G
+ *               (c_k = 1 or 2 on the Hermitian half grid).  Per instance, the
+ *               points are ranked by |G| (quarter-octave buckets); the smallest
+ *               ones stay in FP32 as long as their summed c_k |G_k| tau / prod G
+ *               is at most tol, the others are factorised again in FP64;
+ *               ignored for FP64
  *   flags       0 or CGD_FLAG_* bits
  *   hip_stream  hipStream_t to enqueue on, or NULL for the null stream
  * Errors: CGD_ERR_ARG / CGD_ERR_NONPHYSICAL synchronously, before any launch.
@@ -131,7 +139,7 @@ cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_
  * n_probs_total doubles).  d_err_bound (device, n_inst doubles, or NULL)
  * receives, per instance, a bound on the absolute error added by the mixed
  * path to every probability: (1/prod G) sum over the points kept in FP32 of
- * c_k |G_k| tau, with tau the assumed relative error of an FP32 value of G
+ * c_k |G_k| tau, with tau the modelled relative error of an FP32 value of G
  * (0 on the FP64 path; +inf after a numeric failure).  A numeric failure
  * detected on the device is reported by the next call as CGD_ERR_NUMERIC. */
 cgd_status cgd_eval(cgd_ctx *ctx, double *d_probs, double *d_err_bound);
@@ -174,9 +182,10 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  *                        leaves the matrix the Hessenberg stages reduce
  *   CGD_STAGE_FIX        mixed path: selection of the points whose FP32 value can
  *                        matter, their FP64 re-factorisation and the second combine
- * With timing enabled, cgd_eval records a HIP event pair on the context's
- * stream around every stage; cgd_stage_times waits for the last evaluation
- * and returns each stage's duration in ms (-1 for stages with no work).
+ * With timing enabled, cgd_eval runs eagerly and records a HIP event pair on
+ * the context's stream around every launch of a stage; cgd_stage_times waits
+ * for the last evaluation and returns, per stage, the sum of its launches'
+ * durations in ms (-1 for stages with no work).
  * cgd_stage_work returns each stage's algorithmic work per evaluation:
  * flops (complex LU of order n: 8 sum_m m^2 + 6 sum_m m, m = n-1..0, i.e.
  * about 8n^3/3 real flops; Schur build: 8 nA nB^2 per eliminated-bin value;
@@ -207,6 +216,17 @@ cgd_status cgd_stage_work(const cgd_ctx *ctx, double *flops /* CGD_NSTAGES */, d
  * evaluation.  Waits for the last evaluation.  CGD_ERR_STATE on the FP64 path
  * or before the first evaluation. */
 cgd_status cgd_mixed_stats(cgd_ctx *ctx, int64_t *n_refactored, int64_t *n_total);
+
+/* Autotuner report (JSON text, valid until cgd_destroy; NULL if ctx is NULL).
+ * cgd_create times, for every size class of per-point factorisations in the
+ * context, each candidate kernel shape on a sample of up to 8192 of the
+ * class's own (block, grid point) items: the thread grids of the FP64 register
+ * kernel and, on the mixed path, the wave layouts of the FP32 MFMA kernel, and
+ * keeps the fastest of each kind.  On the mixed path a class whose best FP32
+ * pass is not below 0.85 of its best FP64 time is evaluated directly in FP64
+ * (no FP32 error, nothing to factorise again).  Per class: every time (ms),
+ * the chosen kernels and the precision. */
+const char *cgd_tuning(const cgd_ctx *ctx);
 
 void cgd_destroy(cgd_ctx *ctx);
 

@@ -93,18 +93,3 @@ def wrapped_distribution(inst, grid=None, return_imag=False):
     g = inst["grid"] if grid is None else grid
     P = inverse_dft(grid_values(S, g), inst["cutoff"])
     return (P.real, np.abs(P.imag).max()) if return_imag else P.real
-
-
-def wrapped_sample(inst, b_list, grid=None):
-    """P_wrap(b) for a list of individual patterns b (each by its own explicit
-    sum over the whole grid) -- for spot checks at sizes where the whole box is
-    too large to compute."""
-    S = st.assemble(inst)
-    g = np.asarray(inst["grid"] if grid is None else grid)
-    vals = grid_values(S, g)
-    ks = np.stack(np.meshgrid(*[np.arange(x) for x in g], indexing="ij"), -1)
-    out = []
-    for b in b_list:
-        ph = np.exp(-2j * np.pi * (ks * np.asarray(b)[None] / g).sum(-1))
-        out.append((vals * ph).sum().real / np.prod(g))
-    return np.array(out)

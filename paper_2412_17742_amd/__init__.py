@@ -25,6 +25,7 @@ FLAG_NO_SCHUR = 2
 FLAG_GRAD = 4
 FLAG_HESSENBERG = 8
 FLAG_NO_HESSENBERG = 16
+FLAG_NO_AUTOTUNE = 32
 # launch stages of one evaluation (per-stage timing); LU stages are order buckets
 STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144", "combine", "dft", "fix",
           "hess", "hess_det", "pair"]
@@ -88,6 +89,8 @@ def lib() -> ctypes.CDLL:
     L.cgd_stage_work.argtypes = [vp, vp, vp]
     L.cgd_mixed_stats.restype = i32
     L.cgd_mixed_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.cgd_tuning.restype = ctypes.c_char_p
+    L.cgd_tuning.argtypes = [vp]
     L.cgd_destroy.restype = None
     L.cgd_destroy.argtypes = [vp]
     L.cgd_last_error.restype = ctypes.c_char_p
@@ -211,6 +214,11 @@ class Context:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().cgd_mixed_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def tuning(self):
+        """The autotuner's report (dict): per size class, the timed kernels and the choice."""
+        import json
+        return json.loads(lib().cgd_tuning(self._h).decode())
 
     def close(self):
         if getattr(self, "_h", None):

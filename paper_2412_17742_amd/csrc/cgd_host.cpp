@@ -20,9 +20,12 @@ using namespace cgd;
 
 namespace {
 
-// Mixed path: assumed bound on the relative error of an FP32 generating-function
-// value, in units of (matrix order + 1) * 2^-24 (calibrated against FP64 on the
-// benchmark workloads with a safety factor; see the mixed-path tests).
+// Mixed path: model of the relative error of an FP32 value of G, per internal
+// block of order n: tau = kTauScale (n + 1) 2^-24 (the first-order change of
+// log det under the backward error of an n-step unpivoted elimination of an
+// accretive matrix stored in FP32, log accumulated in FP64).  Measured on every
+// grid point of five workloads, the largest relative error was 0.56 tau; the
+// mixed-path tests check the model on workloads with other seeds and shapes.
 constexpr double kTauScale = 2.0;
 
 thread_local std::string g_err;
@@ -475,10 +478,14 @@ struct cgd_ctx {
     // mixed path
     float2 *d_pool32 = nullptr;
     double2 *d_logg32 = nullptr;
-    int2 *d_list[kG64] = {};
     int64_t list_cap[kG64] = {};
-    int2 **d_list_ptrs = nullptr;
+    int64_t list_off[kG64] = {};       // first entry of each FP64 class's list in d_list (-1: none)
+    int64_t list_total = 0;
+    int2 *d_list = nullptr;
+    int64_t *d_list_off = nullptr;
     int *d_counts = nullptr;
+    unsigned long long *d_hist = nullptr;  // per instance: bucket sums of c_k |G_k| (fixed point)
+    int *d_cut = nullptr;              // per instance: buckets up to cut are factorised again in FP64
     int *d_status = nullptr;
     int *h_status = nullptr;
     hipEvent_t ev_status = nullptr;
@@ -503,8 +510,15 @@ struct cgd_ctx {
     hipGraphExec_t gexec = nullptr;
     double *g_probs = nullptr, *g_err = nullptr;
     bool evaluated = false;
+    int reg_var[kRegClasses] = {};     // autotuner: thread grid of the FP64 register kernel per class
+    int mfma_var[kMfmaClasses] = {};   // autotuner: wave layout of the FP32 MFMA kernel per class
+    std::string tune_json;             // autotuner report
     bool timing = false;
-    hipEvent_t ev[CGD_NSTAGES][2] = {};
+    // per-launch timing: event pairs recorded around each launch of a stage (eager
+    // evaluations with timing on); a stage's time is the sum over its launches
+    std::vector<hipEvent_t> tev;       // pool, two per pair
+    std::vector<int> tev_stage;        // stage of each recorded pair
+    size_t tev_open = 0;
     bool stage_ran[CGD_NSTAGES] = {};
     double work_flops[CGD_NSTAGES] = {}, work_bytes[CGD_NSTAGES] = {};
 };
@@ -516,8 +530,8 @@ void free_ctx(cgd_ctx *c) {
     auto fr = [](void *p) { if (p) (void)hipFree(p); };
     fr(c->d_inst); fr(c->d_blocks); fr(c->d_schur); fr(c->d_schur_prefix); fr(c->d_inst_pt_prefix);
     fr(c->d_pool); fr(c->d_rb); fr(c->d_eig); fr(c->d_contrib); fr(c->d_logg); fr(c->d_gA); fr(c->d_gB);
-    fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list_ptrs); fr(c->d_counts);
-    for (int k = 0; k < kG64; ++k) fr(c->d_list[k]);
+    fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list); fr(c->d_list_off);
+    fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
@@ -529,9 +543,7 @@ void free_ctx(cgd_ctx *c) {
     for (auto &k : c->gadj) { fr(k.d_jobs); fr(k.d_prefix); }
     fr(c->d_gblocks); fr(c->d_gpool); fr(c->d_partial); fr(c->d_z); fr(c->d_adjA); fr(c->d_adjB); fr(c->d_ghat);
     fr(c->d_grb); fr(c->d_z_prefix); fr(c->d_adj_off); fr(c->d_prob_prefix);
-    for (int i = 0; i < CGD_NSTAGES; ++i)
-        for (int j = 0; j < 2; ++j)
-            if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_status) (void)hipHostFree(c->h_status);
@@ -865,6 +877,264 @@ void chain_rule(const cgd_ctx *c, const std::vector<cplx> &zhost, std::vector<do
     }
 }
 
+
+// FP32 MFMA class of an order
+int mfma_class_of(int nb) {
+    int k = 0;
+    while (nb > mfma_class_limit(k)) ++k;
+    return k;
+}
+
+// LU work lists from the block descriptors: FP64 groups (everything on the
+// FP64 path; on the mixed path the blocks without an FP32 pass), FP32 MFMA
+// groups (mixed first pass) and the capacity of the mixed second-pass lists
+// per FP64 group.
+cgd_status make_lu_lists(cgd_ctx *c) {
+    for (int k = 0; k < kG64; ++k) {
+        LuClass &g = c->g64[k];
+        g.cls = k;
+        g.jobs.clear();
+        g.prefix.clear();
+        g.nitems = 0;
+        c->list_cap[k] = 0;
+    }
+    for (int k = 0; k < kMfmaClasses; ++k) {
+        LuClass &g = c->g32[k];
+        g.cls = k;
+        g.jobs.clear();
+        g.prefix.clear();
+        g.nitems = 0;
+    }
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        const BlockDev &d = c->blocks[b];
+        if (c->is_hess[b]) continue;
+        if (d.cls == kRegClasses) {
+            if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
+            c->big_ldw = std::max(c->big_ldw, d.nb);
+        }
+        const int64_t np = c->inst[d.inst].npts;
+        LuClass *lc = &c->g64[d.cls];
+        if (d.fp32) {
+            lc = &c->g32[mfma_class_of(d.nb)];
+            c->list_cap[d.cls] += np;
+        }
+        lc->prefix.push_back(lc->nitems);
+        lc->jobs.push_back((int32_t)b);
+        lc->nitems += np;
+    }
+    const int64_t big_items = c->g64[kRegClasses].nitems + c->list_cap[kRegClasses];
+    if (big_items > 0) c->big_nwg = (int)std::min<int64_t>(big_items, 1024);
+    return CGD_OK;
+}
+
+double lu_flops(double n) {
+    double f = 0;
+    for (int m = 0; m < (int)n; ++m) f += 8.0 * m * m + 6.0 * m;
+    return f;
+}
+
+// algorithmic flops of the LU stages per evaluation (FP32 first pass and
+// FP64 groups; the re-factorised share of the mixed path is not counted)
+void lu_work(cgd_ctx *c) {
+    for (int k = 0; k < kG64; ++k) c->work_flops[lu_stage(k)] = 0.0;
+    for (int k = 0; k < kG64; ++k)
+        for (int32_t bj : c->g64[k].jobs) {
+            const BlockDev &d = c->blocks[bj];
+            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
+        }
+    for (int k = 0; k < kMfmaClasses; ++k)
+        for (int32_t bj : c->g32[k].jobs) {
+            const BlockDev &d = c->blocks[bj];
+            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
+        }
+}
+
+// device copies of the work lists and the mixed path's list layout
+cgd_status upload_lu_lists(cgd_ctx *c) {
+    auto fr = [](void *p) { if (p) (void)hipFree(p); };
+    cgd_status s;
+    for (auto *grp : {&c->g64[0], &c->g32[0]}) {
+        const int n = grp == &c->g64[0] ? kG64 : kMfmaClasses;
+        for (int k = 0; k < n; ++k) {
+            fr(grp[k].d_jobs);
+            fr(grp[k].d_prefix);
+            grp[k].d_jobs = nullptr;
+            grp[k].d_prefix = nullptr;
+            if ((s = upload(&grp[k].d_jobs, grp[k].jobs)) != CGD_OK) return s;
+            if ((s = upload(&grp[k].d_prefix, grp[k].prefix)) != CGD_OK) return s;
+        }
+    }
+    if (c->prec != CGD_PREC_MIXED) return CGD_OK;
+    std::vector<int64_t> offs(kG64, -1);
+    c->list_total = 0;
+    for (int k = 0; k < kG64; ++k)
+        if (c->list_cap[k] > 0) {
+            offs[k] = c->list_off[k] = c->list_total;
+            c->list_total += c->list_cap[k];
+        } else {
+            c->list_off[k] = -1;
+        }
+    fr(c->d_list);
+    fr(c->d_list_off);
+    c->d_list = nullptr;
+    c->d_list_off = nullptr;
+    HIP_OK(hipMalloc((void **)&c->d_list, sizeof(int2) * std::max<int64_t>(1, c->list_total)));
+    return upload(&c->d_list_off, offs);
+}
+
+// Autotuner.  For every size class of per-point factorisations in this
+// context, time each candidate kernel shape on a sample of the class's own
+// (block, grid point) items spread evenly over its blocks (after building the
+// Schur matrices, so that the inputs are the real ones): the thread grids of
+// the FP64 register kernel and, on the mixed path, the wave layouts of the
+// FP32 MFMA kernel.  The fastest shape of each kind is kept.  A mixed class
+// whose best FP32 pass is not clearly faster than its best FP64 kernel (below
+// kMixedFp32Gain of the FP64 time, the share left for the re-factorisation of
+// the points that matter) runs directly in FP64.  Results do not depend on the
+// choice beyond rounding; CGD_FLAG_NO_AUTOTUNE keeps the default shapes and the
+// FP32 pass for every eligible class.
+constexpr double kMixedFp32Gain = 0.85;
+constexpr int64_t kTuneSample = 8192;
+
+cgd_status autotune(cgd_ctx *c) {
+    for (int k = 0; k < kRegClasses; ++k) c->reg_var[k] = 0;
+    for (int k = 0; k < kMfmaClasses; ++k) c->mfma_var[k] = 0;
+    if (c->flags & CGD_FLAG_NO_AUTOTUNE) {
+        c->tune_json = "{\"autotune\": false, \"classes\": []}";
+        return make_lu_lists(c);
+    }
+    std::string rep = "{\"autotune\": true, \"classes\": [";
+    bool first = true;
+    hipStream_t st = c->stream;
+    const bool mixed = c->prec == CGD_PREC_MIXED;
+    if (c->schur_nwg > 0)
+        HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg, c->schur_maxA,
+                                  c->d_pool, c->d_eig, c->d_pool, c->d_pool32, st));
+    int2 *d_items = nullptr;
+    int *d_aux = nullptr;  // [0] list length, [1] status of the tuning launches
+    HIP_OK(hipMalloc((void **)&d_items, sizeof(int2) * kTuneSample));
+    HIP_OK(hipMalloc((void **)&d_aux, 2 * sizeof(int)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    cgd_status result = CGD_OK;
+    auto timed = [&](auto &&launch, double &ms) -> hipError_t {
+        hipError_t e = launch();  // warm-up
+        if (e != hipSuccess) return e;
+        ms = 1e30;
+        for (int rep_i = 0; rep_i < 3; ++rep_i) {
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+            if ((e = launch()) != hipSuccess) return e;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+            float t = 0;
+            if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+            ms = std::min(ms, (double)t);
+        }
+        return hipSuccess;
+    };
+    for (int k = 0; k < kG64 && result == CGD_OK; ++k) {
+        // this class's blocks; on the mixed path a class with FP32 blocks is
+        // sampled over those only (the MFMA kernel takes orders up to its class limit)
+        std::vector<int32_t> blk;
+        int64_t total = 0;
+        int maxn = 0;
+        bool any32 = false;
+        for (size_t b = 0; b < c->blocks.size(); ++b) {
+            const BlockDev &d = c->blocks[b];
+            if (!c->is_hess[b] && d.cls == k && mixed && d.fp32 && mfma_class_of(d.nb) == k) any32 = true;
+        }
+        for (size_t b = 0; b < c->blocks.size(); ++b) {
+            const BlockDev &d = c->blocks[b];
+            if (c->is_hess[b] || d.cls != k) continue;
+            if (any32 && !(d.fp32 && mfma_class_of(d.nb) == k)) continue;
+            blk.push_back((int32_t)b);
+            total += c->inst[d.inst].npts;
+            maxn = std::max(maxn, d.nb);
+        }
+        if (total == 0) continue;
+        const int n64 = k < kRegClasses ? reg_variants(k) : 1;
+        const int n32 = any32 ? mfma_variants(k) : 0;
+        if (n64 < 2 && n32 == 0) continue;  // nothing to choose
+        const int64_t S = std::min<int64_t>(total, kTuneSample);
+        std::vector<int2> items(S);
+        {
+            size_t j = 0;
+            int64_t base = 0;
+            for (int64_t q = 0; q < S; ++q) {
+                const int64_t t = q * total / S;
+                while (base + c->inst[c->blocks[blk[j]].inst].npts <= t) base += c->inst[c->blocks[blk[j++]].inst].npts;
+                items[q] = make_int2(blk[j], (int)(t - base));
+            }
+        }
+        const int cnt[2] = {(int)S, 0};
+        hipError_t e = hipMemcpy(d_items, items.data(), sizeof(int2) * S, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_aux, cnt, sizeof(cnt), hipMemcpyHostToDevice);
+        LuLaunch a{nullptr, nullptr, 0, 0, d_items, d_aux, S, c->d_blocks, c->d_inst, c->d_pool, c->d_rb, c->d_eig,
+                   c->d_contrib, d_aux + 1};
+        std::vector<double> t64(n64, -1.0), t32(n32, -1.0);
+        for (int v = 0; v < n64 && e == hipSuccess; ++v)
+            e = timed([&] { return k < kRegClasses ? launch_lu_reg(k, v, a, st)
+                                                     : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st); },
+                      t64[v]);
+        LuLaunch a32 = a;
+        a32.pool = c->d_pool32;
+        for (int v = 0; v < n32 && e == hipSuccess; ++v)
+            e = timed([&] { return launch_lu_mfma(k, v, a32, st); }, t32[v]);
+        if (e != hipSuccess) {
+            result = fail(CGD_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            break;
+        }
+        const int b64 = (int)(std::min_element(t64.begin(), t64.end()) - t64.begin());
+        if (k < kRegClasses) c->reg_var[k] = b64;
+        int b32 = -1;
+        if (n32 > 0) {
+            b32 = (int)(std::min_element(t32.begin(), t32.end()) - t32.begin());
+            c->mfma_var[k] = b32;
+        }
+        const bool keep32 = n32 > 0 && t32[b32] < kMixedFp32Gain * t64[b64];
+        if (n32 > 0 && !keep32)
+            for (int32_t b : blk) c->blocks[b].fp32 = 0;
+        std::string f64s, f32s;
+        for (int v = 0; v < n64; ++v) {
+            char buf[128];
+            snprintf(buf, sizeof(buf), "%s\"%s\": %.4f", v ? ", " : "",
+                     k < kRegClasses ? reg_variant_name(k, v) : "lu_big_f64", t64[v]);
+            f64s += buf;
+        }
+        for (int v = 0; v < n32; ++v) {
+            char buf[128];
+            snprintf(buf, sizeof(buf), "%s\"%s\": %.4f", v ? ", " : "", mfma_variant_name(k, v), t32[v]);
+            f32s += buf;
+        }
+        char buf[512];
+        snprintf(buf, sizeof(buf),
+                 "%s{\"class\": %d, \"max_order\": %d, \"items\": %lld, \"sample\": %lld, \"fp64_ms\": {%s}, "
+                 "\"fp32_ms\": {%s}, \"fp64_kernel\": \"%s\", \"fp32_kernel\": \"%s\", \"precision\": \"%s\"}",
+                 first ? "" : ", ", k, maxn, (long long)total, (long long)S, f64s.c_str(), f32s.c_str(),
+                 k < kRegClasses ? reg_variant_name(k, b64) : "lu_big_f64", keep32 ? mfma_variant_name(k, b32) : "",
+                 keep32 ? "fp32+fp64" : "fp64");
+        rep += buf;
+        first = false;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_items);
+    (void)hipFree(d_aux);
+    if (result != CGD_OK) return result;
+    c->tune_json = rep + "]}";
+    // tau of each instance from the blocks left with an FP32 pass
+    for (InstDev &I : c->inst) I.tau = 0.0;
+    for (const BlockDev &d : c->blocks)
+        if (d.fp32) c->inst[d.inst].tau += kTauScale * (d.nb + 1) * 5.9604644775390625e-08;
+    HIP_OK(hipMemcpy(c->d_blocks, c->blocks.data(), sizeof(BlockDev) * c->blocks.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDev) * c->inst.size(), hipMemcpyHostToDevice));
+    const cgd_status sl = make_lu_lists(c);
+    if (sl != CGD_OK) return sl;
+    lu_work(c);
+    return CGD_OK;
+}
+
 cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     std::vector<HostInst> hinst(n_inst);
     std::vector<HostBlock> hblocks;
@@ -952,7 +1222,6 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.logpr0_re = h.logpr0;
         d.logpr0_im = 0.0;
         d.first_block = -1;
-        d.theta = INFINITY;
         d.tau = 0.0;
         c->inst_pt_prefix[i] = pt;
         c->prob_offsets[i] = po;
@@ -993,11 +1262,11 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.cls = kRegClasses;
         for (int k = 0; k < kRegClasses; ++k)
             if (h.nb <= reg_class_limit(k)) { d.cls = k; break; }
-        d.fp32 = (!hess && c->prec == CGD_PREC_MIXED && h.nb <= mfma_class_limit(kMfmaClasses - 1)) ? 1 : 0;
+        // blocks of order 0 (one bin: eigenvalues only) have no factorisation to do in FP32
+        d.fp32 = (!hess && c->prec == CGD_PREC_MIXED && h.nb > 0 && h.nb <= mfma_class_limit(kMfmaClasses - 1)) ? 1 : 0;
         if (d.fp32) {
             // relative error of an FP32 value of G: kTauScale (n + 1) 2^-24 per block, summed
             I0.tau += kTauScale * (h.nb + 1) * 5.9604644775390625e-08;
-            I0.theta = c->tol / I0.tau;
         }
         d.inst = h.inst;
         d.blk = h.blk;
@@ -1133,28 +1402,9 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         c->hess_sprefix.push_back(c->hess_spts);
         c->hess_spts += c->inst[hd.inst].npts;
     }
-    for (size_t b = 0; b < c->blocks.size(); ++b) {
-        const BlockDev &d = c->blocks[b];
-        if (c->is_hess[b]) continue;
-        if (d.cls == kRegClasses) {
-            if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
-            c->big_ldw = std::max(c->big_ldw, d.nb);
-        }
-        const int64_t np = c->inst[d.inst].npts;
-        LuClass *lc = &c->g64[d.cls];
-        if (d.fp32) {
-            int k32 = 0;
-            while (d.nb > mfma_class_limit(k32)) ++k32;
-            lc = &c->g32[k32];
-            c->list_cap[d.cls] += np;
-        }
-        lc->prefix.push_back(lc->nitems);
-        lc->jobs.push_back((int32_t)b);
-        lc->nitems += np;
-    }
     {
-        const int64_t big_items = c->g64[kRegClasses].nitems + c->list_cap[kRegClasses];
-        if (big_items > 0) c->big_nwg = (int)std::min<int64_t>(big_items, 1024);
+        const cgd_status sl = make_lu_lists(c);
+        if (sl != CGD_OK) return sl;
     }
 
     // DFT stages; twiddles exp(-2 pi i m / G) for every grid extent in use
@@ -1208,21 +1458,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     }
 
     // algorithmic work per evaluation
-    auto lu_flops = [](double n) {
-        double f = 0;
-        for (int m = 0; m < (int)n; ++m) f += 8.0 * m * m + 6.0 * m;
-        return f;
-    };
-    for (int k = 0; k < kG64; ++k)
-        for (int32_t bj : c->g64[k].jobs) {
-            const BlockDev &d = c->blocks[bj];
-            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
-        }
-    for (int k = 0; k < kMfmaClasses; ++k)
-        for (int32_t bj : c->g32[k].jobs) {
-            const BlockDev &d = c->blocks[bj];
-            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
-        }
+    lu_work(c);
     for (const SchurDev &sj : c->schur) c->work_flops[CGD_STAGE_SCHUR] += 8.0 * sj.nA * (double)sj.nB * sj.nB * sj.nk;
     for (const HessDev &hd : c->hess_all) {
         // reduction: column k with m = n - k - 1 rows below the diagonal costs
@@ -1274,13 +1510,6 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     }
     if ((s = upload(&c->d_rb, rbpool)) != CGD_OK) return s;
     if ((s = upload(&c->d_eig, eigpool)) != CGD_OK) return s;
-    for (auto *grp : {&c->g64[0], &c->g32[0]}) {
-        const int n = grp == &c->g64[0] ? kG64 : kMfmaClasses;
-        for (int k = 0; k < n; ++k) {
-            if ((s = upload(&grp[k].d_jobs, grp[k].jobs)) != CGD_OK) return s;
-            if ((s = upload(&grp[k].d_prefix, grp[k].prefix)) != CGD_OK) return s;
-        }
-    }
     for (auto &st : c->stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
@@ -1317,16 +1546,15 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         }
         if ((s = upload(&c->d_pool32, p32)) != CGD_OK) return s;
         HIP_OK(hipMalloc((void **)&c->d_logg32, sizeof(double2) * np));
-        std::vector<int2 *> ptrs(kG64, nullptr);
-        for (int k = 0; k < kG64; ++k)
-            if (c->list_cap[k] > 0) {
-                HIP_OK(hipMalloc((void **)&c->d_list[k], sizeof(int2) * c->list_cap[k]));
-                ptrs[k] = c->d_list[k];
-            }
-        if ((s = upload(&c->d_list_ptrs, ptrs)) != CGD_OK) return s;
         HIP_OK(hipMalloc((void **)&c->d_counts, sizeof(int) * kG64));
+        HIP_OK(hipMalloc((void **)&c->d_hist, sizeof(unsigned long long) * (size_t)n_inst * kMixedBuckets));
+        HIP_OK(hipMalloc((void **)&c->d_cut, sizeof(int) * n_inst));
     }
     HIP_OK(prepare_kernels(c->big_nwg > 0 ? c->big_ldw : 0, c->schur_maxA, c->npairs > 0 ? c->pair_ldw : 0));
+    // kernel variant (and, on the mixed path, precision) per size class, from
+    // timings on this context's own work; then the work lists
+    if ((s = autotune(c)) != CGD_OK) return s;
+    if ((s = upload_lu_lists(c)) != CGD_OK) return s;
     if (want_grad) {
         cgd_status sg = build_grad(c, n_inst);
         if (sg != CGD_OK) return sg;
@@ -1347,7 +1575,7 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
     if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
     if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD | CGD_FLAG_HESSENBERG |
-                  CGD_FLAG_NO_HESSENBERG))
+                  CGD_FLAG_NO_HESSENBERG | CGD_FLAG_NO_AUTOTUNE))
         return fail(CGD_ERR_ARG, "unknown flags");
     if ((flags & CGD_FLAG_HESSENBERG) && (flags & CGD_FLAG_NO_HESSENBERG))
         return fail(CGD_ERR_ARG, "CGD_FLAG_HESSENBERG and CGD_FLAG_NO_HESSENBERG together");
@@ -1379,14 +1607,42 @@ cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_
 int64_t cgd_points(const cgd_ctx *ctx) { return ctx ? ctx->npts : 0; }
 
 namespace {
+// Device buffers one evaluation writes and reads back (all of them rewritten by
+// every evaluation before they are read).
+struct EvalBufs {
+    double2 *contrib, *logg, *gA, *gB, *logg32, *eigc, *htable;
+    int *counts, *cut;
+    unsigned long long *hist;
+    int2 *list;
+};
+
+EvalBufs ctx_bufs(const cgd_ctx *c) {
+    return EvalBufs{c->d_contrib, c->d_logg, c->d_gA, c->d_gB, c->d_logg32, c->d_eigc, c->d_htable,
+                    c->d_counts, c->d_cut, c->d_hist, c->d_list};
+}
+
 // Enqueue every launch of one evaluation on stream st.
-cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_err_bound) {
+cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_err_bound, const EvalBufs &b) {
+    // mark(stage, 0) opens a timed span, mark(stage, 1) closes it
     auto mark = [&](int stage, int which) -> hipError_t {
         if (!c->timing) return hipSuccess;
         c->stage_ran[stage] = true;
-        return hipEventRecord(c->ev[stage][which], st);
+        if (which == 0) {
+            const size_t k = c->tev_stage.size();
+            while (c->tev.size() < 2 * (k + 1)) {
+                hipEvent_t e;
+                const hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                c->tev.push_back(e);
+            }
+            c->tev_stage.push_back(stage);
+            c->tev_open = k;
+            return hipEventRecord(c->tev[2 * k], st);
+        }
+        return hipEventRecord(c->tev[2 * c->tev_open + 1], st);
     };
     for (int i = 0; i < CGD_NSTAGES; ++i) c->stage_ran[i] = false;
+    c->tev_stage.clear();
     if (c->schur_nwg > 0) {
         HIP_OK(mark(CGD_STAGE_SCHUR, 0));
         HIP_OK(launch_schur_build(c->d_schur, c->d_schur_prefix, (int)c->schur.size(), c->schur_nwg,
@@ -1396,7 +1652,7 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
     if (c->npairs > 0) {
         HIP_OK(mark(CGD_STAGE_PAIR, 0));
         HIP_OK(launch_pair_schur(c->d_pairs, c->d_pair_prefix, (int)c->pairs.size(), c->npairs, c->pair_nwg,
-                                 c->d_pool, c->d_perm, c->d_eig, c->d_pair_work, c->pair_ldw, c->d_eigc,
+                                 c->d_pool, c->d_perm, c->d_eig, c->d_pair_work, c->pair_ldw, b.eigc,
                                  c->d_status, st));
         HIP_OK(mark(CGD_STAGE_PAIR, 1));
     }
@@ -1404,35 +1660,33 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         HIP_OK(mark(CGD_STAGE_HESS, 0));
         for (auto &hc : c->hcls)
             HIP_OK(launch_hess_reduce((int)(&hc - c->hcls), hc.d_jobs, hc.d_rprefix, (int)hc.jobs.size(), hc.rnwg,
-                                      c->d_pool, c->d_eig, c->d_eigc, st));
+                                      c->d_pool, c->d_eig, b.eigc, st));
         HIP_OK(mark(CGD_STAGE_HESS, 1));
         HIP_OK(mark(CGD_STAGE_HESS_DET, 0));
         for (auto &hc : c->hcls)
             HIP_OK(launch_hess_det((int)(&hc - c->hcls), hc.d_jobs, hc.d_dprefix, (int)hc.jobs.size(), hc.dnwg,
-                                   c->d_pool, c->d_eigc, c->d_htable, st));
+                                   c->d_pool, b.eigc, b.htable, c->d_status, st));
         HIP_OK(launch_hess_scatter(c->d_hess_all, c->d_hess_sprefix, (int)c->hess_all.size(), c->hess_spts,
-                                   c->d_inst, c->d_htable, c->d_contrib, st));
+                                   c->d_inst, b.htable, b.contrib, st));
         HIP_OK(mark(CGD_STAGE_HESS_DET, 1));
     }
     const bool mixed = c->prec == CGD_PREC_MIXED;
     // timing: a slot spans from its first launch to its last one in this evaluation
-    auto mark_begin = [&](int stage) -> hipError_t {
-        if (!c->timing || c->stage_ran[stage]) return hipSuccess;
-        return mark(stage, 0);
-    };
+    auto mark_begin = [&](int stage) -> hipError_t { return mark(stage, 0); };
     auto launch64 = [&](int k, const int2 *list, const int *count, int64_t cap) -> hipError_t {
         const LuClass &g = c->g64[k];
         LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, list, count, cap, c->d_blocks,
-                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
-        return k < kRegClasses ? launch_lu_reg(k, false, a, st) : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
+                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status};
+        return k < kRegClasses ? launch_lu_reg(k, c->reg_var[k], a, st)
+                               : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
     };
     if (mixed)
         for (auto &g : c->g32) {
             if (g.nitems == 0) continue;
             LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, nullptr, nullptr, 0, c->d_blocks,
-                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, c->d_contrib, c->d_status};
+                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status};
             HIP_OK(mark_begin(lu_stage(g.cls)));
-            HIP_OK(launch_lu_mfma(g.cls, a, st));
+            HIP_OK(launch_lu_mfma(g.cls, c->mfma_var[g.cls], a, st));
             HIP_OK(mark(lu_stage(g.cls), 1));
         }
     for (int k = 0; k < kG64; ++k) {
@@ -1444,35 +1698,37 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
     HIP_OK(mark(CGD_STAGE_COMBINE, 0));
     if (mixed) {
         // FP32 values -> select the points that matter -> FP64 re-factorisation of those
-        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg32,
-                              c->d_gA, st));
+        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, b.contrib, b.logg32,
+                              b.gA, st));
         HIP_OK(mark(CGD_STAGE_COMBINE, 1));
         HIP_OK(mark(CGD_STAGE_FIX, 0));
-        HIP_OK(launch_zero_ints(c->d_counts, kG64, st));
-        HIP_OK(launch_select_points(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_blocks, c->d_logg32,
-                                    c->d_list_ptrs, c->d_counts, kG64, st));
+        HIP_OK(launch_zero_ints(b.counts, kG64, st));
+        HIP_OK(launch_mixed_cut(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, b.logg32, c->tol, b.hist,
+                                b.cut, st));
+        HIP_OK(launch_select_points(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_blocks, b.logg32,
+                                    b.cut, b.list, c->d_list_off, b.counts, kG64, st));
         for (int k = 0; k < kG64; ++k) {
             if (c->list_cap[k] == 0) continue;
-            HIP_OK(launch64(k, c->d_list[k], c->d_counts + k, c->list_cap[k]));
+            HIP_OK(launch64(k, b.list + c->list_off[k], b.counts + k, c->list_cap[k]));
         }
-        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA,
+        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, b.contrib, b.logg, b.gA,
                               st));
         HIP_OK(mark(CGD_STAGE_FIX, 1));
     } else {
-        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, c->d_contrib, c->d_logg, c->d_gA,
+        HIP_OK(launch_combine(c->d_inst, c->d_inst_pt_prefix, c->n_inst, c->npts, b.contrib, b.logg, b.gA,
                               st));
         HIP_OK(mark(CGD_STAGE_COMBINE, 1));
     }
     HIP_OK(mark(CGD_STAGE_DFT, 0));
     for (size_t si = 0; si < c->stages.size(); ++si) {
         DftStage &S = c->stages[si];
-        const double2 *in = (si % 2 == 0) ? c->d_gA : c->d_gB;
-        double2 *out = (si % 2 == 0) ? c->d_gB : c->d_gA;
+        const double2 *in = (si % 2 == 0) ? b.gA : b.gB;
+        double2 *out = (si % 2 == 0) ? b.gB : b.gA;
         HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, c->d_tw, in, out, d_probs,
                                 mixed ? nullptr : d_err_bound, c->d_status, st));
     }
     HIP_OK(mark(CGD_STAGE_DFT, 1));
-    if (mixed) HIP_OK(launch_mixed_err(c->d_inst, c->n_inst, c->d_logg32, d_err_bound, c->d_status, st));
+    if (mixed) HIP_OK(launch_mixed_err(c->d_inst, c->n_inst, b.logg32, b.cut, d_err_bound, c->d_status, st));
     return CGD_OK;
 }
 }  // namespace
@@ -1484,7 +1740,7 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
     if (s != CGD_OK) return s;
     if (c->timing) {
         // per-stage events need the launches on the caller's stream, one by one
-        s = enqueue_eval(c, c->stream, d_probs, d_err_bound);
+        s = enqueue_eval(c, c->stream, d_probs, d_err_bound, ctx_bufs(c));
         if (s != CGD_OK) return s;
     } else {
         // the launch sequence is captured once on a private stream into a HIP
@@ -1494,7 +1750,7 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
             if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
             if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
             HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            s = enqueue_eval(c, c->cap_stream, d_probs, d_err_bound);
+            s = enqueue_eval(c, c->cap_stream, d_probs, d_err_bound, ctx_bufs(c));
             hipGraph_t graph = nullptr;
             const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
             if (s != CGD_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
@@ -1575,9 +1831,6 @@ cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_
 
 cgd_status cgd_set_timing(cgd_ctx *c, int32_t enable) {
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
-    if (enable && !c->ev[0][0])
-        for (int i = 0; i < CGD_NSTAGES; ++i)
-            for (int j = 0; j < 2; ++j) HIP_OK(hipEventCreate(&c->ev[i][j]));
     c->timing = enable != 0;
     return CGD_OK;
 }
@@ -1585,13 +1838,14 @@ cgd_status cgd_set_timing(cgd_ctx *c, int32_t enable) {
 cgd_status cgd_stage_times(cgd_ctx *c, double *ms) {
     if (!c || !ms) return fail(CGD_ERR_ARG, "NULL argument");
     if (!c->evaluated) return fail(CGD_ERR_STATE, "no evaluation yet");
-    for (int i = 0; i < CGD_NSTAGES; ++i) {
-        ms[i] = -1.0;
-        if (!c->timing || !c->stage_ran[i]) continue;
-        HIP_OK(hipEventSynchronize(c->ev[i][1]));
+    for (int i = 0; i < CGD_NSTAGES; ++i) ms[i] = -1.0;
+    if (!c->timing) return CGD_OK;
+    for (size_t k = 0; k < c->tev_stage.size(); ++k) {
+        HIP_OK(hipEventSynchronize(c->tev[2 * k + 1]));
         float t = 0;
-        HIP_OK(hipEventElapsedTime(&t, c->ev[i][0], c->ev[i][1]));
-        ms[i] = t;
+        HIP_OK(hipEventElapsedTime(&t, c->tev[2 * k], c->tev[2 * k + 1]));
+        double &m = ms[c->tev_stage[k]];
+        m = (m < 0 ? 0.0 : m) + t;
     }
     return CGD_OK;
 }
@@ -1620,6 +1874,14 @@ cgd_status cgd_stage_work(const cgd_ctx *c, double *flops, double *bytes) {
         if (bytes) bytes[i] = c->work_bytes[i];
     }
     return CGD_OK;
+}
+
+const char *cgd_tuning(const cgd_ctx *ctx) {
+    if (!ctx) {
+        fail(CGD_ERR_ARG, "ctx is NULL");
+        return nullptr;
+    }
+    return ctx->tune_json.c_str();
 }
 
 void cgd_destroy(cgd_ctx *ctx) {

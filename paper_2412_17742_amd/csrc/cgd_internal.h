@@ -27,8 +27,8 @@ struct InstDev {
     double logpr0_re, logpr0_im;  // constant part of log G (vacuum probability, traced modes)
     int32_t first_block;      // this instance's blocks are first_block .. first_block + nblocks - 1
     int32_t pad2;
-    double theta;             // mixed path: points with |G| > theta are re-evaluated in FP64
-    double tau;               // mixed path: relative error bound assumed for an FP32 value of G
+    double pad3;
+    double tau;               // mixed path: relative error bound assumed for an FP32 value of G (0: no FP32 block)
 };
 
 // One factorisation job family: an (instance, internal block) pair.  Every
@@ -156,10 +156,17 @@ struct LuLaunch {
 // launchers (cgd_kernels.hip)
 int reg_class_limit(int cls);          // max matrix order of register class cls (0 = none)
 constexpr int kRegClasses = 5;
-hipError_t launch_lu_reg(int cls, bool fp32, const LuLaunch &a, hipStream_t st);
+// shape variants per class: reg_variants(cls) thread grids of the FP64
+// register kernel, mfma_variants(cls) wave layouts of the FP32 MFMA kernel
+// (variant 0 is the default; the autotuner of cgd_create picks one)
+int reg_variants(int cls);
+const char *reg_variant_name(int cls, int v);
+hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st);
 constexpr int kMfmaClasses = 6;
 int mfma_class_limit(int cls);         // max matrix order of FP32 MFMA class cls
-hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st);
+int mfma_variants(int cls);
+const char *mfma_variant_name(int cls, int v);
+hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st);
 size_t lu_big_lds_bytes(int ldw);
 hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw);
 hipError_t launch_lu_big(const LuLaunch &a, double2 *work, int ldw, int nwg, hipStream_t st);
@@ -179,18 +186,24 @@ hipError_t launch_adjoint_seed(const InstDev *insts, const int64_t *prob_prefix,
                                const double *dprobs, const int64_t *buf_off, double2 *out, hipStream_t st);
 // mixed path
 hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
+// buckets of |G| per instance for the FP32/FP64 split of the mixed path
+constexpr int kMixedBucketsPerOctave = 4;
+constexpr int kMixedBuckets = 64 * kMixedBucketsPerOctave;
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
+hipError_t launch_mixed_cut(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                            const double2 *logg, double tol, unsigned long long *hist, int *cut, hipStream_t st);
 hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
-                                const BlockDev *blocks, const double2 *logg, int2 *const *lists, int *counts,
-                                int n_lists, hipStream_t st);
-hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, double *err, const int *status,
-                            hipStream_t st);
+                                const BlockDev *blocks, const double2 *logg, const int *cut, int2 *list_base,
+                                const int64_t *list_off, int *counts, int n_lists, hipStream_t st);
+hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, const int *cut, double *err,
+                            const int *status, hipStream_t st);
 // Hessenberg route
 constexpr int kHessClasses = 4;
 int hess_class_limit(int cls);          // max order of class cls: 32, 64, 96, 144
 hipError_t launch_hess_reduce(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
                               double2 *pool, const double *eigpool, double2 *eigc, hipStream_t st);
 hipError_t launch_hess_det(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
-                           const double2 *pool, const double2 *eigc, double2 *table, hipStream_t st);
+                           const double2 *pool, const double2 *eigc, double2 *table, int *status, hipStream_t st);
 hipError_t launch_pair_schur(const PairDev *jobs, const int64_t *prefix, int njobs, int64_t npairs, int nwg,
                              double2 *pool, const int32_t *permpool, const double *eigpool, double2 *work, int ldw,
                              double2 *eigc, int *status, hipStream_t st);

@@ -1560,6 +1560,7 @@ struct HessDetState {
     double2 prod;               // product of the pivots of the open group
     float aest;                 // rough sum of their arguments
     int ngrp;                   // pivots in the open group
+    bool bad;                   // a pivot left the right half-plane (or was NaN)
 
     __device__ __forceinline__ double2 hload(int row, int j) const {
         const bool in = row < n && j < n;
@@ -1590,6 +1591,7 @@ struct HessDetState {
         ngrp = 0;
     }
     __device__ __forceinline__ void take(double2 p) {
+        bad |= !(p.x > 0.0);
         prod = cmul(prod, p);
         aest += rough_arg((float)p.x, (float)p.y);
         if (++ngrp == 16) flush();
@@ -1675,7 +1677,8 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
                                                                 const int64_t *__restrict__ prefix, int njobs,
                                                                 const double2 *__restrict__ pool,
                                                                 const double2 *__restrict__ eigc,
-                                                                double2 *__restrict__ table)
+                                                                double2 *__restrict__ table,
+                                                                int *__restrict__ status)
 {
     static_assert(kHessDetThreads == 256, "staging maps 16 rows x 16 lanes");
     extern __shared__ __align__(16) double2 hd_lds[];  // [2][16][16 MB]
@@ -1706,6 +1709,7 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     S.prod = cmk(1.0, 0.0);
     S.aest = 0.0f;
     S.ngrp = 0;
+    S.bad = false;
 
     // block M of 16 steps: rows 16 M + 1 + E of the staged block come from
     // thread (E, c0) = (tid / 16, tid % 16), columns 16 M + c0 + 16 i
@@ -1728,6 +1732,10 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     if (valid && S.e == 0) {
         const double2 ec = eigc[J.ec_off + kA];
         table[J.t_off + (int64_t)kA * J.dB + kB] = cmk(-0.5 * (S.logsum + ec.x), -0.5 * (S.argsum + ec.y));
+        // pivots of I - w_B Hh lie in the right half-plane (accretive, unitarily
+        // similar to a Schur complement of S); an infinite one leaves a
+        // non-finite sum
+        if (S.bad || !isfinite(S.logsum) || !isfinite(S.argsum)) atomicOr(status, 1);
     }
 }
 
@@ -2092,21 +2100,94 @@ __global__ void adjoint_seed(const InstDev *__restrict__ insts, const int64_t *_
 }
 
 // ---------------------------------------------------------------------------
-// Mixed path.  After the FP32 pass, a point's value of G carries a relative
-// error of at most tau (per instance); it enters each probability as
-// c_k |G_k| tau / prod G, and sum_k c_k = prod G over the half grid.  So
-// re-evaluating in FP64 every point with |G_k| > theta = tol / tau bounds the
-// error of every probability by tol.  select_points appends the (block, point)
-// items of those points to one list per FP64 size class.
+// Mixed path.  After the FP32 pass, the value of G at point k carries a
+// relative error of at most tau (per instance); it enters every probability as
+// c_k |G_k| tau / prod G (c_k = 1 or 2 on the half grid), so the points left in
+// FP32 add at most (tau / prod G) sum_{k in FP32} c_k |G_k| to any
+// probability.  The points are ranked by |G_k| in buckets of a quarter octave
+// (bucket b holds 2^-(b+1)/4 < |G| <= 2^-b/4, the last one everything
+// smaller); the FP32 set is the longest run of buckets, from the smallest |G|
+// up, whose summed c_k |G_k| stays within the budget tol prod G / tau.  The
+// sums are taken in fixed point (units of 2^-28, rounded up, 64-bit integer
+// atomics), so the cut does not depend on the order of the additions and the
+// true sum of the FP32 set is at most the budget.  Every other point is
+// factorised again in FP64; mixed_err then reports the exact bound of what is
+// left in FP32.
 // ---------------------------------------------------------------------------
 __global__ void zero_ints(int *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
 
+__global__ void zero_u64(unsigned long long *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+constexpr double kMixedScale = 268435456.0;  // 2^28: fixed-point unit of the bucket sums
+
+// bucket of a point from its FP32 log G (NaN lands in bucket 0: always redone)
+__device__ __forceinline__ int mixed_bucket(double logg_re) {
+    const double b = -logg_re * (kMixedBucketsPerOctave * 1.4426950408889634);  // 1 / ln 2
+    if (!(b > 0.0)) return 0;
+    return b >= (double)(kMixedBuckets - 1) ? kMixedBuckets - 1 : (int)b;
+}
+
+__device__ __forceinline__ double half_grid_weight(const InstDev &I, int64_t lp) {
+    int64_t stride = 1;
+    for (int l = 1; l < I.L; ++l) stride *= I.G[l];
+    const int64_t k1 = lp / stride;
+    return (k1 == 0 || 2 * k1 == I.G[0]) ? 1.0 : 2.0;
+}
+
+// hist[i * kMixedBuckets + b] += ceil(c_k |G_k| 2^28) over the points of
+// instance i with an FP32 block
+__global__ void mixed_hist(const InstDev *__restrict__ insts, const int64_t *__restrict__ inst_pt_prefix,
+                           int n_inst, int64_t npts, const double2 *__restrict__ logg,
+                           unsigned long long *__restrict__ hist)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const int i = find_job(inst_pt_prefix, n_inst, p);
+    const InstDev &I = insts[i];
+    if (!(I.tau > 0.0)) return;
+    const double lg = logg[p].x;
+    const double g = exp(fmin(lg, 1.0));  // |G| <= 1 up to rounding; NaN stays NaN
+    const double wgt = half_grid_weight(I, p - I.pt_off) * g * kMixedScale;
+    const unsigned long long q = isfinite(wgt) ? (unsigned long long)ceil(wgt) : (1ull << 40);
+    atomicAdd(&hist[(int64_t)i * kMixedBuckets + mixed_bucket(lg)], q);
+}
+
+// one wave per instance: cut[i] = largest bucket index that is factorised
+// again (-1: none), scanning from the smallest |G| up
+__global__ void mixed_cut(const InstDev *__restrict__ insts, int n_inst, double tol,
+                          const unsigned long long *__restrict__ hist, int *__restrict__ cut)
+{
+    const int i = blockIdx.x;
+    if (i >= n_inst || threadIdx.x != 0) return;
+    const InstDev &I = insts[i];
+    if (!(I.tau > 0.0)) {
+        cut[i] = -1;
+        return;
+    }
+    double gprod = 1;
+    for (int l = 0; l < I.L; ++l) gprod *= I.G[l];
+    const double bd = floor(tol * gprod / I.tau * kMixedScale);
+    const unsigned long long budget = bd >= 4.0e18 ? 4000000000000000000ull : (unsigned long long)bd;
+    const unsigned long long *h = hist + (int64_t)i * kMixedBuckets;
+    unsigned long long acc = 0;
+    int b = kMixedBuckets - 1;
+    for (; b >= 0; --b) {
+        acc += h[b];
+        if (acc > budget) break;
+    }
+    cut[i] = b;  // buckets above b stay in FP32
+}
+
 __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *__restrict__ inst_pt_prefix,
                               int n_inst, int64_t npts, const BlockDev *__restrict__ blocks,
-                              const double2 *__restrict__ logg, int2 *const *__restrict__ lists,
+                              const double2 *__restrict__ logg, const int *__restrict__ cut,
+                              int2 *__restrict__ list_base, const int64_t *__restrict__ list_off,
                               int *__restrict__ counts, int n_lists)
 {
     // every lane takes part in the ballots below: no early return
@@ -2117,7 +2198,7 @@ __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *
     if (p < npts) {
         const int i = find_job(inst_pt_prefix, n_inst, p);
         const InstDev &I = insts[i];
-        if (logg[p].x > log(I.theta)) {
+        if (I.tau > 0.0 && mixed_bucket(logg[p].x) <= cut[i]) {
             nb = I.nblocks;
             first = I.first_block;
             lp = p - I.pt_off;
@@ -2127,7 +2208,7 @@ __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *
         int cls = -1;
         if (b < nb) {
             const BlockDev &B = blocks[first + b];
-            if (B.fp32 && B.cls >= 0 && B.cls < n_lists && lists[B.cls]) cls = B.cls;
+            if (B.fp32 && B.cls >= 0 && B.cls < n_lists && list_off[B.cls] >= 0) cls = B.cls;
         }
         // one atomic per wave and list: lanes of the same list share it
         unsigned long long pending = __ballot(cls >= 0);
@@ -2138,7 +2219,8 @@ __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *
             int base = 0;
             if (lane == leader) base = atomicAdd(&counts[c], __popcll(grp));
             base = __shfl(base, leader);
-            if (cls == c) lists[c][base + __popcll(grp & ((1ull << lane) - 1))] = make_int2(first + b, (int)lp);
+            if (cls == c)
+                list_base[list_off[c] + base + __popcll(grp & ((1ull << lane) - 1))] = make_int2(first + b, (int)lp);
             pending &= ~grp;
         }
     }
@@ -2147,21 +2229,18 @@ __global__ void select_points(const InstDev *__restrict__ insts, const int64_t *
 // Per instance: (1 / prod G) sum over the points left in FP32 of c_k |G_k| tau,
 // the bound on the error of every probability (deterministic order).
 __global__ void mixed_err(const InstDev *__restrict__ insts, const double2 *__restrict__ logg,
-                          double *__restrict__ err, const int *__restrict__ status)
+                          const int *__restrict__ cut, double *__restrict__ err, const int *__restrict__ status)
 {
     __shared__ double2 s_red[256 / 64 + 1];
     const InstDev &I = insts[blockIdx.x];
-    int64_t stride = 1;
-    for (int l = 1; l < I.L; ++l) stride *= I.G[l];
-    const double lt = log(I.theta);
+    const int ci = cut[blockIdx.x];
     double acc = 0.0;
-    for (int64_t p = threadIdx.x; p < I.npts; p += blockDim.x) {
-        const double2 v = logg[I.pt_off + p];
-        if (v.x > lt) continue;
-        const int64_t k1 = p / stride;
-        const double ck = (k1 == 0 || 2 * k1 == I.G[0]) ? 1.0 : 2.0;
-        acc += ck * exp(v.x);
-    }
+    if (I.tau > 0.0)
+        for (int64_t p = threadIdx.x; p < I.npts; p += blockDim.x) {
+            const double lg = logg[I.pt_off + p].x;
+            if (mixed_bucket(lg) <= ci) continue;
+            acc += half_grid_weight(I, p) * exp(lg);
+        }
     double2 t = block_sum<256>(cmk(acc, 0.0), s_red);
     if (threadIdx.x == 0) {
         double gprod = 1;
@@ -2170,11 +2249,7 @@ __global__ void mixed_err(const InstDev *__restrict__ insts, const double2 *__re
     }
 }
 
-// ---------------------------------------------------------------------------
-// launchers (host side)
-// ---------------------------------------------------------------------------
-
-template <typename T, int PR, int PC, int TR, int TC>
+template <int PR, int PC, int TR, int TC>
 static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
              a.rbpool, a.eigpool, a.contrib, a.status};
@@ -2182,7 +2257,7 @@ static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
     // workgroups past the list's length return at once
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((lu_reg<T, PR, PC, TR, TC>), dim3((unsigned)grid), dim3(PR * PC), 0, st, A);
+    hipLaunchKernelGGL((lu_reg<double, PR, PC, TR, TC>), dim3((unsigned)grid), dim3(PR * PC), 0, st, A);
     return hipGetLastError();
 }
 
@@ -2197,14 +2272,31 @@ int reg_class_limit(int cls) {
     }
 }
 
-template <typename T>
-static hipError_t launch_reg_t(int cls, const LuLaunch &a, hipStream_t st) {
-    switch (cls) {
-        case 0: return launch_reg<T, 8, 8, 4, 4>(a, st);
-        case 1: return launch_reg<T, 16, 16, 4, 4>(a, st);
-        case 2: return launch_reg<T, 16, 32, 6, 3>(a, st);
-        case 3: return launch_reg<T, 16, 32, 8, 4>(a, st);
-        case 4: return launch_reg<T, 16, 48, 9, 3>(a, st);
+// thread-grid shapes <PR, PC, TR, TC> per register class (the autotuner picks one)
+int reg_variants(int cls) { return cls == 0 ? 2 : cls == 1 ? 3 : cls == 2 ? 2 : cls < kRegClasses ? 1 : 0; }
+
+const char *reg_variant_name(int cls, int v) {
+    static const char *names[kRegClasses][3] = {
+        {"lu_reg<double,8,8,4,4>", "lu_reg<double,8,16,4,2>", ""},
+        {"lu_reg<double,16,16,4,4>", "lu_reg<double,8,16,8,4>", "lu_reg<double,16,32,4,2>"},
+        {"lu_reg<double,16,32,6,3>", "lu_reg<double,16,16,6,6>", ""},
+        {"lu_reg<double,16,32,8,4>", "", ""},
+        {"lu_reg<double,16,48,9,3>", "", ""}};
+    return (cls >= 0 && cls < kRegClasses && v >= 0 && v < reg_variants(cls)) ? names[cls][v] : "";
+}
+
+hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
+    if (!a.list && a.nitems <= 0) return hipSuccess;
+    switch (cls * 4 + v) {
+        case 0: return launch_reg<8, 8, 4, 4>(a, st);
+        case 1: return launch_reg<8, 16, 4, 2>(a, st);
+        case 4: return launch_reg<16, 16, 4, 4>(a, st);
+        case 5: return launch_reg<8, 16, 8, 4>(a, st);
+        case 6: return launch_reg<16, 32, 4, 2>(a, st);
+        case 8: return launch_reg<16, 32, 6, 3>(a, st);
+        case 9: return launch_reg<16, 16, 6, 6>(a, st);
+        case 12: return launch_reg<16, 32, 8, 4>(a, st);
+        case 16: return launch_reg<16, 48, 9, 3>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2238,22 +2330,38 @@ int mfma_class_limit(int cls) {
     }
 }
 
-hipError_t launch_lu_mfma(int cls, const LuLaunch &a, hipStream_t st) {
-    if (!a.list && a.nitems <= 0) return hipSuccess;
-    switch (cls) {
-        case 0: return launch_mfma<2, 1, 2>(a, st);
-        case 1: return launch_mfma<4, 2, 2>(a, st);
-        case 2: return launch_mfma<6, 2, 4>(a, st);
-        case 3: return launch_mfma<8, 2, 4>(a, st);
-        case 4: return launch_mfma<9, 3, 4>(a, st);
-        case 5: return launch_mfma<12, 2, 4>(a, st);
-        default: return hipErrorInvalidValue;
-    }
+// wave layouts <NTILE, WR, WC> per FP32 MFMA class (the autotuner picks one)
+int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 4 : cls == 2 ? 3 : cls < kMfmaClasses ? 1 : 0; }
+
+const char *mfma_variant_name(int cls, int v) {
+    static const char *names[kMfmaClasses][4] = {
+        {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>", ""},
+        {"lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>"},
+        {"lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>", ""},
+        {"lu_mfma_f32<8,2,4>", "", "", ""},
+        {"lu_mfma_f32<9,3,4>", "", "", ""},
+        {"lu_mfma_f32<12,2,4>", "", "", ""}};
+    return (cls >= 0 && cls < kMfmaClasses && v >= 0 && v < mfma_variants(cls)) ? names[cls][v] : "";
 }
 
-hipError_t launch_lu_reg(int cls, bool fp32, const LuLaunch &a, hipStream_t st) {
+hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st) {
     if (!a.list && a.nitems <= 0) return hipSuccess;
-    return fp32 ? launch_reg_t<float>(cls, a, st) : launch_reg_t<double>(cls, a, st);
+    switch (cls * 4 + v) {
+        case 0: return launch_mfma<2, 1, 2>(a, st);
+        case 1: return launch_mfma<2, 1, 1>(a, st);
+        case 2: return launch_mfma<2, 2, 2>(a, st);
+        case 4: return launch_mfma<4, 2, 2>(a, st);
+        case 5: return launch_mfma<4, 1, 2>(a, st);
+        case 6: return launch_mfma<4, 1, 1>(a, st);
+        case 7: return launch_mfma<4, 2, 4>(a, st);
+        case 8: return launch_mfma<6, 2, 4>(a, st);
+        case 9: return launch_mfma<6, 2, 2>(a, st);
+        case 10: return launch_mfma<6, 3, 2>(a, st);
+        case 12: return launch_mfma<8, 2, 4>(a, st);
+        case 16: return launch_mfma<9, 3, 4>(a, st);
+        case 20: return launch_mfma<12, 2, 4>(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 size_t lu_big_lds_bytes(int ldw) {
@@ -2320,19 +2428,39 @@ hipError_t launch_zero_ints(int *p, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
-                                const BlockDev *blocks, const double2 *logg, int2 *const *lists, int *counts,
-                                int n_lists, hipStream_t st) {
-    if (npts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(select_points, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts,
-                       inst_pt_prefix, n_inst, npts, blocks, logg, lists, counts, n_lists);
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 
-hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, double *err, const int *status,
-                            hipStream_t st) {
+hipError_t launch_mixed_cut(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                            const double2 *logg, double tol, unsigned long long *hist, int *cut, hipStream_t st) {
+    if (n_inst <= 0) return hipSuccess;
+    hipError_t e = launch_zero_u64(hist, (int64_t)n_inst * kMixedBuckets, st);
+    if (e != hipSuccess) return e;
+    if (npts > 0) {
+        hipLaunchKernelGGL(mixed_hist, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts,
+                           inst_pt_prefix, n_inst, npts, logg, hist);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(mixed_cut, dim3(n_inst), dim3(64), 0, st, insts, n_inst, tol, hist, cut);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_points(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
+                                const BlockDev *blocks, const double2 *logg, const int *cut, int2 *list_base,
+                                const int64_t *list_off, int *counts, int n_lists, hipStream_t st) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(select_points, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts,
+                       inst_pt_prefix, n_inst, npts, blocks, logg, cut, list_base, list_off, counts, n_lists);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_err(const InstDev *insts, int n_inst, const double2 *logg, const int *cut, double *err,
+                            const int *status, hipStream_t st) {
     if (n_inst <= 0 || !err) return hipSuccess;
-    hipLaunchKernelGGL(mixed_err, dim3(n_inst), dim3(256), 0, st, insts, logg, err, status);
+    hipLaunchKernelGGL(mixed_err, dim3(n_inst), dim3(256), 0, st, insts, logg, cut, err, status);
     return hipGetLastError();
 }
 }  // namespace cgd
@@ -2428,20 +2556,20 @@ static constexpr int hess_det_lds_bytes(int MB) { return 2 * 16 * 16 * MB * (int
 
 template <int MB>
 static hipError_t launch_hd(const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg, const double2 *pool,
-                            const double2 *eigc, double2 *table, hipStream_t st) {
+                            const double2 *eigc, double2 *table, int *status, hipStream_t st) {
     hipLaunchKernelGGL((hess_det_f64<MB>), dim3((unsigned)nwg), dim3(kHessDetThreads), hess_det_lds_bytes(MB), st,
-                       jobs, prefix, njobs, pool, eigc, table);
+                       jobs, prefix, njobs, pool, eigc, table, status);
     return hipGetLastError();
 }
 
 hipError_t launch_hess_det(int cls, const HessDev *jobs, const int64_t *prefix, int njobs, int64_t nwg,
-                           const double2 *pool, const double2 *eigc, double2 *table, hipStream_t st) {
+                           const double2 *pool, const double2 *eigc, double2 *table, int *status, hipStream_t st) {
     if (nwg <= 0) return hipSuccess;
     switch (cls) {
-        case 0: return launch_hd<2>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
-        case 1: return launch_hd<4>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
-        case 2: return launch_hd<6>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
-        case 3: return launch_hd<9>(jobs, prefix, njobs, nwg, pool, eigc, table, st);
+        case 0: return launch_hd<2>(jobs, prefix, njobs, nwg, pool, eigc, table, status, st);
+        case 1: return launch_hd<4>(jobs, prefix, njobs, nwg, pool, eigc, table, status, st);
+        case 2: return launch_hd<6>(jobs, prefix, njobs, nwg, pool, eigc, table, status, st);
+        case 3: return launch_hd<9>(jobs, prefix, njobs, nwg, pool, eigc, table, status, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2466,8 +2594,11 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          hipFuncSetAttribute((const void *)hess_det_f64<9>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                              hess_det_lds_bytes(9))})
         if (e != hipSuccess) return e;
-    for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<4, 2, 2>(), prepare_mfma<6, 2, 4>(),
-                         prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(), prepare_mfma<12, 2, 4>()})
+    for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<2, 1, 1>(), prepare_mfma<2, 2, 2>(),
+                         prepare_mfma<4, 2, 2>(), prepare_mfma<4, 1, 2>(), prepare_mfma<4, 1, 1>(),
+                         prepare_mfma<4, 2, 4>(), prepare_mfma<6, 2, 4>(), prepare_mfma<6, 2, 2>(),
+                         prepare_mfma<6, 3, 2>(), prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(),
+                         prepare_mfma<12, 2, 4>()})
         if (e != hipSuccess) return e;
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2489,3 +2620,4 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
     return hipSuccess;
 }
 }  // namespace cgd
+

@@ -1,13 +1,17 @@
 """Mixed path (complex FP32 factorisations + FP64 re-factorisation of the grid
-points whose value can matter) against the FP64 path.
+points whose value can matter) against the FP64 path and the oracle.
 
-Bar: every probability of every instance within 1e-9 of the FP64 path, and
-within the per-instance error bound the library reports."""
+Bar: every probability of every instance within 1e-9 of the FP64 path and of
+the oracle, and within the per-instance error bound the library reports.  The
+FP32 error model (relative error of G at most 2 (n + 1) 2^-24 per internal
+block of order n) is checked point by point on workloads whose seeds and shapes
+were not used to set it."""
 import numpy as np
 import pytest
 
 import paper_2412_17742_amd as cgd
 import workloads as W
+from oracle import pgf
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-9
@@ -17,9 +21,10 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _run(instances, precision, tol=TOL, flags=cgd.FLAG_NO_HESSENBERG):
+def _run(instances, precision, tol=TOL, flags=cgd.FLAG_NO_HESSENBERG | cgd.FLAG_NO_AUTOTUNE):
     # the FP32 path is what is tested here: the Hessenberg route (FP64 in both
-    # precisions) is switched off unless a test asks for it
+    # precisions) is switched off unless a test asks for it, and the autotuner,
+    # which may send a size class straight to FP64, is kept out
     import torch
     with cgd.Context(instances, precision=precision, tol=tol, flags=flags) as ctx:
         err = torch.full((ctx.n_inst,), -1.0, dtype=torch.float64, device="cuda")
@@ -76,7 +81,7 @@ def test_mixed_order_192_class_and_elimination_off():
     # the dense no-Schur lossy instance (order 97) the order-128 class
     _say("mixed gbs144_3bins / no-Schur lossy16_k3")
     for insts, flags in (([W.gbs_m144(3)], 0), ([W.lossy_m16_k3()], cgd.FLAG_NO_SCHUR | cgd.FLAG_DENSE_INTERNAL)):
-        flags |= cgd.FLAG_NO_HESSENBERG
+        flags |= cgd.FLAG_NO_HESSENBERG | cgd.FLAG_NO_AUTOTUNE
         p64, _, _, offs = _run(insts, "fp64", flags=flags)
         pm, errm, _, _ = _run(insts, "mixed", flags=flags)
         assert np.abs(pm - p64).max() <= TOL
@@ -93,3 +98,125 @@ def test_mixed_with_hessenberg_route_matches_fp64():
     assert nfix == 0 and ntot == 0
     assert np.all(errm == 0.0)
     assert np.abs(pm - p64).max() <= 1e-14
+
+
+def _heldout_uneven():
+    # instances 512.. of the uneven generator: other seeds than the batch
+    return [W.uneven_instance(i) for i in range(512, 640)]
+
+
+def _heldout_gbs():
+    # a GBS-shaped state of another size and seed: M = 96, 2 and 3 bins
+    rng = W.rng_for(40)
+    M = 96
+    r = rng.uniform(0.4, 1.2, M)
+    U = W.haar_unitary(M, rng)
+    return [W.make_instance(np.sqrt(0.5) * U, r, bin_of=W.contiguous_bins([48, 48]), cutoff=[40, 40]),
+            W.make_instance(np.sqrt(0.5) * U, r, bin_of=W.contiguous_bins([32, 32, 32]), cutoff=[20, 20, 20])]
+
+
+def _heldout_mesh():
+    return W.mesh_batch(80)[64:]
+
+
+def _tau(inst):
+    """The library's assumed relative error of an FP32 value of G for an
+    instance whose modes are all measured, undisplaced, one block per internal
+    mode with the largest bin eliminated: 2 (n + 1) 2^-24 per block."""
+    M = inst["T"].shape[0]
+    K = W.n_internal(inst)
+    bins = np.asarray(inst["bin_of"])
+    n = 2 * M - 2 * max(int((bins == l).sum()) for l in range(len(inst["cutoff"])))
+    return K * 2.0 * (n + 1) * 2.0 ** -24 if n > 0 else 0.0
+
+
+HELDOUT = {"uneven_other_seeds": _heldout_uneven, "gbs96": _heldout_gbs, "mesh_other_sets": _heldout_mesh}
+
+
+@pytest.mark.parametrize("name", sorted(HELDOUT))
+def test_fp32_error_model_holds_point_by_point_on_heldout_workloads(name):
+    """Every grid point of the FP32 pass within |G| tau of the FP64 value."""
+    import torch
+    insts = HELDOUT[name]()
+    vals = {}
+    for prec, tol in (("fp64", TOL), ("mixed", 1e300)):
+        with cgd.Context(insts, precision=prec, tol=tol, flags=cgd.FLAG_NO_HESSENBERG | cgd.FLAG_NO_AUTOTUNE) as ctx:
+            ctx.eval()
+            vals[prec] = ctx.grid_values().cpu().numpy()
+            torch.cuda.synchronize()
+    off, worst = 0, 0.0
+    for x in insts:
+        G = [int(g) for g in x["grid"]]
+        npts = (G[0] // 2 + 1) * int(np.prod(G[1:]))
+        g64 = np.exp(vals["fp64"][off:off + npts])
+        g32 = np.exp(vals["mixed"][off:off + npts])
+        off += npts
+        tau = _tau(x)
+        if tau == 0.0:  # no factorisation (one bin: eigenvalues only), FP64 in both
+            assert np.abs(g32 - g64).max() <= 1e-13
+            continue
+        ratio = np.abs(g32 - g64) / (np.abs(g64) * tau)
+        worst = max(worst, float(ratio.max()))
+    _say(f"  {name}: largest |G32 - G64| / (|G64| tau) = {worst:.3f}")
+    assert off == len(vals["fp64"])
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("name", sorted(HELDOUT))
+def test_mixed_within_bound_on_heldout_workloads(name):
+    insts = HELDOUT[name]()
+    p64, _, _, offs = _run(insts, "fp64")
+    pm, errm, (nfix, ntot), _ = _run(insts, "mixed")
+    d = _per_instance_maxdiff(pm, p64, offs)
+    _say(f"  {name}: max |Pmixed - P64| = {d.max():.3e}, bound {errm.max():.3e}, refactorised {nfix}/{ntot}")
+    assert np.all(errm <= TOL)
+    assert np.all(d <= errm + 1e-15)
+
+
+def _oracle_cases():
+    from test_gpu_parity import _edge_instances
+    lossy = W.lossy_m16_k3(grid=[6, 6, 6, 6])
+    lossy["cutoff"] = np.array([5, 5, 5, 5], np.int32)
+    return [W.plain_m4(), W.plain_m4(grid=[40, 40]), lossy] + _edge_instances()
+
+
+def test_mixed_matches_oracle_within_1e9():
+    insts = _oracle_cases()
+    for flags in (cgd.FLAG_NO_HESSENBERG | cgd.FLAG_NO_AUTOTUNE, 0):
+        pm, errm, _, offs = _run(insts, "mixed", flags=flags)
+        for i, x in enumerate(insts):
+            ref = pgf.wrapped_distribution(x).ravel()
+            d = np.abs(pm[offs[i]:offs[i + 1]] - ref).max()
+            assert d <= TOL, (flags, i, d)
+            assert d <= errm[i] + 1e-12, (flags, i, d, errm[i])
+
+
+def test_autotuner_report_and_choices():
+    """The tuner's report names every size class it timed, keeps the fastest
+    kernel shape of each kind, and sends a mixed class straight to FP64 unless
+    its FP32 pass is below 0.85 of the FP64 time; the mixed result stays within
+    its bound either way."""
+    insts = W.uneven_batch(64)
+    for prec in ("fp64", "mixed"):
+        with cgd.Context(insts, precision=prec, tol=TOL, flags=cgd.FLAG_NO_HESSENBERG) as ctx:
+            rep = ctx.tuning()
+            _say(f"  {prec}: {rep}")
+            assert rep["autotune"] and rep["classes"], rep
+            for c in rep["classes"]:
+                assert c["items"] > 0 and 0 < c["sample"] <= 8192
+                f64, f32 = c["fp64_ms"], c["fp32_ms"]
+                assert f64 and all(t > 0 for t in f64.values())
+                assert c["fp64_kernel"] == min(f64, key=f64.get)
+                if prec == "fp64":
+                    assert not f32 and c["precision"] == "fp64"
+                elif f32:
+                    fast32 = min(f32.values()) < 0.85 * min(f64.values())
+                    assert c["precision"] == ("fp32+fp64" if fast32 else "fp64")
+                    if fast32:
+                        assert c["fp32_kernel"] == min(f32, key=f32.get)
+    with cgd.Context(insts, flags=cgd.FLAG_NO_AUTOTUNE) as ctx:
+        assert ctx.tuning() == {"autotune": False, "classes": []}
+    pm, errm, _, offs = _run(insts, "mixed", flags=cgd.FLAG_NO_HESSENBERG)
+    p64, _, _, _ = _run(insts, "fp64", flags=cgd.FLAG_NO_HESSENBERG)
+    d = _per_instance_maxdiff(pm, p64, offs)
+    assert np.all(errm <= TOL) and np.all(d <= errm + 1e-15)

@@ -263,3 +263,19 @@ def test_graph_replays_match_eager_evaluation(precision):
         ctx.eval(other)
         torch.cuda.synchronize()
         assert torch.equal(other, eager)
+
+
+@pytest.mark.parametrize("flags", [cgd.FLAG_NO_AUTOTUNE, cgd.FLAG_NO_AUTOTUNE | cgd.FLAG_NO_SCHUR])
+def test_one_wave_kernel_forced(flags):
+    """Orders <= 64 on the one-wave kernel (the default without the autotuner):
+    edge cases, a lossy instance and the cheapest uneven instances against the
+    oracle."""
+    _say("one-wave kernel forced, flags", flags)
+    lossy = W.lossy_m16_k3(grid=[5, 5, 5, 5])
+    lossy["cutoff"] = np.array([4, 4, 4, 4], np.int32)
+    uneven = W.uneven_batch(64)
+    # block orders 12, 8, 6 (<= 32) and 40, 58, 40 (33..64, K = 1, 1, 3)
+    insts = _edge_instances() + [lossy, W.plain_m4()] + [uneven[i] for i in (0, 36, 58, 39, 18, 60)]
+    got = gpu_dists(insts, flags)
+    for i, (inst, P) in enumerate(zip(insts, got)):
+        assert np.abs(P - pgf.wrapped_distribution(inst)).max() <= TOL_FP64, i
