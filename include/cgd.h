@@ -144,6 +144,26 @@ cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_
  * detected on the device is reported by the next call as CGD_ERR_NUMERIC. */
 cgd_status cgd_eval(cgd_ctx *ctx, double *d_probs, double *d_err_bound);
 
+/* Evaluation that allocates nothing, for callers that cannot allocate device
+ * memory: code under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result and error behaviour as cgd_eval,
+ * bit for bit, but the launches are enqueued directly on the context's stream
+ * (no HIP graph is instantiated, no per-stage timing) and the per-evaluation
+ * buffers (per-point contributions, log G, the DFT passes, the mixed path's
+ * FP32 values, bucket sums and re-factorisation lists, the Hessenberg route's
+ * tables) live in a static device array of 128 MiB per GPU, held by each GPU
+ * the library runs on until the process ends.  The context's own allocations
+ * from cgd_create (state, matrix pool, blocked-LU workspace, status word) are
+ * used as by cgd_eval.
+ *   Errors: CGD_ERR_ARG if the context needs more than 128 MiB of these
+ *   buffers (the message gives the size) or the current device is not the one
+ *   the context was created on; the other errors as for cgd_eval.
+ *   Every call on one GPU shares that GPU's array and keeps the last call's
+ *   contents: calls that overlap on one GPU (other streams, other host
+ *   threads) race and must be serialised by the caller.  cgd_grid_values,
+ *   cgd_grad and cgd_mixed_stats need a cgd_eval after it (CGD_ERR_STATE). */
+cgd_status cgd_eval_static(cgd_ctx *ctx, double *d_probs, double *d_err_bound);
+
 /* Diagnostic: after cgd_eval, copy log G(w) (complex) at the evaluated grid
  * points into d_logg (device, 2 * cgd_points(ctx) doubles).  Points are
  * instance by instance; within an instance k_1 runs over [0, G_1/2] (the other

@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.cgd_layout.argtypes = [vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64)]
     L.cgd_eval.restype = i32
     L.cgd_eval.argtypes = [vp, vp, vp]
+    L.cgd_eval_static.restype = i32
+    L.cgd_eval_static.argtypes = [vp, vp, vp]
     L.cgd_points.restype = i64
     L.cgd_points.argtypes = [vp]
     L.cgd_grid_values.restype = i32
@@ -164,6 +166,20 @@ class Context:
             assert err.dtype == torch.float64 and err.is_cuda and err.numel() >= self.n_inst
         _check(lib().cgd_eval(self._h, ctypes.c_void_p(probs.data_ptr()),
                               None if err is None else ctypes.c_void_p(err.data_ptr())))
+        return probs
+
+    def eval_static(self, probs=None, err=None):
+        """As eval(), through cgd_eval_static: no device allocation inside the
+        library call (its per-evaluation buffers are a static device array)."""
+        import torch
+        if probs is None:
+            probs = torch.empty(self.n_probs, dtype=torch.float64, device="cuda")
+        assert probs.dtype == torch.float64 and probs.is_cuda and probs.numel() >= self.n_probs
+        assert probs.is_contiguous()
+        if err is not None:
+            assert err.dtype == torch.float64 and err.is_cuda and err.numel() >= self.n_inst
+        _check(lib().cgd_eval_static(self._h, ctypes.c_void_p(probs.data_ptr()),
+                                     None if err is None else ctypes.c_void_p(err.data_ptr())))
         return probs
 
     def split(self, probs):

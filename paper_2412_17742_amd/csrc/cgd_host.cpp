@@ -510,9 +510,11 @@ struct cgd_ctx {
     hipGraphExec_t gexec = nullptr;
     double *g_probs = nullptr, *g_err = nullptr;
     bool evaluated = false;
+    bool last_static = false;          // the last evaluation was cgd_eval_static
     int reg_var[kRegClasses] = {};     // autotuner: thread grid of the FP64 register kernel per class
     int mfma_var[kMfmaClasses] = {};   // autotuner: wave layout of the FP32 MFMA kernel per class
     std::string tune_json;             // autotuner report
+    int device = -1;                   // device current at cgd_create
     bool timing = false;
     // per-launch timing: event pairs recorded around each launch of a stage (eager
     // evaluations with timing on); a stage's time is the sum over its launches
@@ -1586,7 +1588,14 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     c->tol = tol;
     c->flags = flags;
     c->stream = (hipStream_t)hip_stream;
+    // validation errors come back from build before any device call
     cgd_status s = build(c, inst, n_inst);
+    if (s == CGD_OK && hipGetDevice(&c->device) != hipSuccess) s = fail(CGD_ERR_DEVICE, "hipGetDevice failed");
+    if (s == CGD_OK) {
+        // the device address of cgd_eval_static's scratch array, once per device
+        const hipError_t e = static_scratch_setup(c->device);
+        if (e != hipSuccess) s = fail(CGD_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
     if (s != CGD_OK) {
         free_ctx(c);
         return s;
@@ -1608,7 +1617,8 @@ int64_t cgd_points(const cgd_ctx *ctx) { return ctx ? ctx->npts : 0; }
 
 namespace {
 // Device buffers one evaluation writes and reads back (all of them rewritten by
-// every evaluation before they are read).
+// every evaluation before they are read): the context's own (cgd_eval) or
+// slices of the static per-device scratch (cgd_eval_static).
 struct EvalBufs {
     double2 *contrib, *logg, *gA, *gB, *logg32, *eigc, *htable;
     int *counts, *cut;
@@ -1619,6 +1629,21 @@ struct EvalBufs {
 EvalBufs ctx_bufs(const cgd_ctx *c) {
     return EvalBufs{c->d_contrib, c->d_logg, c->d_gA, c->d_gB, c->d_logg32, c->d_eigc, c->d_htable,
                     c->d_counts, c->d_cut, c->d_hist, c->d_list};
+}
+
+// Byte sizes of the EvalBufs fields in field order (0: not used by this context).
+constexpr int kEvalBufs = 11;
+void eval_buf_sizes(const cgd_ctx *c, size_t (&sz)[kEvalBufs]) {
+    const bool mixed = c->prec == CGD_PREC_MIXED;
+    const bool hess = !c->hess_all.empty();
+    const size_t cz = sizeof(double2);
+    const size_t v[kEvalBufs] = {cz * (size_t)c->ncontrib, cz * (size_t)c->npts, cz * (size_t)c->npts,
+                                 cz * (size_t)c->npts, mixed ? cz * (size_t)c->npts : 0,
+                                 hess ? cz * (size_t)c->hess_nec : 0, hess ? cz * (size_t)c->hess_ntab : 0,
+                                 mixed ? sizeof(int) * kG64 : 0, mixed ? sizeof(int) * (size_t)c->n_inst : 0,
+                                 mixed ? sizeof(unsigned long long) * (size_t)c->n_inst * kMixedBuckets : 0,
+                                 mixed ? sizeof(int2) * (size_t)c->list_total : 0};
+    for (int i = 0; i < kEvalBufs; ++i) sz[i] = v[i];
 }
 
 // Enqueue every launch of one evaluation on stream st.
@@ -1767,12 +1792,53 @@ cgd_status cgd_eval(cgd_ctx *c, double *d_probs, double *d_err_bound) {
     HIP_OK(hipEventRecord(c->ev_status, c->stream));
     c->status_pending = true;
     c->evaluated = true;
+    c->last_static = false;
+    return CGD_OK;
+}
+
+cgd_status cgd_eval_static(cgd_ctx *c, double *d_probs, double *d_err_bound) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (!d_probs) return fail(CGD_ERR_ARG, "d_probs is NULL");
+    cgd_status s = check_status(c);
+    if (s != CGD_OK) return s;
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != c->device) return fail(CGD_ERR_ARG, "cgd_eval_static: the context's device is not the current device");
+    unsigned char *base = (unsigned char *)static_scratch(dev);
+    if (!base) return fail(CGD_ERR_STATE, "cgd_eval_static: no static scratch on this device");
+    // slices of the static scratch, 256-byte aligned, in EvalBufs field order
+    size_t sz[kEvalBufs];
+    eval_buf_sizes(c, sz);
+    void *ptr[kEvalBufs] = {};
+    size_t off = 0;
+    for (int i = 0; i < kEvalBufs; ++i) {
+        if (sz[i] == 0) continue;
+        ptr[i] = base + off;
+        off += (sz[i] + 255) & ~(size_t)255;
+    }
+    if (off > kStaticScratchBytes)
+        return fail(CGD_ERR_ARG, "cgd_eval_static: this context needs " + std::to_string(off) +
+                                     " bytes of scratch, more than the " + std::to_string(kStaticScratchBytes) +
+                                     " bytes of the static array");
+    const EvalBufs b{(double2 *)ptr[0], (double2 *)ptr[1], (double2 *)ptr[2], (double2 *)ptr[3], (double2 *)ptr[4],
+                     (double2 *)ptr[5], (double2 *)ptr[6], (int *)ptr[7], (int *)ptr[8],
+                     (unsigned long long *)ptr[9], (int2 *)ptr[10]};
+    // eager launches on the context's stream (no graph to instantiate, no timing events)
+    const bool timing = c->timing;
+    c->timing = false;
+    s = enqueue_eval(c, c->stream, d_probs, d_err_bound, b);
+    c->timing = timing;
+    if (s != CGD_OK) return s;
+    HIP_OK(hipMemcpyAsync(c->h_status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipEventRecord(c->ev_status, c->stream));
+    c->status_pending = true;
+    c->last_static = true;
     return CGD_OK;
 }
 
 cgd_status cgd_grid_values(cgd_ctx *c, double *d_logg) {
     if (!c || !d_logg) return fail(CGD_ERR_ARG, "NULL argument");
-    if (!c->evaluated) return fail(CGD_ERR_STATE, "cgd_grid_values before cgd_eval");
+    if (!c->evaluated || c->last_static) return fail(CGD_ERR_STATE, "cgd_grid_values needs a preceding cgd_eval");
     HIP_OK(hipMemcpyAsync(d_logg, c->d_logg, sizeof(double2) * c->npts, hipMemcpyDeviceToDevice, c->stream));
     return CGD_OK;
 }
@@ -1780,7 +1846,7 @@ cgd_status cgd_grid_values(cgd_ctx *c, double *d_logg) {
 cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_dT, double *d_dalpha) {
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
     if (!(c->flags & CGD_FLAG_GRAD)) return fail(CGD_ERR_STATE, "context created without CGD_FLAG_GRAD");
-    if (!c->evaluated) return fail(CGD_ERR_STATE, "cgd_grad before cgd_eval");
+    if (!c->evaluated || c->last_static) return fail(CGD_ERR_STATE, "cgd_grad needs a preceding cgd_eval");
     if (!d_dprobs) return fail(CGD_ERR_ARG, "d_dprobs is NULL");
     cgd_status s = check_status(c);
     if (s != CGD_OK) return s;
@@ -1852,7 +1918,8 @@ cgd_status cgd_stage_times(cgd_ctx *c, double *ms) {
 
 cgd_status cgd_mixed_stats(cgd_ctx *c, int64_t *n_refactored, int64_t *n_total) {
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
-    if (c->prec != CGD_PREC_MIXED || !c->evaluated) return fail(CGD_ERR_STATE, "no mixed evaluation yet");
+    if (c->prec != CGD_PREC_MIXED || !c->evaluated || c->last_static)
+        return fail(CGD_ERR_STATE, "cgd_mixed_stats needs a preceding mixed cgd_eval");
     int h[kG64];
     if (c->stream) HIP_OK(hipStreamSynchronize(c->stream)); else HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost));

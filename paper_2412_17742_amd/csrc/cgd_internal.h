@@ -217,4 +217,9 @@ hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, in
                             const double2 *in, double2 *out, double *probs, double *err, const int *status,
                             hipStream_t st);
 
+// static per-device scratch of cgd_eval_static (cgd_kernels.hip)
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+hipError_t static_scratch_setup(int dev);  // with device dev current; once per device
+void *static_scratch(int dev);             // its device address, or nullptr before setup
+
 }  // namespace cgd

@@ -2621,3 +2621,41 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
 }
 }  // namespace cgd
 
+// ---------------------------------------------------------------------------
+// Static per-device scratch for cgd_eval_static, the evaluation entry point
+// that allocates nothing.  `scratch` is a host-side stand-in in host code; its
+// device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device (with that device current) and kept in g_scratch.  Every call on a
+// GPU shares that GPU's array.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+namespace cgd {
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[dev] = ptr;
+    return hipSuccess;
+}
+
+void *static_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
+
+}  // namespace cgd
