@@ -154,6 +154,7 @@ def extra_workload(cgd, name, steps, warmup, tol, grad=False):
         t0 = time.perf_counter()
         with cgd.Context(insts, precision=prec, tol=tol) as ctx:
             create_s[prec] = time.perf_counter() - t0
+            wrap_stated = ctx.bounds()[1]
             ms[prec], _, p = run(ctx, steps, warmup)
             probs[prec] = p.clone()
             npts = ctx.n_points
@@ -164,12 +165,13 @@ def extra_workload(cgd, name, steps, warmup, tol, grad=False):
                 err_bound = float(err.max().item())
     maxdiff = float((probs["mixed"] - probs["fp64"]).abs().max().item())
     ok = maxdiff <= tol
+    exact = exact_box(cgd, insts, tol, wrap_stated)
     best = "mixed" if ok and ms["mixed"] < ms["fp64"] else "fp64"
     out = {"workload": f"{name}: {desc}", "value": npts / (ms[best] * 1e-3), "unit": "grid dets/s",
            "precision": best, "ms_per_step": ms[best], "evaluated_points": npts,
            "fp64_ms": ms["fp64"], "mixed_ms": ms["mixed"], "mixed_max_abs_diff_vs_fp64": maxdiff,
            "mixed_err_bound": err_bound, "refactorised_fp64": stats[0], "factorisations": stats[1],
-           "create_s": create_s}
+           "create_s": create_s, "exact_box": exact}
     if grad:
         out["grad"] = grad_timing(cgd, insts, max(2, steps // 4), 1, 0)
     return out
@@ -202,6 +204,22 @@ def fp64_kernel_name(tuning, stage):
     if c is not None and c["fp64_kernel"] == "lu_wave":
         return f"lu_wave<double,{32 if c['class'] == 0 else 64}>"
     return cgd.LU_KERNELS.get(stage, (stage,))[0]
+
+
+def exact_box(cgd, insts, tol, wrap_stated):
+    """Wrap of the stated grid (bound on P_wrap - Pr over the box) and, when it
+    exceeds tol, the automatic grid (cgd grid entries 0) that brings it below
+    tol / 10."""
+    out = {"stated_grid_wrap_bound_max": float(np.max(wrap_stated))}
+    if out["stated_grid_wrap_bound_max"] > tol:
+        auto = [dict(x, grid=np.zeros(len(x["cutoff"]), np.int32)) for x in insts]
+        t0 = time.perf_counter()
+        with cgd.Context(auto, precision="fp64", tol=tol) as ctx:
+            grids, wrap = ctx.bounds()
+            npts = ctx.n_points
+        out.update(auto_grid=sorted(set(grids))[:8], auto_grid_wrap_bound_max=float(np.max(wrap)),
+                   auto_grid_evaluated_points=npts, auto_create_s=time.perf_counter() - t0)
+    return out
 
 
 def stage_profile(ctx, steps):
@@ -270,6 +288,7 @@ def main():
         flops, bytes_ = ctx.stage_work()
         tuning = ctx.tuning()
         tuning["precision"] = prec
+        wrap_stated = ctx.bounds()[1]
         rec = dict(ctx=ctx, ms=ms, wall_ms=wall_ms, probs=probs.clone(), stages=stages, flops=flops,
                    bytes=bytes_, create_s=create_s, tuning=tuning)
         if prec == "mixed":
@@ -349,6 +368,7 @@ def main():
         "fp64": summary(paths["fp64"], "fp64"),
         "mixed": summary(paths["mixed"], "mixed"),
         "roofline": roof,
+        "exact_box": exact_box(cgd, instances, args.tol, wrap_stated),
     }
     if args.grad:
         out["grad"] = grad_timing(cgd, instances, args.steps, args.warmup, args.flags)

@@ -105,7 +105,11 @@ typedef struct {
                                 resolve_internal != 0                                          */
     int32_t resolve_internal;/* 0: detectors see external modes; 1: bins over (i, k) pairs     */
     const int32_t *cutoff;   /* L entries N_l >= 0: output box b_l in [0, N_l]                */
-    const int32_t *grid;     /* L entries G_l >= N_l + 1, or NULL for G_l = N_l + 1           */
+    const int32_t *grid;     /* L entries G_l >= N_l + 1, or NULL for G_l = N_l + 1; an entry 0
+                                asks for the smallest G_l >= N_l + 1 whose tail bound
+                                Pr(b_l >= G_l) (see cgd_bounds) is at most tol / (10 L), so
+                                that the wrapped distribution is within tol / 10 of the exact
+                                binned probabilities (needs a finite tol > 0; G_l <= 4096)    */
 } cgd_instance;
 
 /* Assemble the states (FP64, host) and upload everything the evaluation
@@ -236,6 +240,23 @@ cgd_status cgd_stage_work(const cgd_ctx *ctx, double *flops /* CGD_NSTAGES */, d
  * evaluation.  Waits for the last evaluation.  CGD_ERR_STATE on the FP64 path
  * or before the first evaluation. */
 cgd_status cgd_mixed_stats(cgd_ctx *ctx, int64_t *n_refactored, int64_t *n_total);
+
+/* Grid and wrap bound of every instance (host outputs, may be NULL each):
+ *   grid        sum_i L_i entries: the grid extents G_l in use (automatic
+ *               entries resolved), instances concatenated
+ *   wrap_bound  n_inst entries: sum_l B_l with B_l >= Pr(b_l >= G_l), so that
+ *               0 <= P(b) - Pr(b) <= wrap_bound for every b in the box, P the
+ *               wrapped distribution on the grid and Pr(b) the exact binned
+ *               probability (Eq. coarse_grained_prob).
+ * B_l is the Chernoff bound min_{s > 1} E[s^{b_l}] / s^{G_l} with the marginal
+ * moment generating function of bin l in closed form (Sec. VI C, Eq. M, the
+ * other bins' variables at t = 0): per internal block, with R the bin's rows
+ * and columns of Sigma^(s=1) and zbar its means,
+ *   E[s^b] = exp(1/2 (s-1) zbar^H (I - (s-1) R)^-1 zbar) / sqrt(det(I - (s-1) R)),
+ * evaluated exactly (FP64) from a tridiagonal form of R, and minimised over s
+ * up to the edge of convergence.  With the Hermitian half grid the library
+ * sums, the output has no imaginary part to report. */
+cgd_status cgd_bounds(const cgd_ctx *ctx, int32_t *grid, double *wrap_bound);
 
 /* Autotuner report (JSON text, valid until cgd_destroy; NULL if ctx is NULL).
  * cgd_create times, for every size class of per-point factorisations in the

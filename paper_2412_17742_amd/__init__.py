@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
     L.cgd_stage_work.argtypes = [vp, vp, vp]
     L.cgd_mixed_stats.restype = i32
     L.cgd_mixed_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.cgd_bounds.restype = i32
+    L.cgd_bounds.argtypes = [vp, vp, vp]
     L.cgd_tuning.restype = ctypes.c_char_p
     L.cgd_tuning.argtypes = [vp]
     L.cgd_destroy.restype = None
@@ -230,6 +232,19 @@ class Context:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().cgd_mixed_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def bounds(self):
+        """(grid extents per instance with automatic entries resolved, wrap-tail
+        bound per instance: 0 <= P_wrap(b) - Pr(b) <= bound for every b in the box)."""
+        nL = sum(len(s) for s in self.shapes)
+        g = np.zeros(nL, np.int32)
+        w = np.zeros(self.n_inst, np.float64)
+        _check(lib().cgd_bounds(self._h, g.ctypes.data, w.ctypes.data))
+        out, off = [], 0
+        for s in self.shapes:
+            out.append(tuple(int(x) for x in g[off:off + len(s)]))
+            off += len(s)
+        return out, w
 
     def tuning(self):
         """The autotuner's report (dict): per size class, the timed kernels and the choice."""

@@ -74,12 +74,112 @@ struct HostInstCopy {
     std::vector<std::vector<double>> rk;
 };
 
+// Marginal moment generating function of one bin's count within one
+// internal block (Sec. VI C, Eq. M, with the other bins' variables at t = 0):
+// with R the bin's rows and columns of Sigma - I (the s = 1 ordered covariance)
+// and zbar its means, E[s^b] = exp(1/2 u zbar^H (I - u R)^-1 zbar) /
+// sqrt(det(I - u R)), u = s - 1.  R is kept as a real tridiagonal T (d, e)
+// unitarily similar to it, zbar as z = Q^H zbar in the same basis.
+struct BinMarginal {
+    std::vector<double> d, e;
+    std::vector<cplx> z;  // empty when undisplaced
+};
+
 struct HostInst {
     int L = 1;
     int G[kMaxBins] = {0}, N[kMaxBins] = {0};
+    bool auto_grid[kMaxBins] = {};
     double logpr0 = 0.0;
     int nblocks = 0;
+    std::vector<BinMarginal> marg[kMaxBins];  // per bin, one entry per internal block
+    double wrap_bound = 0.0;                   // sum_l bound on Pr(b_l >= G_l)
 };
+
+// log E[s^b] of a bin, u = s - 1 >= 0, summed over its blocks; +inf outside
+// the domain of convergence (I - u T not positive definite).
+double bin_log_mgf(const std::vector<BinMarginal> &mb, double u) {
+    double acc = 0.0;
+    std::vector<double> piv, yr, yi;
+    for (const BinMarginal &m : mb) {
+        const int n = (int)m.d.size();
+        piv.resize(n);
+        // LDL^T of the tridiagonal I - u T: pivots must stay positive
+        for (int i = 0; i < n; ++i) {
+            double p = 1.0 - u * m.d[i];
+            if (i > 0) {
+                const double o = u * m.e[i - 1];
+                p -= o * o / piv[i - 1];
+            }
+            if (!(p > 0.0)) return INFINITY;
+            piv[i] = p;
+            acc -= 0.5 * std::log(p);
+        }
+        if (!m.z.empty()) {
+            // y = (I - u T)^-1 z by the same factors (T real: real and imaginary parts apart)
+            yr.resize(n);
+            yi.resize(n);
+            for (int i = 0; i < n; ++i) {
+                yr[i] = m.z[i].real();
+                yi[i] = m.z[i].imag();
+                if (i > 0) {
+                    const double l = -u * m.e[i - 1] / piv[i - 1];
+                    yr[i] -= l * yr[i - 1];
+                    yi[i] -= l * yi[i - 1];
+                }
+            }
+            for (int i = n - 1; i >= 0; --i) {
+                yr[i] /= piv[i];
+                yi[i] /= piv[i];
+                if (i + 1 < n) {
+                    const double l = -u * m.e[i] / piv[i];
+                    yr[i] -= l * yr[i + 1];
+                    yi[i] -= l * yi[i + 1];
+                }
+            }
+            double q = 0.0;
+            for (int i = 0; i < n; ++i) q += m.z[i].real() * yr[i] + m.z[i].imag() * yi[i];
+            acc += 0.5 * u * q;
+        }
+    }
+    return acc;
+}
+
+// log of the Chernoff bound Pr(b >= G) <= min over s > 1 of E[s^b] / s^G: the
+// exponent log E[s^b] - G log s is convex in t = log s, minimised by golden
+// section over (0, t_max), t_max the edge of convergence (found by doubling
+// and bisection).  0 means no bound below 1.
+double bin_log_tail(const std::vector<BinMarginal> &mb, int G) {
+    double hi = 1.0;
+    int it = 0;
+    while (std::isfinite(bin_log_mgf(mb, hi)) && it++ < 200) hi *= 2.0;
+    double lo = 0.0;
+    if (it > 200) return -INFINITY;  // no photons in this bin
+    for (int k = 0; k < 100; ++k) {
+        const double mid = 0.5 * (lo + hi);
+        (std::isfinite(bin_log_mgf(mb, mid)) ? lo : hi) = mid;
+    }
+    const double tmax = std::log1p(lo);
+    auto f = [&](double t) { return bin_log_mgf(mb, std::expm1(t)) - G * t; };
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    double a = 0.0, b = tmax;
+    double x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1 = f(x1), f2 = f(x2);
+    for (int k = 0; k < 200 && b - a > 1e-12 * (1.0 + b); ++k) {
+        if (f1 <= f2) {
+            b = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = b - gr * (b - a);
+            f1 = f(x1);
+        } else {
+            a = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = a + gr * (b - a);
+            f2 = f(x2);
+        }
+    }
+    return std::min(0.0, std::min(f1, f2));
+}
 
 cplx cx(const double *p, size_t i) { return cplx(p[2 * i], p[2 * i + 1]); }
 
@@ -90,8 +190,7 @@ bool spectral_norm_sq(const double *T, int M, double &out) {
         for (int j = 0; j < M; ++j) A(i, j) = cx(T, (size_t)i * M + j);
     CMat G = matmul(adjoint(A), A);
     std::vector<double> lam;
-    CMat V;
-    if (!hermitian_eig(G, lam, V)) return false;
+    if (!hermitian_eigvals(G, lam)) return false;
     out = *std::max_element(lam.begin(), lam.end());
     return true;
 }
@@ -136,7 +235,9 @@ cgd_status validate(const cgd_instance &in, int idx) {
     for (int l = 0; l < in.L; ++l) {
         if (in.cutoff[l] < 0 || in.cutoff[l] > 4095) return fail(CGD_ERR_ARG, at + "cutoff out of range");
         const int g = in.grid ? in.grid[l] : in.cutoff[l] + 1;
-        if (g < in.cutoff[l] + 1 || g > 4096) return fail(CGD_ERR_ARG, at + "grid must satisfy cutoff+1 <= G <= 4096");
+        if (g == 0 && in.grid) continue;  // automatic: chosen from the tail bound
+        if (g < in.cutoff[l] + 1 || g > 4096)
+            return fail(CGD_ERR_ARG, at + "grid must satisfy cutoff+1 <= G <= 4096 (or 0: automatic)");
         npts *= g;
         if (npts > (int64_t)1 << 31) return fail(CGD_ERR_ARG, at + "grid too large");
     }
@@ -202,6 +303,26 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
         zbar[i] = beta[i];
         zbar[m + i] = std::conj(beta[i]);
         if (beta[i] != cplx(0, 0)) displaced = true;
+    }
+    // marginal data of every bin for the tail bound (rows of both halves)
+    for (int l = 0; l < in.L; ++l) {
+        std::vector<int> idx;
+        for (int i = 0; i < n2; ++i)
+            if (bin_of_row(in, i, m, kset, dense) == l) idx.push_back(i);
+        if (idx.empty()) continue;
+        const int k = (int)idx.size();
+        CMat R(k, k);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) R(a, b) = Sig(idx[a], idx[b]) - (a == b ? 1.0 : 0.0);
+        BinMarginal bm;
+        CMat Qd;
+        hermitian_tridiag(R, bm.d, bm.e, displaced ? &Qd : nullptr);
+        if (displaced) {
+            bm.z.assign(k, cplx(0, 0));
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) bm.z[a] += std::conj(Qd(b, a)) * zbar[idx[b]];
+        }
+        hi.marg[l].push_back(std::move(bm));
     }
     // uncertainty relation: Sigma - I/2 > 0  <=>  spec(H) inside (-1, 1)
     {
@@ -308,7 +429,7 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
         for (int a = 0; a < na; ++a)
             for (int b = 0; b < na; ++b) Haa(a, b) = 0.5 * (Hr(A[a], A[b]) + std::conj(Hr(A[b], A[a])));
         CMat V;
-        if (!hermitian_eig(Haa, hb.eig, V)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+        if (!hermitian_eig_ql(Haa, hb.eig, V)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
         for (double lam : hb.eig)
             if (!(std::fabs(lam) < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(idx) + ": |eig(H)| >= 1");
         CMat Hba(nbB, na), Hab(na, nbB);
@@ -514,6 +635,8 @@ struct cgd_ctx {
     int reg_var[kRegClasses] = {};     // autotuner: thread grid of the FP64 register kernel per class
     int mfma_var[kMfmaClasses] = {};   // autotuner: wave layout of the FP32 MFMA kernel per class
     std::string tune_json;             // autotuner report
+    std::vector<double> wrap_bound;    // per instance: sum_l bound on Pr(b_l >= G_l)
+    std::vector<int32_t> grid_used;    // grid extents of every instance (auto entries resolved)
     int device = -1;                   // device current at cgd_create
     bool timing = false;
     // per-launch timing: event pairs recorded around each launch of a stage (eager
@@ -1146,15 +1269,28 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     if (want_grad && dense)
         for (int i = 0; i < n_inst; ++i)
             if (inst[i].K > 1) return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD works with internal-mode blocks (no CGD_FLAG_DENSE_INTERNAL)");
-    for (int i = 0; i < n_inst; ++i) {
+    // per instance (validation, assembly, auto grid, tail bound) on up to 16
+    // host threads; results are merged in instance order
+    struct InstOut {
+        cgd_status st = CGD_OK;
+        std::string err;
+        std::vector<HostBlock> blocks;
+        std::vector<GradHost> grads;
+        HostInstCopy copy;
+    };
+    std::vector<InstOut> outs(n_inst);
+    const double tol = c->tol;
+    auto one = [&](int i) -> cgd_status {
         const cgd_instance &in = inst[i];
+        InstOut &o = outs[i];
         cgd_status s = validate(in, i);
         if (s != CGD_OK) return s;
         HostInst &hi = hinst[i];
         hi.L = in.L;
         for (int l = 0; l < in.L; ++l) {
             hi.N[l] = in.cutoff[l];
-            hi.G[l] = in.grid ? in.grid[l] : in.cutoff[l] + 1;
+            hi.auto_grid[l] = in.grid && in.grid[l] == 0;
+            hi.G[l] = hi.auto_grid[l] ? 0 : (in.grid ? in.grid[l] : in.cutoff[l] + 1);
         }
         // per internal mode squeezing: tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j
         std::vector<std::vector<double>> rk(in.M, std::vector<double>(in.K));
@@ -1166,7 +1302,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 rk[j][k] = std::atanh(t);
             }
         if (want_grad) {
-            HostInstCopy hc;
+            HostInstCopy &hc = o.copy;
             hc.M = in.M;
             hc.K = in.K;
             hc.T.resize((size_t)in.M * in.M);
@@ -1178,21 +1314,84 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 for (int j = 0; j < in.M; ++j) hc.alpha_v[j] = cx(in.alpha, j);
             }
             hc.rk = rk;
-            c->hinst_copy.push_back(std::move(hc));
-            c->hinst_copy.back().alpha = c->hinst_copy.back().alpha_v.empty() ? nullptr
-                                                                               : c->hinst_copy.back().alpha_v.data();
         }
         if (dense || in.K == 1) {
             std::vector<int> ks(in.K);
             for (int k = 0; k < in.K; ++k) ks[k] = k;
-            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, hblocks, want_grad ? &c->grads : nullptr);
+            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr);
             if (s != CGD_OK) return s;
         } else {
             for (int k = 0; k < in.K; ++k) {
-                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, hblocks, want_grad ? &c->grads : nullptr);
+                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr);
                 if (s != CGD_OK) return s;
             }
         }
+        // grid entries 0: the smallest G_l >= N_l + 1 whose tail bound
+        // Pr(b_l >= G_l) is at most tol / (10 L); then the wrap bound of the grid
+        bool any_auto = false;
+        for (int l = 0; l < in.L; ++l) any_auto |= hi.auto_grid[l];
+        if (any_auto && !(tol > 0.0 && std::isfinite(tol)))
+            return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": an automatic grid needs a finite tol > 0");
+        const double target = std::log(tol / (10.0 * in.L));
+        int64_t npts = 1;
+        hi.wrap_bound = 0.0;
+        for (int l = 0; l < in.L; ++l) {
+            if (hi.auto_grid[l]) {
+                int lo = hi.N[l] + 1, hi_g = lo;
+                while (hi_g < 4096 && bin_log_tail(hi.marg[l], hi_g) > target) hi_g = std::min(4096, 2 * hi_g);
+                if (bin_log_tail(hi.marg[l], hi_g) > target)
+                    return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": an automatic grid for bin " +
+                                                 std::to_string(l) + " would exceed 4096 points");
+                while (lo < hi_g) {  // smallest G in [lo, hi_g] meeting the target
+                    const int mid = lo + (hi_g - lo) / 2;
+                    if (bin_log_tail(hi.marg[l], mid) <= target) hi_g = mid; else lo = mid + 1;
+                }
+                hi.G[l] = hi_g;
+            }
+            hi.wrap_bound += std::exp(bin_log_tail(hi.marg[l], hi.G[l]));
+            npts *= hi.G[l];
+            if (npts > (int64_t)1 << 31) return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": grid too large");
+        }
+        for (int l = 0; l < in.L; ++l) std::vector<BinMarginal>().swap(hi.marg[l]);
+        return CGD_OK;
+    };
+    {
+        std::atomic<int> next{0};
+        auto work = [&]() {
+            for (int i; (i = next.fetch_add(1)) < n_inst;) {
+                const cgd_status st = one(i);
+                if (st != CGD_OK) {
+                    outs[i].st = st;
+                    outs[i].err = g_err;
+                }
+            }
+        };
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const int nthr = (int)std::min<int64_t>({(int64_t)16, (int64_t)hw, (int64_t)n_inst});
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthr; ++t) pool.emplace_back(work);
+        work();
+        for (auto &t : pool) t.join();
+    }
+    for (int i = 0; i < n_inst; ++i)
+        if (outs[i].st != CGD_OK) {
+            g_err = outs[i].err;
+            return outs[i].st;
+        }
+    for (int i = 0; i < n_inst; ++i) {
+        for (HostBlock &b : outs[i].blocks) hblocks.push_back(std::move(b));
+        for (GradHost &g : outs[i].grads) c->grads.push_back(std::move(g));
+        if (want_grad) {
+            c->hinst_copy.push_back(std::move(outs[i].copy));
+            HostInstCopy &hc = c->hinst_copy.back();
+            hc.alpha = hc.alpha_v.empty() ? nullptr : hc.alpha_v.data();
+        }
+    }
+    c->wrap_bound.resize(n_inst);
+    c->grid_used.clear();
+    for (int i = 0; i < n_inst; ++i) {
+        c->wrap_bound[i] = hinst[i].wrap_bound;
+        for (int l = 0; l < hinst[i].L; ++l) c->grid_used.push_back(hinst[i].G[l]);
     }
 
     // instances
@@ -1940,6 +2139,13 @@ cgd_status cgd_stage_work(const cgd_ctx *c, double *flops, double *bytes) {
         if (flops) flops[i] = c->work_flops[i];
         if (bytes) bytes[i] = c->work_bytes[i];
     }
+    return CGD_OK;
+}
+
+cgd_status cgd_bounds(const cgd_ctx *c, int32_t *grid, double *wrap_bound) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (grid) std::copy(c->grid_used.begin(), c->grid_used.end(), grid);
+    if (wrap_bound) std::copy(c->wrap_bound.begin(), c->wrap_bound.end(), wrap_bound);
     return CGD_OK;
 }
 

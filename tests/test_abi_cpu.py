@@ -69,3 +69,15 @@ def test_create_rejects_bad_call_arguments():
     assert L.cgd_eval(None, None, None) == cgd.CGD_ERR_ARG
     assert L.cgd_grad(None, None, None, None, None) == cgd.CGD_ERR_ARG
     L.cgd_destroy(None)
+
+
+def test_automatic_grid_needs_a_finite_tolerance():
+    # grid entry 0 asks for an automatic grid from the tail bound, which needs tol
+    inst = W.plain_m4()
+    inst["grid"] = np.array([0, 7], np.int32)
+    for tol in (0.0, float("inf")):
+        st, h, msg = _create(inst, tol=tol)
+        assert st == cgd.CGD_ERR_ARG and "tol" in msg, msg
+    inst["grid"] = np.array([0, 5], np.int32)  # the explicit entry is still checked
+    st, h, msg = _create(inst, tol=1e-9)
+    assert st == cgd.CGD_ERR_ARG and "grid" in msg, msg

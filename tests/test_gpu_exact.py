@@ -1,0 +1,139 @@
+"""Exact-box mode: automatic grids from the marginal tail bound, and the wrap
+bound the library reports (cgd_bounds).
+
+The bound B_l >= Pr(b_l >= G_l) (Chernoff bound of the marginal moment
+generating function, Sec. VI C, Eq. M) is checked against the actual tail of
+the oracle's marginal distribution (computed on a grid so oversampled that its
+own wrap is below 1e-15); an automatic grid must bring every probability
+within tol of the exact binned probabilities (brute force, Eq.
+coarse_grained_prob), and within 1e-12 of the oracle's wrapped distribution on
+the grid the library chose."""
+import numpy as np
+import pytest
+
+import paper_2412_17742_amd as cgd
+import workloads as W
+from oracle import brute, pgf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _with_grid(inst, grid):
+    x = dict(inst)
+    x["grid"] = np.asarray(grid, np.int32)
+    return x
+
+
+def _eval(insts, tol=TOL, precision="fp64"):
+    import torch
+    with cgd.Context(insts, precision=precision, tol=tol) as ctx:
+        p = ctx.eval()
+        torch.cuda.synchronize()
+        grids, wrap = ctx.bounds()
+        return [x.cpu().numpy().copy() for x in ctx.split(p)], grids, wrap
+
+
+def _marginal_tails(inst, big):
+    """Pr(b_l >= g) for every bin l and g < big, from the oracle's wrapped
+    distribution on an oversampled grid (big points per axis)."""
+    x = _with_grid(inst, [big] * len(inst["cutoff"]))
+    x["cutoff"] = np.array([big - 1] * len(inst["cutoff"]), np.int32)
+    P = pgf.wrapped_distribution(x)
+    tails = []
+    for l in range(P.ndim):
+        marg = P.sum(axis=tuple(a for a in range(P.ndim) if a != l))
+        tails.append(np.concatenate([np.cumsum(marg[::-1])[::-1], [0.0]]))
+    return tails
+
+
+def _small_cases():
+    rng = W.rng_for(321)
+    U = W.haar_unitary(4, rng)
+    al = 0.4 * (rng.standard_normal(4) + 1j * rng.standard_normal(4))
+    return {
+        "plain_m4": W.plain_m4(),
+        "displaced_k2": W.make_instance(np.sqrt(0.7) * U, np.array([0.3, 0.5, 0.2, 0.4]), alpha=al,
+                                        schmidt=[0.7, 0.3], bin_of=[0, 1, 1, -1], cutoff=[3, 4]),
+        "internal_resolved": W.make_instance(np.sqrt(0.6) * U, np.full(4, 0.45), schmidt=[0.8, 0.2],
+                                             bin_of=[0, 1, 1, -1, 0, 0, 1, 1], resolve_internal=1, cutoff=[3, 3]),
+    }
+
+
+@pytest.mark.parametrize("name", sorted(_small_cases()))
+def test_reported_wrap_bound_covers_the_actual_tail(name):
+    inst = _small_cases()[name]
+    (P,), (grid,), wrap = _eval([inst])
+    tails = _marginal_tails(inst, 48)
+    actual = sum(t[g] for t, g in zip(tails, grid))
+    _say(f"  {name}: grid {grid}, tail {actual:.3e} <= bound {wrap[0]:.3e}")
+    assert grid == tuple(int(c) + 1 for c in inst["cutoff"])
+    assert actual <= wrap[0] * (1 + 1e-9) + 1e-15
+    assert wrap[0] < 1.0
+
+
+@pytest.mark.parametrize("name", sorted(_small_cases()))
+def test_automatic_grid_gives_exact_box_probabilities(name):
+    inst = _small_cases()[name]
+    x = _with_grid(inst, [0] * len(inst["cutoff"]))
+    (P,), (grid,), wrap = _eval([x])
+    _say(f"  {name}: automatic grid {grid}, wrap bound {wrap[0]:.3e}")
+    assert all(g >= int(c) + 1 for g, c in zip(grid, inst["cutoff"]))
+    assert wrap[0] <= TOL / 10
+    # on the grid it chose, the library matches the oracle's wrapped distribution
+    ref = pgf.wrapped_distribution(_with_grid(inst, grid))
+    assert np.abs(P - ref).max() <= 1e-12
+    # and the exact binned probabilities within tol
+    exact = brute.box_probabilities(inst)
+    assert np.abs(P - exact).max() <= TOL
+    # the smallest such grid: one point less on an axis breaks that axis's
+    # share tol / (10 L) of the target
+    L = len(grid)
+    for l, g in enumerate(grid):
+        if g > int(inst["cutoff"][l]) + 1:
+            smaller = list(grid)
+            smaller[l] -= 1
+            (_,), _, wrap2 = _eval([_with_grid(inst, smaller)])
+            assert wrap2[0] > TOL / (10 * L)
+
+
+def test_mixed_explicit_and_automatic_axes_and_batching():
+    cases = _small_cases()
+    a = _with_grid(cases["plain_m4"], [0, 9])
+    b = _with_grid(cases["displaced_k2"], [6, 0])
+    c = cases["internal_resolved"]
+    got, grids, wrap = _eval([a, b, c])
+    assert grids[0][1] == 9 and grids[1][0] == 6
+    assert grids[2] == (4, 4)
+    for x, g, P in zip((a, b, c), grids, got):
+        assert np.abs(P - pgf.wrapped_distribution(_with_grid(x, g))).max() <= 1e-12
+
+
+def test_automatic_grid_on_the_mesh_workload():
+    """The differentiation workload's stated cutoff 12 wraps by about 0.16 per
+    bin; the automatic grid brings the bound below tol / 10.  A grid 16 points
+    larger per axis (closer still to the exact probabilities) must agree with
+    it within tol."""
+    insts = W.mesh_batch(2)
+    auto = [_with_grid(x, [0, 0]) for x in insts]
+    got, grids, wrap = _eval(auto)
+    _, _, wrap_stated = _eval(insts)
+    _say(f"  mesh: stated-grid wrap bounds {wrap_stated}, automatic grids {grids}, bounds {wrap}")
+    assert np.all(wrap_stated > 1e-3) and np.all(wrap <= TOL / 10)
+    bigger = [_with_grid(x, [g + 16 for g in gr]) for x, gr in zip(insts, grids)]
+    ref, _, wrap_big = _eval(bigger)
+    assert np.all(wrap_big <= wrap)
+    for P, R in zip(got, ref):
+        assert np.abs(P - R).max() <= TOL
+        assert P.min() >= -1e-12
+
+
+def test_automatic_grid_needs_a_tolerance():
+    x = _with_grid(W.plain_m4(), [0, 0])
+    with pytest.raises(cgd.CgdError) as e:
+        cgd.Context([x], tol=0.0)
+    assert e.value.status == cgd.CGD_ERR_ARG
