@@ -206,6 +206,33 @@ def fp64_kernel_name(tuning, stage):
     return cgd.LU_KERNELS.get(stage, (stage,))[0]
 
 
+def total_photon_sweep(cgd, steps, warmup, tol):
+    """The paper's GBS total-photon-number workload (one bin over all modes,
+    xi = 0.89, eta = 0.36, M = 16 .. 256 with its N_max), end to end: cgd_create
+    (host state assembly and eigenvalues) plus one evaluation, and the
+    evaluation alone; also the automatic grid that makes the box exact.  The
+    paper's CPU times (f_N route, Ryzen 9 8945HS) are context only."""
+    import torch
+    paper_s = {16: 0.102, 256: 0.69}
+    out = {}
+    for M in sorted(W.TOTAL_PHOTON_CUTOFF):
+        inst = W.gbs_total(M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with cgd.Context([inst], precision="fp64", tol=tol) as ctx:
+            p = ctx.eval()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms, _, _ = run(ctx, steps, warmup)
+            wrap = float(ctx.bounds()[1][0])
+        with cgd.Context([W.gbs_total(M, grid=[0])], precision="fp64", tol=tol) as ctx:
+            auto_grid = ctx.bounds()[0][0][0]
+        out[f"M{M}"] = {"cutoff": int(inst["cutoff"][0]), "create_plus_eval_s": t1 - t0, "eval_ms": ms,
+                        "stated_grid_wrap_bound": wrap, "auto_grid": auto_grid,
+                        "paper_cpu_s": paper_s.get(M)}
+    return out
+
+
 def exact_box(cgd, insts, tol, wrap_stated):
     """Wrap of the stated grid (bound on P_wrap - Pr over the box) and, when it
     exceeds tol, the automatic grid (cgd grid entries 0) that brings it below
@@ -380,6 +407,8 @@ def main():
             if name != args.workload:
                 out["other_workloads"][name] = extra_workload(cgd, name, args.steps, args.warmup, args.tol,
                                                               grad=name == "mesh32_k4")
+    if not args.no_extra:
+        out["total_photon"] = total_photon_sweep(cgd, args.steps, args.warmup, args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(instances, args.cpu_seconds)
         out["cpu_baseline"]["one_core"] = cpu_baseline(instances, args.cpu_seconds, threads=1)

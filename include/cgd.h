@@ -180,16 +180,20 @@ cgd_status cgd_grid_values(cgd_ctx *ctx, double *d_logg);
  * n_probs_total doubles, same layout as the probabilities).  Requires a
  * context created with CGD_FLAG_GRAD and a preceding cgd_eval (CGD_ERR_STATE
  * otherwise).  Outputs (device, may be NULL each; instances concatenated):
- *   d_dr      sum_i M_i doubles               dLoss/dr
- *   d_dT      sum_i M_i*M_i complex            dLoss/dRe T + i dLoss/dIm T
- *   d_dalpha  sum_i M_i complex                dLoss/dRe alpha + i dLoss/dIm alpha
+ *   d_dr        sum_i M_i doubles               dLoss/dr
+ *   d_dT        sum_i M_i*M_i complex            dLoss/dRe T + i dLoss/dIm T
+ *   d_dalpha    sum_i M_i complex                dLoss/dRe alpha + i dLoss/dIm alpha
+ *   d_dschmidt  sum_i K_i doubles                dLoss/dlambda_k, each Schmidt weight
+ *               taken as a free variable (the state depends on lambda_k / lambda_0
+ *               only, through tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j, so
+ *               sum_k lambda_k dLoss/dlambda_k = 0; 0 for K = 1)
  * Per grid point and internal block, S' (bordered) is inverted in FP64 on the
  * GPU (d log det S = tr(S^-1 dS)); the sums over the grid are reduced in a
  * fixed order (bitwise reproducible); the chain rule from H = I - Sigma^-1,
- * gamma and log Pr(0) to (r, T, alpha) runs on the host in FP64.  The call
- * waits for the device (the host chain rule needs the reduced sums). */
-cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *d_dT,
-                    double *d_dalpha);
+ * gamma and log Pr(0) to (r, T, alpha, lambda) runs on the host in FP64.  The
+ * call waits for the device (the host chain rule needs the reduced sums). */
+cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *d_dT, double *d_dalpha,
+                    double *d_dschmidt);
 
 /* Profiling.  The evaluation is a fixed sequence of launch stages:
  *   CGD_STAGE_SCHUR      Schur matrices of the bins left after eliminating one bin

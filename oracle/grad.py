@@ -3,9 +3,12 @@ infrastructure only).
 
 The same formulas as state.py and pgf.py, written with torch complex128
 tensors on the CPU so that autograd can differentiate the probabilities with
-respect to the squeezing parameters r, the transfer matrix T and the
-displacements alpha (Sec. II: Sigma, A = X(I - Sigma^-1), gamma = X Sigma^-1
-zbar, vacuum probability; Eq. q_d; Eq. Lamb_lhaf_master; explicit inverse DFT).
+respect to the squeezing parameters r, the transfer matrix T, the
+displacements alpha and the Schmidt weights lambda (each weight a free
+variable: the state depends on them through lambda_k / lambda_0 only,
+Eq. relation_between_sqz_par generalised to K modes), through Sec. II (Sigma,
+A = X(I - Sigma^-1), gamma = X Sigma^-1 zbar, vacuum probability), Eq. q_d,
+Eq. Lamb_lhaf_master and the explicit inverse DFT.
 
 log det[I - D X A] is evaluated for its value through the eigenvalues (the
 continuous branch, see pgf.py) and for its derivative through torch's
@@ -24,7 +27,7 @@ CT = torch.complex128
 def _internal_r(r, schmidt):
     if schmidt is None:
         return r[:, None]
-    lam = torch.as_tensor(np.asarray(schmidt), dtype=torch.float64)
+    lam = schmidt if isinstance(schmidt, torch.Tensor) else torch.as_tensor(np.asarray(schmidt), dtype=torch.float64)
     ratio = lam / lam[0]
     return torch.atanh(torch.sqrt(ratio)[None, :] * torch.tanh(r)[:, None])
 
@@ -61,9 +64,11 @@ def _state(T, r, alpha, schmidt):
     return A, gamma, log_pr0, X
 
 
-def wrapped_distribution_torch(T, r, alpha, inst):
-    """P_wrap for the instance's binning, differentiable in (T, r, alpha)."""
-    schmidt = inst.get("schmidt")
+def wrapped_distribution_torch(T, r, alpha, inst, schmidt=None):
+    """P_wrap for the instance's binning, differentiable in (T, r, alpha) and,
+    when given as a tensor, in the Schmidt weights."""
+    if schmidt is None:
+        schmidt = inst.get("schmidt")
     A, gamma, log_pr0, X = _state(T, r, alpha, schmidt)
     M = T.shape[0]
     K = 1 if schmidt is None else len(schmidt)
@@ -96,15 +101,27 @@ def wrapped_distribution_torch(T, r, alpha, inst):
     return out.real
 
 
-def gradients(inst, dP):
-    """dL/dr, dL/dRe T + i dL/dIm T, dL/dRe alpha + i dL/dIm alpha for
-    L = sum_b dP(b) P_wrap(b)."""
+def gradients_full(inst, dP):
+    """Gradient of L = sum_b dP(b) P_wrap(b): dict with r (dL/dr), T and alpha
+    (dL/dRe x + i dL/dIm x), schmidt (dL/dlambda_k, each weight free; None for
+    K = 1) and P."""
     T = torch.tensor(np.asarray(inst["T"]), dtype=CT, requires_grad=True)
     r = torch.tensor(np.asarray(inst["r"]), dtype=torch.float64, requires_grad=True)
     alpha = None
     if inst.get("alpha") is not None:
         alpha = torch.tensor(np.asarray(inst["alpha"]), dtype=CT, requires_grad=True)
-    P = wrapped_distribution_torch(T, r, alpha, inst)
+    lam = None
+    if inst.get("schmidt") is not None:
+        lam = torch.tensor(np.asarray(inst["schmidt"]), dtype=torch.float64, requires_grad=True)
+    P = wrapped_distribution_torch(T, r, alpha, inst, schmidt=lam)
     L = (P * torch.as_tensor(np.asarray(dP), dtype=torch.float64)).sum()
     L.backward()
-    return (r.grad.numpy(), T.grad.numpy(), None if alpha is None else alpha.grad.numpy(), P.detach().numpy())
+    return dict(r=r.grad.numpy(), T=T.grad.numpy(), alpha=None if alpha is None else alpha.grad.numpy(),
+                schmidt=None if lam is None else lam.grad.numpy(), P=P.detach().numpy())
+
+
+def gradients(inst, dP):
+    """dL/dr, dL/dRe T + i dL/dIm T, dL/dRe alpha + i dL/dIm alpha for
+    L = sum_b dP(b) P_wrap(b)."""
+    g = gradients_full(inst, dP)
+    return g["r"], g["T"], g["alpha"], g["P"]

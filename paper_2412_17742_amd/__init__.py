@@ -82,7 +82,7 @@ def lib() -> ctypes.CDLL:
     L.cgd_grid_values.restype = i32
     L.cgd_grid_values.argtypes = [vp, vp]
     L.cgd_grad.restype = i32
-    L.cgd_grad.argtypes = [vp, vp, vp, vp, vp]
+    L.cgd_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cgd_set_timing.restype = i32
     L.cgd_set_timing.argtypes = [vp, i32]
     L.cgd_stage_times.restype = i32
@@ -156,6 +156,7 @@ class Context:
         self.n_points = L.cgd_points(self._h)
         self.shapes = [tuple(int(c) + 1 for c in x["cutoff"]) for x in instances]
         self._M = [np.asarray(x["T"]).shape[0] for x in instances]
+        self._K = [1 if x.get("schmidt") is None else len(x["schmidt"]) for x in instances]
 
     def eval(self, probs=None, err=None):
         """Wrapped distributions of all instances, concatenated (device float64)."""
@@ -196,10 +197,12 @@ class Context:
         _check(lib().cgd_grid_values(self._h, ctypes.c_void_p(out.data_ptr())))
         return torch.view_as_complex(out.view(-1, 2))
 
-    def grad(self, dprobs):
+    def grad(self, dprobs, schmidt=False):
         """Gradient of L with dL/dP = dprobs (device float64, n_probs): returns
         (dL/dr, dL/dRe T + i dL/dIm T, dL/dRe alpha + i dL/dIm alpha) as device
-        tensors (instances concatenated; T flattened row-major)."""
+        tensors (instances concatenated; T flattened row-major), and with
+        schmidt=True also dL/dlambda (each Schmidt weight free, instances
+        concatenated)."""
         import torch
         assert dprobs.dtype == torch.float64 and dprobs.is_cuda and dprobs.is_contiguous()
         nM = int(sum(self._M))
@@ -207,9 +210,12 @@ class Context:
         dr = torch.zeros(nM, dtype=torch.float64, device="cuda")
         dT = torch.zeros(2 * nT, dtype=torch.float64, device="cuda")
         da = torch.zeros(2 * nM, dtype=torch.float64, device="cuda")
+        ds = torch.zeros(int(sum(self._K)), dtype=torch.float64, device="cuda")
         _check(lib().cgd_grad(self._h, ctypes.c_void_p(dprobs.data_ptr()), ctypes.c_void_p(dr.data_ptr()),
-                              ctypes.c_void_p(dT.data_ptr()), ctypes.c_void_p(da.data_ptr())))
-        return dr, torch.view_as_complex(dT.view(-1, 2)), torch.view_as_complex(da.view(-1, 2))
+                              ctypes.c_void_p(dT.data_ptr()), ctypes.c_void_p(da.data_ptr()),
+                              ctypes.c_void_p(ds.data_ptr())))
+        out = (dr, torch.view_as_complex(dT.view(-1, 2)), torch.view_as_complex(da.view(-1, 2)))
+        return out + (ds,) if schmidt else out
 
     def set_timing(self, enable: bool = True):
         _check(lib().cgd_set_timing(self._h, int(enable)))
@@ -288,33 +294,37 @@ class _Distribution:
 
         class Fn(torch.autograd.Function):
             @staticmethod
-            def forward(ctx, r, T, alpha, spec):
+            def forward(ctx, r, T, alpha, schmidt, spec):
                 B, M = r.shape
                 insts = []
                 for b in range(B):
+                    lam = spec.get("schmidt") if schmidt is None else schmidt[b].detach().cpu().numpy()
                     insts.append(dict(
                         T=T[b].detach().cpu().numpy(), r=r[b].detach().cpu().numpy(),
                         alpha=None if alpha is None else alpha[b].detach().cpu().numpy(),
-                        schmidt=spec.get("schmidt"), bin_of=spec["bin_of"], cutoff=spec["cutoff"],
+                        schmidt=lam, bin_of=spec["bin_of"], cutoff=spec["cutoff"],
                         grid=spec.get("grid"), resolve_internal=spec.get("resolve_internal", 0)))
                 c = Context(insts, flags=FLAG_GRAD)
                 P = c.eval().clone()
                 ctx.c = c
                 ctx.B, ctx.M = B, M
                 ctx.has_alpha = alpha is not None
-                ctx.devices = (r.device, T.device, None if alpha is None else alpha.device)
+                ctx.has_schmidt = schmidt is not None
+                ctx.devices = (r.device, T.device, None if alpha is None else alpha.device,
+                               None if schmidt is None else schmidt.device)
                 shape = tuple(int(x) + 1 for x in spec["cutoff"])
                 return P.view(B, *shape)
 
             @staticmethod
             def backward(ctx, gP):
-                dr, dT, da = ctx.c.grad(gP.contiguous().view(-1).to(torch.float64))
+                dr, dT, da, ds = ctx.c.grad(gP.contiguous().view(-1).to(torch.float64), schmidt=True)
                 ctx.c.close()
                 B, M = ctx.B, ctx.M
                 dr = dr.view(B, M).to(ctx.devices[0])
                 dT = dT.view(B, M, M).to(ctx.devices[1])
                 da = da.view(B, M).to(ctx.devices[2]) if ctx.has_alpha else None
-                return dr, dT, da, None
+                ds = ds.view(B, -1).to(ctx.devices[3]) if ctx.has_schmidt else None
+                return dr, dT, da, ds, None
 
         return Fn
 
@@ -322,14 +332,17 @@ class _Distribution:
 _fn = None
 
 
-def distribution(r, T, alpha, spec):
+def distribution(r, T, alpha, spec, schmidt=None):
     """Differentiable binned distributions of a batch of states with one binning.
 
-    r: (B, M) float64, T: (B, M, M) complex128, alpha: (B, M) complex128 or None
-    (torch tensors, any device); spec: dict with schmidt, bin_of, cutoff and
-    optionally grid and resolve_internal.  Returns a (B, N_1+1, ..., N_L+1)
-    float64 CUDA tensor; backward runs the library's adjoint."""
+    r: (B, M) float64, T: (B, M, M) complex128, alpha: (B, M) complex128 or None,
+    schmidt: (B, K) float64 Schmidt weights or None (then spec["schmidt"] for
+    every instance, not differentiated) (torch tensors, any device); spec: dict
+    with schmidt, bin_of, cutoff and optionally grid and resolve_internal.
+    Returns a (B, N_1+1, ..., N_L+1) float64 CUDA tensor; backward runs the
+    library's adjoint (gradients with respect to r, T, alpha and schmidt, each
+    Schmidt weight a free variable)."""
     global _fn
     if _fn is None:
         _fn = _Distribution.make()
-    return _fn.apply(r, T, alpha, spec)
+    return _fn.apply(r, T, alpha, schmidt, spec)

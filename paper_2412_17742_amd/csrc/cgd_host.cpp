@@ -429,7 +429,9 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
         for (int a = 0; a < na; ++a)
             for (int b = 0; b < na; ++b) Haa(a, b) = 0.5 * (Hr(A[a], A[b]) + std::conj(Hr(A[b], A[a])));
         CMat V;
-        if (!hermitian_eig_ql(Haa, hb.eig, V)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+        // with no rows left after the elimination (one bin) only the eigenvalues matter
+        const bool ok = nbB == 0 ? hermitian_eigvals(Haa, hb.eig) : hermitian_eig_ql(Haa, hb.eig, V);
+        if (!ok) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
         for (double lam : hb.eig)
             if (!(std::fabs(lam) < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(idx) + ": |eig(H)| >= 1");
         CMat Hba(nbB, na), Hab(na, nbB);
@@ -440,8 +442,10 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
         }
         for (int a = 0; a < na; ++a)
             for (int b = 0; b < nbB; ++b) Hab(a, b) = Hr(A[a], Bv[b]);
-        hb.P = matmul(Hba, V);
-        hb.Q = matmul(adjoint(V), Hab);
+        if (nbB > 0) {
+            hb.P = matmul(Hba, V);
+            hb.Q = matmul(adjoint(V), Hab);
+        }
         hb.schur_axis = axis;
         hb.nb = nbB;
         hb.rowbin.resize(nbB);
@@ -875,7 +879,7 @@ cgd_status build_grad(cgd_ctx *c, int n_inst) {
 // Contribution of internal block b to dL/dr (M), dL/dT (M*M) and dL/dalpha (M)
 // of its instance, written to gr, gT, ga (zero-initialised by the caller).
 void chain_rule_block(const cgd_ctx *c, size_t b, const std::vector<cplx> &zhost, std::vector<double> &gr,
-                      std::vector<cplx> &gT, std::vector<cplx> &ga) {
+                      std::vector<cplx> &gT, std::vector<cplx> &ga, std::vector<double> &gs) {
     const int64_t to = 0, ro = 0;
     {
         const GradHost &g = c->grads[b];
@@ -941,9 +945,17 @@ void chain_rule_block(const cgd_ctx *c, size_t b, const std::vector<cplx> &zhost
         CMat Cn = matmul(matmul(Tt, PhiN), Tc), Cm1 = matmul(matmul(Tt, G21), T), Cm2 = matmul(matmul(Th, G12), Tc);
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) gT[to + (size_t)i * M + j] += std::conj(Xa(j, i)) + Xb(j, i);
+        // dL/dr_jk, then through r_jk = artanh(x), x = sqrt(lambda_k / lambda_0) tanh r_j,
+        // to r_j and (k > 0) to lambda_k and lambda_0, each weight a free variable
         for (int j = 0; j < M; ++j) {
             const double dl = Cn(j, j).real() * dn[j] + (Cm1(j, j) + Cm2(j, j)).real() * dm[j];
             gr[ro + j] += dl * drk[j];
+            if (hc.K > 1 && g.k > 0) {
+                const double x = std::sqrt(hc.schmidt[g.k] / hc.schmidt[0]) * std::tanh(hc.r[j]);
+                const double f = dl * x / (2.0 * (1.0 - x * x));  // dL/dr_jk * d r_jk / d log(lambda_k / lambda_0)
+                gs[g.k] += f / hc.schmidt[g.k];
+                gs[0] -= f / hc.schmidt[0];
+            }
         }
         // displacement: zbar = (beta, beta*), beta = T alpha on internal mode 0
         if (g.k == 0 && hc.alpha) {
@@ -972,9 +984,10 @@ void chain_rule_block(const cgd_ctx *c, size_t b, const std::vector<cplx> &zhost
 // Chain rule over all blocks on up to 16 host threads; each block writes its own
 // buffers and the sums into gr, gT, ga are taken in block order (reproducible).
 void chain_rule(const cgd_ctx *c, const std::vector<cplx> &zhost, std::vector<double> &gr, std::vector<cplx> &gT,
-                std::vector<cplx> &ga, const std::vector<int64_t> &roff, const std::vector<int64_t> &toff) {
+                std::vector<cplx> &ga, std::vector<double> &gs, const std::vector<int64_t> &roff,
+                const std::vector<int64_t> &toff, const std::vector<int64_t> &soff) {
     const size_t nb = c->grads.size();
-    std::vector<std::vector<double>> bgr(nb);
+    std::vector<std::vector<double>> bgr(nb), bgs(nb);
     std::vector<std::vector<cplx>> bgT(nb), bga(nb);
     std::atomic<size_t> next{0};
     auto work = [&]() {
@@ -983,7 +996,8 @@ void chain_rule(const cgd_ctx *c, const std::vector<cplx> &zhost, std::vector<do
             bgr[b].assign(M, 0.0);
             bgT[b].assign((size_t)M * M, cplx(0, 0));
             bga[b].assign(M, cplx(0, 0));
-            chain_rule_block(c, b, zhost, bgr[b], bgT[b], bga[b]);
+            bgs[b].assign(c->hinst_copy[c->grads[b].inst].K, 0.0);
+            chain_rule_block(c, b, zhost, bgr[b], bgT[b], bga[b], bgs[b]);
         }
     };
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
@@ -999,6 +1013,7 @@ void chain_rule(const cgd_ctx *c, const std::vector<cplx> &zhost, std::vector<do
             ga[roff[inst] + j] += bga[b][j];
         }
         for (size_t e = 0; e < bgT[b].size(); ++e) gT[toff[inst] + e] += bgT[b][e];
+        for (size_t k = 0; k < bgs[b].size(); ++k) gs[soff[inst] + k] += bgs[b][k];
     }
 }
 
@@ -2042,7 +2057,8 @@ cgd_status cgd_grid_values(cgd_ctx *c, double *d_logg) {
     return CGD_OK;
 }
 
-cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_dT, double *d_dalpha) {
+cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_dT, double *d_dalpha,
+                    double *d_dschmidt) {
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
     if (!(c->flags & CGD_FLAG_GRAD)) return fail(CGD_ERR_STATE, "context created without CGD_FLAG_GRAD");
     if (!c->evaluated || c->last_static) return fail(CGD_ERR_STATE, "cgd_grad needs a preceding cgd_eval");
@@ -2078,18 +2094,21 @@ cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_
     HIP_OK(hipMemcpyAsync(zh.data(), c->d_z, sizeof(double2) * c->z_total, hipMemcpyDeviceToHost, st));
     if (st) HIP_OK(hipStreamSynchronize(st)); else HIP_OK(hipDeviceSynchronize());
     // chain rule on the host (FP64), then upload
-    std::vector<int64_t> roff(c->n_inst + 1, 0), toff(c->n_inst + 1, 0);
+    std::vector<int64_t> roff(c->n_inst + 1, 0), toff(c->n_inst + 1, 0), soff(c->n_inst + 1, 0);
     for (int i = 0; i < c->n_inst; ++i) {
         const int M = c->hinst_copy[i].M;
         roff[i + 1] = roff[i] + M;
         toff[i + 1] = toff[i] + (int64_t)M * M;
+        soff[i + 1] = soff[i] + c->hinst_copy[i].K;
     }
-    std::vector<double> gr(roff[c->n_inst], 0.0);
+    std::vector<double> gr(roff[c->n_inst], 0.0), gs(soff[c->n_inst], 0.0);
     std::vector<cplx> gT(toff[c->n_inst], cplx(0, 0)), ga(roff[c->n_inst], cplx(0, 0));
-    chain_rule(c, zh, gr, gT, ga, roff, toff);
+    chain_rule(c, zh, gr, gT, ga, gs, roff, toff, soff);
     if (d_dr) HIP_OK(hipMemcpyAsync(d_dr, gr.data(), sizeof(double) * gr.size(), hipMemcpyHostToDevice, st));
     if (d_dT) HIP_OK(hipMemcpyAsync(d_dT, gT.data(), sizeof(cplx) * gT.size(), hipMemcpyHostToDevice, st));
     if (d_dalpha) HIP_OK(hipMemcpyAsync(d_dalpha, ga.data(), sizeof(cplx) * ga.size(), hipMemcpyHostToDevice, st));
+    if (d_dschmidt)
+        HIP_OK(hipMemcpyAsync(d_dschmidt, gs.data(), sizeof(double) * gs.size(), hipMemcpyHostToDevice, st));
     if (st) HIP_OK(hipStreamSynchronize(st)); else HIP_OK(hipDeviceSynchronize());
     return check_status(c);
 }

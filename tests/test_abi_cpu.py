@@ -67,7 +67,7 @@ def test_create_rejects_bad_call_arguments():
     both = cgd.FLAG_HESSENBERG | cgd.FLAG_NO_HESSENBERG
     assert L.cgd_create(ctypes.byref(h), arr, 1, 0, 1e-9, both, None) == cgd.CGD_ERR_ARG
     assert L.cgd_eval(None, None, None) == cgd.CGD_ERR_ARG
-    assert L.cgd_grad(None, None, None, None, None) == cgd.CGD_ERR_ARG
+    assert L.cgd_grad(None, None, None, None, None, None) == cgd.CGD_ERR_ARG
     L.cgd_destroy(None)
 
 

@@ -55,3 +55,23 @@ def test_autograd_matches_central_differences():
             fd = (_loss(p, dP) - _loss(m, dP)) / (2 * h)
             ref = ga[j].real if part == "re" else ga[j].imag
             assert abs(fd - ref) < 1e-8, (j, part, fd, ref)
+
+
+def test_schmidt_weight_gradient_matches_central_differences():
+    """dL/dlambda_k with each weight free (the state depends on lambda_k /
+    lambda_0 only, so sum_k lambda_k dL/dlambda_k = 0)."""
+    rng = W.rng_for(78)
+    M = 3
+    T = np.sqrt(0.7) * W.haar_unitary(M, rng)
+    inst = W.make_instance(T, rng.uniform(0.3, 0.7, M), schmidt=[0.5, 0.3, 0.2], bin_of=[0, 1, 1],
+                           cutoff=[2, 3], grid=[5, 6])
+    dP = np.random.default_rng(4).standard_normal((3, 4))
+    g = og.gradients_full(inst, dP)
+    h = 1e-6
+    for k in range(3):
+        p, m = dict(inst, schmidt=inst["schmidt"].copy()), dict(inst, schmidt=inst["schmidt"].copy())
+        p["schmidt"][k] += h
+        m["schmidt"][k] -= h
+        fd = (_loss(p, dP) - _loss(m, dP)) / (2 * h)
+        assert abs(fd - g["schmidt"][k]) < 1e-8, (k, fd, g["schmidt"][k])
+    assert abs(float(np.dot(inst["schmidt"], g["schmidt"]))) < 1e-12

@@ -312,3 +312,22 @@ def test_fock_heralding_fidelities_match_paper():
         for n, F_paper in zip((1, 2, 3), case["F"]):
             F = np.sqrt(P[n, n] / P[n].sum())
             assert abs(F - F_paper) <= 0.5 * 10 ** (-case["decimals"]) + 1e-12, (case, n, F)
+
+
+def test_uniform_loss_total_photon_law_is_a_convolution():
+    """One bin over all modes, T = sqrt(eta) U: the total photon number does not
+    depend on U and is the sum of M independent single-mode lossy squeezed
+    counts (a passive unitary conserves the total number; uniform loss commutes
+    with it), so its law is the M-fold convolution of the single-mode law."""
+    M, N, G = 4, 14, 64
+    single = W.make_instance(np.array([[np.sqrt(0.36)]]), [0.89], bin_of=[0], cutoff=[G - 1], grid=[G])
+    p1 = pgf.wrapped_distribution(single)
+    law = np.zeros(1)
+    law[0] = 1.0
+    for _ in range(M):
+        law = np.convolve(law, p1)
+    for seed in (6, 7):
+        U = W.haar_unitary(M, W.rng_for(seed, M))
+        inst = W.make_instance(np.sqrt(0.36) * U, np.full(M, 0.89), bin_of=np.zeros(M), cutoff=[N], grid=[G])
+        P = pgf.wrapped_distribution(inst)
+        assert np.abs(P - law[:N + 1]).max() < 1e-13

@@ -140,6 +140,23 @@ def gbs_m144(bins: int = 2) -> dict:
     return make_instance(np.sqrt(0.3) * U, r, bin_of=contiguous_bins([48, 48, 48]), cutoff=[40, 40, 40])
 
 
+# --- total photon number of a GBS setup (the paper's Sec. VIII C) ----------
+
+# cutoffs N_max the paper uses for M = 16 .. 256 (Fig. total_probs_time_comparison)
+TOTAL_PHOTON_CUTOFF = {16: 27, 32: 45, 64: 71, 128: 109, 256: 170}
+
+
+def gbs_total(M: int, cutoff: int | None = None, grid=None) -> dict:
+    """M spectrally pure single-mode squeezed vacua with equal squeezing
+    xi = 0.89 on T = sqrt(0.36) U, U Haar, no displacement, one bin over all
+    modes (total photon number), cutoff N_max from the paper's list."""
+    rng = rng_for(6, M)
+    U = haar_unitary(M, rng)
+    N = TOTAL_PHOTON_CUTOFF.get(M, 2 * M) if cutoff is None else cutoff
+    return make_instance(np.sqrt(0.36) * U, np.full(M, 0.89), bin_of=np.zeros(M, np.int32), cutoff=[N],
+                         grid=grid)
+
+
 # --- workload 5: differentiable state-preparation parameters -----------------
 
 def mesh_layout(M: int):
