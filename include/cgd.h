@@ -86,6 +86,22 @@ typedef enum {
 #define CGD_FLAG_NO_HESSENBERG 16u /* never take the Hessenberg route                        */
 #define CGD_FLAG_GRAD 4u           /* prepare cgd_grad (keeps each internal block's full
                                       matrix on the device); needs 2M(+1) <= 96 per block */
+#define CGD_FLAG_MOMENTS 64u       /* cgd_eval writes, per instance and in the layout of the
+                                      probabilities, the coarse-grained joint moments
+                                      E[prod_l b_l^{p_l}] for p_l in [0, cutoff_l] (Sec. VI C,
+                                      Eq. CGmom) instead of probabilities; see below       */
+#define CGD_FLAG_CUMULANTS 128u    /* as CGD_FLAG_MOMENTS, with the joint cumulants
+                                      <<prod_l b_l^{p_l}>> (Eq. CGmom2; p = 0 gives 0)
+   Moments and cumulants are the Taylor coefficients of the moment generating
+   function M(t) = G(e^t) (Eq. M) and of log M(t) times p!: G (or log G, on the
+   continuous branch) is evaluated on a polydisk t_l = rho exp(2 pi i k / G_l)
+   and inverted with the same DFT (the finite-difference sieve with a shared
+   variable per bin, nodes on a circle).  rho is a quarter of the distance
+   log(1 / ||H||_2) to the nearest singularity, where I - D(e^t) H stays
+   accretive; G_l defaults to max(24, 2 (cutoff_l + 1)) points (grid NULL or 0),
+   so the aliasing of the coefficients scales as 4^-G_l (cgd_bounds reports it
+   as wrap_bound) and rounding grows as (4 / log(1/||H||))^{|p|} p!.  FP64 only,
+   no CGD_FLAG_GRAD. */
 #define CGD_FLAG_NO_AUTOTUNE 32u   /* skip the autotuner of cgd_create: default kernel shape
                                       per size class, FP32 pass for every eligible class on
                                       the mixed path (see cgd_tuning)                      */

@@ -26,6 +26,8 @@ FLAG_GRAD = 4
 FLAG_HESSENBERG = 8
 FLAG_NO_HESSENBERG = 16
 FLAG_NO_AUTOTUNE = 32
+FLAG_MOMENTS = 64
+FLAG_CUMULANTS = 128
 # launch stages of one evaluation (per-stage timing); LU stages are order buckets
 STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144", "combine", "dft", "fix",
           "hess", "hess_det", "pair"]

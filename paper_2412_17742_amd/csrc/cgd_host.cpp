@@ -28,6 +28,9 @@ namespace {
 // mixed-path tests check the model on workloads with other seeds and shapes.
 constexpr double kTauScale = 2.0;
 
+// moments mode: default number of points per axis on the circle in t
+constexpr int kMomentPoints = 24;
+
 thread_local std::string g_err;
 
 cgd_status fail(cgd_status s, const std::string &msg) {
@@ -93,6 +96,8 @@ struct HostInst {
     int nblocks = 0;
     std::vector<BinMarginal> marg[kMaxBins];  // per bin, one entry per internal block
     double wrap_bound = 0.0;                   // sum_l bound on Pr(b_l >= G_l)
+    double hnorm = 0.0;                        // moments mode: max over blocks of ||I - Sigma^-1||_2
+    double rho = 0.0;                          // moments mode: radius of the circle in t
 };
 
 // log E[s^b] of a bin, u = s - 1 >= 0, summed over its blocks; +inf outside
@@ -254,7 +259,7 @@ cgd_status validate(const cgd_instance &in, int idx) {
 // eigenbasis.
 cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int> &kset, bool dense,
                           bool use_schur, const std::vector<std::vector<double>> &rk, HostInst &hi,
-                          std::vector<HostBlock> &out, std::vector<GradHost> *grads) {
+                          std::vector<HostBlock> &out, std::vector<GradHost> *grads, bool want_hnorm) {
     const int M = in.M;
     const int nk = (int)kset.size();
     const int m = M * nk;  // modes in this block
@@ -330,6 +335,11 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
         for (int i = 0; i < n2; ++i) Sh(i, i) -= 0.5;
         if (!hermitian_positive_definite(Sh))
             return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(idx) + ": covariance violates Sigma > I/2");
+    }
+    if (want_hnorm) {  // ||H||_2 = max_i |1 - 1/sigma_i| over the eigenvalues sigma_i of Sigma
+        std::vector<double> sg;
+        if (!hermitian_eigvals(Sig, sg)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+        for (double v : sg) hi.hnorm = std::max(hi.hnorm, std::fabs(1.0 - 1.0 / v));
     }
     CMat Sinv;
     if (!inverse(Sig, Sinv)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": singular covariance");
@@ -1281,6 +1291,9 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     const bool dense = c->flags & CGD_FLAG_DENSE_INTERNAL;
     const bool use_schur = !(c->flags & CGD_FLAG_NO_SCHUR);
     const bool want_grad = c->flags & CGD_FLAG_GRAD;
+    const bool moments = c->flags & (CGD_FLAG_MOMENTS | CGD_FLAG_CUMULANTS);
+    if (moments && (want_grad || c->prec != CGD_PREC_FP64))
+        return fail(CGD_ERR_ARG, "CGD_FLAG_MOMENTS / CGD_FLAG_CUMULANTS need CGD_PREC_FP64 and no CGD_FLAG_GRAD");
     if (want_grad && dense)
         for (int i = 0; i < n_inst; ++i)
             if (inst[i].K > 1) return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD works with internal-mode blocks (no CGD_FLAG_DENSE_INTERNAL)");
@@ -1306,6 +1319,11 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             hi.N[l] = in.cutoff[l];
             hi.auto_grid[l] = in.grid && in.grid[l] == 0;
             hi.G[l] = hi.auto_grid[l] ? 0 : (in.grid ? in.grid[l] : in.cutoff[l] + 1);
+            if (moments && (!in.grid || in.grid[l] == 0)) {
+                // points on the circle in t: enough to keep the aliasing (rho / R)^G = 4^-G negligible
+                hi.auto_grid[l] = false;
+                hi.G[l] = std::max(kMomentPoints, 2 * (in.cutoff[l] + 1));
+            }
         }
         // per internal mode squeezing: tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j
         std::vector<std::vector<double>> rk(in.M, std::vector<double>(in.K));
@@ -1333,16 +1351,35 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         if (dense || in.K == 1) {
             std::vector<int> ks(in.K);
             for (int k = 0; k < in.K; ++k) ks[k] = k;
-            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr);
+            s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr,
+                               moments);
             if (s != CGD_OK) return s;
         } else {
             for (int k = 0; k < in.K; ++k) {
-                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr);
+                s = assemble_block(in, i, {k}, false, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr,
+                                   moments);
                 if (s != CGD_OK) return s;
             }
         }
         // grid entries 0: the smallest G_l >= N_l + 1 whose tail bound
         // Pr(b_l >= G_l) is at most tol / (10 L); then the wrap bound of the grid
+        if (moments) {
+            // circle radius in t a quarter of the distance to the nearest singularity,
+            // |t| = log(1 / ||H||): there I - D(e^t) H stays accretive
+            if (!(hi.hnorm < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(i) + ": ||H|| >= 1");
+            hi.rho = 0.25 * std::log(1.0 / std::max(hi.hnorm, 1e-300));
+            hi.rho = std::min(hi.rho, 1.0);
+            int gmin = 1 << 30;
+            int64_t np2 = 1;
+            for (int l = 0; l < in.L; ++l) {
+                gmin = std::min(gmin, hi.G[l]);
+                np2 *= hi.G[l];
+                if (np2 > (int64_t)1 << 31) return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": grid too large");
+            }
+            hi.wrap_bound = std::pow(0.25, gmin);  // relative aliasing scale of the Taylor coefficients
+            for (int l = 0; l < in.L; ++l) std::vector<BinMarginal>().swap(hi.marg[l]);
+            return CGD_OK;
+        }
         bool any_auto = false;
         for (int l = 0; l < in.L; ++l) any_auto |= hi.auto_grid[l];
         if (any_auto && !(tol > 0.0 && std::isfinite(tol)))
@@ -1437,6 +1474,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.nprobs = nprob;
         d.logpr0_re = h.logpr0;
         d.logpr0_im = 0.0;
+        d.rho = h.rho;
+        d.dft_log = (c->flags & CGD_FLAG_CUMULANTS) ? 1 : 0;
         d.first_block = -1;
         d.tau = 0.0;
         c->inst_pt_prefix[i] = pt;
@@ -1508,6 +1547,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             sj.q_off = push_mat(h.Q);
             sj.hbb_off = push_mat(h.H);
             sj.eig_off = d.eig_off;
+            sj.rho = I.rho;
             const int64_t csize = (int64_t)sj.nk * h.nb * h.nb;
             sj.c_off = (int64_t)pool.size();
             pool.resize(pool.size() + csize, make_double2(0, 0));
@@ -1534,6 +1574,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 hd.n_eig = d.n_eig;
                 hd.c_off = sj.c_off;
                 hd.eig_off = d.eig_off;
+                hd.rho = I.rho;
                 const int pbin = pbins[b];
                 if (pbin >= 0) {
                     // pair route: rows of bin P first, S (rows of bin B) per pair after
@@ -1558,6 +1599,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                     pd.c_off = sj.c_off;
                     pd.hs_stride = (int64_t)h.nb * h.nb;
                     pd.eig_off = d.eig_off;
+                    pd.rho = I.rho;
                     const int nH = h.nb - pd.nP;
                     pd.s_off = c->s_region;
                     c->s_region += (int64_t)pd.dA * pd.dP * nH * nH;
@@ -1667,6 +1709,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             double gprod = 1;
             for (int l = 0; l < I.L; ++l) gprod *= I.G[l];
             d.scale = 1.0 / gprod;
+            d.moments = I.rho > 0.0 ? 1 : 0;
+            d.rho = I.rho;
             st.prefix.push_back(st.total);
             st.total += d.outer * d.Bout * d.inner;
             st.desc.push_back(d);
@@ -1791,8 +1835,10 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
     if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
     if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD | CGD_FLAG_HESSENBERG |
-                  CGD_FLAG_NO_HESSENBERG | CGD_FLAG_NO_AUTOTUNE))
+                  CGD_FLAG_NO_HESSENBERG | CGD_FLAG_NO_AUTOTUNE | CGD_FLAG_MOMENTS | CGD_FLAG_CUMULANTS))
         return fail(CGD_ERR_ARG, "unknown flags");
+    if ((flags & CGD_FLAG_MOMENTS) && (flags & CGD_FLAG_CUMULANTS))
+        return fail(CGD_ERR_ARG, "CGD_FLAG_MOMENTS and CGD_FLAG_CUMULANTS together");
     if ((flags & CGD_FLAG_HESSENBERG) && (flags & CGD_FLAG_NO_HESSENBERG))
         return fail(CGD_ERR_ARG, "CGD_FLAG_HESSENBERG and CGD_FLAG_NO_HESSENBERG together");
     cgd_ctx *c = new (std::nothrow) cgd_ctx();

@@ -27,8 +27,11 @@ struct InstDev {
     double logpr0_re, logpr0_im;  // constant part of log G (vacuum probability, traced modes)
     int32_t first_block;      // this instance's blocks are first_block .. first_block + nblocks - 1
     int32_t pad2;
-    double pad3;
+    double rho;               // 0: grid on the unit circle, w = exp(2 pi i k / G); > 0 (moments mode):
+                              // w = exp(t), t = rho exp(2 pi i k / G) on a circle of radius rho
     double tau;               // mixed path: relative error bound assumed for an FP32 value of G (0: no FP32 block)
+    int32_t dft_log;          // 1: the DFT takes log G instead of G (cumulants)
+    int32_t pad4;
 };
 
 // One factorisation job family: an (instance, internal block) pair.  Every
@@ -61,6 +64,7 @@ struct SchurDev {
     int32_t nk;               // number of k values (H1 for axis 0, else G_axis)
     int32_t Gax;              // grid extent of the eliminated axis
     int64_t p_off, q_off, hbb_off, eig_off, c_off;
+    double rho;               // circle radius of the instance (see InstDev)
 };
 
 // Hessenberg route: a block whose rows left after eliminating bin A (axis
@@ -79,6 +83,7 @@ struct HessDev {
     int32_t axP, dP;          // pair route: the middle axis and its number of values (axP = -1: none);
                               // the matrix index kA then runs over (k_A, k_P) pairs, kA_axis * dP + k_P
     int64_t c_off, eig_off, t_off, ec_off;
+    double rho;               // circle radius of the instance (see InstDev)
 };
 
 // Pair route: a block whose rows left after the eigenbasis elimination of
@@ -97,6 +102,7 @@ struct PairDev {
     int64_t eig_off;
     int64_t s_off;            // S, (n - nP)^2 per pair, in the matrix pool
     int64_t ec_off;           // per pair: sum Log(1 - w_A lambda_i) + log det(I - w_P C_PP)
+    double rho;               // circle radius of the instance (see InstDev)
 };
 
 // Gradient: one internal block with its full (bordered) matrix, no reduction.
@@ -130,10 +136,11 @@ struct AdjArgs {
 // One axis pass of the separable inverse DFT for one instance.
 struct DftStageDev {
     int32_t inst, K, Bout, G;
-    int32_t final_stage, pad;
+    int32_t final_stage, moments;  // moments: scale output index b by b! / rho^b (Taylor coefficient -> derivative)
     int64_t outer, inner, in_off, out_off;
     int64_t tw_off;           // exp(-2 pi i m / G), m = 0 .. G-1, in the twiddle pool
     double scale;
+    double rho;
 };
 
 struct LuLaunch {

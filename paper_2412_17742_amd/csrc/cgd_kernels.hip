@@ -67,16 +67,27 @@ __device__ __forceinline__ double2 clog(double2 d) {
     return cmk(0.5 * log(d.x * d.x + d.y * d.y), atan2(d.y, d.x));
 }
 
+// Value of w at grid index k of an axis of extent G: the root of unity
+// exp(2 pi i k / G), or, on a circle of radius rho > 0 in t (moments mode),
+// w = exp(t) with t = rho exp(2 pi i k / G).
+__device__ __forceinline__ double2 grid_w(int k, int G, double rho) {
+    double s, c;
+    sincospi(2.0 * (double)k / (double)G, &s, &c);
+    if (rho == 0.0) return cmk(c, s);
+    double s2, c2;
+    sincos(rho * s, &s2, &c2);
+    const double m = exp(rho * c);
+    return cmk(m * c2, m * s2);
+}
+
 // Grid coordinates of evaluated point p of instance I (half grid on axis 0)
-// and the corresponding roots of unity.
+// and the corresponding value of w.
 __device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, double2 &w) {
     int64_t stride = 1;
     for (int m = I.L - 1; m > l; --m) stride *= I.G[m];
     int64_t k = p / stride;
     if (l > 0) k %= I.G[l];
-    double s, c;
-    sincospi(2.0 * (double)k / (double)I.G[l], &s, &c);
-    w = cmk(c, s);
+    w = grid_w((int)k, I.G[l], I.rho);
 }
 __device__ __forceinline__ int point_k(const InstDev &I, int64_t p, int l) {
     int64_t stride = 1;
@@ -1016,7 +1027,7 @@ pair_schur_f64(const PairDev *__restrict__ jobs, const int64_t *__restrict__ pre
         const int kA = (int)(lp / J.dP), kP = (int)(lp % J.dP);
         const int n = J.n, nP = J.nP, nH = J.n - J.nP;
         double sn, cs;
-        sincospi(2.0 * (double)kP / (double)J.GP, &sn, &cs);
+        { const double2 t_ = grid_w(kP, J.GP, J.rho); cs = t_.x; sn = t_.y; }
         const double2 wP = cmk(cs, sn);
         __syncthreads();  // the previous pair is done with s_perm, s_piv and W
         for (int i = tid; i < n; i += kBigThreads) s_perm[i] = permpool[J.perm_off + i];
@@ -1047,7 +1058,7 @@ pair_schur_f64(const PairDev *__restrict__ jobs, const int64_t *__restrict__ pre
             acc.x += lg.x;
             acc.y += lg.y;
         }
-        sincospi(2.0 * (double)kA / (double)J.GA, &sn, &cs);
+        { const double2 t_ = grid_w(kA, J.GA, J.rho); cs = t_.x; sn = t_.y; }
         const double *__restrict__ lam = eigpool + J.eig_off;
         for (int i = tid; i < J.n_eig; i += kBigThreads) {
             const double2 lg = clog(cmk(1.0 - cs * lam[i], -sn * lam[i]));
@@ -1087,9 +1098,7 @@ schur_build_f64(const SchurDev *__restrict__ jobs, const int64_t *__restrict__ j
     const int r0 = (int)(local % nrb) * kSchurRows;
     double2 *s_f = s_dyn;                 // nA
     double2 *s_pf = s_f + J.nA;           // kSchurRows x nA
-    double s, c;
-    sincospi(2.0 * (double)k / (double)J.Gax, &s, &c);
-    const double2 w = cmk(c, s);
+    const double2 w = grid_w(k, J.Gax, J.rho);
     const double *lam = eigpool + J.eig_off;
     for (int i = threadIdx.x; i < J.nA; i += blockDim.x)
         s_f[i] = cmul(w, cinv(cmk(1.0 - w.x * lam[i], -w.y * lam[i])));
@@ -1515,7 +1524,7 @@ __global__ void __launch_bounds__(TX * TY) hess_reduce_f64(const HessDev *__rest
     // Schur complement (pair_schur_f64)
     if (J.axP >= 0) return;
     double sn, cs;
-    sincospi(2.0 * (double)kA / (double)J.GA, &sn, &cs);
+    { const double2 t_ = grid_w(kA, J.GA, J.rho); cs = t_.x; sn = t_.y; }
     const double *__restrict__ lam = eigpool + J.eig_off;
     double2 acc = cmk(0.0, 0.0);
     for (int i = tid; i < J.n_eig; i += NT) {
@@ -1698,7 +1707,7 @@ __global__ void __launch_bounds__(kHessDetThreads) hess_det_f64(const HessDev *_
     S.n = n;
     S.e = lane & 15;
     double sn, cs;
-    sincospi(2.0 * (double)(valid ? kB : 0) / (double)J.GB, &sn, &cs);
+    { const double2 t_ = grid_w(valid ? kB : 0, J.GB, J.rho); cs = t_.x; sn = t_.y; }
     S.w = cmk(cs, sn);
     #pragma unroll
     for (int q = 0; q < MB; ++q) {
@@ -1777,6 +1786,10 @@ __global__ void combine_points(const InstDev *__restrict__ insts, const int64_t 
         acc.y += c[b].y;
     }
     logg[p] = acc;
+    if (I.dft_log) {  // cumulants: the DFT takes log G itself
+        gval[p] = acc;
+        return;
+    }
     double s, co;
     sincos(acc.y, &s, &co);
     const double m = exp(acc.x);
@@ -1845,6 +1858,12 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
     acc.x += quad_swap<0x4E>(acc.x);
     acc.y += quad_swap<0x4E>(acc.y);
     if (c != 0) return;
+    if (S.moments) {  // Taylor coefficient of t^b -> b-th derivative: times b! / rho^b
+        double f = 1.0;
+        for (int j = 1; j <= b; ++j) f *= (double)j / S.rho;
+        acc.x *= f;
+        acc.y *= f;
+    }
     if (S.final_stage) {
         probs[S.out_off + lq] = acc.x * S.scale;
         if (lq == 0 && err) err[S.inst] = (*status) ? INFINITY : 0.0;
