@@ -11,12 +11,15 @@ An *instance* is a plain dict:
     r                M float64 squeezing parameters of Schmidt mode 0
     alpha            M complex128 displacements of Schmidt mode 0, or None
     schmidt          K float64 Schmidt weights (sum 1, descending) or None (K=1)
-    bin_of           int32 bin index per measured mode, -1 = not measured;
-                     length M (bins over external modes) or M*K when
-                     resolve_internal is 1 (index i*K + k)
+    bin_of           int32 bin index per measured mode, -1 = not measured
+                     (traced out), KEEP = -2 = kept (the heralded modes whose
+                     density matrix is returned); length M (bins over external
+                     modes) or M*K when resolve_internal is 1 (index i*K + k)
     resolve_internal 0 or 1
     cutoff           int32 per bin: output box b_l in [0, cutoff_l]
     grid             int32 per bin: roots-of-unity grid extent G_l >= cutoff_l+1
+    fock_cutoff      (only with kept modes) Fock cutoff N of every kept mode:
+                     density matrix elements <v|rho|u> for u, v in [0, N]
 
 Workload shapes follow the paper's physical settings: single-mode squeezed
 inputs on a lossy interferometer (Sec. II, Sec. VIII C), internal Schmidt
@@ -27,6 +30,7 @@ from __future__ import annotations
 import numpy as np
 
 SEED_ROOT = (2412, 17742)
+KEEP = -2  # bin_of value of a kept (heralded) mode
 
 
 def rng_for(stream: int, inst: int = 0) -> np.random.Generator:
@@ -56,12 +60,13 @@ def schmidt_geometric(K: int, ratio: float) -> np.ndarray | None:
 
 
 def make_instance(T, r, alpha=None, schmidt=None, bin_of=None, cutoff=None, grid=None,
-                  resolve_internal=0) -> dict:
+                  resolve_internal=0, fock_cutoff=None) -> dict:
     T = np.ascontiguousarray(T, dtype=np.complex128)
     M = T.shape[0]
     cutoff = np.asarray(cutoff, dtype=np.int32)
     grid = cutoff + 1 if grid is None else np.asarray(grid, dtype=np.int32)
-    return dict(
+    extra = {} if fock_cutoff is None else {"fock_cutoff": int(fock_cutoff)}
+    return dict(**extra,
         T=T,
         r=np.ascontiguousarray(r, dtype=np.float64),
         alpha=None if alpha is None else np.ascontiguousarray(alpha, dtype=np.complex128),
@@ -258,3 +263,41 @@ def fock_herald_instance(p: float, eta: float, xi: float = 1.1, cutoff=(3, 3), g
         bin_of = np.array([0, 0, 1, -1], np.int32)  # index i*K + k
     return make_instance(T, np.full(2, xi), schmidt=schmidt, bin_of=bin_of, cutoff=list(cutoff),
                          grid=grid, resolve_internal=1)
+
+
+def gkp_like(p: float, eta: float, seed: int = 0, herald=(5, 7), fock_cutoff: int = 26) -> dict:
+    """The shape of the approximate-GKP heralding setup of Sec. VIII B: three
+    squeezed inputs on sqrt(eta) x a 3 x 3 unitary, two spectral modes with
+    weights (p, 1 - p) (one mode for p >= 1), the first two output ports
+    measured (one bin each, both spectral modes; cutoffs = the heralding
+    pattern (5, 7)), spectral mode 0 of port 2 kept with Fock cutoff 26 and
+    its spectral mode 1 traced out.  The paper takes the squeezing and the
+    unitary from a reference that is not available here; these are seeded
+    draws (r ~ U[0.6, 1.2], Haar U) of the same shape."""
+    rng = rng_for(70, seed)
+    U = haar_unitary(3, rng)
+    r = rng.uniform(0.6, 1.2, 3)
+    if p >= 1.0:
+        schmidt, bin_of = None, [0, 1, KEEP]
+    else:
+        schmidt, bin_of = np.array([p, 1.0 - p]), [0, 0, 1, 1, KEEP, -1]
+    return make_instance(np.sqrt(eta) * U, r, schmidt=schmidt, bin_of=bin_of, cutoff=list(herald),
+                         resolve_internal=1, fock_cutoff=fock_cutoff)
+
+
+def gkp_like_map(n: int = 50, seed: int = 0) -> list[dict]:
+    """n x n grid of gkp_like states over p in [0.7, 0.99] and eta in [0.8, 1.0]
+    (the parameter ranges of the paper's GKP fidelity map), same unitary and
+    squeezing for all; p runs slowest."""
+    return [gkp_like(p, eta, seed) for p in np.linspace(0.7, 0.99, n) for eta in np.linspace(0.8, 1.0, n)]
+
+
+def fock_herald_density(p: float, eta: float, xi: float = 1.1, herald: int = 3, fock_cutoff: int = 6) -> dict:
+    """fock_herald_instance with port 1, spectral mode 0 kept instead of
+    binned: the heralded state's density matrix for the pattern `herald` in
+    port 0 (and every smaller one)."""
+    inst = fock_herald_instance(p, eta, xi, cutoff=(herald, 0))
+    b = inst["bin_of"].copy()
+    b[b == 1] = KEEP
+    return make_instance(inst["T"], inst["r"], schmidt=inst["schmidt"], bin_of=b, cutoff=[herald],
+                         resolve_internal=1, fock_cutoff=fock_cutoff)
