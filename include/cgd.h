@@ -116,8 +116,10 @@ typedef struct {
     const double *r;         /* M squeezing parameters >= 0 (internal mode 0)                 */
     const double *alpha;     /* M complex displacements of internal mode 0, or NULL (zero)    */
     const double *schmidt;   /* K weights > 0 summing to 1, lambda_k <= lambda_0; NULL iff K==1 */
-    const int32_t *bin_of;   /* bin index in [0, L) or -1 (not measured) per mode: M entries
-                                (external modes) or M*K entries (index i*K+k) if
+    const int32_t *bin_of;   /* per mode: bin index in [0, L), -1 (not measured: traced out) or
+                                CGD_KEEP (-2: kept, see "Heralded density matrices" below); M
+                                entries (external modes; a kept external mode keeps all its K
+                                internal modes) or M*K entries (index i*K+k) if
                                 resolve_internal != 0                                          */
     int32_t resolve_internal;/* 0: detectors see external modes; 1: bins over (i, k) pairs     */
     const int32_t *cutoff;   /* L entries N_l >= 0: output box b_l in [0, N_l]                */
@@ -126,7 +128,38 @@ typedef struct {
                                 Pr(b_l >= G_l) (see cgd_bounds) is at most tol / (10 L), so
                                 that the wrapped distribution is within tol / 10 of the exact
                                 binned probabilities (needs a finite tol > 0; G_l <= 4096)    */
+    int32_t fock_cutoff;     /* with kept modes: Fock cutoff N >= 0 of every kept mode; ignored
+                                otherwise                                                      */
 } cgd_instance;
+
+#define CGD_KEEP (-2)
+
+/* Heralded density matrices (Sec. VII, Eq. heralded_state_internal).  An
+ * instance with g >= 1 kept modes returns, for every heralding pattern b~ of
+ * its L bins in the box, the unnormalised state of the kept modes conditioned
+ * on b~:
+ *     rho(b~)[v][u] = <v| rho_G(b~) |u> = sum_{n~ in K(b~)} <n~, v| rho |n~, u>,
+ * u, v Fock patterns of the kept modes with entries in [0, fock_cutoff]; modes
+ * with bin -1 are traced out.  Its trace over all u is Pr(b~).  Like the
+ * probabilities, the output is the wrapped sum over b~ + m o G; each element
+ * is within cgd_bounds' wrap_bound of the exact one.
+ * Layout of the instance's output: 2 D^2 prod_l (N_l + 1) doubles (interleaved
+ * complex), [b~][v][u], D = (fock_cutoff + 1)^g, the multi-indices u and v
+ * row-major over the kept modes in mode order (last kept mode fastest); the
+ * instance's offset from cgd_layout is even.
+ * Method: per grid point, the kept modes' rows and columns of A and their
+ * loop-vector entries border the heralding block, whose elimination leaves
+ * the quadratic form of the generating function
+ *     sum_{u,v} <v| rho_G(w) |u> x^u y^v / sqrt(u! v!)
+ *         = G_H(w) exp(l(w)^T c + 1/2 c^T Q(w) c),  c = (y, x)
+ * (the master theorem, Eq. lhaf_master, with a loop vector that depends on the
+ * kept modes' variables); a recurrence expands it into the D^2 elements, and
+ * the inverse DFT over the heralding grid runs for each of them.  The
+ * permutation trick of Sec. VII (a larger matrix per (u, v)) is not used.
+ * Restrictions: CGD_PREC_FP64; no CGD_FLAG_GRAD, CGD_FLAG_MOMENTS,
+ * CGD_FLAG_CUMULANTS; 2 g <= 16; D^2 <= 2^22; every internal block of order
+ * <= 144 (heralding rows left after eliminating one bin, plus 2 g_k + 1 border
+ * rows); at most 2^31 values per instance (grid points times D^2). */
 
 /* Assemble the states (FP64, host) and upload everything the evaluation
  * needs.  n_inst instances are evaluated together by cgd_eval.
@@ -147,16 +180,18 @@ typedef struct {
 cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst,
                       cgd_precision prec, double tol, uint32_t flags, void *hip_stream);
 
-/* Sizes of the outputs.  n_probs_total = sum_i prod_l (N_l + 1);
- * prob_offsets (n_inst + 1 entries, may be NULL) gives each instance's first
- * probability; n_grid_total (may be NULL) is the number of grid points whose
- * values are produced (sum_i prod_l G_l).  Probabilities are row-major over
- * (b_1, ..., b_L) with b_L fastest. */
+/* Sizes of the outputs, in doubles.  n_probs_total = sum_i of prod_l (N_l + 1)
+ * (2 D^2 prod_l (N_l + 1) for an instance with kept modes, after one double of
+ * padding if needed to keep its offset even); prob_offsets (n_inst + 1
+ * entries, may be NULL) gives each instance's first double; n_grid_total (may
+ * be NULL) is the number of grid points whose values are produced
+ * (sum_i prod_l G_l).  Probabilities are row-major over (b_1, ..., b_L) with
+ * b_L fastest. */
 cgd_status cgd_layout(const cgd_ctx *ctx, int64_t *n_probs_total, int64_t *prob_offsets,
                       int64_t *n_grid_total);
 
-/* Evaluate the wrapped distributions of all instances into d_probs (device,
- * n_probs_total doubles).  d_err_bound (device, n_inst doubles, or NULL)
+/* Evaluate the wrapped distributions (density matrices for instances with
+ * kept modes) of all instances into d_probs (device, n_probs_total doubles).  d_err_bound (device, n_inst doubles, or NULL)
  * receives, per instance, a bound on the absolute error added by the mixed
  * path to every probability: (1/prod G) sum over the points kept in FP32 of
  * c_k |G_k| tau, with tau the modelled relative error of an FP32 value of G
@@ -226,6 +261,8 @@ cgd_status cgd_grad(cgd_ctx *ctx, const double *d_dprobs, double *d_dr, double *
  *                        leaves the matrix the Hessenberg stages reduce
  *   CGD_STAGE_FIX        mixed path: selection of the points whose FP32 value can
  *                        matter, their FP64 re-factorisation and the second combine
+ *   CGD_STAGE_DENSITY    density mode: expansion of every point's generating function
+ *                        into matrix elements, and rho = R + R^H after the DFT
  * With timing enabled, cgd_eval runs eagerly and records a HIP event pair on
  * the context's stream around every launch of a stage; cgd_stage_times waits
  * for the last evaluation and returns, per stage, the sum of its launches'
@@ -249,7 +286,8 @@ enum {
     CGD_STAGE_HESS = 10,
     CGD_STAGE_HESS_DET = 11,
     CGD_STAGE_PAIR = 12,
-    CGD_NSTAGES = 13
+    CGD_STAGE_DENSITY = 13,
+    CGD_NSTAGES = 14
 };
 cgd_status cgd_set_timing(cgd_ctx *ctx, int32_t enable);
 cgd_status cgd_stage_times(cgd_ctx *ctx, double *ms /* CGD_NSTAGES */);

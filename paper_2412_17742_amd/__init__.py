@@ -28,9 +28,10 @@ FLAG_NO_HESSENBERG = 16
 FLAG_NO_AUTOTUNE = 32
 FLAG_MOMENTS = 64
 FLAG_CUMULANTS = 128
+KEEP = -2  # bin_of value of a kept mode (heralded density matrices)
 # launch stages of one evaluation (per-stage timing); LU stages are order buckets
 STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144", "combine", "dft", "fix",
-          "hess", "hess_det", "pair"]
+          "hess", "hess_det", "pair", "density"]
 # the kernels behind each LU bucket: (FP64 path, FP32 first pass of the mixed path)
 LU_KERNELS = {
     "lu_le32": ("lu_reg<double,8,8,4,4>", "lu_mfma_f32<2,1,2>"),
@@ -55,6 +56,7 @@ class CgdInstance(ctypes.Structure):
         ("schmidt", ctypes.c_void_p), ("bin_of", ctypes.c_void_p),
         ("resolve_internal", ctypes.c_int32),
         ("cutoff", ctypes.c_void_p), ("grid", ctypes.c_void_p),
+        ("fock_cutoff", ctypes.c_int32),
     ]
 
 
@@ -126,7 +128,16 @@ def _marshal(inst: dict, keep: list) -> CgdInstance:
     keep.append(arrays)
     ptr = {k: (None if v is None else v.ctypes.data) for k, v in arrays.items()}
     return CgdInstance(M, K, len(arrays["cutoff"]), ptr["T"], ptr["r"], ptr["alpha"], ptr["schmidt"],
-                       ptr["bin_of"], int(inst.get("resolve_internal", 0)), ptr["cutoff"], ptr["grid"])
+                       ptr["bin_of"], int(inst.get("resolve_internal", 0)), ptr["cutoff"], ptr["grid"],
+                       int(inst.get("fock_cutoff", 0)))
+
+
+def _density_dim(inst: dict):
+    """D = (fock_cutoff + 1)^g for an instance with g kept modes, else None."""
+    b = np.asarray(inst["bin_of"])
+    K = 1 if inst.get("schmidt") is None else len(inst["schmidt"])
+    g = int((b == KEEP).sum()) * (1 if inst.get("resolve_internal", 0) else K)
+    return (int(inst.get("fock_cutoff", 0)) + 1) ** g if g else None
 
 
 class Context:
@@ -157,6 +168,7 @@ class Context:
         self.n_grid = ng.value
         self.n_points = L.cgd_points(self._h)
         self.shapes = [tuple(int(c) + 1 for c in x["cutoff"]) for x in instances]
+        self.density_dims = [_density_dim(x) for x in instances]
         self._M = [np.asarray(x["T"]).shape[0] for x in instances]
         self._K = [1 if x.get("schmidt") is None else len(x["schmidt"]) for x in instances]
 
@@ -188,9 +200,21 @@ class Context:
         return probs
 
     def split(self, probs):
-        """Split the concatenated output into one array per instance (reshaped to the box)."""
-        return [probs[self.prob_offsets[i]:self.prob_offsets[i + 1]].reshape(self.shapes[i])
-                for i in range(self.n_inst)]
+        """Split the concatenated output into one array per instance: reshaped to
+        the box, or for an instance with kept modes a complex view of shape
+        box + (D, D) holding <v|rho(b~)|u> at [b~][v][u]."""
+        import torch
+        out = []
+        for i in range(self.n_inst):
+            lo = int(self.prob_offsets[i])  # a density instance's offset is even; a double of
+            D = self.density_dims[i]         # padding before it ends the previous range
+            nb = int(np.prod(self.shapes[i]))
+            if D is None:
+                out.append(probs[lo:lo + nb].reshape(self.shapes[i]))
+            else:
+                seg = probs[lo:lo + 2 * D * D * nb]
+                out.append(torch.view_as_complex(seg.view(-1, 2)).reshape(self.shapes[i] + (D, D)))
+        return out
 
     def grid_values(self):
         """log G at the evaluated grid points (complex128 device tensor)."""

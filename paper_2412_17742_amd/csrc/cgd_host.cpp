@@ -50,6 +50,8 @@ struct HostBlock {
     int inst = 0, blk = 0;
     int nb = 0;                 // order of the matrix factorised per point
     int bordered = 0;
+    int nkeep = 0;              // density mode: kept-mode border rows (before the gamma border)
+    std::vector<int32_t> kv;    // their generating-function variable positions
     std::vector<int32_t> rowbin;
     CMat H;                     // nb x nb: the matrix itself, or H_BB under elimination
     int schur_axis = -1;        // eliminated bin
@@ -98,6 +100,7 @@ struct HostInst {
     double wrap_bound = 0.0;                   // sum_l bound on Pr(b_l >= G_l)
     double hnorm = 0.0;                        // moments mode: max over blocks of ||I - Sigma^-1||_2
     double rho = 0.0;                          // moments mode: radius of the circle in t
+    int nvar = 0, fock_n = 0;                  // density mode: 2 g variables, Fock cutoff
 };
 
 // log E[s^b] of a bin, u = s - 1 >= 0, summed over its blocks; +inf outside
@@ -152,16 +155,24 @@ double bin_log_mgf(const std::vector<BinMarginal> &mb, double u) {
 // log of the Chernoff bound Pr(b >= G) <= min over s > 1 of E[s^b] / s^G: the
 // exponent log E[s^b] - G log s is convex in t = log s, minimised by golden
 // section over (0, t_max), t_max the edge of convergence (found by doubling
-// and bisection).  0 means no bound below 1.
+// and bisection) or, when E[s^b] is finite up to s = 1 + 2^60 (a bin without
+// squeezed or thermal light: coherent light only, or no light), log(1 + 2^60).
+// 0 means no bound below 1.
 double bin_log_tail(const std::vector<BinMarginal> &mb, int G) {
-    double hi = 1.0;
+    double hi = 1.0, lo = 0.0;
     int it = 0;
-    while (std::isfinite(bin_log_mgf(mb, hi)) && it++ < 200) hi *= 2.0;
-    double lo = 0.0;
-    if (it > 200) return -INFINITY;  // no photons in this bin
-    for (int k = 0; k < 100; ++k) {
-        const double mid = 0.5 * (lo + hi);
-        (std::isfinite(bin_log_mgf(mb, mid)) ? lo : hi) = mid;
+    while (it < 60 && std::isfinite(bin_log_mgf(mb, hi))) {
+        lo = hi;
+        hi *= 2.0;
+        ++it;
+    }
+    if (std::isfinite(bin_log_mgf(mb, hi))) {
+        lo = hi;
+    } else {
+        for (int k = 0; k < 100; ++k) {
+            const double mid = 0.5 * (lo + hi);
+            (std::isfinite(bin_log_mgf(mb, mid)) ? lo : hi) = mid;
+        }
     }
     const double tmax = std::log1p(lo);
     auto f = [&](double t) { return bin_log_mgf(mb, std::expm1(t)) - G * t; };
@@ -209,6 +220,18 @@ int bin_of_row(const cgd_instance &in, int row, int m, const std::vector<int> &k
     return in.resolve_internal ? in.bin_of[i * in.K + k] : in.bin_of[i];
 }
 
+// Fine indices i*K + k of the kept modes, ascending (the order of the density
+// matrix's multi-indices).
+std::vector<int> kept_fine_modes(const cgd_instance &in) {
+    std::vector<int> out;
+    for (int i = 0; i < in.M; ++i)
+        for (int k = 0; k < in.K; ++k) {
+            const int b = in.resolve_internal ? in.bin_of[i * in.K + k] : in.bin_of[i];
+            if (b == CGD_KEEP) out.push_back(i * in.K + k);
+        }
+    return out;
+}
+
 cgd_status validate(const cgd_instance &in, int idx) {
     const std::string at = "instance " + std::to_string(idx) + ": ";
     if (in.M < 1 || in.K < 1 || in.L < 1 || in.L > kMaxBins) return fail(CGD_ERR_ARG, at + "need M >= 1, K >= 1, 1 <= L <= 8");
@@ -235,7 +258,15 @@ cgd_status validate(const cgd_instance &in, int idx) {
     }
     const int nbin = in.resolve_internal ? in.M * in.K : in.M;
     for (int i = 0; i < nbin; ++i)
-        if (in.bin_of[i] < -1 || in.bin_of[i] >= in.L) return fail(CGD_ERR_ARG, at + "bin index out of range");
+        if (in.bin_of[i] < CGD_KEEP || in.bin_of[i] >= in.L) return fail(CGD_ERR_ARG, at + "bin index out of range");
+    const int g = (int)kept_fine_modes(in).size();
+    if (g > 0) {
+        if (2 * g > kMaxKeepVars) return fail(CGD_ERR_ARG, at + "at most 8 kept modes");
+        if (in.fock_cutoff < 0) return fail(CGD_ERR_ARG, at + "fock_cutoff must be >= 0");
+        double e = 1.0;
+        for (int k = 0; k < 2 * g; ++k) e *= (double)in.fock_cutoff + 1.0;
+        if (e > (double)(1 << 22)) return fail(CGD_ERR_ARG, at + "(fock_cutoff + 1)^(2 g) exceeds 2^22");
+    }
     int64_t npts = 1;
     for (int l = 0; l < in.L; ++l) {
         if (in.cutoff[l] < 0 || in.cutoff[l] > 4095) return fail(CGD_ERR_ARG, at + "cutoff out of range");
@@ -352,19 +383,47 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
     if (!std::isfinite(ld)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": log det Sigma");
     hi.logpr0 += -0.5 * quad.real() - 0.5 * ld;  // Eq. vacuum_probability
 
-    // bordered H' (order n2 + displaced): H, column -X gamma = -Sigma^-1 zbar, row -gamma^T
-    const int nf = n2 + (displaced ? 1 : 0);
+    // Bordered H' over the state rows srow (every row that is not kept): H,
+    // column -X gamma = -Sigma^-1 zbar, row -gamma^T (last).  Density mode: the
+    // kept modes' rows krow (first half, then second half) come between them as
+    // a border with columns -H_{srow, g}, rows -A_{g, srow} = -H_{X g, srow}, the
+    // block A_GG = H_{X g, g'} and gamma_G = v_{X g} against the gamma border,
+    // so that the Schur complement left after eliminating the state rows holds
+    // the kept modes' quadratic form (see density_expand).
+    auto xp = [m](int i) { return i < m ? i + m : i - m; };
+    std::vector<int> srow, krow;
+    {
+        std::vector<int> kA;
+        for (int i = 0; i < m; ++i)
+            if (bin_of_row(in, i, m, kset, dense) == CGD_KEEP) kA.push_back(i);
+        for (int i = 0; i < n2; ++i)
+            if (bin_of_row(in, i, m, kset, dense) != CGD_KEEP) srow.push_back(i);
+        for (int i : kA) krow.push_back(i);
+        for (int i : kA) krow.push_back(i + m);
+    }
+    const int ns = (int)srow.size(), nkr = (int)krow.size();
+    const int ig = ns + nkr;  // gamma border
+    const int nf = ig + (displaced ? 1 : 0);
     CMat Hf(nf, nf);
-    for (int i = 0; i < n2; ++i)
-        for (int j = 0; j < n2; ++j) Hf(i, j) = (i == j ? 1.0 : 0.0) - Sinv(i, j);
-    std::vector<int32_t> rb(nf, -1);
-    for (int i = 0; i < n2; ++i) rb[i] = bin_of_row(in, i, m, kset, dense);
-    if (displaced) {
-        for (int i = 0; i < n2; ++i) {
-            Hf(i, n2) = -v[i];                     // X gamma = Sigma^-1 zbar
-            Hf(n2, i) = -v[i < m ? i + m : i - m]; // gamma = X Sigma^-1 zbar
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) Hf(a, b) = (srow[a] == srow[b] ? 1.0 : 0.0) - Sinv(srow[a], srow[b]);
+    for (int a = 0; a < ns; ++a)
+        for (int q = 0; q < nkr; ++q) {
+            Hf(a, ns + q) = Sinv(srow[a], krow[q]);
+            Hf(ns + q, a) = Sinv(xp(krow[q]), srow[a]);
         }
-        Hf(n2, n2) = 0.0;
+    for (int q = 0; q < nkr; ++q)
+        for (int q2 = 0; q2 < nkr; ++q2)
+            Hf(ns + q, ns + q2) = (xp(krow[q]) == krow[q2] ? 1.0 : 0.0) - Sinv(xp(krow[q]), krow[q2]);
+    std::vector<int32_t> rb(nf, -1);
+    for (int a = 0; a < ns; ++a) rb[a] = bin_of_row(in, srow[a], m, kset, dense);
+    if (displaced) {
+        for (int a = 0; a < ns; ++a) {
+            Hf(a, ig) = -v[srow[a]];      // X gamma = Sigma^-1 zbar
+            Hf(ig, a) = -v[xp(srow[a])];  // gamma = X Sigma^-1 zbar
+        }
+        for (int q = 0; q < nkr; ++q) Hf(ns + q, ig) = Hf(ig, ns + q) = v[xp(krow[q])];
+        Hf(ig, ig) = 0.0;
     }
 
     if (grads) {
@@ -383,11 +442,8 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
     // integrate out unmeasured modes: det S = det(I - H_UU) det(I - D_R H_red),
     // H_red = H_RR + H_RU (I - H_UU)^-1 H_UR (the reduced Gaussian state)
     std::vector<int> U, R;
-    for (int i = 0; i < nf; ++i) {
-        if (displaced && i == n2) continue;
-        (rb[i] < 0 ? U : R).push_back(i);
-    }
-    if (displaced) R.push_back(n2);
+    for (int i = 0; i < ns; ++i) (rb[i] < 0 ? U : R).push_back(i);
+    for (int i = ns; i < nf; ++i) R.push_back(i);  // borders last
     CMat Hr;
     std::vector<int32_t> rbr;
     if (!U.empty()) {
@@ -421,6 +477,19 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
     hb.inst = idx;
     hb.blk = hi.nblocks;
     hb.bordered = displaced ? 1 : 0;
+    hb.nkeep = nkr;
+    if (nkr) {
+        // variable positions: (v_1..v_g, u_1..u_g); a first-half row is the ket
+        // variable x of its mode (u), a second-half row the bra variable y (v)
+        const std::vector<int> kf = kept_fine_modes(in);
+        const int g = (int)kf.size();
+        for (int q = 0; q < nkr; ++q) {
+            const int md = krow[q] % m;
+            const int fine = dense ? (md / nk) * in.K + kset[md % nk] : md * in.K + kset[0];
+            const int kidx = (int)(std::lower_bound(kf.begin(), kf.end(), fine) - kf.begin());
+            hb.kv.push_back(krow[q] < m ? g + kidx : kidx);
+        }
+    }
     // eliminate the bin with most rows through the eigenbasis of its (Hermitian) block
     int axis = -1;
     if (use_schur) {
@@ -497,7 +566,7 @@ struct LuClass {
 // its eigenbasis, no displacement border, order within the reduction
 // kernels' limit, and every row left in one other bin.  Returns that bin, or -1.
 static int hess_bin(const HostBlock &h) {
-    if (h.schur_axis < 0 || h.bordered || h.nb < 1 || h.nb > hess_class_limit(kHessClasses - 1)) return -1;
+    if (h.schur_axis < 0 || h.bordered || h.nkeep || h.nb < 1 || h.nb > hess_class_limit(kHessClasses - 1)) return -1;
     int hbin = -1;
     for (int32_t rb : h.rowbin) {
         if (rb < 0 || (hbin >= 0 && rb != hbin)) return -1;
@@ -515,7 +584,7 @@ constexpr int kPairMaxOrder = 480;
 constexpr bool kPairRoute = false;
 static bool pair_bins(const HostBlock &h, const InstDev &I, int &pbin, int &hbin) {
     if (!kPairRoute) return false;
-    if (h.schur_axis < 0 || h.bordered || h.nb < 2 || h.nb > kPairMaxOrder) return false;
+    if (h.schur_axis < 0 || h.bordered || h.nkeep || h.nb < 2 || h.nb > kPairMaxOrder) return false;
     int b1 = -1, b2 = -1, n1 = 0, n2 = 0;
     for (int32_t rb : h.rowbin) {
         if (rb < 0 || rb == h.schur_axis) return false;
@@ -600,6 +669,15 @@ struct cgd_ctx {
     double2 *d_tw = nullptr;           // exp(-2 pi i m / G), m < G, for every G in use
     std::vector<int64_t> prob_offsets, inst_pt_prefix;
     int64_t nprobs = 0, npts = 0, ngrid = 0, ncontrib = 0;
+    int64_t ntab = 0;                  // values per evaluation: sum_i points_i * E_i
+    // density mode: instances with kept modes, prefix of their points and of
+    // their output elements, trailing Schur complement pool
+    std::vector<int32_t> dinst;
+    std::vector<int64_t> dprefix, hprefix;
+    int64_t dnpts = 0, htotal = 0, ntpool = 0, dens_lds = 0;
+    int32_t *d_dinst = nullptr;
+    int64_t *d_dprefix = nullptr, *d_hprefix = nullptr;
+    double2 *d_tpool = nullptr;
     // device
     InstDev *d_inst = nullptr;
     BlockDev *d_blocks = nullptr;
@@ -669,6 +747,7 @@ void free_ctx(cgd_ctx *c) {
     auto fr = [](void *p) { if (p) (void)hipFree(p); };
     fr(c->d_inst); fr(c->d_blocks); fr(c->d_schur); fr(c->d_schur_prefix); fr(c->d_inst_pt_prefix);
     fr(c->d_pool); fr(c->d_rb); fr(c->d_eig); fr(c->d_contrib); fr(c->d_logg); fr(c->d_gA); fr(c->d_gB);
+    fr(c->d_tpool); fr(c->d_dinst); fr(c->d_dprefix); fr(c->d_hprefix);
     fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list); fr(c->d_list_off);
     fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
@@ -1083,6 +1162,16 @@ double lu_flops(double n) {
     return f;
 }
 
+// flops of one block's factorisation: a density-mode block stops after the
+// pivots of S, the border rows (m < nb - nS) are updated but not eliminated
+double block_flops(const BlockDev &d) {
+    if (!d.nkeep) return lu_flops(d.nb);
+    const int nS = d.nb - d.nkeep - d.bordered;
+    double f = 0;
+    for (int m = d.nb - 1; m >= d.nb - nS; --m) f += 8.0 * m * m + 6.0 * m;
+    return f;
+}
+
 // algorithmic flops of the LU stages per evaluation (FP32 first pass and
 // FP64 groups; the re-factorised share of the mixed path is not counted)
 void lu_work(cgd_ctx *c) {
@@ -1090,7 +1179,7 @@ void lu_work(cgd_ctx *c) {
     for (int k = 0; k < kG64; ++k)
         for (int32_t bj : c->g64[k].jobs) {
             const BlockDev &d = c->blocks[bj];
-            c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
+            c->work_flops[lu_stage(k)] += block_flops(d) * c->inst[d.inst].npts;
         }
     for (int k = 0; k < kMfmaClasses; ++k)
         for (int32_t bj : c->g32[k].jobs) {
@@ -1221,7 +1310,7 @@ cgd_status autotune(cgd_ctx *c) {
         hipError_t e = hipMemcpy(d_items, items.data(), sizeof(int2) * S, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(d_aux, cnt, sizeof(cnt), hipMemcpyHostToDevice);
         LuLaunch a{nullptr, nullptr, 0, 0, d_items, d_aux, S, c->d_blocks, c->d_inst, c->d_pool, c->d_rb, c->d_eig,
-                   c->d_contrib, d_aux + 1};
+                   c->d_contrib, d_aux + 1, c->d_tpool};
         std::vector<double> t64(n64, -1.0), t32(n32, -1.0);
         for (int v = 0; v < n64 && e == hipSuccess; ++v)
             e = timed([&] { return k < kRegClasses ? launch_lu_reg(k, v, a, st)
@@ -1315,6 +1404,11 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         if (s != CGD_OK) return s;
         HostInst &hi = hinst[i];
         hi.L = in.L;
+        hi.nvar = 2 * (int)kept_fine_modes(in).size();
+        hi.fock_n = hi.nvar ? in.fock_cutoff : 0;
+        if (hi.nvar && (moments || want_grad || c->prec != CGD_PREC_FP64))
+            return fail(CGD_ERR_ARG, "instance " + std::to_string(i) +
+                                         ": kept modes need CGD_PREC_FP64 and no CGD_FLAG_GRAD / MOMENTS / CUMULANTS");
         for (int l = 0; l < in.L; ++l) {
             hi.N[l] = in.cutoff[l];
             hi.auto_grid[l] = in.grid && in.grid[l] == 0;
@@ -1450,7 +1544,12 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     c->inst.resize(n_inst);
     c->prob_offsets.assign(n_inst + 1, 0);
     c->inst_pt_prefix.assign(n_inst, 0);
-    int64_t pt = 0, co = 0, po = 0, ng = 0;
+    int64_t pt = 0, co = 0, po = 0, ng = 0, tab = 0;
+    c->dinst.clear();
+    c->dprefix.clear();
+    c->hprefix.clear();
+    c->dnpts = c->htotal = 0;
+    c->dens_lds = 0;
     for (int i = 0; i < n_inst; ++i) {
         InstDev &d = c->inst[i];
         std::memset(&d, 0, sizeof(d));
@@ -1467,6 +1566,26 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         }
         d.H1 = h.G[0] / 2 + 1;
         np *= d.H1;
+        d.nvar = h.nvar;
+        d.fock_n = h.fock_n;
+        d.E = 1;
+        for (int k = 0; k < h.nvar; ++k) d.E *= h.fock_n + 1;
+        if (h.nvar) {
+            if (np * d.E > ((int64_t)1 << 31))
+                return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": grid points times (fock_cutoff+1)^(2g) exceed 2^31");
+            po += po & 1;  // complex output: even offset
+            c->dinst.push_back(i);
+            c->dprefix.push_back(c->dnpts);
+            c->hprefix.push_back(c->htotal);
+            c->dnpts += np;
+            c->htotal += nprob * d.E;
+            if (d.E <= kDensityLdsValues) c->dens_lds = std::max(c->dens_lds, d.E);
+            nprob *= 2 * d.E;
+        }
+        d.gv_off = tab;
+        // the region also holds the last DFT pass's complex output, prod (N_l + 1)
+        // values per element, which can exceed the points (H1 < N_1 + 1)
+        tab += (h.nvar ? std::max(np, nprob / (2 * d.E)) : np) * d.E;
         d.npts = np;
         d.pt_off = pt;
         d.c_off = co;
@@ -1486,6 +1605,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         ng += ngi;
     }
     c->prob_offsets[n_inst] = po;
+    c->ntab = tab;
     c->npts = pt;
     c->ncontrib = co;
     c->nprobs = po;
@@ -1527,6 +1647,17 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.blk = h.blk;
         d.nb = h.nb;
         d.bordered = h.bordered;
+        d.nkeep = h.nkeep;
+        if (h.nkeep) {
+            if (d.cls >= kRegClasses)
+                return fail(CGD_ERR_ARG, "instance " + std::to_string(h.inst) + ": a block with kept modes has order " +
+                                             std::to_string(h.nb) + " > " + std::to_string(reg_class_limit(kRegClasses - 1)));
+            const int nt = h.nkeep + h.bordered;
+            d.t_off = c->ntpool;
+            c->ntpool += I0.npts * nt * nt;
+            d.kv_off = (int64_t)rbpool.size();
+            rbpool.insert(rbpool.end(), h.kv.begin(), h.kv.end());
+        }
         d.schur_axis = h.schur_axis;
         d.n_eig = (int32_t)h.eig.size();
         d.rb_off = (int64_t)rbpool.size();
@@ -1702,10 +1833,11 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             d.final_stage = a == 0;
             d.outer = 1;
             for (int l = 0; l < a; ++l) d.outer *= dims[l];
-            d.inner = 1;
+            d.inner = I.E;  // density mode: every matrix element is a DFT of its own
             for (int l = a + 1; l < I.L; ++l) d.inner *= dims[l];
-            d.in_off = I.pt_off;
-            d.out_off = a == 0 ? I.prob_off : I.pt_off;
+            d.in_off = I.gv_off;
+            d.out_off = (a == 0 && !I.nvar) ? I.prob_off : I.gv_off;
+            d.density = I.nvar ? 1 : 0;
             double gprod = 1;
             for (int l = 0; l < I.L; ++l) gprod *= I.G[l];
             d.scale = 1.0 / gprod;
@@ -1743,7 +1875,16 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     }
     for (const DftStage &st : c->stages)
         for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
-    c->work_bytes[CGD_STAGE_DFT] = 16.0 * c->npts + 8.0 * c->nprobs;
+    c->work_bytes[CGD_STAGE_DFT] = 16.0 * c->ntab + 8.0 * c->nprobs;
+    for (int j : c->dinst) {
+        // per value: one complex multiply for l, one per later position, of the
+        // recurrence (about 1 + nvar / 2 on average); rho = R + R^H: one add
+        const InstDev &I = c->inst[j];
+        c->work_flops[CGD_STAGE_DENSITY] += 8.0 * (1.0 + 0.5 * I.nvar) * (double)I.npts * (double)I.E;
+        c->work_bytes[CGD_STAGE_DENSITY] += 16.0 * (double)I.npts * (double)I.E;
+    }
+    c->work_flops[CGD_STAGE_DENSITY] += 2.0 * (double)c->htotal;
+    c->work_bytes[CGD_STAGE_DENSITY] += 48.0 * (double)c->htotal;
     c->work_bytes[CGD_STAGE_COMBINE] = 16.0 * (c->ncontrib + 2 * c->npts);
 
     // uploads
@@ -1786,10 +1927,17 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         HIP_OK(hipMalloc((void **)&c->d_htable, sizeof(double2) * c->hess_ntab));
     }
     const int64_t nc = std::max<int64_t>(c->ncontrib, 1), np = std::max<int64_t>(c->npts, 1);
+    const int64_t ntab = std::max<int64_t>(c->ntab, 1);
     HIP_OK(hipMalloc((void **)&c->d_contrib, sizeof(double2) * nc));
     HIP_OK(hipMalloc((void **)&c->d_logg, sizeof(double2) * np));
-    HIP_OK(hipMalloc((void **)&c->d_gA, sizeof(double2) * np));
-    HIP_OK(hipMalloc((void **)&c->d_gB, sizeof(double2) * np));
+    HIP_OK(hipMalloc((void **)&c->d_gA, sizeof(double2) * ntab));
+    HIP_OK(hipMalloc((void **)&c->d_gB, sizeof(double2) * ntab));
+    HIP_OK(hipMalloc((void **)&c->d_tpool, sizeof(double2) * std::max<int64_t>(c->ntpool, 1)));
+    if (!c->dinst.empty()) {
+        if ((s = upload(&c->d_dinst, c->dinst)) != CGD_OK) return s;
+        if ((s = upload(&c->d_dprefix, c->dprefix)) != CGD_OK) return s;
+        if ((s = upload(&c->d_hprefix, c->hprefix)) != CGD_OK) return s;
+    }
     HIP_OK(hipMalloc((void **)&c->d_status, sizeof(int)));
     HIP_OK(hipMemset(c->d_status, 0, sizeof(int)));
     HIP_OK(hipHostMalloc((void **)&c->h_status, sizeof(int), hipHostMallocDefault));
@@ -1884,25 +2032,26 @@ struct EvalBufs {
     int *counts, *cut;
     unsigned long long *hist;
     int2 *list;
+    double2 *tpool;
 };
 
 EvalBufs ctx_bufs(const cgd_ctx *c) {
     return EvalBufs{c->d_contrib, c->d_logg, c->d_gA, c->d_gB, c->d_logg32, c->d_eigc, c->d_htable,
-                    c->d_counts, c->d_cut, c->d_hist, c->d_list};
+                    c->d_counts, c->d_cut, c->d_hist, c->d_list, c->d_tpool};
 }
 
 // Byte sizes of the EvalBufs fields in field order (0: not used by this context).
-constexpr int kEvalBufs = 11;
+constexpr int kEvalBufs = 12;
 void eval_buf_sizes(const cgd_ctx *c, size_t (&sz)[kEvalBufs]) {
     const bool mixed = c->prec == CGD_PREC_MIXED;
     const bool hess = !c->hess_all.empty();
     const size_t cz = sizeof(double2);
-    const size_t v[kEvalBufs] = {cz * (size_t)c->ncontrib, cz * (size_t)c->npts, cz * (size_t)c->npts,
-                                 cz * (size_t)c->npts, mixed ? cz * (size_t)c->npts : 0,
+    const size_t v[kEvalBufs] = {cz * (size_t)c->ncontrib, cz * (size_t)c->npts, cz * (size_t)c->ntab,
+                                 cz * (size_t)c->ntab, mixed ? cz * (size_t)c->npts : 0,
                                  hess ? cz * (size_t)c->hess_nec : 0, hess ? cz * (size_t)c->hess_ntab : 0,
                                  mixed ? sizeof(int) * kG64 : 0, mixed ? sizeof(int) * (size_t)c->n_inst : 0,
                                  mixed ? sizeof(unsigned long long) * (size_t)c->n_inst * kMixedBuckets : 0,
-                                 mixed ? sizeof(int2) * (size_t)c->list_total : 0};
+                                 mixed ? sizeof(int2) * (size_t)c->list_total : 0, cz * (size_t)c->ntpool};
     for (int i = 0; i < kEvalBufs; ++i) sz[i] = v[i];
 }
 
@@ -1961,7 +2110,7 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
     auto launch64 = [&](int k, const int2 *list, const int *count, int64_t cap) -> hipError_t {
         const LuClass &g = c->g64[k];
         LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, list, count, cap, c->d_blocks,
-                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status};
+                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool};
         return k < kRegClasses ? launch_lu_reg(k, c->reg_var[k], a, st)
                                : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
     };
@@ -1969,7 +2118,7 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         for (auto &g : c->g32) {
             if (g.nitems == 0) continue;
             LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, nullptr, nullptr, 0, c->d_blocks,
-                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status};
+                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool};
             HIP_OK(mark_begin(lu_stage(g.cls)));
             HIP_OK(launch_lu_mfma(g.cls, c->mfma_var[g.cls], a, st));
             HIP_OK(mark(lu_stage(g.cls), 1));
@@ -2004,6 +2153,12 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
                               st));
         HIP_OK(mark(CGD_STAGE_COMBINE, 1));
     }
+    if (c->dnpts > 0) {
+        HIP_OK(mark(CGD_STAGE_DENSITY, 0));
+        HIP_OK(launch_density_expand(c->d_inst, c->d_dinst, c->d_dprefix, (int)c->dinst.size(), c->dnpts,
+                                     c->dens_lds, c->d_blocks, c->d_rb, b.contrib, b.tpool, b.logg, b.gA, st));
+        HIP_OK(mark(CGD_STAGE_DENSITY, 1));
+    }
     HIP_OK(mark(CGD_STAGE_DFT, 0));
     for (size_t si = 0; si < c->stages.size(); ++si) {
         DftStage &S = c->stages[si];
@@ -2013,6 +2168,12 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
                                 mixed ? nullptr : d_err_bound, c->d_status, st));
     }
     HIP_OK(mark(CGD_STAGE_DFT, 1));
+    if (c->htotal > 0) {
+        HIP_OK(mark(CGD_STAGE_DENSITY, 0));
+        HIP_OK(launch_density_hermitize(c->d_inst, c->d_dinst, c->d_hprefix, (int)c->dinst.size(), c->htotal, b.gA,
+                                        b.gB, d_probs, st));
+        HIP_OK(mark(CGD_STAGE_DENSITY, 1));
+    }
     if (mixed) HIP_OK(launch_mixed_err(c->d_inst, c->n_inst, b.logg32, b.cut, d_err_bound, c->d_status, st));
     return CGD_OK;
 }
@@ -2082,7 +2243,7 @@ cgd_status cgd_eval_static(cgd_ctx *c, double *d_probs, double *d_err_bound) {
                                      " bytes of the static array");
     const EvalBufs b{(double2 *)ptr[0], (double2 *)ptr[1], (double2 *)ptr[2], (double2 *)ptr[3], (double2 *)ptr[4],
                      (double2 *)ptr[5], (double2 *)ptr[6], (int *)ptr[7], (int *)ptr[8],
-                     (unsigned long long *)ptr[9], (int2 *)ptr[10]};
+                     (unsigned long long *)ptr[9], (int2 *)ptr[10], (double2 *)ptr[11]};
     // eager launches on the context's stream (no graph to instantiate, no timing events)
     const bool timing = c->timing;
     c->timing = false;

@@ -31,7 +31,11 @@ struct InstDev {
                               // w = exp(t), t = rho exp(2 pi i k / G) on a circle of radius rho
     double tau;               // mixed path: relative error bound assumed for an FP32 value of G (0: no FP32 block)
     int32_t dft_log;          // 1: the DFT takes log G instead of G (cumulants)
-    int32_t pad4;
+    int32_t nvar;             // density mode: 2 g generating-function variables of the g kept modes (0: off)
+    int32_t fock_n;           // density mode: Fock cutoff N of every kept mode
+    int32_t pad5;
+    int64_t E;                // values per evaluated point: (N + 1)^(2 g) in density mode, else 1
+    int64_t gv_off;           // first value of this instance in the per-point value table (and DFT buffers)
 };
 
 // One factorisation job family: an (instance, internal block) pair.  Every
@@ -52,6 +56,10 @@ struct BlockDev {
     int64_t eig_off;          // offset of the eliminated bin's eigenvalues
     int32_t cls;              // FP64 size class: register classes 0..kRegClasses-1, kRegClasses = blocked
     int32_t fp32;             // mixed path: 1 if the first pass factorises this block in FP32
+    int32_t nkeep;            // density mode: rows of the kept-mode border (2 g_k), before the gamma border
+    int32_t pad;
+    int64_t t_off;            // density mode: trailing Schur complement (nkeep + bordered)^2 per point
+    int64_t kv_off;           // density mode: nkeep generating-function variable indices (in rbpool)
 };
 
 // Build of the Schur matrices C(w_A) = H_BB + P diag(w_A / (1 - w_A lambda)) Q
@@ -137,6 +145,7 @@ struct AdjArgs {
 struct DftStageDev {
     int32_t inst, K, Bout, G;
     int32_t final_stage, moments;  // moments: scale output index b by b! / rho^b (Taylor coefficient -> derivative)
+    int32_t density, pad;          // density mode: complex output to `out`, half-grid weights already applied
     int64_t outer, inner, in_off, out_off;
     int64_t tw_off;           // exp(-2 pi i m / G), m = 0 .. G-1, in the twiddle pool
     double scale;
@@ -158,6 +167,7 @@ struct LuLaunch {
     const double *eigpool;
     double2 *contrib;
     int *status;
+    double2 *tpool;            // density mode: trailing Schur complements
 };
 
 // launchers (cgd_kernels.hip)
@@ -220,6 +230,17 @@ hipError_t launch_hess_scatter(const HessDev *jobs, const int64_t *prefix, int n
 int schur_rows_per_wg();
 hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, int n_inst, int64_t npts,
                           const double2 *contrib, double2 *logg, double2 *gval, hipStream_t st);
+// density mode: per point, the kept modes' generating function from the
+// trailing Schur complements, expanded into the (N+1)^(2g) matrix elements
+constexpr int kMaxKeepVars = 16;
+constexpr int64_t kDensityLdsValues = 4096;
+hipError_t launch_density_expand(const InstDev *insts, const int32_t *dinst, const int64_t *dprefix, int nd,
+                                 int64_t npts, int64_t lds_values, const BlockDev *blocks, const int32_t *rbpool,
+                                 const double2 *contrib, const double2 *tpool, double2 *logg, double2 *table,
+                                 hipStream_t st);
+hipError_t launch_density_hermitize(const InstDev *insts, const int32_t *dinst, const int64_t *dprefix, int nd,
+                                    int64_t total, const double2 *bufA, const double2 *bufB, double *out,
+                                    hipStream_t st);
 hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total, const double2 *tw,
                             const double2 *in, double2 *out, double *probs, double *err, const int *status,
                             hipStream_t st);

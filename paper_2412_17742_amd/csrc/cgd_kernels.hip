@@ -181,6 +181,7 @@ struct LuArgs {
     const double *eigpool;
     double2 *contrib;
     int *status;
+    double2 *tpool;           // density mode: trailing Schur complements (nkeep + bordered)^2 per point
 };
 
 template <typename T, int PR, int PC, int TR, int TC>
@@ -220,6 +221,10 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
         const BlockDev B = A.blocks[bi];
         const InstDev &I = A.insts[B.inst];
         const int nb = B.nb;
+        // pivots of S; a density-mode block stops there and keeps the trailing
+        // (kept-mode and displacement) border as its Schur complement
+        const int nS = nb - B.bordered - B.nkeep;
+        const int nstop = B.nkeep ? nS : nb;
 
         if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
         if (tid == 0) s_bad = 0;
@@ -256,7 +261,7 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
         #pragma unroll
         for (int r = 0; r < TR; ++r) {
             const int cown = (r * PR) / PC;
-            int kend = nb - r * PR;
+            int kend = nstop - r * PR;
             kend = kend < 0 ? 0 : (kend > PR ? PR : kend);
             for (int kk = 0; kk < kend; ++kk) {
                 const int k = r * PR + kk;
@@ -272,7 +277,7 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
                             const C d = a[r][c];
                             s_piv[k] = d;
                             // pivots of S lie in the right half-plane; the border's (1 - 2E) need not
-                            if (!isfinite(d.x) || !isfinite(d.y) || (k < nb - B.bordered && !(d.x > T(0)))) s_bad = 1;
+                            if (!isfinite(d.x) || !isfinite(d.y) || (k < nS && !(d.x > T(0)))) s_bad = 1;
                         }
                     }
                 }
@@ -301,9 +306,25 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
             }
         }
         __syncthreads();
+        if (B.nkeep) {
+            // density mode: the trailing (nkeep + bordered)^2 Schur complement, each
+            // thread from its own registers
+            const int nt = nb - nS;
+            double2 *__restrict__ Tout = A.tpool + B.t_off + pt * (int64_t)(nt * nt);
+            #pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                const int i = r * PR + ty;
+                #pragma unroll
+                for (int c = 0; c < TC; ++c) {
+                    const int j = c * PC + tx;
+                    if (i >= nS && j >= nS && i < nb && j < nb)
+                        Tout[(i - nS) * nt + (j - nS)] = cmk((double)a[r][c].x, (double)a[r][c].y);
+                }
+            }
+        }
 
         // epilogue: -1/2 [sum_i Log(pivot_i) + sum_i Log(1 - w_A lambda_i)] + E, in FP64
-        const int nlog = nb - B.bordered;
+        const int nlog = nS;
         double2 acc = cmk(0.0, 0.0);
         for (int i = tid; i < nlog; i += NT) {
             const double2 lg = clog(cmk((double)s_piv[i].x, (double)s_piv[i].y));
@@ -322,7 +343,7 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
         acc = block_sum<NT>(acc, s_red);
         if (tid == 0) {
             double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
-            if (B.bordered) {
+            if (B.bordered && !B.nkeep) {
                 const C p = s_piv[nb - 1];
                 res.x += 0.5 * (1.0 - (double)p.x);
                 res.y += 0.5 * (0.0 - (double)p.y);
@@ -1778,6 +1799,7 @@ __global__ void combine_points(const InstDev *__restrict__ insts, const int64_t 
     if (p >= npts_total) return;
     const int i = find_job(inst_pt_prefix, n_inst, p);
     const InstDev &I = insts[i];
+    if (I.nvar) return;  // density mode: density_expand writes log G and the point's values
     const int64_t lp = p - I.pt_off;
     double2 acc = cmk(I.logpr0_re, I.logpr0_im);
     const double2 *c = contrib + I.c_off + lp * I.nblocks;
@@ -1787,13 +1809,13 @@ __global__ void combine_points(const InstDev *__restrict__ insts, const int64_t 
     }
     logg[p] = acc;
     if (I.dft_log) {  // cumulants: the DFT takes log G itself
-        gval[p] = acc;
+        gval[I.gv_off + lp] = acc;
         return;
     }
     double s, co;
     sincos(acc.y, &s, &co);
     const double m = exp(acc.x);
-    gval[p] = cmk(m * co, m * s);
+    gval[I.gv_off + lp] = cmk(m * co, m * s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1823,7 +1845,7 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
     const double2 *tw = twpool + S.tw_off;
     double2 acc = cmk(0.0, 0.0);
     auto term = [&](int k, double2 v, double2 t) {
-        if (S.final_stage) {
+        if (S.final_stage && !S.density) {
             const double wk = (k == 0 || 2 * k == S.G) ? 1.0 : 2.0;
             v.x *= wk;
             v.y *= wk;
@@ -1864,12 +1886,179 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
         acc.x *= f;
         acc.y *= f;
     }
-    if (S.final_stage) {
+    if (S.final_stage && !S.density) {
         probs[S.out_off + lq] = acc.x * S.scale;
+        if (lq == 0 && err) err[S.inst] = (*status) ? INFINITY : 0.0;
+    } else if (S.final_stage) {  // density mode: R = (1/prod G) sum over the half grid, complex
+        out[S.out_off + lq] = cmk(acc.x * S.scale, acc.y * S.scale);
         if (lq == 0 && err) err[S.inst] = (*status) ? INFINITY : 0.0;
     } else {
         out[S.out_off + lq] = acc;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Density mode (heralded states, Sec. VII).
+//
+// The heralding and traced rows of each internal block are eliminated per
+// grid point as for probabilities; the kept modes' rows of A (and the loop
+// vector) form a border of 2 g_k (+ 1) rows whose trailing Schur complement
+// T is written by the LU kernel.  With the border built as
+//     H'' = [[H_HH, -H_HG, -X gamma_H], [-A_GH, A_GG, gamma_G], [-gamma_H^T, gamma_G^T, 0]],
+// S'' = I - diag(d) H'' has T = I - H''_BB - Gamma^T S^-1 D X Gamma with
+// Gamma = [A_HG | gamma_H], so the generating function of the kept modes'
+// matrix elements at this point,
+//     sum_{u,v} <v|rho_G(w)|u> x^u y^v / sqrt(u! v!)
+//         = G_H(w) exp(l^T c + 1/2 c^T Q c),   c = (y, x),
+// (the master theorem, Eq. lhaf_master, on the heralding block with the
+// c-dependent loop vector gamma_H + A_HG c) has Q = I - T_GG, l = -T_Ggamma and
+// G_H(w) = Pr(0) prod_blocks det(S)^-1/2 exp(E), E = (1 - T_gammagamma) / 2.
+//
+// density_expand: one workgroup per evaluated point.  The normalised
+// coefficients b_s = sqrt(s!) [c^s] (G_H exp(l^T c + 1/2 c^T Q c)) -- which
+// are the matrix elements themselves -- satisfy (from d/dc_i of the
+// exponential)
+//     sqrt(s_i) b_s = l_i b_{s - e_i} + sum_j Q_ij sqrt(s_j - delta_ij) b_{s - e_i - e_j}
+// for any i with s_i > 0.  Taking i as the first non-zero position of s
+// (positions v_1..v_g, u_1..u_g, the last fastest in memory), every term on
+// the right has the same leading zeros and only positions j >= i matter
+// (s_j = 0 for j < i); the elements with first non-zero position i and s_i = t
+// depend only on s_i = t - 1, t - 2 and on later positions, so positions are
+// filled from the last one back, t = 1..N in order, the (N+1)^(2g-1-i)
+// elements of each (i, t) in parallel.  b_0 = G_H(w) c_k / 2 folds in the
+// half-grid weight (see density_hermitize).  Values stay in LDS when they
+// fit, else in the output table itself.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) density_expand(const InstDev *__restrict__ insts,
+                                                      const int32_t *__restrict__ dinst,
+                                                      const int64_t *__restrict__ dprefix, int nd, int64_t lds_values,
+                                                      const BlockDev *__restrict__ blocks,
+                                                      const int32_t *__restrict__ rbpool,
+                                                      const double2 *__restrict__ contrib,
+                                                      const double2 *__restrict__ tpool, double2 *__restrict__ logg,
+                                                      double2 *__restrict__ table)
+{
+    extern __shared__ double2 s_vals[];
+    __shared__ double2 s_Q[kMaxKeepVars][kMaxKeepVars];
+    __shared__ double2 s_l[kMaxKeepVars];
+    __shared__ double2 s_acc;
+    const int tid = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    const int j0 = find_job(dprefix, nd, item);
+    const InstDev &I = insts[dinst[j0]];
+    const int64_t lp = item - dprefix[j0];
+    const int nv = I.nvar;
+    const int64_t E = I.E;
+    const int N1 = I.fock_n + 1;
+    for (int e = tid; e < kMaxKeepVars * kMaxKeepVars; e += blockDim.x) s_Q[e / kMaxKeepVars][e % kMaxKeepVars] = cmk(0.0, 0.0);
+    if (tid < kMaxKeepVars) s_l[tid] = cmk(0.0, 0.0);
+    if (tid == 0) {
+        double2 acc = cmk(I.logpr0_re, I.logpr0_im);
+        const double2 *c = contrib + I.c_off + lp * I.nblocks;
+        for (int b = 0; b < I.nblocks; ++b) {
+            acc.x += c[b].x;
+            acc.y += c[b].y;
+            const BlockDev &B = blocks[I.first_block + b];
+            if (B.nkeep && B.bordered) {  // E = (1 - T_gammagamma) / 2
+                const int nt = B.nkeep + 1;
+                const double2 tg = tpool[B.t_off + lp * nt * nt + (int64_t)B.nkeep * nt + B.nkeep];
+                acc.x += 0.5 * (1.0 - tg.x);
+                acc.y -= 0.5 * tg.y;
+            }
+        }
+        s_acc = acc;
+    }
+    __syncthreads();
+    // Q = I - T_GG and l = -T_Ggamma per block, symmetrised, at the blocks' variable positions
+    for (int b = 0; b < I.nblocks; ++b) {
+        const BlockDev &B = blocks[I.first_block + b];
+        if (!B.nkeep) continue;
+        const int nk = B.nkeep, nt = nk + B.bordered;
+        const double2 *__restrict__ T = tpool + B.t_off + lp * nt * nt;
+        const int32_t *__restrict__ kv = rbpool + B.kv_off;
+        for (int e = tid; e < nk * nk; e += blockDim.x) {
+            const int a = e / nk, c = e % nk;
+            const double2 t1 = T[a * nt + c], t2 = T[c * nt + a];
+            s_Q[kv[a]][kv[c]] = cmk((a == c ? 1.0 : 0.0) - 0.5 * (t1.x + t2.x), -0.5 * (t1.y + t2.y));
+        }
+        if (B.bordered)
+            for (int a = tid; a < nk; a += blockDim.x) {
+                const double2 t1 = T[a * nt + nk], t2 = T[nk * nt + a];
+                s_l[kv[a]] = cmk(-0.5 * (t1.x + t2.x), -0.5 * (t1.y + t2.y));
+            }
+    }
+    double2 *__restrict__ gout = table + I.gv_off + lp * E;
+    double2 *__restrict__ buf = E <= lds_values ? s_vals : gout;
+    if (tid == 0) {
+        const double2 acc = s_acc;
+        logg[I.pt_off + lp] = acc;
+        const int k1 = point_k(I, lp, 0);
+        const double wk = (k1 == 0 || 2 * k1 == I.G[0]) ? 0.5 : 1.0;
+        double sn, cs;
+        sincos(acc.y, &sn, &cs);
+        const double m = wk * exp(acc.x);
+        buf[0] = cmk(m * cs, m * sn);
+    }
+    __syncthreads();
+    int64_t st_i = 1;  // stride of position i: N1^(nv - 1 - i)
+    for (int i = nv - 1; i >= 0; --i) {
+        const double2 li = s_l[i];
+        const double2 qii = s_Q[i][i];
+        for (int t = 1; t < N1; ++t) {
+            const double rt = 1.0 / sqrt((double)t);
+            const double sq1 = sqrt((double)(t - 1));
+            for (int64_t r = tid; r < st_i; r += blockDim.x) {
+                const int64_t e = t * st_i + r;
+                double2 acc = cmul(li, buf[e - st_i]);
+                if (t >= 2) {
+                    const double2 q = cmk(qii.x * sq1, qii.y * sq1);
+                    acc = cfma(q, buf[e - 2 * st_i], acc);
+                }
+                int64_t rr = r, st_j = 1;
+                for (int jj = nv - 1; jj > i; --jj) {
+                    const int sj = (int)(rr % N1);
+                    rr /= N1;
+                    if (sj) {
+                        const double f = sqrt((double)sj);
+                        const double2 q = s_Q[i][jj];
+                        acc = cfma(cmk(q.x * f, q.y * f), buf[e - st_i - st_j], acc);
+                    }
+                    st_j *= N1;
+                }
+                buf[e] = cmk(acc.x * rt, acc.y * rt);
+            }
+            __syncthreads();
+        }
+        st_i *= N1;
+    }
+    if (buf != gout)
+        for (int64_t e = tid; e < E; e += blockDim.x) gout[e] = s_vals[e];
+}
+
+// rho(b~) = R + R^H per heralding pattern, with R the inverse DFT over the
+// half grid (weights c_k / 2): the points w and conj(w) carry conjugate
+// transposes of each other, rho_G(conj w) = rho_G(w)^H.  One thread per
+// output element; R is in the buffer the instance's last DFT stage wrote.
+__global__ void density_hermitize(const InstDev *__restrict__ insts, const int32_t *__restrict__ dinst,
+                                  const int64_t *__restrict__ dprefix, int nd, int64_t total,
+                                  const double2 *__restrict__ bufA, const double2 *__restrict__ bufB,
+                                  double *__restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int j0 = find_job(dprefix, nd, q);
+    const InstDev &I = insts[dinst[j0]];
+    const int64_t lq = q - dprefix[j0];
+    const int64_t E = I.E;
+    int64_t D = 1;
+    for (int k = 0; k < I.nvar / 2; ++k) D *= I.fock_n + 1;
+    const int64_t b = lq / E, e = lq % E;
+    const int64_t v = e / D, u = e % D;
+    // stage s (0-based) writes bufB when s is even; the last stage of an instance is s = L - 1
+    const double2 *__restrict__ R = ((I.L - 1) % 2 == 0 ? bufB : bufA) + I.gv_off + b * E;
+    const double2 x = R[v * D + u], y = R[u * D + v];
+    double2 *o = (double2 *)(out + I.prob_off) + lq;
+    *o = cmk(x.x + y.x, x.y - y.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -2271,7 +2460,7 @@ __global__ void mixed_err(const InstDev *__restrict__ insts, const double2 *__re
 template <int PR, int PC, int TR, int TC>
 static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
     // one item per workgroup; for a device-built list the grid covers its capacity and
     // workgroups past the list's length return at once
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
@@ -2323,7 +2512,7 @@ hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
 template <int NTILE, int WR, int WC>
 static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC>), dim3((unsigned)grid), dim3(64 * WR * WC),
@@ -2425,6 +2614,26 @@ hipError_t launch_combine(const InstDev *insts, const int64_t *inst_pt_prefix, i
     if (npts <= 0) return hipSuccess;
     hipLaunchKernelGGL(combine_points, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, insts,
                        inst_pt_prefix, n_inst, npts, contrib, logg, gval);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_expand(const InstDev *insts, const int32_t *dinst, const int64_t *dprefix, int nd,
+                                 int64_t npts, int64_t lds_values, const BlockDev *blocks, const int32_t *rbpool,
+                                 const double2 *contrib, const double2 *tpool, double2 *logg, double2 *table,
+                                 hipStream_t st) {
+    if (npts <= 0) return hipSuccess;
+    if (lds_values < 0 || lds_values > kDensityLdsValues) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(density_expand, dim3((unsigned)npts), dim3(256), sizeof(double2) * (size_t)lds_values, st,
+                       insts, dinst, dprefix, nd, lds_values, blocks, rbpool, contrib, tpool, logg, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_hermitize(const InstDev *insts, const int32_t *dinst, const int64_t *dprefix, int nd,
+                                    int64_t total, const double2 *bufA, const double2 *bufB, double *out,
+                                    hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(density_hermitize, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, insts, dinst,
+                       dprefix, nd, total, bufA, bufB, out);
     return hipGetLastError();
 }
 
@@ -2611,7 +2820,9 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          hipFuncSetAttribute((const void *)hess_reduce_f64<32, 16, 5, 9>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(HessLds<32, 16, 5, 9>)),
                          hipFuncSetAttribute((const void *)hess_det_f64<9>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             hess_det_lds_bytes(9))})
+                                             hess_det_lds_bytes(9)),
+                         hipFuncSetAttribute((const void *)density_expand, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(sizeof(double2) * kDensityLdsValues))})
         if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<2, 1, 1>(), prepare_mfma<2, 2, 2>(),
                          prepare_mfma<4, 2, 2>(), prepare_mfma<4, 1, 2>(), prepare_mfma<4, 1, 1>(),

@@ -81,3 +81,28 @@ def test_automatic_grid_needs_a_finite_tolerance():
     inst["grid"] = np.array([0, 5], np.int32)  # the explicit entry is still checked
     st, h, msg = _create(inst, tol=1e-9)
     assert st == cgd.CGD_ERR_ARG and "grid" in msg, msg
+
+
+def test_density_mode_arguments_are_checked_before_the_device():
+    """Kept modes (bin CGD_KEEP): FP64 only, no gradient or moments flags,
+    valid bin codes and Fock cutoffs, at most 2^22 matrix elements per point."""
+    base = W.gkp_like(0.9, 0.95)
+    bad = [
+        (dict(prec=cgd.PREC_MIXED), "FP64"),
+        (dict(flags=cgd.FLAG_GRAD), "FP64"),
+        (dict(flags=cgd.FLAG_MOMENTS), "FP64"),
+    ]
+    for kw, word in bad:
+        st, h, msg = _create(base, **kw)
+        assert st == cgd.CGD_ERR_ARG and word in msg, msg
+        assert h.value is None
+    for mutate, word in [
+        (lambda x: x["bin_of"].__setitem__(0, -3), "bin index"),
+        (lambda x: x.update(fock_cutoff=-1), "fock_cutoff"),
+        (lambda x: x.update(fock_cutoff=4095), "2^22"),
+        (lambda x: x.update(bin_of=np.full(6, cgd.KEEP, np.int32)), "kept modes"),  # 2g = 12 but N = 26
+    ]:
+        x = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+        mutate(x)
+        st, h, msg = _create(x)
+        assert st == cgd.CGD_ERR_ARG and (word in msg or "2^22" in msg), msg

@@ -137,3 +137,23 @@ def test_automatic_grid_needs_a_tolerance():
     with pytest.raises(cgd.CgdError) as e:
         cgd.Context([x], tol=0.0)
     assert e.value.status == cgd.CGD_ERR_ARG
+
+
+def test_bins_with_coherent_light_only():
+    """A bin that holds coherent light only has a moment generating function
+    finite for every s (Poisson: E[s^b] = exp((s - 1) mu)); its tail bound
+    must still be minimised, not taken as zero.  Two coherent modes on a lossy
+    interferometer: each bin count is Poisson with mean |beta_l|^2, and the
+    automatic grid must give that law within the reported bound."""
+    import math
+    rng = W.rng_for(322)
+    T = np.sqrt(0.8) * W.haar_unitary(2, rng)
+    alpha = np.array([1.3 - 0.4j, -0.5 + 1.1j])
+    x = W.make_instance(T, np.zeros(2), alpha=alpha, bin_of=[0, 1], cutoff=[4, 5], grid=[0, 0])
+    (P,), (grid,), wrap = _eval([x], tol=1e-12)
+    mu = np.abs(T @ alpha) ** 2
+    pois = [np.array([math.exp(-m) * m ** k / math.factorial(k) for k in range(n + 1)]) for m, n in zip(mu, (4, 5))]
+    tail = sum(1.0 - sum(math.exp(-m) * m ** k / math.factorial(k) for k in range(g)) for m, g in zip(mu, grid))
+    _say(f"  grid {grid}, reported bound {wrap[0]:.2e}, true tail {tail:.2e}")
+    assert wrap[0] >= tail and wrap[0] <= 1e-12 / 10 * 1.0001
+    assert np.abs(P - np.outer(pois[0], pois[1])).max() <= wrap[0] + 1e-14
