@@ -233,6 +233,31 @@ def total_photon_sweep(cgd, steps, warmup, tol):
     return out
 
 
+def heralded_density(cgd, steps, warmup):
+    """Density matrices of heralded states (Sec. VII) in the shape of the
+    paper's approximate-GKP setup (three squeezed inputs, two spectral modes,
+    heralding pattern (5, 7) on two ports, Fock cutoff 26 on the kept mode;
+    seeded squeezing and unitary): one state, and the 50 x 50 map over
+    (p, eta) in one context.  Every pattern of the heralding box comes out of
+    one evaluation.  The paper's CPU time for one such density matrix at
+    cutoff 26 (64-core EPYC) is context only."""
+    import torch
+    out = {}
+    for name, insts in (("gkp_like_one", [W.gkp_like(0.9, 0.95)]), ("gkp_like_map_50x50", W.gkp_like_map(50))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with cgd.Context(insts, precision="fp64") as ctx:
+            create_s = time.perf_counter() - t0
+            ms, _, _ = run(ctx, steps, warmup)
+            stages = stage_profile(ctx, max(1, min(steps, 5)))
+            elems = sum(int(np.prod(sh)) * d * d for sh, d in zip(ctx.shapes, ctx.density_dims))
+            out[name] = {"instances": len(insts), "create_s": create_s, "ms_per_eval": ms,
+                         "evaluated_points": ctx.n_points, "matrix_elements": elems,
+                         "elements_per_s": elems / (ms * 1e-3), "stage_ms": stages}
+    out["gkp_like_one"]["paper_cpu_s"] = 0.97
+    return out
+
+
 def exact_box(cgd, insts, tol, wrap_stated):
     """Wrap of the stated grid (bound on P_wrap - Pr over the box) and, when it
     exceeds tol, the automatic grid (cgd grid entries 0) that brings it below
@@ -409,6 +434,7 @@ def main():
                                                               grad=name == "mesh32_k4")
     if not args.no_extra:
         out["total_photon"] = total_photon_sweep(cgd, args.steps, args.warmup, args.tol)
+        out["heralded_density"] = heralded_density(cgd, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(instances, args.cpu_seconds)
         out["cpu_baseline"]["one_core"] = cpu_baseline(instances, args.cpu_seconds, threads=1)

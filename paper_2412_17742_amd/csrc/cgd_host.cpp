@@ -624,6 +624,12 @@ struct DftStage {
     int64_t total = 0;
     DftStageDev *d_desc = nullptr;
     int64_t *d_prefix = nullptr;
+    // descriptors with extent K <= kDftColsK (dft_cols: one thread per column)
+    std::vector<DftStageDev> cdesc;
+    std::vector<int64_t> cprefix;
+    int64_t ctotal = 0;
+    DftStageDev *d_cdesc = nullptr;
+    int64_t *d_cprefix = nullptr;
 };
 
 }  // namespace
@@ -671,10 +677,10 @@ struct cgd_ctx {
     int64_t nprobs = 0, npts = 0, ngrid = 0, ncontrib = 0;
     int64_t ntab = 0;                  // values per evaluation: sum_i points_i * E_i
     // density mode: instances with kept modes, prefix of their points and of
-    // their output elements, trailing Schur complement pool
+    // their output matrices (one per heralding pattern), trailing Schur complement pool
     std::vector<int32_t> dinst;
     std::vector<int64_t> dprefix, hprefix;
-    int64_t dnpts = 0, htotal = 0, ntpool = 0, dens_lds = 0;
+    int64_t dnpts = 0, htotal = 0, nmat = 0, ntpool = 0, dens_lds = 0;
     int32_t *d_dinst = nullptr;
     int64_t *d_dprefix = nullptr, *d_hprefix = nullptr;
     double2 *d_tpool = nullptr;
@@ -752,7 +758,7 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
-    for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); }
+    for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); fr(s.d_cdesc); fr(s.d_cprefix); }
     fr(c->d_tw);
     for (auto &s : c->adj_stages) { fr(s.d_desc); fr(s.d_prefix); }
     for (auto &h : c->hcls) { fr(h.d_jobs); fr(h.d_rprefix); fr(h.d_dprefix); }
@@ -1548,7 +1554,7 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     c->dinst.clear();
     c->dprefix.clear();
     c->hprefix.clear();
-    c->dnpts = c->htotal = 0;
+    c->dnpts = c->htotal = c->nmat = 0;
     c->dens_lds = 0;
     for (int i = 0; i < n_inst; ++i) {
         InstDev &d = c->inst[i];
@@ -1576,9 +1582,10 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             po += po & 1;  // complex output: even offset
             c->dinst.push_back(i);
             c->dprefix.push_back(c->dnpts);
-            c->hprefix.push_back(c->htotal);
+            c->hprefix.push_back(c->nmat);
             c->dnpts += np;
             c->htotal += nprob * d.E;
+            c->nmat += nprob;
             if (d.E <= kDensityLdsValues) c->dens_lds = std::max(c->dens_lds, d.E);
             nprob *= 2 * d.E;
         }
@@ -1843,9 +1850,15 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             d.scale = 1.0 / gprod;
             d.moments = I.rho > 0.0 ? 1 : 0;
             d.rho = I.rho;
-            st.prefix.push_back(st.total);
-            st.total += d.outer * d.Bout * d.inner;
-            st.desc.push_back(d);
+            if (d.K <= kDftColsK) {
+                st.cprefix.push_back(st.ctotal);
+                st.ctotal += d.outer * d.inner;
+                st.cdesc.push_back(d);
+            } else {
+                st.prefix.push_back(st.total);
+                st.total += d.outer * d.Bout * d.inner;
+                st.desc.push_back(d);
+            }
         }
     }
 
@@ -1873,8 +1886,10 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         }
         c->work_flops[CGD_STAGE_PAIR] += f * pd.dA * pd.dP;
     }
-    for (const DftStage &st : c->stages)
+    for (const DftStage &st : c->stages) {
         for (const DftStageDev &d : st.desc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
+        for (const DftStageDev &d : st.cdesc) c->work_flops[CGD_STAGE_DFT] += 8.0 * d.outer * d.Bout * d.inner * d.K;
+    }
     c->work_bytes[CGD_STAGE_DFT] = 16.0 * c->ntab + 8.0 * c->nprobs;
     for (int j : c->dinst) {
         // per value: one complex multiply for l, one per later position, of the
@@ -1914,6 +1929,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     for (auto &st : c->stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
+        if ((s = upload(&st.d_cdesc, st.cdesc)) != CGD_OK) return s;
+        if ((s = upload(&st.d_cprefix, st.cprefix)) != CGD_OK) return s;
     }
     if (!c->hess_all.empty()) {
         for (auto &hc : c->hcls) {
@@ -2164,14 +2181,16 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         DftStage &S = c->stages[si];
         const double2 *in = (si % 2 == 0) ? b.gA : b.gB;
         double2 *out = (si % 2 == 0) ? b.gB : b.gA;
+        HIP_OK(launch_dft_cols(S.d_cdesc, S.d_cprefix, (int)S.cdesc.size(), S.ctotal, c->d_tw, in, out, d_probs,
+                               mixed ? nullptr : d_err_bound, c->d_status, st));
         HIP_OK(launch_dft_stage(S.d_desc, S.d_prefix, (int)S.desc.size(), S.total, c->d_tw, in, out, d_probs,
                                 mixed ? nullptr : d_err_bound, c->d_status, st));
     }
     HIP_OK(mark(CGD_STAGE_DFT, 1));
     if (c->htotal > 0) {
         HIP_OK(mark(CGD_STAGE_DENSITY, 0));
-        HIP_OK(launch_density_hermitize(c->d_inst, c->d_dinst, c->d_hprefix, (int)c->dinst.size(), c->htotal, b.gA,
-                                        b.gB, d_probs, st));
+        HIP_OK(launch_density_hermitize(c->d_inst, c->d_dinst, c->d_hprefix, (int)c->dinst.size(), c->nmat,
+                                        c->dens_lds, b.gA, b.gB, d_probs, st));
         HIP_OK(mark(CGD_STAGE_DENSITY, 1));
     }
     if (mixed) HIP_OK(launch_mixed_err(c->d_inst, c->n_inst, b.logg32, b.cut, d_err_bound, c->d_status, st));

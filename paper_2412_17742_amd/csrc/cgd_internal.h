@@ -238,9 +238,14 @@ hipError_t launch_density_expand(const InstDev *insts, const int32_t *dinst, con
                                  int64_t npts, int64_t lds_values, const BlockDev *blocks, const int32_t *rbpool,
                                  const double2 *contrib, const double2 *tpool, double2 *logg, double2 *table,
                                  hipStream_t st);
-hipError_t launch_density_hermitize(const InstDev *insts, const int32_t *dinst, const int64_t *dprefix, int nd,
-                                    int64_t total, const double2 *bufA, const double2 *bufB, double *out,
-                                    hipStream_t st);
+hipError_t launch_density_hermitize(const InstDev *insts, const int32_t *dinst, const int64_t *mprefix, int nd,
+                                    int64_t nmat, int64_t lds_values, const double2 *bufA, const double2 *bufB,
+                                    double *out, hipStream_t st);
+// axis passes with extent K <= kDftColsK: one thread per column (dft_cols)
+constexpr int kDftColsK = 16;
+hipError_t launch_dft_cols(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total, const double2 *tw,
+                           const double2 *in, double2 *out, double *probs, double *err, const int *status,
+                           hipStream_t st);
 hipError_t launch_dft_stage(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total, const double2 *tw,
                             const double2 *in, double2 *out, double *probs, double *err, const int *status,
                             hipStream_t st);

@@ -1897,6 +1897,60 @@ __global__ void dft_stage(const DftStageDev *__restrict__ st, const int64_t *__r
     }
 }
 
+// The same axis pass for extents K <= kDftColsK: one thread per (o, i) column
+// loads its K inputs once into registers and writes all Bout outputs (no
+// per-output index arithmetic or instance search, loads and stores coalesced
+// along i).  Used for every descriptor with a small extent.
+template <int KMAX>
+__global__ void __launch_bounds__(256) dft_cols(const DftStageDev *__restrict__ st, const int64_t *__restrict__ prefix,
+                                                int n, int64_t total, const double2 *__restrict__ twpool,
+                                                const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                double *__restrict__ probs, double *__restrict__ err,
+                                                const int *__restrict__ status)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int e = find_job(prefix, n, q);
+    const DftStageDev S = st[e];
+    const int64_t lq = q - prefix[e];
+    const int64_t i = lq % S.inner, o = lq / S.inner;
+    const double2 *__restrict__ src = in + S.in_off + o * S.K * S.inner + i;
+    const double2 *__restrict__ tw = twpool + S.tw_off;
+    double2 v[KMAX];
+    #pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        v[k] = k < S.K ? src[(int64_t)k * S.inner] : cmk(0.0, 0.0);
+        if (S.final_stage && !S.density && !(k == 0 || 2 * k == S.G)) {
+            v[k].x *= 2.0;
+            v[k].y *= 2.0;
+        }
+    }
+    const int64_t obase = S.out_off + o * S.Bout * S.inner + i;
+    for (int b = 0; b < S.Bout; ++b) {
+        double2 acc = cmk(0.0, 0.0);
+        int m = 0;
+        #pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < S.K) {
+                acc = cfma(v[k], tw[m], acc);
+                m += b;
+                if (m >= S.G) m -= S.G;
+            }
+        }
+        if (S.moments) {
+            double f = 1.0;
+            for (int j = 1; j <= b; ++j) f *= (double)j / S.rho;
+            acc.x *= f;
+            acc.y *= f;
+        }
+        const int64_t oi = obase + (int64_t)b * S.inner;
+        if (S.final_stage && !S.density) probs[oi] = acc.x * S.scale;
+        else if (S.final_stage) out[oi] = cmk(acc.x * S.scale, acc.y * S.scale);
+        else out[oi] = acc;
+    }
+    if (S.final_stage && lq == 0 && err) err[S.inst] = (*status) ? INFINITY : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Density mode (heralded states, Sec. VII).
 //
@@ -2037,28 +2091,38 @@ __global__ void __launch_bounds__(256) density_expand(const InstDev *__restrict_
 
 // rho(b~) = R + R^H per heralding pattern, with R the inverse DFT over the
 // half grid (weights c_k / 2): the points w and conj(w) carry conjugate
-// transposes of each other, rho_G(conj w) = rho_G(w)^H.  One thread per
-// output element; R is in the buffer the instance's last DFT stage wrote.
-__global__ void density_hermitize(const InstDev *__restrict__ insts, const int32_t *__restrict__ dinst,
-                                  const int64_t *__restrict__ dprefix, int nd, int64_t total,
-                                  const double2 *__restrict__ bufA, const double2 *__restrict__ bufB,
-                                  double *__restrict__ out)
+// transposes of each other, rho_G(conj w) = rho_G(w)^H.  One workgroup per
+// (instance, b~) matrix; R is in the buffer the instance's last DFT stage
+// wrote, staged through LDS when it fits so that the transposed reads stay
+// on chip.
+__global__ void __launch_bounds__(256) density_hermitize(const InstDev *__restrict__ insts,
+                                                         const int32_t *__restrict__ dinst,
+                                                         const int64_t *__restrict__ mprefix, int nd,
+                                                         int64_t lds_values, const double2 *__restrict__ bufA,
+                                                         const double2 *__restrict__ bufB, double *__restrict__ out)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    const int j0 = find_job(dprefix, nd, q);
+    extern __shared__ double2 s_vals[];
+    const int64_t item = blockIdx.x;
+    const int j0 = find_job(mprefix, nd, item);
     const InstDev &I = insts[dinst[j0]];
-    const int64_t lq = q - dprefix[j0];
+    const int64_t b = item - mprefix[j0];
     const int64_t E = I.E;
     int64_t D = 1;
     for (int k = 0; k < I.nvar / 2; ++k) D *= I.fock_n + 1;
-    const int64_t b = lq / E, e = lq % E;
-    const int64_t v = e / D, u = e % D;
     // stage s (0-based) writes bufB when s is even; the last stage of an instance is s = L - 1
     const double2 *__restrict__ R = ((I.L - 1) % 2 == 0 ? bufB : bufA) + I.gv_off + b * E;
-    const double2 x = R[v * D + u], y = R[u * D + v];
-    double2 *o = (double2 *)(out + I.prob_off) + lq;
-    *o = cmk(x.x + y.x, x.y - y.y);
+    double2 *__restrict__ o = (double2 *)(out + I.prob_off) + b * E;
+    const bool lds = E <= lds_values;
+    if (lds) {
+        for (int64_t e = threadIdx.x; e < E; e += blockDim.x) s_vals[e] = R[e];
+        __syncthreads();
+    }
+    const double2 *__restrict__ src = lds ? s_vals : R;
+    for (int64_t e = threadIdx.x; e < E; e += blockDim.x) {
+        const int64_t v = e / D, u = e - v * D;
+        const double2 x = src[e], y = src[u * D + v];
+        o[e] = cmk(x.x + y.x, x.y - y.y);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2628,12 +2692,22 @@ hipError_t launch_density_expand(const InstDev *insts, const int32_t *dinst, con
     return hipGetLastError();
 }
 
-hipError_t launch_density_hermitize(const InstDev *insts, const int32_t *dinst, const int64_t *dprefix, int nd,
-                                    int64_t total, const double2 *bufA, const double2 *bufB, double *out,
-                                    hipStream_t st) {
+hipError_t launch_density_hermitize(const InstDev *insts, const int32_t *dinst, const int64_t *mprefix, int nd,
+                                    int64_t nmat, int64_t lds_values, const double2 *bufA, const double2 *bufB,
+                                    double *out, hipStream_t st) {
+    if (nmat <= 0) return hipSuccess;
+    if (lds_values < 0 || lds_values > kDensityLdsValues) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(density_hermitize, dim3((unsigned)nmat), dim3(256), sizeof(double2) * (size_t)lds_values, st,
+                       insts, dinst, mprefix, nd, lds_values, bufA, bufB, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_cols(const DftStageDev *st_dev, const int64_t *prefix, int n, int64_t total, const double2 *tw,
+                           const double2 *in, double2 *out, double *probs, double *err, const int *status,
+                           hipStream_t st) {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(density_hermitize, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, insts, dinst,
-                       dprefix, nd, total, bufA, bufB, out);
+    hipLaunchKernelGGL(dft_cols<kDftColsK>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, st_dev, prefix,
+                       n, total, tw, in, out, probs, err, status);
     return hipGetLastError();
 }
 
@@ -2822,6 +2896,8 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          hipFuncSetAttribute((const void *)hess_det_f64<9>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                              hess_det_lds_bytes(9)),
                          hipFuncSetAttribute((const void *)density_expand, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(sizeof(double2) * kDensityLdsValues)),
+                         hipFuncSetAttribute((const void *)density_hermitize, hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)(sizeof(double2) * kDensityLdsValues))})
         if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<2, 1, 1>(), prepare_mfma<2, 2, 2>(),
