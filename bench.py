@@ -199,11 +199,21 @@ def lu_precision(tuning, stage):
 
 
 def fp64_kernel_name(tuning, stage):
+    """The FP64 kernel the autotuner kept for an LU stage (the default shape without a report)."""
     import paper_2412_17742_amd as cgd
     c = _tuned_class(tuning, stage) if stage in cgd_stages_lu() else None
-    if c is not None and c["fp64_kernel"] == "lu_wave":
-        return f"lu_wave<double,{32 if c['class'] == 0 else 64}>"
+    if c is not None and c.get("fp64_kernel"):
+        return c["fp64_kernel"]
     return cgd.LU_KERNELS.get(stage, (stage,))[0]
+
+
+def fp32_kernel_name(tuning, stage):
+    """The FP32 MFMA kernel the autotuner kept for an LU stage of the mixed path."""
+    import paper_2412_17742_amd as cgd
+    c = _tuned_class(tuning, stage) if stage in cgd_stages_lu() else None
+    if c is not None and c.get("fp32_kernel"):
+        return c["fp32_kernel"]
+    return cgd.LU_KERNELS.get(stage, (stage, stage))[1]
 
 
 def total_photon_sweep(cgd, steps, warmup, tol):
@@ -376,7 +386,7 @@ def main():
         # first pass of the mixed path: complex FP32 elimination on MFMA (16x16x4 f32)
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
         roof = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s")
-        kname = cgd.LU_KERNELS[dom][1]
+        kname = fp32_kernel_name(B["tuning"], dom)
     else:
         achieved = flops[dom] / (dom_ms * 1e-3) / 1e12
         # FP64 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s

@@ -1234,11 +1234,15 @@ cgd_status upload_lu_lists(cgd_ctx *c) {
 // the FP64 register kernel and, on the mixed path, the wave layouts of the
 // FP32 MFMA kernel.  The fastest shape of each kind is kept.  A mixed class
 // whose best FP32 pass is not clearly faster than its best FP64 kernel (below
-// kMixedFp32Gain of the FP64 time, the share left for the re-factorisation of
-// the points that matter) runs directly in FP64.  Results do not depend on the
-// choice beyond rounding; CGD_FLAG_NO_AUTOTUNE keeps the default shapes and the
-// FP32 pass for every eligible class.
-constexpr double kMixedFp32Gain = 0.85;
+// kMixedFp32Gain of the FP64 time) runs directly in FP64: besides its own
+// points that the budget sends back to FP64, an FP32 block raises the error
+// bound of every point it belongs to and so the re-factorisation of that
+// point's other FP32 blocks (on the 512-instance batch, orders <= 32 at 0.84
+// of the FP64 time raised the re-factorised items from 121k to 677k and the
+// evaluation time by 2.5 ms).  Results do not depend on the choice beyond
+// rounding; CGD_FLAG_NO_AUTOTUNE keeps the default shapes and the FP32 pass for
+// every eligible class.
+constexpr double kMixedFp32Gain = 0.7;
 constexpr int64_t kTuneSample = 8192;
 
 cgd_status autotune(cgd_ctx *c) {

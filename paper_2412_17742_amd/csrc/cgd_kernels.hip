@@ -376,7 +376,10 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 //      waves carry on with the rest of the update;
 //   2. barrier; the owners of tile row J+1 form W = D^-1 Y on MFMA and write
 //      it to LDS; barrier.
-// X and W are double-buffered by step parity.  Padding rows and columns hold
+// X is double-buffered by step parity (step J+1's is written while step J's
+// second pass still reads); W is read only before the barrier that precedes
+// its next write, so one buffer serves.  OCC > 1 caps the registers so that
+// OCC waves fit per SIMD (the autotuner times both).  Padding rows and columns hold
 // the identity and stay decoupled, so they add pivots equal to 1.  The
 // epilogue (FP64) is the same as in the register kernel.
 // ---------------------------------------------------------------------------
@@ -474,7 +477,7 @@ struct MfmaLds {
     static constexpr int N = 16 * NTILE;
     static constexpr int XS = N + 1;  // padded stride of the transposed X panel
     float2 XT[2][16][XS];             // -X^T of the step's tile column, by step parity
-    float2 W[2][16][N];               // W = D^-1 Y, by step parity
+    float2 W[16][N];                  // W = D^-1 Y
     float2 Y[16][N];                  // tile row of the next step (each wave its own tiles)
     float2 DiT[16][17];               // (D^-1)^T
     float2 d[N];
@@ -484,8 +487,8 @@ struct MfmaLds {
     int bad;
 };
 
-template <int NTILE, int WR, int WC>
-__global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
+template <int NTILE, int WR, int WC, int OCC = 1>
+__global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(OCC))) lu_mfma_f32(const LuArgs A)
 {
     constexpr int NW = WR * WC;
     constexpr int NT = 64 * NW;
@@ -633,7 +636,7 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                     wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(di[s], y.x, wi_, 0, 0, 0);
                 }
                 #pragma unroll
-                for (int v = 0; v < 4; ++v) S.W[buf][4 * lg + v][Jt * 16 + lc] = f2(wr_[v], wi_[v]);
+                for (int v = 0; v < 4; ++v) S.W[4 * lg + v][Jt * 16 + lc] = f2(wr_[v], wi_[v]);
             }
         }
     };
@@ -660,7 +663,7 @@ __global__ void __launch_bounds__(64 * WR * WC) lu_mfma_f32(const LuArgs A)
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     float2 w = f2(0.f, 0.f);
-                    if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[buf][4 * s + lg][Jt * 16 + lc];
+                    if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[4 * s + lg][Jt * 16 + lc];
                     wr_[tj][s] = w.x;
                     wi_[tj][s] = w.y;
                 }
@@ -2573,20 +2576,20 @@ hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
     }
 }
 
-template <int NTILE, int WR, int WC>
+template <int NTILE, int WR, int WC, int OCC = 1>
 static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
              a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC>), dim3((unsigned)grid), dim3(64 * WR * WC),
+    hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
                        sizeof(MfmaLds<NTILE, WR, WC>), st, A);
     return hipGetLastError();
 }
 
-template <int NTILE, int WR, int WC>
+template <int NTILE, int WR, int WC, int OCC = 1>
 static hipError_t prepare_mfma() {
-    return hipFuncSetAttribute((const void *)lu_mfma_f32<NTILE, WR, WC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    return hipFuncSetAttribute((const void *)lu_mfma_f32<NTILE, WR, WC, OCC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)sizeof(MfmaLds<NTILE, WR, WC>));
 }
 
@@ -2603,35 +2606,40 @@ int mfma_class_limit(int cls) {
 }
 
 // wave layouts <NTILE, WR, WC> per FP32 MFMA class (the autotuner picks one)
-int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 4 : cls == 2 ? 3 : cls < kMfmaClasses ? 1 : 0; }
+int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 6 : cls == 2 ? 4 : cls < kMfmaClasses ? 1 : 0; }
 
+// <NTILE, WR, WC> or <NTILE, WR, WC, OCC> (register cap for OCC waves per SIMD)
 const char *mfma_variant_name(int cls, int v) {
-    static const char *names[kMfmaClasses][4] = {
-        {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>", ""},
-        {"lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>"},
-        {"lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>", ""},
-        {"lu_mfma_f32<8,2,4>", "", "", ""},
-        {"lu_mfma_f32<9,3,4>", "", "", ""},
-        {"lu_mfma_f32<12,2,4>", "", "", ""}};
+    static const char *names[kMfmaClasses][8] = {
+        {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>"},
+        {"lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>",
+         "lu_mfma_f32<4,2,2,4>", "lu_mfma_f32<4,1,2,3>"},
+        {"lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>", "lu_mfma_f32<6,2,2,3>"},
+        {"lu_mfma_f32<8,2,4>"},
+        {"lu_mfma_f32<9,3,4>"},
+        {"lu_mfma_f32<12,2,4>"}};
     return (cls >= 0 && cls < kMfmaClasses && v >= 0 && v < mfma_variants(cls)) ? names[cls][v] : "";
 }
 
 hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st) {
     if (!a.list && a.nitems <= 0) return hipSuccess;
-    switch (cls * 4 + v) {
+    switch (cls * 8 + v) {
         case 0: return launch_mfma<2, 1, 2>(a, st);
         case 1: return launch_mfma<2, 1, 1>(a, st);
         case 2: return launch_mfma<2, 2, 2>(a, st);
-        case 4: return launch_mfma<4, 2, 2>(a, st);
-        case 5: return launch_mfma<4, 1, 2>(a, st);
-        case 6: return launch_mfma<4, 1, 1>(a, st);
-        case 7: return launch_mfma<4, 2, 4>(a, st);
-        case 8: return launch_mfma<6, 2, 4>(a, st);
-        case 9: return launch_mfma<6, 2, 2>(a, st);
-        case 10: return launch_mfma<6, 3, 2>(a, st);
-        case 12: return launch_mfma<8, 2, 4>(a, st);
-        case 16: return launch_mfma<9, 3, 4>(a, st);
-        case 20: return launch_mfma<12, 2, 4>(a, st);
+        case 8: return launch_mfma<4, 2, 2>(a, st);
+        case 9: return launch_mfma<4, 1, 2>(a, st);
+        case 10: return launch_mfma<4, 1, 1>(a, st);
+        case 11: return launch_mfma<4, 2, 4>(a, st);
+        case 12: return launch_mfma<4, 2, 2, 4>(a, st);
+        case 13: return launch_mfma<4, 1, 2, 3>(a, st);
+        case 16: return launch_mfma<6, 2, 4>(a, st);
+        case 17: return launch_mfma<6, 2, 2>(a, st);
+        case 18: return launch_mfma<6, 3, 2>(a, st);
+        case 19: return launch_mfma<6, 2, 2, 3>(a, st);
+        case 24: return launch_mfma<8, 2, 4>(a, st);
+        case 32: return launch_mfma<9, 3, 4>(a, st);
+        case 40: return launch_mfma<12, 2, 4>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2904,7 +2912,8 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          prepare_mfma<4, 2, 2>(), prepare_mfma<4, 1, 2>(), prepare_mfma<4, 1, 1>(),
                          prepare_mfma<4, 2, 4>(), prepare_mfma<6, 2, 4>(), prepare_mfma<6, 2, 2>(),
                          prepare_mfma<6, 3, 2>(), prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(),
-                         prepare_mfma<12, 2, 4>()})
+                         prepare_mfma<12, 2, 4>(), prepare_mfma<4, 2, 2, 4>(), prepare_mfma<4, 1, 2, 3>(),
+                         prepare_mfma<6, 2, 2, 3>()})
         if (e != hipSuccess) return e;
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
