@@ -1356,14 +1356,13 @@ cgd_status autotune(cgd_ctx *c) {
             snprintf(buf, sizeof(buf), "%s\"%s\": %.4f", v ? ", " : "", mfma_variant_name(k, v), t32[v]);
             f32s += buf;
         }
-        char buf[512];
-        snprintf(buf, sizeof(buf),
-                 "%s{\"class\": %d, \"max_order\": %d, \"items\": %lld, \"sample\": %lld, \"fp64_ms\": {%s}, "
-                 "\"fp32_ms\": {%s}, \"fp64_kernel\": \"%s\", \"fp32_kernel\": \"%s\", \"precision\": \"%s\"}",
-                 first ? "" : ", ", k, maxn, (long long)total, (long long)S, f64s.c_str(), f32s.c_str(),
-                 k < kRegClasses ? reg_variant_name(k, b64) : "lu_big_f64", keep32 ? mfma_variant_name(k, b32) : "",
-                 keep32 ? "fp32+fp64" : "fp64");
-        rep += buf;
+        // no fixed-size buffer: the timing lists grow with the variants
+        rep += std::string(first ? "" : ", ") + "{\"class\": " + std::to_string(k) +
+               ", \"max_order\": " + std::to_string(maxn) + ", \"items\": " + std::to_string((long long)total) +
+               ", \"sample\": " + std::to_string((long long)S) + ", \"fp64_ms\": {" + f64s + "}, \"fp32_ms\": {" +
+               f32s + "}, \"fp64_kernel\": \"" + (k < kRegClasses ? reg_variant_name(k, b64) : "lu_big_f64") +
+               "\", \"fp32_kernel\": \"" + (keep32 ? mfma_variant_name(k, b32) : "") + "\", \"precision\": \"" +
+               (keep32 ? "fp32+fp64" : "fp64") + "\"}";
         first = false;
     }
     (void)hipEventDestroy(e0);

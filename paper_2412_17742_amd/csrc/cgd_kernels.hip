@@ -369,17 +369,18 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 // det S is the product of det D over the steps, and the pivots of D's own
 // unpivoted elimination are the pivots of S.  One step J:
 //   1. every wave updates its tiles, those of tile row and column J+1 first;
-//      the owners then write X (negated, transposed) and Y of step J+1 to
-//      LDS, and the owner of tile (J+1, J+1) inverts it by Gauss-Jordan
-//      elimination in registers (row broadcast by lane-swap permutes, column
-//      broadcast by DPP row_newbcast), recording its pivots, while the other
-//      waves carry on with the rest of the update;
-//   2. barrier; the owners of tile row J+1 form W = D^-1 Y on MFMA and write
-//      it to LDS; barrier.
-// X is double-buffered by step parity (step J+1's is written while step J's
-// second pass still reads); W is read only before the barrier that precedes
-// its next write, so one buffer serves.  OCC > 1 caps the registers so that
-// OCC waves fit per SIMD (the autotuner times both).  Padding rows and columns hold
+//      the owners then write Y of step J+1 to LDS, and the owner of tile
+//      (J+1, J+1) inverts it by Gauss-Jordan elimination in registers (row
+//      broadcast by lane-swap permutes, column broadcast by DPP
+//      row_newbcast), recording its pivots, while the other waves carry on
+//      with the rest of the update;
+//   2. barrier; the owners of tile column J+1 write X (negated, transposed)
+//      to LDS and the owners of tile row J+1 form W = D^-1 Y on MFMA and
+//      write it to LDS; barrier.
+// Every LDS panel is read only before the barrier that precedes its next
+// write, so each has one buffer (36.4 -> 28.1 KB for order 64, five
+// workgroups per CU).  OCC > 1 caps the registers so that OCC waves fit per
+// SIMD (the autotuner times both).  Padding rows and columns hold
 // the identity and stay decoupled, so they add pivots equal to 1.  The
 // epilogue (FP64) is the same as in the register kernel.
 // ---------------------------------------------------------------------------
@@ -476,7 +477,7 @@ template <int NTILE, int WR, int WC>
 struct MfmaLds {
     static constexpr int N = 16 * NTILE;
     static constexpr int XS = N + 1;  // padded stride of the transposed X panel
-    float2 XT[2][16][XS];             // -X^T of the step's tile column, by step parity
+    float2 XT[16][XS];                // -X^T of the step's tile column
     float2 W[16][N];                  // W = D^-1 Y
     float2 Y[16][N];                  // tile row of the next step (each wave its own tiles)
     float2 DiT[16][17];               // (D^-1)^T
@@ -559,21 +560,30 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
     // addressed only with compile-time indices under wave-uniform branches (a
     // runtime-indexed copy of the accumulators would go through scratch); the
     // diagonal tile reaches the Gauss-Jordan registers through LDS.
-    auto publish = [&](int Jn) {
-        const int buf = Jn & 1;
-        const int sti = Jn / WR, stj = Jn / WC;
-        const bool own_r = (wr == Jn % WR), own_c = (wc == Jn % WC);
+    // -X^T of tile column Jn (after the barrier that ends the previous step's reads)
+    auto publish_x = [&](int Jn) {
+        const int stj = Jn / WC;
+        if (wc != Jn % WC) return;
         #pragma unroll
         for (int ti = 0; ti < TRW; ++ti) {
             const int It = wr + ti * WR;
             #pragma unroll
             for (int tj = 0; tj < TCW; ++tj) {
-                const int Jt = wc + tj * WC;
-                if (own_c && tj == stj && It > Jn && It < ntl) {
+                if (tj == stj && It > Jn && It < ntl) {
                     #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        S.XT[buf][lc][It * 16 + 4 * lg + v] = f2(-ar[ti][tj][v], -ai[ti][tj][v]);
+                    for (int v = 0; v < 4; ++v) S.XT[lc][It * 16 + 4 * lg + v] = f2(-ar[ti][tj][v], -ai[ti][tj][v]);
                 }
+            }
+        }
+    };
+    auto publish = [&](int Jn) {
+        const int sti = Jn / WR, stj = Jn / WC;
+        const bool own_r = (wr == Jn % WR), own_c = (wc == Jn % WC);
+        #pragma unroll
+        for (int ti = 0; ti < TRW; ++ti) {
+            #pragma unroll
+            for (int tj = 0; tj < TCW; ++tj) {
+                const int Jt = wc + tj * WC;
                 if (own_r && ti == sti && Jt > Jn && Jt < ntl) {
                     #pragma unroll
                     for (int v = 0; v < 4; ++v) S.Y[4 * lg + v][Jt * 16 + lc] = f2(ar[ti][tj][v], ai[ti][tj][v]);
@@ -613,7 +623,6 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
     // publishes D^-1).
     auto form_w = [&](int Jn) {
         if (wr != Jn % WR) return;
-        const int buf = Jn & 1;
         float dr[4], di[4], dn[4];
         #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -644,13 +653,13 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
     if (ntl > 0) {
         publish(0);
         __syncthreads();
+        publish_x(0);
         form_w(0);
         __syncthreads();
     }
 
     #pragma unroll 1
     for (int J = 0; J + 1 < ntl; ++J) {
-        const int buf = J & 1;
         const int Jn = J + 1;
         // A += (-X) W: real part (-Xr) Wr + Xi Wi, imaginary part (-Xr) Wi + (-Xi) Wr.
         // Operands from LDS: A = -X[row, 16J + 4s + l/16] per tile row, B =
@@ -676,7 +685,7 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
                 float xr[4], xi[4], xn[4];
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float2 x = S.XT[buf][4 * s + lg][It * 16 + lc];
+                    const float2 x = S.XT[4 * s + lg][It * 16 + lc];
                     xr[s] = x.x;
                     xi[s] = x.y;
                     xn[s] = -x.y;
@@ -701,6 +710,7 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
         publish(Jn);
         update(1);
         __syncthreads();
+        publish_x(Jn);
         form_w(Jn);
         __syncthreads();
     }
@@ -2606,14 +2616,14 @@ int mfma_class_limit(int cls) {
 }
 
 // wave layouts <NTILE, WR, WC> per FP32 MFMA class (the autotuner picks one)
-int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 6 : cls == 2 ? 4 : cls < kMfmaClasses ? 1 : 0; }
+int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 7 : cls == 2 ? 4 : cls < kMfmaClasses ? 1 : 0; }
 
 // <NTILE, WR, WC> or <NTILE, WR, WC, OCC> (register cap for OCC waves per SIMD)
 const char *mfma_variant_name(int cls, int v) {
     static const char *names[kMfmaClasses][8] = {
         {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>"},
         {"lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>",
-         "lu_mfma_f32<4,2,2,4>", "lu_mfma_f32<4,1,2,3>"},
+         "lu_mfma_f32<4,2,2,4>", "lu_mfma_f32<4,1,2,3>", "lu_mfma_f32<4,2,2,5>"},
         {"lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>", "lu_mfma_f32<6,2,2,3>"},
         {"lu_mfma_f32<8,2,4>"},
         {"lu_mfma_f32<9,3,4>"},
@@ -2633,6 +2643,7 @@ hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st) {
         case 11: return launch_mfma<4, 2, 4>(a, st);
         case 12: return launch_mfma<4, 2, 2, 4>(a, st);
         case 13: return launch_mfma<4, 1, 2, 3>(a, st);
+        case 14: return launch_mfma<4, 2, 2, 5>(a, st);
         case 16: return launch_mfma<6, 2, 4>(a, st);
         case 17: return launch_mfma<6, 2, 2>(a, st);
         case 18: return launch_mfma<6, 3, 2>(a, st);
@@ -2913,7 +2924,7 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          prepare_mfma<4, 2, 4>(), prepare_mfma<6, 2, 4>(), prepare_mfma<6, 2, 2>(),
                          prepare_mfma<6, 3, 2>(), prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(),
                          prepare_mfma<12, 2, 4>(), prepare_mfma<4, 2, 2, 4>(), prepare_mfma<4, 1, 2, 3>(),
-                         prepare_mfma<6, 2, 2, 3>()})
+                         prepare_mfma<6, 2, 2, 3>(), prepare_mfma<4, 2, 2, 5>()})
         if (e != hipSuccess) return e;
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
