@@ -317,7 +317,13 @@ def main():
                     help="cgd_create flags (e.g. 8 = CGD_FLAG_HESSENBERG, 16 = CGD_FLAG_NO_HESSENBERG)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
                     help="paths to time (the JSON line needs both for the mixed-vs-FP64 check)")
+    ap.add_argument("--heralded-density-only", action="store_true",
+                    help="time only the heralded density-matrix workloads and print their JSON (for profiling)")
     args = ap.parse_args()
+    if args.heralded_density_only:
+        import paper_2412_17742_amd as cgd
+        print(json.dumps(heralded_density(cgd, args.steps, args.warmup)), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         n = 256 * 2 ** 20 // 8

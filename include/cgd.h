@@ -321,7 +321,8 @@ cgd_status cgd_bounds(const cgd_ctx *ctx, int32_t *grid, double *wrap_bound);
  * context, each candidate kernel shape on a sample of up to 8192 of the
  * class's own (block, grid point) items: the thread grids of the FP64 register
  * kernel and, on the mixed path, the wave layouts of the FP32 MFMA kernel, and
- * keeps the fastest of each kind.  On the mixed path a class whose best FP32
+ * keeps, of each kind, the first shape within 2% of the fastest (so that
+ * shapes that time alike do not flip between runs).  On the mixed path a class whose best FP32
  * pass is not below 0.7 of its best FP64 time is evaluated directly in FP64
  * (no FP32 error, nothing to factorise again).  Per class: every time (ms),
  * the chosen kernels and the precision. */

@@ -1244,6 +1244,7 @@ cgd_status upload_lu_lists(cgd_ctx *c) {
 // every eligible class.
 constexpr double kMixedFp32Gain = 0.7;
 constexpr int64_t kTuneSample = 8192;
+constexpr double kTuneTie = 0.02;
 
 cgd_status autotune(cgd_ctx *c) {
     for (int k = 0; k < kRegClasses; ++k) c->reg_var[k] = 0;
@@ -1334,11 +1335,19 @@ cgd_status autotune(cgd_ctx *c) {
             result = fail(CGD_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
             break;
         }
-        const int b64 = (int)(std::min_element(t64.begin(), t64.end()) - t64.begin());
+        // the first variant within kTuneTie of the fastest: shapes that time alike
+        // do not flip from one context (or run) to the next
+        auto pick = [](const std::vector<double> &t) {
+            const double best = *std::min_element(t.begin(), t.end());
+            for (size_t v = 0; v < t.size(); ++v)
+                if (t[v] <= best * (1.0 + kTuneTie)) return (int)v;
+            return 0;
+        };
+        const int b64 = pick(t64);
         if (k < kRegClasses) c->reg_var[k] = b64;
         int b32 = -1;
         if (n32 > 0) {
-            b32 = (int)(std::min_element(t32.begin(), t32.end()) - t32.begin());
+            b32 = pick(t32);
             c->mfma_var[k] = b32;
         }
         const bool keep32 = n32 > 0 && t32[b32] < kMixedFp32Gain * t64[b64];

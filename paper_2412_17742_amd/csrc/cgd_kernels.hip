@@ -2618,13 +2618,14 @@ int mfma_class_limit(int cls) {
 // wave layouts <NTILE, WR, WC> per FP32 MFMA class (the autotuner picks one)
 int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 7 : cls == 2 ? 4 : cls < kMfmaClasses ? 1 : 0; }
 
-// <NTILE, WR, WC> or <NTILE, WR, WC, OCC> (register cap for OCC waves per SIMD)
+// <NTILE, WR, WC> or <NTILE, WR, WC, OCC> (register cap for OCC waves per SIMD);
+// variant 0 is the default shape (CGD_FLAG_NO_AUTOTUNE) and wins ties
 const char *mfma_variant_name(int cls, int v) {
     static const char *names[kMfmaClasses][8] = {
         {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>"},
-        {"lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>",
-         "lu_mfma_f32<4,2,2,4>", "lu_mfma_f32<4,1,2,3>", "lu_mfma_f32<4,2,2,5>"},
-        {"lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>", "lu_mfma_f32<6,2,2,3>"},
+        {"lu_mfma_f32<4,1,2,3>", "lu_mfma_f32<4,2,2,5>", "lu_mfma_f32<4,2,2,4>", "lu_mfma_f32<4,2,2>",
+         "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>"},
+        {"lu_mfma_f32<6,2,2,3>", "lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>"},
         {"lu_mfma_f32<8,2,4>"},
         {"lu_mfma_f32<9,3,4>"},
         {"lu_mfma_f32<12,2,4>"}};
@@ -2637,17 +2638,17 @@ hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st) {
         case 0: return launch_mfma<2, 1, 2>(a, st);
         case 1: return launch_mfma<2, 1, 1>(a, st);
         case 2: return launch_mfma<2, 2, 2>(a, st);
-        case 8: return launch_mfma<4, 2, 2>(a, st);
-        case 9: return launch_mfma<4, 1, 2>(a, st);
-        case 10: return launch_mfma<4, 1, 1>(a, st);
-        case 11: return launch_mfma<4, 2, 4>(a, st);
-        case 12: return launch_mfma<4, 2, 2, 4>(a, st);
-        case 13: return launch_mfma<4, 1, 2, 3>(a, st);
-        case 14: return launch_mfma<4, 2, 2, 5>(a, st);
-        case 16: return launch_mfma<6, 2, 4>(a, st);
-        case 17: return launch_mfma<6, 2, 2>(a, st);
-        case 18: return launch_mfma<6, 3, 2>(a, st);
-        case 19: return launch_mfma<6, 2, 2, 3>(a, st);
+        case 8: return launch_mfma<4, 1, 2, 3>(a, st);
+        case 9: return launch_mfma<4, 2, 2, 5>(a, st);
+        case 10: return launch_mfma<4, 2, 2, 4>(a, st);
+        case 11: return launch_mfma<4, 2, 2>(a, st);
+        case 12: return launch_mfma<4, 1, 2>(a, st);
+        case 13: return launch_mfma<4, 1, 1>(a, st);
+        case 14: return launch_mfma<4, 2, 4>(a, st);
+        case 16: return launch_mfma<6, 2, 2, 3>(a, st);
+        case 17: return launch_mfma<6, 2, 4>(a, st);
+        case 18: return launch_mfma<6, 2, 2>(a, st);
+        case 19: return launch_mfma<6, 3, 2>(a, st);
         case 24: return launch_mfma<8, 2, 4>(a, st);
         case 32: return launch_mfma<9, 3, 4>(a, st);
         case 40: return launch_mfma<12, 2, 4>(a, st);

@@ -191,9 +191,18 @@ def test_mixed_matches_oracle_within_1e9():
             assert d <= errm[i] + 1e-12, (flags, i, d, errm[i])
 
 
+def _check_pick(times, chosen):
+    """The first shape within 2% of the fastest (the report rounds to 1e-4 ms)."""
+    best = min(times.values())
+    names = list(times)
+    assert times[chosen] <= best * 1.025 + 1e-4, (times, chosen)
+    for n in names[:names.index(chosen)]:
+        assert times[n] >= best * 1.015 - 1e-4, (times, chosen)
+
+
 def test_autotuner_report_and_choices():
-    """The tuner's report names every size class it timed, keeps the fastest
-    kernel shape of each kind, and sends a mixed class straight to FP64 unless
+    """The tuner's report names every size class it timed, keeps the first
+    kernel shape of each kind within 2% of the fastest, and sends a mixed class straight to FP64 unless
     its FP32 pass is below 0.7 of the FP64 time; the mixed result stays within
     its bound either way."""
     insts = W.uneven_batch(64)
@@ -206,14 +215,14 @@ def test_autotuner_report_and_choices():
                 assert c["items"] > 0 and 0 < c["sample"] <= 8192
                 f64, f32 = c["fp64_ms"], c["fp32_ms"]
                 assert f64 and all(t > 0 for t in f64.values())
-                assert c["fp64_kernel"] == min(f64, key=f64.get)
+                _check_pick(f64, c["fp64_kernel"])
                 if prec == "fp64":
                     assert not f32 and c["precision"] == "fp64"
                 elif f32:
                     fast32 = min(f32.values()) < 0.7 * min(f64.values())
                     assert c["precision"] == ("fp32+fp64" if fast32 else "fp64")
                     if fast32:
-                        assert c["fp32_kernel"] == min(f32, key=f32.get)
+                        _check_pick(f32, c["fp32_kernel"])
     with cgd.Context(insts, flags=cgd.FLAG_NO_AUTOTUNE) as ctx:
         assert ctx.tuning() == {"autotune": False, "classes": []}
     pm, errm, _, offs = _run(insts, "mixed", flags=cgd.FLAG_NO_HESSENBERG)
