@@ -35,7 +35,7 @@ STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_
 # the kernels behind each LU bucket: (FP64 path, FP32 first pass of the mixed path)
 LU_KERNELS = {
     "lu_le32": ("lu_reg<double,8,8,4,4>", "lu_mfma_f32<2,1,2>"),
-    "lu_le64": ("lu_reg<double,16,16,4,4>", "lu_mfma_f32<4,1,2,3>"),
+    "lu_le64": ("lu_reg<double,16,16,4,4>", "lu_mfma_f32<4,1,2,4>"),
     "lu_le96": ("lu_reg<double,16,32,6,3>", "lu_mfma_f32<6,2,2,3>"),
     "lu_le128": ("lu_reg<double,16,32,8,4>", "lu_mfma_f32<8,2,4>"),
     "lu_le144": ("lu_reg<double,16,48,9,3>", "lu_mfma_f32<9,3,4>"),

@@ -369,17 +369,17 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 // det S is the product of det D over the steps, and the pivots of D's own
 // unpivoted elimination are the pivots of S.  One step J:
 //   1. every wave updates its tiles, those of tile row and column J+1 first;
-//      the owners then write Y of step J+1 to LDS, and the owner of tile
-//      (J+1, J+1) inverts it by Gauss-Jordan elimination in registers (row
+//      the owner of tile (J+1, J+1) then inverts it by Gauss-Jordan elimination in registers (row
 //      broadcast by lane-swap permutes, column broadcast by DPP
 //      row_newbcast), recording its pivots, while the other waves carry on
 //      with the rest of the update;
 //   2. barrier; the owners of tile column J+1 write X (negated, transposed)
-//      to LDS and the owners of tile row J+1 form W = D^-1 Y on MFMA and
-//      write it to LDS; barrier.
+//      to LDS and the owners of tile row J+1 form W = D^-1 Y on MFMA from
+//      their own accumulators and write it to LDS; barrier.
 // Every LDS panel is read only before the barrier that precedes its next
-// write, so each has one buffer (36.4 -> 28.1 KB for order 64, five
-// workgroups per CU).  OCC > 1 caps the registers so that OCC waves fit per
+// write, so each has one buffer; Y stays in its owner's accumulators (W is
+// formed by the wave that holds the tile).  Order 64: 19.4 KB per workgroup,
+// eight workgroups per CU.  OCC > 1 caps the registers so that OCC waves fit per
 // SIMD (the autotuner times both).  Padding rows and columns hold
 // the identity and stay decoupled, so they add pivots equal to 1.  The
 // epilogue (FP64) is the same as in the register kernel.
@@ -402,6 +402,31 @@ __device__ __forceinline__ float group_to_all(float x) {
     const unsigned y = (G < 2) ? h[0] : h[1];
     const auto q = __builtin_amdgcn_permlane16_swap(y, y, false, false);
     return __builtin_bit_cast(float, (G & 1) ? q[1] : q[0]);
+}
+
+// 4 x 4 transpose between the lane group (lane / 16) and the register index:
+// out[s] in lane group g is in[g] of lane group s, same lane within the group.
+// v_permlane32_swap exchanges groups (2, 3) of its first operand with groups
+// (0, 1) of its second, v_permlane16_swap groups (1, 3) of the first with
+// (0, 2) of the second: two stages of two swaps (VALU only).
+__device__ __forceinline__ void swap32(float a, float b, float &na, float &nb) {
+    const auto h = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                    false, false);
+    na = __builtin_bit_cast(float, (unsigned)h[0]);
+    nb = __builtin_bit_cast(float, (unsigned)h[1]);
+}
+__device__ __forceinline__ void swap16(float a, float b, float &na, float &nb) {
+    const auto h = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                    false, false);
+    na = __builtin_bit_cast(float, (unsigned)h[0]);
+    nb = __builtin_bit_cast(float, (unsigned)h[1]);
+}
+__device__ __forceinline__ void group_reg_transpose(const f32x4 &in, float (&out)[4]) {
+    float a0, a1, a2, a3;
+    swap32(in[0], in[2], a0, a2);  // a0 = (in0[0], in0[1], in2[0], in2[1]), a2 = (in0[2], in0[3], in2[2], in2[3])
+    swap32(in[1], in[3], a1, a3);
+    swap16(a0, a1, out[0], out[1]);  // out0 = (in0[0], in1[0], in2[0], in3[0]), out1 = (.. [1])
+    swap16(a2, a3, out[2], out[3]);
 }
 
 __device__ __forceinline__ float uniform_read(float x, int src_lane) {
@@ -479,7 +504,6 @@ struct MfmaLds {
     static constexpr int XS = N + 1;  // padded stride of the transposed X panel
     float2 XT[16][XS];                // -X^T of the step's tile column
     float2 W[16][N];                  // W = D^-1 Y
-    float2 Y[16][N];                  // tile row of the next step (each wave its own tiles)
     float2 DiT[16][17];               // (D^-1)^T
     float2 d[N];
     float2 piv[N];
@@ -583,11 +607,6 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
         for (int ti = 0; ti < TRW; ++ti) {
             #pragma unroll
             for (int tj = 0; tj < TCW; ++tj) {
-                const int Jt = wc + tj * WC;
-                if (own_r && ti == sti && Jt > Jn && Jt < ntl) {
-                    #pragma unroll
-                    for (int v = 0; v < 4; ++v) S.Y[4 * lg + v][Jt * 16 + lc] = f2(ar[ti][tj][v], ai[ti][tj][v]);
-                }
                 if (own_r && own_c && ti == sti && tj == stj) {
                     #pragma unroll
                     for (int v = 0; v < 4; ++v) S.DiT[4 * lg + v][lc] = f2(ar[ti][tj][v], ai[ti][tj][v]);
@@ -621,8 +640,12 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
 
     // W = D^-1 Y for this wave's tiles of tile row Jn (after the barrier that
     // publishes D^-1).
+    // The B operand of chunk s at lane (g, c) is Y[4s + g][c], which the
+    // owner holds in lane (s, c), register g: a lane-group/register
+    // transpose of its accumulators (no LDS panel for Y).
     auto form_w = [&](int Jn) {
         if (wr != Jn % WR) return;
+        const int sti = Jn / WR;
         float dr[4], di[4], dn[4];
         #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -635,14 +658,20 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
         for (int tj = 0; tj < TCW; ++tj) {
             const int Jt = wc + tj * WC;
             if (Jt > Jn && Jt < ntl) {
+                float yr[4] = {0.f, 0.f, 0.f, 0.f}, yi[4] = {0.f, 0.f, 0.f, 0.f};
+                #pragma unroll
+                for (int ti = 0; ti < TRW; ++ti)
+                    if (ti == sti) {
+                        group_reg_transpose(ar[ti][tj], yr);
+                        group_reg_transpose(ai[ti][tj], yi);
+                    }
                 f32x4 wr_ = {0.f, 0.f, 0.f, 0.f}, wi_ = {0.f, 0.f, 0.f, 0.f};
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float2 y = S.Y[4 * s + lg][Jt * 16 + lc];  // B operand: Y[4s + l/16][l%16]
-                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], y.x, wr_, 0, 0, 0);
-                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dn[s], y.y, wr_, 0, 0, 0);
-                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], y.y, wi_, 0, 0, 0);
-                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(di[s], y.x, wi_, 0, 0, 0);
+                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], yr[s], wr_, 0, 0, 0);
+                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dn[s], yi[s], wr_, 0, 0, 0);
+                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], yi[s], wi_, 0, 0, 0);
+                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(di[s], yr[s], wi_, 0, 0, 0);
                 }
                 #pragma unroll
                 for (int v = 0; v < 4; ++v) S.W[4 * lg + v][Jt * 16 + lc] = f2(wr_[v], wi_[v]);
@@ -2616,16 +2645,17 @@ int mfma_class_limit(int cls) {
 }
 
 // wave layouts <NTILE, WR, WC> per FP32 MFMA class (the autotuner picks one)
-int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 7 : cls == 2 ? 4 : cls < kMfmaClasses ? 1 : 0; }
+int mfma_variants(int cls) { return cls == 0 ? 3 : cls == 1 ? 8 : cls == 2 ? 5 : cls < kMfmaClasses ? 1 : 0; }
 
 // <NTILE, WR, WC> or <NTILE, WR, WC, OCC> (register cap for OCC waves per SIMD);
 // variant 0 is the default shape (CGD_FLAG_NO_AUTOTUNE) and wins ties
 const char *mfma_variant_name(int cls, int v) {
     static const char *names[kMfmaClasses][8] = {
         {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>"},
-        {"lu_mfma_f32<4,1,2,3>", "lu_mfma_f32<4,2,2,5>", "lu_mfma_f32<4,2,2,4>", "lu_mfma_f32<4,2,2>",
-         "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>"},
-        {"lu_mfma_f32<6,2,2,3>", "lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>"},
+        {"lu_mfma_f32<4,1,2,4>", "lu_mfma_f32<4,1,2,3>", "lu_mfma_f32<4,2,2,5>", "lu_mfma_f32<4,2,2,4>",
+         "lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>"},
+        {"lu_mfma_f32<6,2,2,3>", "lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>",
+         "lu_mfma_f32<6,2,2,4>"},
         {"lu_mfma_f32<8,2,4>"},
         {"lu_mfma_f32<9,3,4>"},
         {"lu_mfma_f32<12,2,4>"}};
@@ -2638,17 +2668,19 @@ hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st) {
         case 0: return launch_mfma<2, 1, 2>(a, st);
         case 1: return launch_mfma<2, 1, 1>(a, st);
         case 2: return launch_mfma<2, 2, 2>(a, st);
-        case 8: return launch_mfma<4, 1, 2, 3>(a, st);
-        case 9: return launch_mfma<4, 2, 2, 5>(a, st);
-        case 10: return launch_mfma<4, 2, 2, 4>(a, st);
-        case 11: return launch_mfma<4, 2, 2>(a, st);
-        case 12: return launch_mfma<4, 1, 2>(a, st);
-        case 13: return launch_mfma<4, 1, 1>(a, st);
-        case 14: return launch_mfma<4, 2, 4>(a, st);
+        case 8: return launch_mfma<4, 1, 2, 4>(a, st);
+        case 9: return launch_mfma<4, 1, 2, 3>(a, st);
+        case 10: return launch_mfma<4, 2, 2, 5>(a, st);
+        case 11: return launch_mfma<4, 2, 2, 4>(a, st);
+        case 12: return launch_mfma<4, 2, 2>(a, st);
+        case 13: return launch_mfma<4, 1, 2>(a, st);
+        case 14: return launch_mfma<4, 1, 1>(a, st);
+        case 15: return launch_mfma<4, 2, 4>(a, st);
         case 16: return launch_mfma<6, 2, 2, 3>(a, st);
         case 17: return launch_mfma<6, 2, 4>(a, st);
         case 18: return launch_mfma<6, 2, 2>(a, st);
         case 19: return launch_mfma<6, 3, 2>(a, st);
+        case 20: return launch_mfma<6, 2, 2, 4>(a, st);
         case 24: return launch_mfma<8, 2, 4>(a, st);
         case 32: return launch_mfma<9, 3, 4>(a, st);
         case 40: return launch_mfma<12, 2, 4>(a, st);
@@ -2925,7 +2957,8 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          prepare_mfma<4, 2, 4>(), prepare_mfma<6, 2, 4>(), prepare_mfma<6, 2, 2>(),
                          prepare_mfma<6, 3, 2>(), prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(),
                          prepare_mfma<12, 2, 4>(), prepare_mfma<4, 2, 2, 4>(), prepare_mfma<4, 1, 2, 3>(),
-                         prepare_mfma<6, 2, 2, 3>(), prepare_mfma<4, 2, 2, 5>()})
+                         prepare_mfma<6, 2, 2, 3>(), prepare_mfma<4, 2, 2, 5>(), prepare_mfma<4, 1, 2, 4>(),
+                         prepare_mfma<6, 2, 2, 4>()})
         if (e != hipSuccess) return e;
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
