@@ -328,6 +328,18 @@ cgd_status cgd_bounds(const cgd_ctx *ctx, int32_t *grid, double *wrap_bound);
  * the chosen kernels and the precision. */
 const char *cgd_tuning(const cgd_ctx *ctx);
 
+/* Pin the kernel shape of a size class (0..4: orders <= 32, 64, 96, 128, 144),
+ * overriding the autotuner: fp64_shape indexes the class's FP64 shapes in the
+ * order of the report's "fp64_ms" (register-kernel thread grids first, then
+ * FP64 MFMA wave layouts), fp32_shape its FP32 MFMA shapes ("fp32_ms"); -1
+ * keeps the current one.  For tests, profiling (the same kernel in every
+ * run) and callers that want reproducible launch shapes; results differ only
+ * by rounding.  Precision choices (which classes run an FP32 pass) are not
+ * changed.  Errors: CGD_ERR_ARG for a shape out of range, an FP32 shape for a
+ * class without an FP32 pass, or an FP64 MFMA shape for a class with kept
+ * modes (density mode needs the register kernel). */
+cgd_status cgd_set_kernel_shape(cgd_ctx *ctx, int32_t size_class, int32_t fp64_shape, int32_t fp32_shape);
+
 void cgd_destroy(cgd_ctx *ctx);
 
 /* Message of the last failure on this thread (valid until the next call). */

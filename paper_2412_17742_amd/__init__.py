@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
     L.cgd_mixed_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.cgd_bounds.restype = i32
     L.cgd_bounds.argtypes = [vp, vp, vp]
+    L.cgd_set_kernel_shape.restype = i32
+    L.cgd_set_kernel_shape.argtypes = [vp, i32, i32, i32]
     L.cgd_tuning.restype = ctypes.c_char_p
     L.cgd_tuning.argtypes = [vp]
     L.cgd_destroy.restype = None
@@ -277,6 +279,11 @@ class Context:
             out.append(tuple(int(x) for x in g[off:off + len(s)]))
             off += len(s)
         return out, w
+
+    def set_kernel_shape(self, size_class: int, fp64_shape: int = -1, fp32_shape: int = -1):
+        """Pin a size class's FP64 and/or FP32 kernel shape (indices into the
+        tuning report's per-class timing lists; -1 keeps the current one)."""
+        _check(lib().cgd_set_kernel_shape(self._h, int(size_class), int(fp64_shape), int(fp32_shape)))
 
     def tuning(self):
         """The autotuner's report (dict): per size class, the timed kernels and the choice."""

@@ -1304,7 +1304,12 @@ cgd_status autotune(cgd_ctx *c) {
             maxn = std::max(maxn, d.nb);
         }
         if (total == 0) continue;
-        const int n64 = k < kRegClasses ? reg_variants(k) : 1;
+        // a class with density-mode blocks keeps to register-kernel shapes (they
+        // write the trailing Schur complement the expansion reads)
+        bool keeps = false;
+        for (size_t b = 0; b < c->blocks.size(); ++b)
+            if (!c->is_hess[b] && c->blocks[b].cls == k && c->blocks[b].nkeep) keeps = true;
+        const int n64 = k < kRegClasses ? (keeps ? reg_kernel_variants(k) : reg_variants(k)) : 1;
         const int n32 = any32 ? mfma_variants(k) : 0;
         if (n64 < 2 && n32 == 0) continue;  // nothing to choose
         const int64_t S = std::min<int64_t>(total, kTuneSample);
@@ -2404,6 +2409,36 @@ cgd_status cgd_bounds(const cgd_ctx *c, int32_t *grid, double *wrap_bound) {
     if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
     if (grid) std::copy(c->grid_used.begin(), c->grid_used.end(), grid);
     if (wrap_bound) std::copy(c->wrap_bound.begin(), c->wrap_bound.end(), wrap_bound);
+    return CGD_OK;
+}
+
+cgd_status cgd_set_kernel_shape(cgd_ctx *c, int32_t size_class, int32_t fp64_shape, int32_t fp32_shape) {
+    if (!c) return fail(CGD_ERR_ARG, "ctx is NULL");
+    if (size_class < 0 || size_class >= kRegClasses) return fail(CGD_ERR_ARG, "size class out of range");
+    const int k = size_class;
+    bool keeps = false, fp32 = false;
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        const BlockDev &d = c->blocks[b];
+        if (c->is_hess[b] || d.cls != k) continue;
+        keeps |= d.nkeep > 0;
+        fp32 |= d.fp32 && mfma_class_of(d.nb) == k;
+    }
+    if (fp64_shape >= 0) {
+        const int lim = keeps ? reg_kernel_variants(k) : reg_variants(k);
+        if (fp64_shape >= lim)
+            return fail(CGD_ERR_ARG, "fp64 shape out of range for this class" +
+                                         std::string(keeps ? " (blocks with kept modes need a register-kernel shape)" : ""));
+    }
+    if (fp32_shape >= 0) {
+        if (!fp32) return fail(CGD_ERR_ARG, "this class has no FP32 pass");
+        if (fp32_shape >= mfma_variants(k)) return fail(CGD_ERR_ARG, "fp32 shape out of range for this class");
+    }
+    if (fp64_shape >= 0) c->reg_var[k] = fp64_shape;
+    if (fp32_shape >= 0) c->mfma_var[k] = fp32_shape;
+    if (c->gexec) {  // the captured launch sequence names the old kernels
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
     return CGD_OK;
 }
 

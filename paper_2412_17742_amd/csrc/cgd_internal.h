@@ -177,6 +177,7 @@ constexpr int kRegClasses = 5;
 // register kernel, mfma_variants(cls) wave layouts of the FP32 MFMA kernel
 // (variant 0 is the default; the autotuner of cgd_create picks one)
 int reg_variants(int cls);
+int reg_kernel_variants(int cls);      // the first ones: register-kernel shapes (density mode needs one)
 const char *reg_variant_name(int cls, int v);
 hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st);
 constexpr int kMfmaClasses = 6;

@@ -385,30 +385,71 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 // epilogue (FP64) is the same as in the register kernel.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Element-type traits of the MFMA LU: FP32 uses v_mfma_f32_16x16x4f32, whose
+// accumulator holds element (4g + v, c) in lane (g, c) = (l / 16, l % 16),
+// register v; FP64 uses v_mfma_f64_16x16x4f64, whose accumulator holds
+// element (g + 4v, c).  Both take A[i][k] from lane (k, i) and B[k][j] from
+// lane (k, j).
+template <typename T> struct MfmaT;
+template <> struct MfmaT<float> {
+    typedef f32x4 V4;
+    __device__ static __forceinline__ V4 mfma(float a, float b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int g, int v) { return 4 * g + v; }
+    __device__ static __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+template <> struct MfmaT<double> {
+    typedef f64x4 V4;
+    __device__ static __forceinline__ V4 mfma(double a, double b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int g, int v) { return g + 4 * v; }
+    __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
+};
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
+// Cross-lane moves on 32-bit registers; the FP64 forms move both halves.
+template <int K> __device__ __forceinline__ unsigned dpp_row_bcast(unsigned x) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x150 + K, 0xf, 0xf, true);
+}
 template <int K>
 __device__ __forceinline__ float row_bcast(float x) {  // lane K of each 16-lane row to the whole row
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x150 + K, 0xf, 0xf, true));
+    return __builtin_bit_cast(float, dpp_row_bcast<K>(__builtin_bit_cast(unsigned, x)));
+}
+template <int K>
+__device__ __forceinline__ double row_bcast(double x) {
+    const uint2 u = __builtin_bit_cast(uint2, x);
+    return __builtin_bit_cast(double, make_uint2(dpp_row_bcast<K>(u.x), dpp_row_bcast<K>(u.y)));
 }
 
 // 16-lane row G to all four rows: the 32-lane swap pairs rows (0,1) or
 // (2,3), the 16-lane swap then spreads the wanted one (VALU only).
-template <int G>
-__device__ __forceinline__ float group_to_all(float x) {
-    const unsigned u = __builtin_bit_cast(unsigned, x);
+template <int G> __device__ __forceinline__ unsigned group_to_all_u(unsigned u) {
     const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);  // rows (0 1 0 1), (2 3 2 3)
     const unsigned y = (G < 2) ? h[0] : h[1];
     const auto q = __builtin_amdgcn_permlane16_swap(y, y, false, false);
-    return __builtin_bit_cast(float, (G & 1) ? q[1] : q[0]);
+    return (G & 1) ? q[1] : q[0];
+}
+template <int G>
+__device__ __forceinline__ float group_to_all(float x) {
+    return __builtin_bit_cast(float, group_to_all_u<G>(__builtin_bit_cast(unsigned, x)));
+}
+template <int G>
+__device__ __forceinline__ double group_to_all(double x) {
+    const uint2 u = __builtin_bit_cast(uint2, x);
+    return __builtin_bit_cast(double, make_uint2(group_to_all_u<G>(u.x), group_to_all_u<G>(u.y)));
 }
 
 // 4 x 4 transpose between the lane group (lane / 16) and the register index:
 // out[s] in lane group g is in[g] of lane group s, same lane within the group.
 // v_permlane32_swap exchanges groups (2, 3) of its first operand with groups
 // (0, 1) of its second, v_permlane16_swap groups (1, 3) of the first with
-// (0, 2) of the second: two stages of two swaps (VALU only).
+// (0, 2) of the second: two stages of two swaps (VALU only).  Needed for the
+// FP32 layout only (FP64 accumulators are already in the B-operand layout).
 __device__ __forceinline__ void swap32(float a, float b, float &na, float &nb) {
     const auto h = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
                                                     false, false);
@@ -432,37 +473,42 @@ __device__ __forceinline__ void group_reg_transpose(const f32x4 &in, float (&out
 __device__ __forceinline__ float uniform_read(float x, int src_lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src_lane));
 }
+__device__ __forceinline__ double uniform_read(double x, int src_lane) {
+    const uint2 u = __builtin_bit_cast(uint2, x);
+    return __builtin_bit_cast(double, make_uint2((unsigned)__builtin_amdgcn_readlane((int)u.x, src_lane),
+                                                 (unsigned)__builtin_amdgcn_readlane((int)u.y, src_lane)));
+}
 
-// Gauss-Jordan inversion of the 16 x 16 tile held in the accumulator layout
-// (lane (g, c), register v: element (4g + v, c)).  Step k, with p = a[k][k]:
+// Gauss-Jordan inversion of a 16 x 16 tile held as lane (g, c), register v:
+// element (4g + v, c) (both element types; the FP64 kernel stages its tile
+// through LDS into this layout).  Step k, with p = a[k][k]:
 // a[k][c] <- a[k][c]/p, a[r][k] <- -a[r][k]/p, a[k][k] <- 1/p and
 // a[r][c] <- a[r][c] - a[r][k] a[k][c]/p elsewhere.  After the 16 steps the
 // tile holds its inverse; p is the k-th pivot of the unpivoted LU.  Row k
 // reaches every lane by two lane-swap permutes and column k by DPP
 // row_newbcast, all in VALU; each step updates row k+1 first, so that its
 // broadcast overlaps the rest.
-template <int K>
-__device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int g, int c, float &rowr, float &rowi,
-                                        float &pr, float &pi) {
+template <int K, typename T>
+__device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T &rowr, T &rowi, T &pr, T &pi) {
     constexpr int KG = K >> 2, KV = K & 3;
     constexpr int V1 = (K + 1) & 3, G1 = (K + 1) >> 2;
-    float colr[4], coli[4];
+    T colr[4], coli[4];
     #pragma unroll
     for (int v = 0; v < 4; ++v) {
         colr[v] = row_bcast<K>(ar[v]);
         coli[v] = row_bcast<K>(ai[v]);
     }
-    const float s = __builtin_amdgcn_rcpf(pr * pr + pi * pi);
-    const float rpr = pr * s, rpi = -pi * s;
+    const T s = MfmaT<T>::rcp(pr * pr + pi * pi);
+    const T rpr = pr * s, rpi = -pi * s;
     // t = a[k][c] / p off column k.  On column k, t = 1 + 1/p, so that the
     // common update a - a[r][k] t leaves -a[r][k] / p there with no zeroing of
     // a (|1/p| > 1/2 for an accretive matrix, so nothing cancels badly).
     const bool isk = (c == K);
-    const float tr = isk ? 1.f + rpr : fmaf(rowr, rpr, -rowi * rpi);
-    const float ti = isk ? rpi : fmaf(rowr, rpi, rowi * rpr);
+    const T tr = isk ? T(1) + rpr : fma(rowr, rpr, -rowi * rpi);
+    const T ti = isk ? rpi : fma(rowr, rpi, rowi * rpr);
     auto upd = [&](int v) {
-        ar[v] = fmaf(coli[v], ti, fmaf(-colr[v], tr, ar[v]));
-        ai[v] = fmaf(-coli[v], tr, fmaf(-colr[v], ti, ai[v]));
+        ar[v] = fma(coli[v], ti, fma(-colr[v], tr, ar[v]));
+        ai[v] = fma(-coli[v], tr, fma(-colr[v], ti, ai[v]));
     };
     if (K < 15) {
         upd(V1);  // row K+1 (on group G1) first
@@ -481,12 +527,12 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int g, i
 }
 
 // Runs the 16 steps; pivot k ends up in lane k of (pvr, pvi).
-template <int... K>
-__device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], int g, int c, float &pvr, float &pvi,
+template <typename T, int... K>
+__device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &pvr, T &pvi,
                                        std::integer_sequence<int, K...>) {
     const int lane = g * 16 + c;
-    float rowr = group_to_all<0>(ar[0]), rowi = group_to_all<0>(ai[0]);
-    float pr = uniform_read(ar[0], 0), pi = uniform_read(ai[0], 0);
+    T rowr = group_to_all<0>(ar[0]), rowi = group_to_all<0>(ai[0]);
+    T pr = uniform_read(ar[0], 0), pi = uniform_read(ai[0], 0);
     pvr = pr;
     pvi = pi;
     auto keep = [&](int k) {
@@ -498,28 +544,33 @@ __device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], int g, in
     ((gj_step<K>(ar, ai, g, c, rowr, rowi, pr, pi), keep(K + 1)), ...);
 }
 
-template <int NTILE, int WR, int WC>
+template <typename T, int NTILE, int WR, int WC>
 struct MfmaLds {
+    typedef cx2<T> C;
     static constexpr int N = 16 * NTILE;
     static constexpr int XS = N + 1;  // padded stride of the transposed X panel
-    float2 XT[16][XS];                // -X^T of the step's tile column
-    float2 W[16][N];                  // W = D^-1 Y
-    float2 DiT[16][17];               // (D^-1)^T
-    float2 d[N];
-    float2 piv[N];
+    C XT[16][XS];                     // -X^T of the step's tile column
+    C W[16][N];                       // W = D^-1 Y
+    C DiT[16][17];                    // (D^-1)^T
+    C d[N];
+    C piv[N];
     double2 w[kMaxBins];
     double2 red[WR * WC + 1];
     int bad;
 };
 
-template <int NTILE, int WR, int WC, int OCC = 1>
-__global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(OCC))) lu_mfma_f32(const LuArgs A)
+template <typename T, int NTILE, int WR, int WC>
+__device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
 {
+    typedef cx2<T> C;
+    typedef typename PoolT<T>::type PT;
+    typedef typename MfmaT<T>::V4 V4;
+    constexpr bool F64 = sizeof(T) == 8;
     constexpr int NW = WR * WC;
     constexpr int NT = 64 * NW;
     constexpr int TRW = (NTILE + WR - 1) / WR;
     constexpr int TCW = (NTILE + WC - 1) / WC;
-    using Lds = MfmaLds<NTILE, WR, WC>;
+    using Lds = MfmaLds<T, NTILE, WR, WC>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Lds &S = *reinterpret_cast<Lds *>(lds_raw);
 
@@ -552,14 +603,14 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
     __syncthreads();
     for (int i = tid; i < nb; i += NT) {
         const int b = A.rbpool[B.rb_off + i];
-        S.d[i] = b < 0 ? f2(1.0f, 0.0f) : f2((float)S.w[b].x, (float)S.w[b].y);
+        S.d[i] = b < 0 ? mk2<T>(T(1), T(0)) : mk2<T>((T)S.w[b].x, (T)S.w[b].y);
     }
     __syncthreads();
 
-    const float2 *__restrict__ Hs = (const float2 *)A.pool + B.h_off;
+    const PT *__restrict__ Hs = (const PT *)A.pool + B.h_off;
     if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
 
-    f32x4 ar[TRW][TCW], ai[TRW][TCW];
+    V4 ar[TRW][TCW], ai[TRW][TCW];
     #pragma unroll
     for (int ti = 0; ti < TRW; ++ti)
         #pragma unroll
@@ -568,13 +619,13 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
             #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 // clamped, unconditional loads: all of them are in flight at once
-                const int i = It * 16 + 4 * lg + v, j = Jt * 16 + lc;
+                const int i = It * 16 + MfmaT<T>::row(lg, v), j = Jt * 16 + lc;
                 const bool in = i < nb && j < nb;
                 const int ic = in ? i : 0, jc = in ? j : 0;
-                float2 h = Hs[(int64_t)ic * nb + jc];
-                const float2 d = S.d[ic];
-                if (!in) h = f2(0.f, 0.f);
-                ar[ti][tj][v] = ((i == j) ? 1.0f : 0.0f) - (d.x * h.x - d.y * h.y);
+                PT h = Hs[(int64_t)ic * nb + jc];
+                const C d = S.d[ic];
+                if (!in) h.x = h.y = T(0);
+                ar[ti][tj][v] = ((i == j) ? T(1) : T(0)) - (d.x * h.x - d.y * h.y);
                 ai[ti][tj][v] = -(d.x * h.y + d.y * h.x);
             }
         }
@@ -595,7 +646,8 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
             for (int tj = 0; tj < TCW; ++tj) {
                 if (tj == stj && It > Jn && It < ntl) {
                     #pragma unroll
-                    for (int v = 0; v < 4; ++v) S.XT[lc][It * 16 + 4 * lg + v] = f2(-ar[ti][tj][v], -ai[ti][tj][v]);
+                    for (int v = 0; v < 4; ++v)
+                        S.XT[lc][It * 16 + MfmaT<T>::row(lg, v)] = mk2<T>(-ar[ti][tj][v], -ai[ti][tj][v]);
                 }
             }
         }
@@ -609,7 +661,7 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
             for (int tj = 0; tj < TCW; ++tj) {
                 if (own_r && own_c && ti == sti && tj == stj) {
                     #pragma unroll
-                    for (int v = 0; v < 4; ++v) S.DiT[4 * lg + v][lc] = f2(ar[ti][tj][v], ai[ti][tj][v]);
+                    for (int v = 0; v < 4; ++v) S.DiT[MfmaT<T>::row(lg, v)][lc] = mk2<T>(ar[ti][tj][v], ai[ti][tj][v]);
                 }
             }
         }
@@ -618,22 +670,22 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            float gr[4], gi[4];
+            T gr[4], gi[4];
             #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float2 x = S.DiT[4 * lg + v][lc];
+                const C x = S.DiT[4 * lg + v][lc];
                 gr[v] = x.x;
                 gi[v] = x.y;
             }
             __builtin_amdgcn_wave_barrier();
-            float pvr, pvi;
+            T pvr, pvi;
             gj_all(gr, gi, lg, lc, pvr, pvi, std::make_integer_sequence<int, 16>{});
             #pragma unroll
-            for (int v = 0; v < 4; ++v) S.DiT[lc][4 * lg + v] = f2(gr[v], gi[v]);
+            for (int v = 0; v < 4; ++v) S.DiT[lc][4 * lg + v] = mk2<T>(gr[v], gi[v]);
             const int gk = Jn * 16 + lane;
             if (lane < 16 && gk < nb) {
-                S.piv[gk] = f2(pvr, pvi);
-                if (!isfinite(pvr) || !isfinite(pvi) || (gk < nl && !(pvr > 0.f))) S.bad = 1;
+                S.piv[gk] = mk2<T>(pvr, pvi);
+                if (!isfinite(pvr) || !isfinite(pvi) || (gk < nl && !(pvr > T(0)))) S.bad = 1;
             }
         }
     };
@@ -646,10 +698,10 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
     auto form_w = [&](int Jn) {
         if (wr != Jn % WR) return;
         const int sti = Jn / WR;
-        float dr[4], di[4], dn[4];
+        T dr[4], di[4], dn[4];
         #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const float2 x = S.DiT[4 * s + lg][lc];  // A operand: D^-1[l%16][4s + l/16]
+            const C x = S.DiT[4 * s + lg][lc];  // A operand: D^-1[l%16][4s + l/16]
             dr[s] = x.x;
             di[s] = x.y;
             dn[s] = -x.y;
@@ -658,23 +710,33 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
         for (int tj = 0; tj < TCW; ++tj) {
             const int Jt = wc + tj * WC;
             if (Jt > Jn && Jt < ntl) {
-                float yr[4] = {0.f, 0.f, 0.f, 0.f}, yi[4] = {0.f, 0.f, 0.f, 0.f};
+                // B operand of chunk s: Y[4s + g][c]; in the FP64 layout that is
+                // register s of the same lane, in the FP32 layout a transpose
+                T yr[4] = {T(0), T(0), T(0), T(0)}, yi[4] = {T(0), T(0), T(0), T(0)};
                 #pragma unroll
                 for (int ti = 0; ti < TRW; ++ti)
                     if (ti == sti) {
-                        group_reg_transpose(ar[ti][tj], yr);
-                        group_reg_transpose(ai[ti][tj], yi);
+                        if constexpr (F64) {
+                            #pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                yr[s] = ar[ti][tj][s];
+                                yi[s] = ai[ti][tj][s];
+                            }
+                        } else {
+                            group_reg_transpose(ar[ti][tj], yr);
+                            group_reg_transpose(ai[ti][tj], yi);
+                        }
                     }
-                f32x4 wr_ = {0.f, 0.f, 0.f, 0.f}, wi_ = {0.f, 0.f, 0.f, 0.f};
+                V4 wr_ = {T(0), T(0), T(0), T(0)}, wi_ = {T(0), T(0), T(0), T(0)};
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], yr[s], wr_, 0, 0, 0);
-                    wr_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dn[s], yi[s], wr_, 0, 0, 0);
-                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[s], yi[s], wi_, 0, 0, 0);
-                    wi_ = __builtin_amdgcn_mfma_f32_16x16x4f32(di[s], yr[s], wi_, 0, 0, 0);
+                    wr_ = MfmaT<T>::mfma(dr[s], yr[s], wr_);
+                    wr_ = MfmaT<T>::mfma(dn[s], yi[s], wr_);
+                    wi_ = MfmaT<T>::mfma(dr[s], yi[s], wi_);
+                    wi_ = MfmaT<T>::mfma(di[s], yr[s], wi_);
                 }
                 #pragma unroll
-                for (int v = 0; v < 4; ++v) S.W[4 * lg + v][Jt * 16 + lc] = f2(wr_[v], wi_[v]);
+                for (int v = 0; v < 4; ++v) S.W[MfmaT<T>::row(lg, v)][Jt * 16 + lc] = mk2<T>(wr_[v], wi_[v]);
             }
         }
     };
@@ -694,13 +756,13 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
         // Operands from LDS: A = -X[row, 16J + 4s + l/16] per tile row, B =
         // W[4s + l/16, col] per pass (not held across the diagonal inversion).
         auto update = [&](int pass) {
-            float wr_[TCW][4], wi_[TCW][4];
+            T wr_[TCW][4], wi_[TCW][4];
             #pragma unroll
             for (int tj = 0; tj < TCW; ++tj) {
                 const int Jt = wc + tj * WC;
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    float2 w = f2(0.f, 0.f);
+                    C w = mk2<T>(T(0), T(0));
                     if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[4 * s + lg][Jt * 16 + lc];
                     wr_[tj][s] = w.x;
                     wi_[tj][s] = w.y;
@@ -711,10 +773,10 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
                 const int It = wr + ti * WR;
                 if (It <= J || It >= ntl) continue;
                 if (pass == 1 && It == Jn) continue;  // tile row Jn went entirely in pass 0
-                float xr[4], xi[4], xn[4];
+                T xr[4], xi[4], xn[4];
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float2 x = S.XT[4 * s + lg][It * 16 + lc];
+                    const C x = S.XT[4 * s + lg][It * 16 + lc];
                     xr[s] = x.x;
                     xi[s] = x.y;
                     xn[s] = -x.y;
@@ -727,10 +789,10 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
                     if (first != (pass == 0)) continue;
                     #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[s], wr_[tj][s], ar[ti][tj], 0, 0, 0);
-                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[s], wi_[tj][s], ai[ti][tj], 0, 0, 0);
-                        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xn[s], wi_[tj][s], ar[ti][tj], 0, 0, 0);
-                        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[s], wr_[tj][s], ai[ti][tj], 0, 0, 0);
+                        ar[ti][tj] = MfmaT<T>::mfma(xr[s], wr_[tj][s], ar[ti][tj]);
+                        ai[ti][tj] = MfmaT<T>::mfma(xr[s], wi_[tj][s], ai[ti][tj]);
+                        ar[ti][tj] = MfmaT<T>::mfma(xn[s], wi_[tj][s], ar[ti][tj]);
+                        ai[ti][tj] = MfmaT<T>::mfma(xi[s], wr_[tj][s], ai[ti][tj]);
                     }
                 }
             }
@@ -763,13 +825,28 @@ __global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_
     if (tid == 0) {
         double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
         if (B.bordered) {
-            const float2 pb = S.piv[nb - 1];
+            const C pb = S.piv[nb - 1];
             res.x += 0.5 * (1.0 - (double)pb.x);
             res.y += 0.5 * (0.0 - (double)pb.y);
         }
         A.contrib[I.c_off + pt * I.nblocks + B.blk] = res;
         if (S.bad) atomicOr(A.status, 1);
     }
+}
+
+
+template <int NTILE, int WR, int WC, int OCC = 1>
+__global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(OCC))) lu_mfma_f32(const LuArgs A)
+{
+    lu_mfma_body<float, NTILE, WR, WC>(A);
+}
+
+// The same elimination in complex FP64 on v_mfma_f64_16x16x4f64 (an FP64
+// kernel shape the autotuner times against the register kernel).
+template <int NTILE, int WR, int WC, int OCC = 1>
+__global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(OCC))) lu_mfma_f64(const LuArgs A)
+{
+    lu_mfma_body<double, NTILE, WR, WC>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -2587,30 +2664,53 @@ int reg_class_limit(int cls) {
 }
 
 // thread-grid shapes <PR, PC, TR, TC> per register class (the autotuner picks one)
-int reg_variants(int cls) { return cls == 0 ? 2 : cls == 1 ? 3 : cls == 2 ? 2 : cls < kRegClasses ? 1 : 0; }
+// FP64 kernel shapes per register class (the autotuner picks one): the
+// register kernel's thread grids <PR, PC, TR, TC>, then (classes 0..2) FP64
+// MFMA wave layouts <NTILE, WR, WC, OCC>.  Variant 0 is the default; blocks
+// with kept modes (density mode) need a register-kernel shape
+// (reg_kernel_variants), which writes the trailing Schur complement.
+static constexpr int kRegShapes[kRegClasses] = {2, 3, 2, 1, 1};
+static constexpr int kMfma64Shapes[kRegClasses] = {3, 3, 3, 0, 0};
+int reg_variants(int cls) { return cls >= 0 && cls < kRegClasses ? kRegShapes[cls] + kMfma64Shapes[cls] : 0; }
+int reg_kernel_variants(int cls) { return cls >= 0 && cls < kRegClasses ? kRegShapes[cls] : 0; }
 
 const char *reg_variant_name(int cls, int v) {
-    static const char *names[kRegClasses][3] = {
-        {"lu_reg<double,8,8,4,4>", "lu_reg<double,8,16,4,2>", ""},
-        {"lu_reg<double,16,16,4,4>", "lu_reg<double,8,16,8,4>", "lu_reg<double,16,32,4,2>"},
-        {"lu_reg<double,16,32,6,3>", "lu_reg<double,16,16,6,6>", ""},
-        {"lu_reg<double,16,32,8,4>", "", ""},
-        {"lu_reg<double,16,48,9,3>", "", ""}};
+    static const char *names[kRegClasses][6] = {
+        {"lu_reg<double,8,8,4,4>", "lu_reg<double,8,16,4,2>", "lu_mfma_f64<2,1,1>", "lu_mfma_f64<2,1,2>",
+         "lu_mfma_f64<2,2,2>"},
+        {"lu_reg<double,16,16,4,4>", "lu_reg<double,8,16,8,4>", "lu_reg<double,16,32,4,2>", "lu_mfma_f64<4,2,2>",
+         "lu_mfma_f64<4,1,2>", "lu_mfma_f64<4,2,2,3>"},
+        {"lu_reg<double,16,32,6,3>", "lu_reg<double,16,16,6,6>", "lu_mfma_f64<6,2,2>", "lu_mfma_f64<6,2,4>",
+         "lu_mfma_f64<6,3,2>"},
+        {"lu_reg<double,16,32,8,4>"},
+        {"lu_reg<double,16,48,9,3>"}};
     return (cls >= 0 && cls < kRegClasses && v >= 0 && v < reg_variants(cls)) ? names[cls][v] : "";
 }
 
+template <int NTILE, int WR, int WC, int OCC = 1>
+static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st);
+
 hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
     if (!a.list && a.nitems <= 0) return hipSuccess;
-    switch (cls * 4 + v) {
+    switch (cls * 8 + v) {
         case 0: return launch_reg<8, 8, 4, 4>(a, st);
         case 1: return launch_reg<8, 16, 4, 2>(a, st);
-        case 4: return launch_reg<16, 16, 4, 4>(a, st);
-        case 5: return launch_reg<8, 16, 8, 4>(a, st);
-        case 6: return launch_reg<16, 32, 4, 2>(a, st);
-        case 8: return launch_reg<16, 32, 6, 3>(a, st);
-        case 9: return launch_reg<16, 16, 6, 6>(a, st);
-        case 12: return launch_reg<16, 32, 8, 4>(a, st);
-        case 16: return launch_reg<16, 48, 9, 3>(a, st);
+        case 2: return launch_mfma64<2, 1, 1>(a, st);
+        case 3: return launch_mfma64<2, 1, 2>(a, st);
+        case 4: return launch_mfma64<2, 2, 2>(a, st);
+        case 8: return launch_reg<16, 16, 4, 4>(a, st);
+        case 9: return launch_reg<8, 16, 8, 4>(a, st);
+        case 10: return launch_reg<16, 32, 4, 2>(a, st);
+        case 11: return launch_mfma64<4, 2, 2>(a, st);
+        case 12: return launch_mfma64<4, 1, 2>(a, st);
+        case 13: return launch_mfma64<4, 2, 2, 3>(a, st);
+        case 16: return launch_reg<16, 32, 6, 3>(a, st);
+        case 17: return launch_reg<16, 16, 6, 6>(a, st);
+        case 18: return launch_mfma64<6, 2, 2>(a, st);
+        case 19: return launch_mfma64<6, 2, 4>(a, st);
+        case 20: return launch_mfma64<6, 3, 2>(a, st);
+        case 24: return launch_reg<16, 32, 8, 4>(a, st);
+        case 32: return launch_reg<16, 48, 9, 3>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2622,14 +2722,31 @@ static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
-                       sizeof(MfmaLds<NTILE, WR, WC>), st, A);
+                       sizeof(MfmaLds<float, NTILE, WR, WC>), st, A);
+    return hipGetLastError();
+}
+
+template <int NTILE, int WR, int WC, int OCC>
+static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st) {
+    LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
+    const int64_t grid = a.list ? a.list_capacity : a.nitems;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((lu_mfma_f64<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
+                       sizeof(MfmaLds<double, NTILE, WR, WC>), st, A);
     return hipGetLastError();
 }
 
 template <int NTILE, int WR, int WC, int OCC = 1>
 static hipError_t prepare_mfma() {
     return hipFuncSetAttribute((const void *)lu_mfma_f32<NTILE, WR, WC, OCC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sizeof(MfmaLds<NTILE, WR, WC>));
+                               (int)sizeof(MfmaLds<float, NTILE, WR, WC>));
+}
+
+template <int NTILE, int WR, int WC, int OCC = 1>
+static hipError_t prepare_mfma64() {
+    return hipFuncSetAttribute((const void *)lu_mfma_f64<NTILE, WR, WC, OCC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sizeof(MfmaLds<double, NTILE, WR, WC>));
 }
 
 int mfma_class_limit(int cls) {
@@ -2958,7 +3075,10 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
                          prepare_mfma<6, 3, 2>(), prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(),
                          prepare_mfma<12, 2, 4>(), prepare_mfma<4, 2, 2, 4>(), prepare_mfma<4, 1, 2, 3>(),
                          prepare_mfma<6, 2, 2, 3>(), prepare_mfma<4, 2, 2, 5>(), prepare_mfma<4, 1, 2, 4>(),
-                         prepare_mfma<6, 2, 2, 4>()})
+                         prepare_mfma<6, 2, 2, 4>(), prepare_mfma64<2, 1, 1>(), prepare_mfma64<2, 1, 2>(),
+                         prepare_mfma64<2, 2, 2>(), prepare_mfma64<4, 2, 2>(), prepare_mfma64<4, 1, 2>(),
+                         prepare_mfma64<4, 2, 2, 3>(), prepare_mfma64<6, 2, 2>(), prepare_mfma64<6, 2, 4>(),
+                         prepare_mfma64<6, 3, 2>()})
         if (e != hipSuccess) return e;
     if (big_ldw > 0) {
         const hipError_t e = hipFuncSetAttribute((const void *)lu_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,

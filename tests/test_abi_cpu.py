@@ -106,3 +106,8 @@ def test_density_mode_arguments_are_checked_before_the_device():
         mutate(x)
         st, h, msg = _create(x)
         assert st == cgd.CGD_ERR_ARG and (word in msg or "2^22" in msg), msg
+
+
+def test_set_kernel_shape_checks_its_arguments():
+    L = cgd.lib()
+    assert L.cgd_set_kernel_shape(None, 0, 0, -1) == cgd.CGD_ERR_ARG

@@ -120,3 +120,53 @@ def test_gbs144_2bins_routes_agree_at_every_grid_point():
     dphase = np.angle(np.exp(1j * (a.imag - b.imag)))
     assert np.abs(a.real - b.real)[big].max() <= 1e-9
     assert np.abs(dphase)[big].max() <= 1e-9
+
+
+def _shape_counts(insts, precision):
+    with cgd.Context(insts, precision=precision, tol=TOL_MIXED, flags=cgd.FLAG_NO_HESSENBERG) as ctx:
+        rep = ctx.tuning()
+    return {c["class"]: (len(c["fp64_ms"]), len(c["fp32_ms"]) if c["precision"] == "fp32+fp64" else 0)
+            for c in rep["classes"] if c["class"] < 3}
+
+
+def _shape_cases():
+    # the 8 heaviest batch instances hold blocks of orders 33..96 (classes 1, 2);
+    # the mesh sets blocks of order 32 (class 0)
+    batch = W.uneven_batch()
+    which = [int(i) for i in _golden("uneven512_heavy")["index"]]
+    return {"uneven512_heavy": ([batch[i] for i in which], {1, 2}),
+            "mesh32_k4": (make_golden.CASES["mesh32_k4"](), {0})}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["uneven512_heavy", "mesh32_k4"])
+def test_every_kernel_shape_of_classes_0_to_2(case, precision):
+    """Each FP64 shape (register kernel and FP64 MFMA) and, on the mixed path,
+    each FP32 MFMA shape of the size classes <= 96, pinned in turn with
+    cgd_set_kernel_shape, against the oracle's boxes (factorisation per
+    point): the 8 heaviest instances of the batch (classes 1, 2) and the 64
+    mesh sets (class 0)."""
+    import torch
+    insts, classes = _shape_cases()[case]
+    g = _golden(case)
+    counts = _shape_counts(insts, precision)
+    assert classes <= set(counts), counts
+    for cls in sorted(classes):
+        n64, n32 = counts[cls]
+        for kind, n in (("fp64", n64), ("fp32", n32)):
+            for v in range(n):
+                with cgd.Context(insts, precision=precision, tol=TOL_MIXED, flags=cgd.FLAG_NO_HESSENBERG) as ctx:
+                    ctx.set_kernel_shape(cls, v if kind == "fp64" else -1, v if kind == "fp32" else -1)
+                    rep = {c["class"]: c for c in ctx.tuning()["classes"]}
+                    name = list(rep[cls][f"{kind}_ms"])[v]
+                    err = torch.full((ctx.n_inst,), -1.0, dtype=torch.float64, device="cuda")
+                    p = ctx.eval(err=err)
+                    torch.cuda.synchronize()
+                    got = [x.cpu().numpy() for x in ctx.split(p)]
+                    err = err.cpu().numpy()
+                worst = max(float(np.abs(got[j] - g[f"P_{j}"]).max()) for j in range(len(insts)))
+                _say(f"  {case} {precision} class {cls} {name}: max |P - P_oracle| {worst:.2e}, bound {err.max():.2e}")
+                if precision == "fp64":
+                    assert worst <= TOL_FP64 and err.max() == 0.0, (name, worst)
+                else:
+                    assert worst <= TOL_MIXED and err.max() <= TOL_MIXED and worst <= err.max() + TOL_FP64, name
