@@ -82,19 +82,17 @@ __device__ __forceinline__ double2 grid_w(int k, int G, double rho) {
 
 // Grid coordinates of evaluated point p of instance I (half grid on axis 0)
 // and the corresponding value of w.
-__device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, double2 &w) {
-    int64_t stride = 1;
-    for (int m = I.L - 1; m > l; --m) stride *= I.G[m];
-    int64_t k = p / stride;
-    if (l > 0) k %= I.G[l];
-    w = grid_w((int)k, I.G[l], I.rho);
-}
+// An instance has at most 2^31 grid points (checked at create), so the index
+// arithmetic is 32-bit.
 __device__ __forceinline__ int point_k(const InstDev &I, int64_t p, int l) {
-    int64_t stride = 1;
-    for (int m = I.L - 1; m > l; --m) stride *= I.G[m];
-    int64_t k = p / stride;
-    if (l > 0) k %= I.G[l];
+    unsigned stride = 1;
+    for (int m = I.L - 1; m > l; --m) stride *= (unsigned)I.G[m];
+    unsigned k = (unsigned)p / stride;
+    if (l > 0) k %= (unsigned)I.G[l];
     return (int)k;
+}
+__device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, double2 &w) {
+    w = grid_w(point_k(I, p, l), I.G[l], I.rho);
 }
 
 // Largest c with prefix[c] <= item (prefix[0] = 0, strictly usable entries n).
@@ -167,6 +165,42 @@ template <typename T> struct PoolT;
 template <> struct PoolT<double> { typedef double2 type; };
 template <> struct PoolT<float> { typedef float2 type; };
 
+// Raw buffer view of one block's nb x nb matrix (row-major).  The buffer's own
+// range check returns zero for every offset past its end, so padding rows and
+// columns are read with no clamped addresses or selects: an element's offset
+// is row_off + col_off, and either part is kPastEnd outside the matrix (the
+// sum then lies past the end and below 2^31).
+constexpr unsigned kPastEnd = 0x40000000u;
+constexpr int kRawBufferWord3 = 0x00020000;  // untyped raw buffer, gfx9 family
+template <typename PT> struct MatrixBuf {
+    __amdgpu_buffer_rsrc_t r;
+    int nb;
+    __device__ __forceinline__ MatrixBuf(const PT *p, int n)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(static_cast<const void *>(p)), (short)0,
+                                              n * n * (int)sizeof(PT), kRawBufferWord3)),
+          nb(n) {}
+    __device__ __forceinline__ unsigned row_off(int i) const {
+        return i < nb ? (unsigned)(i * nb) * (unsigned)sizeof(PT) : kPastEnd;
+    }
+    __device__ __forceinline__ unsigned col_off(int j) const {
+        return j < nb ? (unsigned)j * (unsigned)sizeof(PT) : kPastEnd;
+    }
+    __device__ __forceinline__ PT load(unsigned off) const;
+};
+// The loaded vector is reinterpreted as a whole: with one bit cast per 32-bit
+// element, this compiler narrows the b64 load to a single dword and returns
+// it for both components.
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+template <> __device__ __forceinline__ float2 MatrixBuf<float2>::load(unsigned off) const {
+    const f32x2v v = __builtin_bit_cast(f32x2v, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    return make_float2(v.x, v.y);
+}
+template <> __device__ __forceinline__ double2 MatrixBuf<double2>::load(unsigned off) const {
+    const f64x2v v = __builtin_bit_cast(f64x2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    return make_double2(v.x, v.y);
+}
+
 struct LuArgs {
     const int32_t *job_block;
     const int64_t *job_prefix;
@@ -229,31 +263,37 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
         if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
         if (tid == 0) s_bad = 0;
         __syncthreads();
-        for (int i = tid; i < nb; i += NT) {
-            const int b = A.rbpool[B.rb_off + i];
-            s_d[i] = b < 0 ? mk2<T>(T(1), T(0)) : mk2<T>((T)s_w[b].x, (T)s_w[b].y);
+        // s_d = -d on the matrix rows, 0 on the padding: S = I + (-D) H
+        for (int i = tid; i < N; i += NT) {
+            C nd = mk2<T>(T(0), T(0));
+            if (i < nb) {
+                const int b = A.rbpool[B.rb_off + i];
+                nd = b < 0 ? mk2<T>(T(-1), T(0)) : mk2<T>(-(T)s_w[b].x, -(T)s_w[b].y);
+            }
+            s_d[i] = nd;
         }
         __syncthreads();
 
         const PT *__restrict__ Hs = (const PT *)A.pool + B.h_off;
         if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
+        const MatrixBuf<PT> hm(Hs, nb);
 
         C a[TR][TC];
+        unsigned coff[TC];
+        #pragma unroll
+        for (int c = 0; c < TC; ++c) coff[c] = hm.col_off(c * PC + tx);
         #pragma unroll
         for (int r = 0; r < TR; ++r) {
             const int i = r * PR + ty;
+            const unsigned roff = hm.row_off(i);
+            const C nd = s_d[i];
             #pragma unroll
             for (int c = 0; c < TC; ++c) {
-                const int j = c * PC + tx;
-                // clamped, unconditional loads: all of them are in flight at once
-                const bool in = i < nb && j < nb;
-                const int ic = in ? i : 0, jc = in ? j : 0;
-                PT h = Hs[(int64_t)ic * nb + jc];
-                if (!in) h.x = h.y = 0;
-                const C d = s_d[ic];
-                C v = mk2<T>(i == j ? T(1) : T(0), T(0));
-                v.x -= d.x * h.x - d.y * h.y;
-                v.y -= d.x * h.y + d.y * h.x;
+                const PT h = hm.load(roff + coff[c]);  // zero outside the matrix
+                C v;
+                v.x = fma(nd.x, h.x, -(nd.y * h.y));
+                v.y = fma(nd.x, h.y, nd.y * h.x);
+                if (i == c * PC + tx) v.x += T(1);
                 a[r][c] = v;
             }
         }
@@ -426,22 +466,35 @@ __device__ __forceinline__ double row_bcast(double x) {
     return __builtin_bit_cast(double, make_uint2(dpp_row_bcast<K>(u.x), dpp_row_bcast<K>(u.y)));
 }
 
-// 16-lane row G to all four rows: the 32-lane swap pairs rows (0,1) or
-// (2,3), the 16-lane swap then spreads the wanted one (VALU only).
-template <int G> __device__ __forceinline__ unsigned group_to_all_u(unsigned u) {
-    const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);  // rows (0 1 0 1), (2 3 2 3)
-    const unsigned y = (G < 2) ? h[0] : h[1];
-    const auto q = __builtin_amdgcn_permlane16_swap(y, y, false, false);
-    return (G & 1) ? q[1] : q[0];
+// 16-lane row G of a pair of registers (x, y) to all four rows of both, in
+// three lane swaps: the 32-lane swap of (x, y) gives (x0 x1 y0 y1) and
+// (x2 x3 y2 y3); the 16-lane swap of the half holding row G spreads it to
+// (xG xG yG yG); a last 32-lane swap separates (xG xG xG xG) and
+// (yG yG yG yG).  VALU only.
+template <int G> __device__ __forceinline__ void group_to_all_pair_u(unsigned x, unsigned y, unsigned &ox, unsigned &oy) {
+    const auto h = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    const unsigned z = (G < 2) ? h[0] : h[1];
+    const auto q = __builtin_amdgcn_permlane16_swap(z, z, false, false);
+    const unsigned t = (G & 1) ? q[1] : q[0];
+    const auto r = __builtin_amdgcn_permlane32_swap(t, t, false, false);
+    ox = r[0];
+    oy = r[1];
 }
 template <int G>
-__device__ __forceinline__ float group_to_all(float x) {
-    return __builtin_bit_cast(float, group_to_all_u<G>(__builtin_bit_cast(unsigned, x)));
+__device__ __forceinline__ void group_to_all_pair(float x, float y, float &ox, float &oy) {
+    unsigned a, b;
+    group_to_all_pair_u<G>(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y), a, b);
+    ox = __builtin_bit_cast(float, a);
+    oy = __builtin_bit_cast(float, b);
 }
 template <int G>
-__device__ __forceinline__ double group_to_all(double x) {
-    const uint2 u = __builtin_bit_cast(uint2, x);
-    return __builtin_bit_cast(double, make_uint2(group_to_all_u<G>(u.x), group_to_all_u<G>(u.y)));
+__device__ __forceinline__ void group_to_all_pair(double x, double y, double &ox, double &oy) {
+    const uint2 u = __builtin_bit_cast(uint2, x), v = __builtin_bit_cast(uint2, y);
+    uint2 a, b;
+    group_to_all_pair_u<G>(u.x, v.x, a.x, b.x);
+    group_to_all_pair_u<G>(u.y, v.y, a.y, b.y);
+    ox = __builtin_bit_cast(double, a);
+    oy = __builtin_bit_cast(double, b);
 }
 
 // 4 x 4 transpose between the lane group (lane / 16) and the register index:
@@ -485,8 +538,8 @@ __device__ __forceinline__ double uniform_read(double x, int src_lane) {
 // a[k][c] <- a[k][c]/p, a[r][k] <- -a[r][k]/p, a[k][k] <- 1/p and
 // a[r][c] <- a[r][c] - a[r][k] a[k][c]/p elsewhere.  After the 16 steps the
 // tile holds its inverse; p is the k-th pivot of the unpivoted LU.  Row k
-// reaches every lane by two lane-swap permutes and column k by DPP
-// row_newbcast, all in VALU; each step updates row k+1 first, so that its
+// (real and imaginary part together) reaches every lane by three lane swaps
+// and column k by DPP row_newbcast, all in VALU; each step updates row k+1 first, so that its
 // broadcast overlaps the rest.
 template <int K, typename T>
 __device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T &rowr, T &rowi, T &pr, T &pi) {
@@ -512,8 +565,7 @@ __device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T 
     };
     if (K < 15) {
         upd(V1);  // row K+1 (on group G1) first
-        rowr = group_to_all<G1>(ar[V1]);
-        rowi = group_to_all<G1>(ai[V1]);
+        group_to_all_pair<G1>(ar[V1], ai[V1], rowr, rowi);
         pr = uniform_read(ar[V1], G1 * 16 + K + 1);
         pi = uniform_read(ai[V1], G1 * 16 + K + 1);
     }
@@ -531,7 +583,8 @@ template <typename T, int... K>
 __device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &pvr, T &pvi,
                                        std::integer_sequence<int, K...>) {
     const int lane = g * 16 + c;
-    T rowr = group_to_all<0>(ar[0]), rowi = group_to_all<0>(ai[0]);
+    T rowr, rowi;
+    group_to_all_pair<0>(ar[0], ai[0], rowr, rowi);
     T pr = uniform_read(ar[0], 0), pi = uniform_read(ai[0], 0);
     pvr = pr;
     pvi = pi;
@@ -601,34 +654,60 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
     if (tid < I.L) point_w(I, pt, tid, S.w[tid]);
     if (tid == 0) S.bad = 0;
     __syncthreads();
-    for (int i = tid; i < nb; i += NT) {
-        const int b = A.rbpool[B.rb_off + i];
-        S.d[i] = b < 0 ? mk2<T>(T(1), T(0)) : mk2<T>((T)S.w[b].x, (T)S.w[b].y);
+    // S.d = -d on the matrix rows, 0 on the padding: S = I + (-D) H
+    for (int i = tid; i < Lds::N; i += NT) {
+        C nd = mk2<T>(T(0), T(0));
+        if (i < nb) {
+            const int b = A.rbpool[B.rb_off + i];
+            nd = b < 0 ? mk2<T>(T(-1), T(0)) : mk2<T>(-(T)S.w[b].x, -(T)S.w[b].y);
+        }
+        S.d[i] = nd;
     }
     __syncthreads();
 
     const PT *__restrict__ Hs = (const PT *)A.pool + B.h_off;
     if (B.hs_stride) Hs += (int64_t)point_k(I, pt, B.schur_axis) * B.hs_stride;
+    const MatrixBuf<PT> hm(Hs, nb);
 
+    // Tile rows past the last tile in use stay zero (never read); in the
+    // others, columns past the matrix read as zero from the buffer and the
+    // diagonal tile adds the identity (padding included).
     V4 ar[TRW][TCW], ai[TRW][TCW];
+    unsigned coff[TCW];
     #pragma unroll
-    for (int ti = 0; ti < TRW; ++ti)
+    for (int tj = 0; tj < TCW; ++tj) coff[tj] = hm.col_off((wc + tj * WC) * 16 + lc);
+    #pragma unroll
+    for (int ti = 0; ti < TRW; ++ti) {
+        const int It = wr + ti * WR;
         #pragma unroll
         for (int tj = 0; tj < TCW; ++tj) {
-            const int It = wr + ti * WR, Jt = wc + tj * WC;
+            ar[ti][tj] = V4{T(0), T(0), T(0), T(0)};
+            ai[ti][tj] = V4{T(0), T(0), T(0), T(0)};
+        }
+        if (It >= ntl) continue;
+        unsigned roff[4];
+        C nd[4];
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = It * 16 + MfmaT<T>::row(lg, v);
+            roff[v] = hm.row_off(i);
+            nd[v] = S.d[i];
+        }
+        #pragma unroll
+        for (int tj = 0; tj < TCW; ++tj) {
             #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                // clamped, unconditional loads: all of them are in flight at once
-                const int i = It * 16 + MfmaT<T>::row(lg, v), j = Jt * 16 + lc;
-                const bool in = i < nb && j < nb;
-                const int ic = in ? i : 0, jc = in ? j : 0;
-                PT h = Hs[(int64_t)ic * nb + jc];
-                const C d = S.d[ic];
-                if (!in) h.x = h.y = T(0);
-                ar[ti][tj][v] = ((i == j) ? T(1) : T(0)) - (d.x * h.x - d.y * h.y);
-                ai[ti][tj][v] = -(d.x * h.y + d.y * h.x);
+                const PT h = hm.load(roff[v] + coff[tj]);
+                ar[ti][tj][v] = fma(nd[v].x, h.x, -(nd[v].y * h.y));
+                ai[ti][tj][v] = fma(nd[v].x, h.y, nd[v].y * h.x);
+            }
+            if (It == wc + tj * WC) {
+                #pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (MfmaT<T>::row(lg, v) == lc) ar[ti][tj][v] += T(1);
             }
         }
+    }
 
     // Publish what step Jn needs: -X^T (tiles below the diagonal), Y (tiles
     // right of it), and D^-1 with the pivots (diagonal tile).  Tiles are
