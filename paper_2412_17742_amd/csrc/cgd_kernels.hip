@@ -578,9 +578,12 @@ __device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T 
     }
 }
 
-// Runs the 16 steps; pivot k ends up in lane k of (pvr, pvi).
+// Runs steps 0 .. kstop - 1 (kstop wave-uniform); pivot k ends up in lane k
+// of (pvr, pvi).  With kstop < 16 the tile is not inverted, but its first
+// kstop pivots are exact: the last tile of a matrix needs only its pivots,
+// and its rows and columns past the matrix are decoupled identity.
 template <typename T, int... K>
-__device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &pvr, T &pvi,
+__device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &pvr, T &pvi, int kstop,
                                        std::integer_sequence<int, K...>) {
     const int lane = g * 16 + c;
     T rowr, rowi;
@@ -594,7 +597,7 @@ __device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &
             pvi = pi;
         }
     };
-    ((gj_step<K>(ar, ai, g, c, rowr, rowi, pr, pi), keep(K + 1)), ...);
+    ((K < kstop ? (gj_step<K>(ar, ai, g, c, rowr, rowi, pr, pi), keep(K + 1)) : void()), ...);
 }
 
 template <typename T, int NTILE, int WR, int WC>
@@ -628,7 +631,8 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
     Lds &S = *reinterpret_cast<Lds *>(lds_raw);
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    // the wave index as a scalar: every tile condition is a scalar branch
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int wr = wave / WC, wc = wave % WC;
     const int lg = lane >> 4, lc = lane & 15;
 
@@ -758,7 +762,9 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
             }
             __builtin_amdgcn_wave_barrier();
             T pvr, pvi;
-            gj_all(gr, gi, lg, lc, pvr, pvi, std::make_integer_sequence<int, 16>{});
+            // the last tile: only its pivots (no trailing tiles use its inverse)
+            const int kstop = (Jn + 1 == ntl) ? nb - 16 * Jn : 16;
+            gj_all(gr, gi, lg, lc, pvr, pvi, kstop, std::make_integer_sequence<int, 16>{});
             #pragma unroll
             for (int v = 0; v < 4; ++v) S.DiT[lc][4 * lg + v] = mk2<T>(gr[v], gi[v]);
             const int gk = Jn * 16 + lane;

@@ -171,10 +171,13 @@ def test_batch_with_probability_instances_and_static_entry_point():
     mod = _moderate()
     insts = [W.plain_m4(), mod["two_kept_modes_displaced"], W.lossy_m16_k3(),
              mod["fock_heralding"], _tiny()["displaced_one_bin"]]
-    got, _ = _gpu(insts)
-    got_s, _ = _gpu(insts, static=True)
+    # bitwise equality needs the same kernel shapes in every context: the
+    # autotuner, timing a different mix of work, may pick others
+    fl = cgd.FLAG_NO_AUTOTUNE
+    got, _ = _gpu(insts, flags=fl)
+    got_s, _ = _gpu(insts, flags=fl, static=True)
     for i, x in enumerate(insts):
-        (alone,), _ = _gpu([x])
+        (alone,), _ = _gpu([x], flags=fl)
         assert np.array_equal(got[i], alone), i
         assert np.array_equal(got_s[i], alone), i
     assert got[1].shape == (3, 3, 16, 16) and got[3].shape == (4, 7, 7)
