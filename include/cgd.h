@@ -323,7 +323,7 @@ cgd_status cgd_bounds(const cgd_ctx *ctx, int32_t *grid, double *wrap_bound);
  * kernel and, on the mixed path, the wave layouts of the FP32 MFMA kernel, and
  * keeps, of each kind, the first shape within 2% of the fastest (so that
  * shapes that time alike do not flip between runs).  On the mixed path a class whose best FP32
- * pass is not below 0.6 of its best FP64 time is evaluated directly in FP64
+ * pass is not below 0.5 of its best FP64 time is evaluated directly in FP64
  * (no FP32 error, nothing to factorise again).  Per class: every time (ms),
  * the chosen kernels and the precision. */
 const char *cgd_tuning(const cgd_ctx *ctx);

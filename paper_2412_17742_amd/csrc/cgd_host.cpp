@@ -1237,13 +1237,13 @@ cgd_status upload_lu_lists(cgd_ctx *c) {
 // kMixedFp32Gain of the FP64 time) runs directly in FP64: besides its own
 // points that the budget sends back to FP64, an FP32 block raises the error
 // bound of every point it belongs to and so the re-factorisation of that
-// point's other FP32 blocks (on the 512-instance batch, orders <= 32 at 0.70
-// to 0.84 of the FP64 time raised the re-factorised items from 121k to 677k
-// and the evaluation time by 1.6 to 2.5 ms, while orders 33..96 at 0.34 to
-// 0.51 gain).  Results do not depend on the choice beyond rounding;
-// CGD_FLAG_NO_AUTOTUNE keeps the default shapes and the FP32 pass for every
-// eligible class.
-constexpr double kMixedFp32Gain = 0.6;
+// point's other FP32 blocks (on the 512-instance batch, orders <= 32 at 0.59
+// of the FP64 time raised the re-factorisation pass from 4.6 to 8.0 ms and
+// the evaluation from 21.2 to 22.7 ms; at 0.70 to 0.84 the re-factorised
+// items rose from 121k to 677k; orders 33..96 at 0.28 to 0.42 gain).  Results
+// do not depend on the choice beyond rounding; CGD_FLAG_NO_AUTOTUNE keeps the
+// default shapes and the FP32 pass for every eligible class.
+constexpr double kMixedFp32Gain = 0.5;
 constexpr int64_t kTuneSample = 8192;
 constexpr double kTuneTie = 0.02;
 
