@@ -157,8 +157,16 @@ template <typename T> __device__ __forceinline__ cx2<T> fnms2(cx2<T> a, cx2<T> l
     a.y = fma(-l.y, u.x, a.y);
     return a;
 }
+// 1/x from the hardware estimate and two Newton-Raphson steps
+// y <- y + y (1 - x y) (the relative error squares at each step)
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
 template <typename T> __device__ __forceinline__ cx2<T> inv2(cx2<T> d) {
-    const T s = T(1) / (d.x * d.x + d.y * d.y);
+    const T s = rcp_nr(d.x * d.x + d.y * d.y);
     return mk2<T>(d.x * s, -d.y * s);
 }
 template <typename T> struct PoolT;
@@ -447,7 +455,7 @@ template <> struct MfmaT<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int g, int v) { return g + 4 * v; }
-    __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
+    __device__ static __forceinline__ double rcp(double x) { return rcp_nr(x); }
 };
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
@@ -461,9 +469,8 @@ __device__ __forceinline__ float row_bcast(float x) {  // lane K of each 16-lane
     return __builtin_bit_cast(float, dpp_row_bcast<K>(__builtin_bit_cast(unsigned, x)));
 }
 template <int K>
-__device__ __forceinline__ double row_bcast(double x) {
-    const uint2 u = __builtin_bit_cast(uint2, x);
-    return __builtin_bit_cast(double, make_uint2(dpp_row_bcast<K>(u.x), dpp_row_bcast<K>(u.y)));
+__device__ __forceinline__ double row_bcast(double x) {  // one 64-bit DPP move (row_newbcast)
+    return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + K, 0xf, 0xf, true);
 }
 
 // 16-lane row G of a pair of registers (x, y) to all four rows of both, in
