@@ -611,9 +611,13 @@ template <typename T, int NTILE, int WR, int WC>
 struct MfmaLds {
     typedef cx2<T> C;
     static constexpr int N = 16 * NTILE;
-    static constexpr int XS = N + 1;  // padded stride of the transposed X panel
-    C XT[16][XS];                     // -X^T of the step's tile column
-    C W[16][N];                       // W = D^-1 Y
+    // The panels hold tile rows (X) and tile columns (W) 1 .. NTILE - 1 only:
+    // tile 0 is never below or right of a diagonal tile.
+    static_assert(NTILE >= 2, "one tile needs no panels");
+    static constexpr int NP = N - 16;  // panel width
+    static constexpr int XS = NP + 1;  // padded stride of the transposed X panel
+    C XT[16][XS];                      // -X^T of the step's tile column, tile rows 1 ..
+    C W[16][NP];                       // W = D^-1 Y, tile columns 1 ..
     C DiT[16][17];                    // (D^-1)^T
     C d[N];
     C piv[N];
@@ -737,7 +741,7 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
                 if (tj == stj && It > Jn && It < ntl) {
                     #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        S.XT[lc][It * 16 + MfmaT<T>::row(lg, v)] = mk2<T>(-ar[ti][tj][v], -ai[ti][tj][v]);
+                        S.XT[lc][(It - 1) * 16 + MfmaT<T>::row(lg, v)] = mk2<T>(-ar[ti][tj][v], -ai[ti][tj][v]);
                 }
             }
         }
@@ -828,7 +832,7 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
                     wi_ = MfmaT<T>::mfma(di[s], yr[s], wi_);
                 }
                 #pragma unroll
-                for (int v = 0; v < 4; ++v) S.W[MfmaT<T>::row(lg, v)][Jt * 16 + lc] = mk2<T>(wr_[v], wi_[v]);
+                for (int v = 0; v < 4; ++v) S.W[MfmaT<T>::row(lg, v)][(Jt - 1) * 16 + lc] = mk2<T>(wr_[v], wi_[v]);
             }
         }
     };
@@ -855,7 +859,7 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     C w = mk2<T>(T(0), T(0));
-                    if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[4 * s + lg][Jt * 16 + lc];
+                    if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[4 * s + lg][(Jt - 1) * 16 + lc];
                     wr_[tj][s] = w.x;
                     wi_[tj][s] = w.y;
                 }
@@ -868,7 +872,7 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
                 T xr[4], xi[4], xn[4];
                 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const C x = S.XT[4 * s + lg][It * 16 + lc];
+                    const C x = S.XT[4 * s + lg][(It - 1) * 16 + lc];
                     xr[s] = x.x;
                     xi[s] = x.y;
                     xn[s] = -x.y;
@@ -2769,7 +2773,7 @@ int reg_kernel_variants(int cls) { return cls >= 0 && cls < kRegClasses ? kRegSh
 const char *reg_variant_name(int cls, int v) {
     static const char *names[kRegClasses][6] = {
         {"lu_reg<double,8,8,4,4>", "lu_reg<double,8,16,4,2>", "lu_mfma_f64<2,1,1>", "lu_mfma_f64<2,1,2>",
-         "lu_mfma_f64<2,2,2>"},
+         "lu_mfma_f64<2,1,1,3>"},
         {"lu_reg<double,16,16,4,4>", "lu_reg<double,8,16,8,4>", "lu_reg<double,16,32,4,2>", "lu_mfma_f64<4,2,2>",
          "lu_mfma_f64<4,1,2>", "lu_mfma_f64<4,2,2,3>"},
         {"lu_reg<double,16,32,6,3>", "lu_reg<double,16,16,6,6>", "lu_mfma_f64<6,2,2>", "lu_mfma_f64<6,2,4>",
@@ -2789,7 +2793,7 @@ hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
         case 1: return launch_reg<8, 16, 4, 2>(a, st);
         case 2: return launch_mfma64<2, 1, 1>(a, st);
         case 3: return launch_mfma64<2, 1, 2>(a, st);
-        case 4: return launch_mfma64<2, 2, 2>(a, st);
+        case 4: return launch_mfma64<2, 1, 1, 3>(a, st);
         case 8: return launch_reg<16, 16, 4, 4>(a, st);
         case 9: return launch_reg<8, 16, 8, 4>(a, st);
         case 10: return launch_reg<16, 32, 4, 2>(a, st);
@@ -2862,7 +2866,7 @@ const char *mfma_variant_name(int cls, int v) {
     static const char *names[kMfmaClasses][8] = {
         {"lu_mfma_f32<2,1,2>", "lu_mfma_f32<2,1,1>", "lu_mfma_f32<2,2,2>"},
         {"lu_mfma_f32<4,1,2,4>", "lu_mfma_f32<4,1,2,3>", "lu_mfma_f32<4,2,2,5>", "lu_mfma_f32<4,2,2,4>",
-         "lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,2,4>"},
+         "lu_mfma_f32<4,2,2>", "lu_mfma_f32<4,1,2>", "lu_mfma_f32<4,1,1>", "lu_mfma_f32<4,1,1,3>"},
         {"lu_mfma_f32<6,2,2,3>", "lu_mfma_f32<6,2,4>", "lu_mfma_f32<6,2,2>", "lu_mfma_f32<6,3,2>",
          "lu_mfma_f32<6,2,2,4>"},
         {"lu_mfma_f32<8,2,4>"},
@@ -2884,7 +2888,7 @@ hipError_t launch_lu_mfma(int cls, int v, const LuLaunch &a, hipStream_t st) {
         case 12: return launch_mfma<4, 2, 2>(a, st);
         case 13: return launch_mfma<4, 1, 2>(a, st);
         case 14: return launch_mfma<4, 1, 1>(a, st);
-        case 15: return launch_mfma<4, 2, 4>(a, st);
+        case 15: return launch_mfma<4, 1, 1, 3>(a, st);
         case 16: return launch_mfma<6, 2, 2, 3>(a, st);
         case 17: return launch_mfma<6, 2, 4>(a, st);
         case 18: return launch_mfma<6, 2, 2>(a, st);
@@ -3163,12 +3167,12 @@ hipError_t prepare_kernels(int big_ldw, int schur_maxA, int pair_ldw) {
         if (e != hipSuccess) return e;
     for (hipError_t e : {prepare_mfma<2, 1, 2>(), prepare_mfma<2, 1, 1>(), prepare_mfma<2, 2, 2>(),
                          prepare_mfma<4, 2, 2>(), prepare_mfma<4, 1, 2>(), prepare_mfma<4, 1, 1>(),
-                         prepare_mfma<4, 2, 4>(), prepare_mfma<6, 2, 4>(), prepare_mfma<6, 2, 2>(),
+                         prepare_mfma<4, 1, 1, 3>(), prepare_mfma<6, 2, 4>(), prepare_mfma<6, 2, 2>(),
                          prepare_mfma<6, 3, 2>(), prepare_mfma<8, 2, 4>(), prepare_mfma<9, 3, 4>(),
                          prepare_mfma<12, 2, 4>(), prepare_mfma<4, 2, 2, 4>(), prepare_mfma<4, 1, 2, 3>(),
                          prepare_mfma<6, 2, 2, 3>(), prepare_mfma<4, 2, 2, 5>(), prepare_mfma<4, 1, 2, 4>(),
                          prepare_mfma<6, 2, 2, 4>(), prepare_mfma64<2, 1, 1>(), prepare_mfma64<2, 1, 2>(),
-                         prepare_mfma64<2, 2, 2>(), prepare_mfma64<4, 2, 2>(), prepare_mfma64<4, 1, 2>(),
+                         prepare_mfma64<2, 1, 1, 3>(), prepare_mfma64<4, 2, 2>(), prepare_mfma64<4, 1, 2>(),
                          prepare_mfma64<4, 2, 2, 3>(), prepare_mfma64<6, 2, 2>(), prepare_mfma64<6, 2, 4>(),
                          prepare_mfma64<6, 3, 2>()})
         if (e != hipSuccess) return e;
