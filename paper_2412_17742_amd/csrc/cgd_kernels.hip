@@ -851,17 +851,24 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
         // A += (-X) W: real part (-Xr) Wr + Xi Wi, imaginary part (-Xr) Wi + (-Xi) Wr.
         // Operands from LDS: A = -X[row, 16J + 4s + l/16] per tile row, B =
         // W[4s + l/16, col] per pass (not held across the diagonal inversion).
+        // The real part needs one negated operand (-Xi Wi): it is taken on
+        // the W side when a wave holds fewer tile columns than tile rows, else
+        // on the X side.  W is read only for the tile columns in use (the MFMA
+        // loop below skips exactly the others).
         auto update = [&](int pass) {
-            T wr_[TCW][4], wi_[TCW][4];
+            constexpr bool NEG_W = TCW < TRW;
+            T wr_[TCW][4], wi_[TCW][4], wn_[TCW][4];
             #pragma unroll
             for (int tj = 0; tj < TCW; ++tj) {
                 const int Jt = wc + tj * WC;
-                #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    C w = mk2<T>(T(0), T(0));
-                    if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) w = S.W[4 * s + lg][(Jt - 1) * 16 + lc];
-                    wr_[tj][s] = w.x;
-                    wi_[tj][s] = w.y;
+                if (Jt > J && Jt < ntl && (pass == 0 || Jt != Jn)) {
+                    #pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const C w = S.W[4 * s + lg][(Jt - 1) * 16 + lc];
+                        wr_[tj][s] = w.x;
+                        wi_[tj][s] = w.y;
+                        if constexpr (NEG_W) wn_[tj][s] = -w.y;
+                    }
                 }
             }
             #pragma unroll
@@ -875,7 +882,7 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
                     const C x = S.XT[4 * s + lg][(It - 1) * 16 + lc];
                     xr[s] = x.x;
                     xi[s] = x.y;
-                    xn[s] = -x.y;
+                    if constexpr (!NEG_W) xn[s] = -x.y;
                 }
                 #pragma unroll
                 for (int tj = 0; tj < TCW; ++tj) {
@@ -887,7 +894,10 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
                     for (int s = 0; s < 4; ++s) {
                         ar[ti][tj] = MfmaT<T>::mfma(xr[s], wr_[tj][s], ar[ti][tj]);
                         ai[ti][tj] = MfmaT<T>::mfma(xr[s], wi_[tj][s], ai[ti][tj]);
-                        ar[ti][tj] = MfmaT<T>::mfma(xn[s], wi_[tj][s], ar[ti][tj]);
+                        if constexpr (NEG_W)
+                            ar[ti][tj] = MfmaT<T>::mfma(xi[s], wn_[tj][s], ar[ti][tj]);
+                        else
+                            ar[ti][tj] = MfmaT<T>::mfma(xn[s], wi_[tj][s], ar[ti][tj]);
                         ai[ti][tj] = MfmaT<T>::mfma(xi[s], wr_[tj][s], ai[ti][tj]);
                     }
                 }
