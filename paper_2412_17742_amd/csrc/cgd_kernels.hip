@@ -67,6 +67,33 @@ __device__ __forceinline__ double2 clog(double2 d) {
     return cmk(0.5 * log(d.x * d.x + d.y * d.y), atan2(d.y, d.x));
 }
 
+// Sum over i = tid, tid + nt, ... of the principal logarithms of pivot i
+// (i < nl) and of the eigenvalue factor 1 - w_A lambda_i (i < n_eig).  Where
+// both factors of an index lie in the right half-plane their arguments add
+// up to less than pi in modulus, so the logarithm of their product is the
+// sum of the two logarithms: one log and one atan2 per index instead of two.
+template <typename PV>
+__device__ __forceinline__ double2 pivot_eig_logs(const PV *piv, int nl, const double *__restrict__ lam, int n_eig,
+                                                  double2 wa, int tid, int nt) {
+    double2 acc = cmk(0.0, 0.0);
+    const int n = nl > n_eig ? nl : n_eig;
+    for (int i = tid; i < n; i += nt) {
+        double2 f = cmk(1.0, 0.0), g = cmk(1.0, 0.0);
+        if (i < nl) f = cmk((double)piv[i].x, (double)piv[i].y);
+        if (i < n_eig) g = cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]);
+        double2 lg;
+        if (f.x > 0.0 && g.x > 0.0) {
+            lg = clog(cmul(f, g));
+        } else {
+            const double2 a = clog(f), b = clog(g);
+            lg = cmk(a.x + b.x, a.y + b.y);
+        }
+        acc.x += lg.x;
+        acc.y += lg.y;
+    }
+    return acc;
+}
+
 // Value of w at grid index k of an axis of extent G: the root of unity
 // exp(2 pi i k / G), or, on a circle of radius rho > 0 in t (moments mode),
 // w = exp(t) with t = rho exp(2 pi i k / G).
@@ -373,21 +400,8 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
 
         // epilogue: -1/2 [sum_i Log(pivot_i) + sum_i Log(1 - w_A lambda_i)] + E, in FP64
         const int nlog = nS;
-        double2 acc = cmk(0.0, 0.0);
-        for (int i = tid; i < nlog; i += NT) {
-            const double2 lg = clog(cmk((double)s_piv[i].x, (double)s_piv[i].y));
-            acc.x += lg.x;
-            acc.y += lg.y;
-        }
-        if (B.n_eig > 0) {
-            const double2 wa = s_w[B.schur_axis];
-            const double *__restrict__ lam = A.eigpool + B.eig_off;
-            for (int i = tid; i < B.n_eig; i += NT) {
-                const double2 lg = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
-                acc.x += lg.x;
-                acc.y += lg.y;
-            }
-        }
+        double2 acc = pivot_eig_logs(s_piv, nlog, A.eigpool + B.eig_off, B.n_eig,
+                                     B.n_eig > 0 ? s_w[B.schur_axis] : cmk(0.0, 0.0), tid, NT);
         acc = block_sum<NT>(acc, s_red);
         if (tid == 0) {
             double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
@@ -912,21 +926,8 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
         __syncthreads();
     }
 
-    double2 acc = cmk(0.0, 0.0);
-    for (int i = tid; i < nl; i += NT) {
-        const double2 lgv = clog(cmk((double)S.piv[i].x, (double)S.piv[i].y));
-        acc.x += lgv.x;
-        acc.y += lgv.y;
-    }
-    if (B.n_eig > 0) {
-        const double2 wa = S.w[B.schur_axis];
-        const double *__restrict__ lam = A.eigpool + B.eig_off;
-        for (int i = tid; i < B.n_eig; i += NT) {
-            const double2 lgv = clog(cmk(1.0 - wa.x * lam[i], -wa.y * lam[i]));
-            acc.x += lgv.x;
-            acc.y += lgv.y;
-        }
-    }
+    double2 acc = pivot_eig_logs(S.piv, nl, A.eigpool + B.eig_off, B.n_eig,
+                                 B.n_eig > 0 ? S.w[B.schur_axis] : cmk(0.0, 0.0), tid, NT);
     acc = block_sum<NT>(acc, S.red);
     if (tid == 0) {
         double2 res = cmk(-0.5 * acc.x, -0.5 * acc.y);
