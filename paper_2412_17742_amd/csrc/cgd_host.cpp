@@ -1327,7 +1327,7 @@ cgd_status autotune(cgd_ctx *c) {
         hipError_t e = hipMemcpy(d_items, items.data(), sizeof(int2) * S, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(d_aux, cnt, sizeof(cnt), hipMemcpyHostToDevice);
         LuLaunch a{nullptr, nullptr, 0, 0, d_items, d_aux, S, c->d_blocks, c->d_inst, c->d_pool, c->d_rb, c->d_eig,
-                   c->d_contrib, d_aux + 1, c->d_tpool};
+                   c->d_contrib, d_aux + 1, c->d_tpool, c->d_tw};
         std::vector<double> t64(n64, -1.0), t32(n32, -1.0);
         for (int v = 0; v < n64 && e == hipSuccess; ++v)
             e = timed([&] { return k < kRegClasses ? launch_lu_reg(k, v, a, st)
@@ -1826,15 +1826,17 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     for (auto &d : c->inst) Lmax = std::max(Lmax, d.L);
     {
         std::vector<double2> tw;
-        for (const InstDev &I : c->inst)
+        for (InstDev &I : c->inst)
             for (int l = 0; l < I.L; ++l) {
                 const int G = I.G[l];
-                if (c->tw_of.count(G)) continue;
-                c->tw_of[G] = (int64_t)tw.size();
-                for (int m = 0; m < G; ++m) {
-                    const double a = -2.0 * M_PI * (double)m / (double)G;
-                    tw.push_back(make_double2(std::cos(a), std::sin(a)));
+                if (!c->tw_of.count(G)) {
+                    c->tw_of[G] = (int64_t)tw.size();
+                    for (int m = 0; m < G; ++m) {
+                        const double a = -2.0 * M_PI * (double)m / (double)G;
+                        tw.push_back(make_double2(std::cos(a), std::sin(a)));
+                    }
                 }
+                I.tw_off[l] = (int32_t)c->tw_of[G];  // the LU kernels read their roots of unity here
             }
         cgd_status s;
         if ((s = upload(&c->d_tw, tw)) != CGD_OK) return s;
@@ -2145,7 +2147,7 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
     auto launch64 = [&](int k, const int2 *list, const int *count, int64_t cap) -> hipError_t {
         const LuClass &g = c->g64[k];
         LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, list, count, cap, c->d_blocks,
-                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool};
+                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw};
         return k < kRegClasses ? launch_lu_reg(k, c->reg_var[k], a, st)
                                : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
     };
@@ -2153,7 +2155,7 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         for (auto &g : c->g32) {
             if (g.nitems == 0) continue;
             LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, nullptr, nullptr, 0, c->d_blocks,
-                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool};
+                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw};
             HIP_OK(mark_begin(lu_stage(g.cls)));
             HIP_OK(launch_lu_mfma(g.cls, c->mfma_var[g.cls], a, st));
             HIP_OK(mark(lu_stage(g.cls), 1));

@@ -36,6 +36,7 @@ struct InstDev {
     int32_t pad5;
     int64_t E;                // values per evaluated point: (N + 1)^(2 g) in density mode, else 1
     int64_t gv_off;           // first value of this instance in the per-point value table (and DFT buffers)
+    int32_t tw_off[kMaxBins]; // axis l: first of its G_l twiddles exp(-2 pi i m / G_l) in the twiddle table
 };
 
 // One factorisation job family: an (instance, internal block) pair.  Every
@@ -168,6 +169,7 @@ struct LuLaunch {
     double2 *contrib;
     int *status;
     double2 *tpool;            // density mode: trailing Schur complements
+    const double2 *tw;         // twiddles exp(-2 pi i m / G) (InstDev::tw_off), or nullptr
 };
 
 // launchers (cgd_kernels.hip)

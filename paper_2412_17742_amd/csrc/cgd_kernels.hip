@@ -118,8 +118,17 @@ __device__ __forceinline__ int point_k(const InstDev &I, int64_t p, int l) {
     if (l > 0) k %= (unsigned)I.G[l];
     return (int)k;
 }
-__device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, double2 &w) {
-    w = grid_w(point_k(I, p, l), I.G[l], I.rho);
+// On the unit circle w is read from the twiddle table when one is given:
+// exp(2 pi i k / G) is the conjugate of the stored exp(-2 pi i k / G).
+__device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, double2 &w,
+                                        const double2 *__restrict__ tw = nullptr) {
+    const int k = point_k(I, p, l);
+    if (tw != nullptr && I.rho == 0.0) {
+        const double2 t = tw[I.tw_off[l] + k];
+        w = cmk(t.x, -t.y);
+    } else {
+        w = grid_w(k, I.G[l], I.rho);
+    }
 }
 
 // Largest c with prefix[c] <= item (prefix[0] = 0, strictly usable entries n).
@@ -251,6 +260,7 @@ struct LuArgs {
     double2 *contrib;
     int *status;
     double2 *tpool;           // density mode: trailing Schur complements (nkeep + bordered)^2 per point
+    const double2 *tw;        // twiddle table (roots of unity read instead of computed), or nullptr
 };
 
 template <typename T, int PR, int PC, int TR, int TC>
@@ -295,7 +305,7 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
         const int nS = nb - B.bordered - B.nkeep;
         const int nstop = B.nkeep ? nS : nb;
 
-        if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+        if (tid < I.L) point_w(I, pt, tid, s_w[tid], A.tw);
         if (tid == 0) s_bad = 0;
         __syncthreads();
         // s_d = -d on the matrix rows, 0 on the padding: S = I + (-D) H
@@ -680,7 +690,7 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
     const int nl = nb - B.bordered;  // pivots of S (the border's need not be in the right half-plane)
     const int ntl = (nb + 15) >> 4;  // tiles in use
 
-    if (tid < I.L) point_w(I, pt, tid, S.w[tid]);
+    if (tid < I.L) point_w(I, pt, tid, S.w[tid], A.tw);
     if (tid == 0) S.bad = 0;
     __syncthreads();
     // S.d = -d on the matrix rows, 0 on the padding: S = I + (-D) H
@@ -2750,7 +2760,7 @@ __global__ void mixed_err(const InstDev *__restrict__ insts, const double2 *__re
 template <int PR, int PC, int TR, int TC>
 static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw};
     // one item per workgroup; for a device-built list the grid covers its capacity and
     // workgroups past the list's length return at once
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
@@ -2825,7 +2835,7 @@ hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
 template <int NTILE, int WR, int WC, int OCC = 1>
 static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
@@ -2836,7 +2846,7 @@ static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
 template <int NTILE, int WR, int WC, int OCC>
 static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((lu_mfma_f64<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
