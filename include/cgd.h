@@ -85,7 +85,9 @@ typedef enum {
                                       reduction). */
 #define CGD_FLAG_NO_HESSENBERG 16u /* never take the Hessenberg route                        */
 #define CGD_FLAG_GRAD 4u           /* prepare cgd_grad (keeps each internal block's full
-                                      matrix on the device); needs 2M(+1) <= 96 per block */
+                                      matrix on the device); needs 2M(+1) <= 481 per block
+                                      (above 96: a blocked inverse with an HBM workspace
+                                      of up to 512 x order^2 x 16 bytes) */
 #define CGD_FLAG_MOMENTS 64u       /* cgd_eval writes, per instance and in the layout of the
                                       probabilities, the coarse-grained joint moments
                                       E[prod_l b_l^{p_l}] for p_l in [0, cutoff_l] (Sec. VI C,

@@ -722,6 +722,8 @@ struct cgd_ctx {
     GradBlockDev *d_gblocks = nullptr;
     double2 *d_gpool = nullptr, *d_partial = nullptr, *d_z = nullptr, *d_adjA = nullptr, *d_adjB = nullptr,
             *d_ghat = nullptr;
+    double2 *d_adj_work = nullptr;  // adjoint class 3: adj_nwg workspaces of adj_ldw x adj_ldw
+    int adj_ldw = 0, adj_nwg = 0;
     int32_t *d_grb = nullptr;
     int64_t *d_z_prefix = nullptr, *d_adj_off = nullptr, *d_prob_prefix = nullptr;
     // HIP graph of the evaluation
@@ -765,6 +767,7 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_hess_all); fr(c->d_hess_sprefix); fr(c->d_eigc); fr(c->d_htable);
     fr(c->d_pairs); fr(c->d_pair_prefix); fr(c->d_perm); fr(c->d_pair_work);
     for (auto &k : c->gadj) { fr(k.d_jobs); fr(k.d_prefix); }
+    fr(c->d_adj_work);
     fr(c->d_gblocks); fr(c->d_gpool); fr(c->d_partial); fr(c->d_z); fr(c->d_adjA); fr(c->d_adjB); fr(c->d_ghat);
     fr(c->d_grb); fr(c->d_z_prefix); fr(c->d_adj_off); fr(c->d_prob_prefix);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
@@ -875,7 +878,9 @@ cgd_status build_grad(cgd_ctx *c, int n_inst) {
         int cls = -1;
         for (int k = 0; k < kAdjClasses; ++k)
             if (d.nb <= adj_class_limit(k)) { cls = k; break; }
-        if (cls < 0) return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD: block order above 96 is not supported");
+        if (cls < 0)
+            return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD: block order above " + std::to_string(kAdjBigMax) +
+                                         " is not supported");
         bcls[b] = cls;
         d.h_off = (int64_t)gpool.size();
         for (const cplx &z : g.Hf.a) gpool.push_back(make_double2(z.real(), z.imag()));
@@ -957,6 +962,22 @@ cgd_status build_grad(cgd_ctx *c, int n_inst) {
     for (auto &st : c->adj_stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
+    }
+    // class 3 (orders above the register kernels): a persistent grid, one
+    // ldw x ldw workspace per workgroup
+    {
+        int64_t items3 = 0;
+        c->adj_ldw = 0;
+        for (int32_t b : c->gadj[3].jobs) {
+            items3 += c->gblocks[b].nchunks;
+            c->adj_ldw = std::max(c->adj_ldw, c->gblocks[b].nb);
+        }
+        c->adj_nwg = (int)std::min<int64_t>(items3, 512);
+        if (c->adj_nwg > 0) {
+            HIP_OK(prepare_adj_big(c->adj_ldw));
+            HIP_OK(hipMalloc((void **)&c->d_adj_work,
+                             sizeof(double2) * (size_t)c->adj_nwg * c->adj_ldw * c->adj_ldw));
+        }
     }
     HIP_OK(hipMalloc((void **)&c->d_partial, sizeof(double2) * std::max<int64_t>(1, c->adj_items * c->part_stride)));
     HIP_OK(hipMalloc((void **)&c->d_z, sizeof(double2) * std::max<int64_t>(1, c->z_total)));
@@ -2331,7 +2352,8 @@ cgd_status cgd_grad(cgd_ctx *c, const double *d_dprobs, double *d_dr, double *d_
         for (int32_t bj : g.jobs) nitems += c->gblocks[bj].nchunks;
         // job prefix holds absolute item indices; the launch covers this class's items
         AdjArgs a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), c->adj_chunk, c->d_gblocks, c->d_inst, c->d_gpool,
-                  c->d_grb, c->d_logg, c->d_ghat, c->d_partial, c->part_stride};
+                  c->d_grb, c->d_logg, c->d_ghat, c->d_partial, c->part_stride, 0, c->d_adj_work, c->adj_ldw,
+                  c->adj_nwg};
         HIP_OK(launch_adjoint(g.cls, a, nitems, g.prefix[0], st));
     }
     HIP_OK(launch_adjoint_reduce(c->d_gblocks, c->d_z_prefix, (int)c->gblocks.size(), c->z_total, c->d_partial,

@@ -140,6 +140,9 @@ struct AdjArgs {
     double2 *partial;
     int64_t part_stride;
     int item_base;             // absolute index of the launch's first item
+    double2 *work;             // orders above the register classes: ldw x ldw workspace per workgroup
+    int ldw;
+    int nwg;                   // workgroups (each loops over items)
 };
 
 // One axis pass of the separable inverse DFT for one instance.
@@ -195,7 +198,10 @@ hipError_t launch_schur_build(const SchurDev *jobs, const int64_t *prefix, int n
                               hipStream_t st);
 // adjoint
 int adj_class_limit(int cls);
-constexpr int kAdjClasses = 3;
+constexpr int kAdjClasses = 4;  // 0..2: register kernels (orders <= 96); 3: blocked, workspace in HBM
+constexpr int kAdjBigMax = 481;  // largest bordered order of class 3 (its LDS: 151 KB)
+size_t adj_big_lds_bytes(int ldw);
+hipError_t prepare_adj_big(int ldw);
 hipError_t launch_adjoint(int cls, const AdjArgs &a, int nitems, int64_t item_base, hipStream_t st);
 hipError_t launch_adjoint_reduce(const GradBlockDev *gblocks, const int64_t *elem_prefix, int ngb, int64_t total,
                                  const double2 *partial, int64_t part_stride, double2 *zout, hipStream_t st);

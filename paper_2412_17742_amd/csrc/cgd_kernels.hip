@@ -2559,6 +2559,232 @@ lu_adjoint(const AdjArgs A)
     if (tid == 0) out[(int64_t)n * n + n] = z0;
 }
 
+// Adjoint for blocks of order above the register classes: the same per-point
+// sums as lu_adjoint, with Q = S'^-1 formed by a blocked Gauss-Jordan
+// inversion in a per-workgroup workspace in HBM, kPanel columns per step.
+// With K the step's rows and columns and D = A_KK (its inverse by
+// Gauss-Jordan in LDS),
+//     A_KK <- D^-1,   A_Kj <- D^-1 A_Kj,   A_iK <- -A_iK D^-1,
+//     A_ij <- A_ij - A_iK D^-1 A_Kj        (i, j outside K),
+// which leaves S'^-1 in place after the last step (no pivoting: each D is a
+// trailing Schur complement block of S', whose pivots are those of the LU).
+// The weighted sums are added into the item's slot of the partials (each
+// element always by the same thread).  Persistent: workgroups loop over items.
+// ---------------------------------------------------------------------------
+size_t adj_big_lds_bytes(int ldw) {
+    return sizeof(double2) * ((size_t)ldw * kPanel + kPanel * 64 + kPanel * kPanel + (size_t)ldw);
+}
+
+__global__ void __launch_bounds__(kBigThreads) adj_big_f64(const AdjArgs A, int nitems)
+{
+    static_assert(kBigThreads == kPanel * kPanel, "one thread per element of the pivot block");
+    extern __shared__ double2 s_dyn[];
+    const int ldw = A.ldw;
+    double2 *s_panel = s_dyn;                           // ldw x kPanel: the step's column panel, all rows
+    double2 *s_utile = s_panel + (size_t)ldw * kPanel;  // kPanel x 64: a tile of the new row panel
+    double2 *s_dinv = s_utile + kPanel * 64;            // kPanel x kPanel: D, then D^-1
+    double2 *s_d = s_dinv + kPanel * kPanel;            // ldw: d(w) per row
+    double2 *s_qc = s_panel;                            // after the inversion: column n of Q
+    double2 *s_qr = s_panel + ldw;                      //                      row n of Q
+    __shared__ double2 s_w[kMaxBins];
+    __shared__ double2 s_om;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    double2 *__restrict__ W = A.work + (size_t)blockIdx.x * ldw * ldw;
+
+    for (int it_ = blockIdx.x; it_ < nitems; it_ += gridDim.x) {
+        const int item = A.item_base + it_;
+        const int job = find_job(A.job_prefix, A.njobs, item);
+        const GradBlockDev GB = A.gblocks[A.job_block[job]];
+        const InstDev &I = A.insts[GB.inst];
+        const int nb = GB.nb;
+        const int n = nb - GB.bordered;
+        const int64_t p0 = (int64_t)(item - A.job_prefix[job]) * A.chunk;
+        const int64_t p1 = p0 + A.chunk < I.npts ? p0 + A.chunk : I.npts;
+        const double2 *__restrict__ H = A.pool + GB.h_off;
+        double2 *__restrict__ out = A.partial + (int64_t)item * A.part_stride;
+        const int64_t nout = (int64_t)n * n + n + 1;
+        int64_t stride0 = 1;
+        for (int l = 1; l < I.L; ++l) stride0 *= I.G[l];
+        __syncthreads();  // the previous item's last reads are done
+        for (int64_t e = tid; e < nout; e += kBigThreads) out[e] = cmk(0.0, 0.0);
+
+        for (int64_t pt = p0; pt < p1; ++pt) {
+            __syncthreads();
+            if (tid < I.L) point_w(I, pt, tid, s_w[tid]);
+            if (tid == 0) {
+                const double2 lg = A.logg[I.pt_off + pt];
+                const double2 gh = A.ghat[I.pt_off + pt];
+                const int64_t k1 = pt / stride0;
+                const double ck = (k1 == 0 || 2 * k1 == I.G[0]) ? 1.0 : 2.0;
+                double sn, cs;
+                sincos(lg.y, &sn, &cs);
+                const double m = ck * exp(lg.x);
+                s_om = cmul(cmk(m * cs, m * sn), gh);
+            }
+            __syncthreads();
+            for (int i = tid; i < nb; i += kBigThreads) {
+                const int b = A.rbpool[GB.rb_off + i];
+                s_d[i] = b < 0 ? cmk(1.0, 0.0) : s_w[b];
+            }
+            __syncthreads();
+            const double2 om = s_om;
+            for (int64_t e = tid; e < (int64_t)nb * nb; e += kBigThreads) {
+                const int i = (int)(e / nb), j = (int)(e - (int64_t)i * nb);
+                const double2 h = H[e];
+                const double2 d = s_d[i];
+                double2 v = cmk(i == j ? 1.0 : 0.0, 0.0);
+                v.x -= d.x * h.x - d.y * h.y;
+                v.y -= d.x * h.y + d.y * h.x;
+                W[(size_t)i * ldw + j] = v;
+            }
+            __syncthreads();
+
+            for (int k0 = 0; k0 < nb; k0 += kPanel) {
+                const int kb = min(kPanel, nb - k0);
+                for (int e = tid; e < nb * kPanel; e += kBigThreads) {
+                    const int i = e / kPanel, t = e - i * kPanel;
+                    s_panel[e] = t < kb ? W[(size_t)i * ldw + k0 + t] : cmk(0.0, 0.0);
+                }
+                __syncthreads();
+                // D^-1 in LDS, one element per thread (identity outside kb x kb)
+                const int r = tid / kPanel, c = tid - (tid / kPanel) * kPanel;
+                s_dinv[tid] = (r < kb && c < kb) ? s_panel[(size_t)(k0 + r) * kPanel + c]
+                                                 : cmk(r == c ? 1.0 : 0.0, 0.0);
+                __syncthreads();
+                for (int kk = 0; kk < kb; ++kk) {
+                    const double2 pinv = cinv(s_dinv[kk * kPanel + kk]);
+                    const double2 a_rk = s_dinv[r * kPanel + kk];
+                    const double2 a_kc = s_dinv[kk * kPanel + c];
+                    const double2 a_rc = s_dinv[tid];
+                    __syncthreads();
+                    const double2 u = cmul(a_kc, pinv);
+                    double2 v;
+                    if (r == kk && c == kk) v = pinv;
+                    else if (r == kk) v = u;
+                    else if (c == kk) v = cmk(-(a_rk.x * pinv.x - a_rk.y * pinv.y), -(a_rk.x * pinv.y + a_rk.y * pinv.x));
+                    else v = cfnms(a_rc, a_rk, u);
+                    s_dinv[tid] = v;
+                    __syncthreads();
+                }
+                // row panel: A_Kj <- D^-1 A_Kj, one column j outside K per thread
+                for (int j = tid; j < nb; j += kBigThreads) {
+                    if (j >= k0 && j < k0 + kb) continue;
+                    double2 x[kPanel];
+                    #pragma unroll
+                    for (int t = 0; t < kPanel; ++t) x[t] = t < kb ? W[(size_t)(k0 + t) * ldw + j] : cmk(0.0, 0.0);
+                    #pragma unroll
+                    for (int t = 0; t < kPanel; ++t) {
+                        if (t >= kb) break;
+                        double2 y = cmk(0.0, 0.0);
+                        #pragma unroll
+                        for (int s2 = 0; s2 < kPanel; ++s2) y = cfma(s_dinv[t * kPanel + s2], x[s2], y);
+                        W[(size_t)(k0 + t) * ldw + j] = y;
+                    }
+                }
+                __syncthreads();
+                // A_ij -= C_i (D^-1 A_Kj) for every i, j outside K, in 64 x 64 tiles
+                for (int jt = 0; jt < nb; jt += 64) {
+                    for (int e = tid; e < kPanel * 64; e += kBigThreads) {
+                        const int t = e / 64, jj = jt + (e - (e / 64) * 64);
+                        const bool ok = t < kb && jj < nb && (jj < k0 || jj >= k0 + kb);
+                        s_utile[e] = ok ? W[(size_t)(k0 + t) * ldw + jj] : cmk(0.0, 0.0);
+                    }
+                    __syncthreads();
+                    for (int it = 0; it < nb; it += 64) {
+                        double2 acc[4][4];
+                        #pragma unroll
+                        for (int a = 0; a < 4; ++a)
+                            #pragma unroll
+                            for (int b = 0; b < 4; ++b) {
+                                const int i = it + ty + 16 * a, j = jt + tx + 16 * b;
+                                acc[a][b] = (i < nb && j < nb) ? W[(size_t)i * ldw + j] : cmk(0.0, 0.0);
+                            }
+                        for (int t = 0; t < kb; ++t) {
+                            double2 l[4], u[4];
+                            #pragma unroll
+                            for (int a = 0; a < 4; ++a) {
+                                const int i = it + ty + 16 * a;
+                                l[a] = (i < nb && (i < k0 || i >= k0 + kb)) ? s_panel[(size_t)i * kPanel + t]
+                                                                            : cmk(0.0, 0.0);
+                            }
+                            #pragma unroll
+                            for (int b = 0; b < 4; ++b) u[b] = s_utile[t * 64 + tx + 16 * b];
+                            #pragma unroll
+                            for (int a = 0; a < 4; ++a)
+                                #pragma unroll
+                                for (int b = 0; b < 4; ++b) acc[a][b] = cfnms(acc[a][b], l[a], u[b]);
+                        }
+                        #pragma unroll
+                        for (int a = 0; a < 4; ++a)
+                            #pragma unroll
+                            for (int b = 0; b < 4; ++b) {
+                                const int i = it + ty + 16 * a, j = jt + tx + 16 * b;
+                                if (i < nb && j < nb && (i < k0 || i >= k0 + kb) && (j < k0 || j >= k0 + kb))
+                                    W[(size_t)i * ldw + j] = acc[a][b];
+                            }
+                    }
+                    __syncthreads();
+                }
+                // column panel: A_iK <- -C_i D^-1 outside K, and D^-1 on K
+                for (int e = tid; e < nb * kPanel; e += kBigThreads) {
+                    const int i = e / kPanel, cc = e - i * kPanel;
+                    if (cc >= kb) continue;
+                    double2 v;
+                    if (i >= k0 && i < k0 + kb) {
+                        v = s_dinv[(i - k0) * kPanel + cc];
+                    } else {
+                        double2 y = cmk(0.0, 0.0);
+                        for (int s2 = 0; s2 < kb; ++s2) y = cfma(s_panel[(size_t)i * kPanel + s2], s_dinv[s2 * kPanel + cc], y);
+                        v = cmk(-y.x, -y.y);
+                    }
+                    W[(size_t)i * ldw + k0 + cc] = v;
+                }
+                __syncthreads();
+            }
+
+            // accumulate omega W, omega g, omega (as lu_adjoint)
+            if (GB.bordered)
+                for (int i = tid; i < nb; i += kBigThreads) {
+                    s_qc[i] = W[(size_t)i * ldw + n];
+                    s_qr[i] = W[(size_t)n * ldw + i];
+                }
+            __syncthreads();
+            const double2 qnn = GB.bordered ? s_qc[n] : cmk(1.0, 0.0);
+            const double2 pb = cinv(qnn);
+            const double2 pp = cmk(pb.x * pb.x - pb.y * pb.y - pb.x, 2.0 * pb.x * pb.y - pb.y);  // p^2 - p
+            for (int64_t e = tid; e < (int64_t)n * n; e += kBigThreads) {
+                const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+                double2 q = W[(size_t)i * ldw + j];
+                if (GB.bordered) {
+                    const double2 t = cmul(pp, cmul(s_qc[i], s_qr[j]));
+                    q.x += t.x;
+                    q.y += t.y;
+                }
+                const double2 ow = cmul(om, cmul(cmk(0.5 * q.x, 0.5 * q.y), s_d[j]));
+                out[e].x += ow.x;
+                out[e].y += ow.y;
+            }
+            if (GB.bordered) {
+                const int half = n / 2;
+                for (int i = tid; i < n; i += kBigThreads) {
+                    const int ip = i < half ? i + half : i - half;
+                    const double2 t = cmul(s_d[ip], s_qr[ip]);
+                    const double2 g = cmul(cmk(-0.5 * pb.x, -0.5 * pb.y), cmk(s_qc[i].x + t.x, s_qc[i].y + t.y));
+                    const double2 og = cmul(om, g);
+                    out[(int64_t)n * n + i].x += og.x;
+                    out[(int64_t)n * n + i].y += og.y;
+                }
+            }
+            if (tid == 0) {
+                out[(int64_t)n * n + n].x += om.x;
+                out[(int64_t)n * n + n].y += om.y;
+            }
+        }
+    }
+}
+
 // Sum the chunk partials of every gradient block in a fixed order.
 __global__ void adjoint_reduce(const GradBlockDev *__restrict__ gblocks, const int64_t *__restrict__ elem_prefix,
                                int ngb, int64_t total, const double2 *__restrict__ partial, int64_t part_stride,
@@ -3065,8 +3291,14 @@ int adj_class_limit(int cls) {
         case 0: return 32;
         case 1: return 64;
         case 2: return 96;
+        case 3: return kAdjBigMax;
         default: return 0;
     }
+}
+
+hipError_t prepare_adj_big(int ldw) {
+    return hipFuncSetAttribute((const void *)adj_big_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)adj_big_lds_bytes(ldw));
 }
 
 hipError_t launch_adjoint(int cls, const AdjArgs &a0, int nitems, int64_t item_base, hipStream_t st) {
@@ -3077,6 +3309,12 @@ hipError_t launch_adjoint(int cls, const AdjArgs &a0, int nitems, int64_t item_b
         case 0: return launch_adj<8, 8, 4, 4>(a, nitems, st);
         case 1: return launch_adj<16, 16, 4, 4>(a, nitems, st);
         case 2: return launch_adj<16, 32, 6, 3>(a, nitems, st);
+        case 3: {
+            if (a.work == nullptr || a.ldw <= 0 || a.nwg <= 0) return hipErrorInvalidValue;
+            const int grid = nitems < a.nwg ? nitems : a.nwg;
+            hipLaunchKernelGGL(adj_big_f64, dim3(grid), dim3(kBigThreads), adj_big_lds_bytes(a.ldw), st, a, nitems);
+            return hipGetLastError();
+        }
         default: return hipErrorInvalidValue;
     }
 }

@@ -159,3 +159,78 @@ def test_mesh_gradient_matches_autograd_oracle_at_full_shape():
     es = np.abs(ds.cpu().numpy() - g["schmidt"]).max() / np.abs(g["schmidt"]).max()
     _say(f"  mesh set 0: relative max error r {er:.2e}, T {eT:.2e}, lambda {es:.2e}")
     assert er < 1e-9 and eT < 1e-9 and es < 1e-9
+
+
+def test_adjoint_above_order_96_matches_autograd_oracle():
+    """Blocks of order 98 to 105 (M = 49..52, two bins, one displaced) take the
+    blocked adjoint (Gauss-Jordan inverse in an HBM workspace), batched with a
+    small instance on the register kernel: dL/dr, dL/dT, dL/dalpha and
+    dL/dlambda against the autograd oracle."""
+    import torch
+    rng = W.rng_for(81)
+    insts = []
+    M = 52
+    T = np.sqrt(0.6) * W.haar_unitary(M, rng)
+    alpha = 0.2 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    insts.append(W.make_instance(T, rng.uniform(0.2, 0.6, M), alpha=alpha, bin_of=W.contiguous_bins([26, 26]),
+                                 cutoff=[2, 2], grid=[3, 3]))
+    M = 49
+    T = np.sqrt(0.7) * W.haar_unitary(M, rng)
+    insts.append(W.make_instance(T, rng.uniform(0.2, 0.6, M), schmidt=[0.7, 0.3], bin_of=W.contiguous_bins([24, 25]),
+                                 cutoff=[2, 3], grid=[3, 4]))
+    insts.append(_small_instances()[1])
+    dPs = [np.random.default_rng(11 + i).standard_normal(tuple(int(c) + 1 for c in x["cutoff"]))
+           for i, x in enumerate(insts)]
+    _say("adjoint above order 96 vs autograd oracle")
+    with cgd.Context(insts, flags=cgd.FLAG_GRAD) as ctx:
+        ctx.eval()
+        dP = torch.tensor(np.concatenate([d.ravel() for d in dPs]), dtype=torch.float64, device="cuda")
+        dr, dT, da, ds = ctx.grad(dP, schmidt=True)
+        torch.cuda.synchronize()
+        dr, dT, da, ds = (t.cpu().numpy() for t in (dr, dT, da, ds))
+    ro = to = so = 0
+    for x, d in zip(insts, dPs):
+        M = x["T"].shape[0]
+        K = 1 if x.get("schmidt") is None else len(x["schmidt"])
+        g = og.gradients_full(x, d)
+
+        def rel(a, b):
+            return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+        er = rel(dr[ro:ro + M], g["r"])
+        eT = rel(dT[to:to + M * M].reshape(M, M), g["T"])
+        _say(f"  M = {M}: relative max error r {er:.2e}, T {eT:.2e}")
+        assert er < 1e-9 and eT < 1e-9
+        if g["alpha"] is not None:
+            assert rel(da[ro:ro + M], g["alpha"]) < 1e-9
+        else:
+            assert np.abs(da[ro:ro + M]).max() == 0.0
+        if g["schmidt"] is not None:
+            assert rel(ds[so:so + K], g["schmidt"]) < 1e-9
+        ro += M
+        to += M * M
+        so += K
+
+
+def test_adjoint_at_order_243_matches_autograd_oracle():
+    """A displaced 121-mode instance (bordered order 243: fifteen full
+    16-column steps of the blocked inverse and a last one of 3) against the
+    autograd oracle."""
+    import torch
+    rng = W.rng_for(82)
+    M = 121
+    T = np.sqrt(0.5) * W.haar_unitary(M, rng)
+    alpha = 0.1 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    x = W.make_instance(T, rng.uniform(0.1, 0.4, M), alpha=alpha, bin_of=W.contiguous_bins([60, 61]),
+                        cutoff=[1, 2], grid=[2, 3])
+    d = np.random.default_rng(13).standard_normal((2, 3))
+    _say("adjoint at order 243 vs autograd oracle")
+    with cgd.Context([x], flags=cgd.FLAG_GRAD) as ctx:
+        ctx.eval()
+        dr, dT, da = (t.cpu().numpy() for t in ctx.grad(torch.tensor(d.ravel(), dtype=torch.float64, device="cuda")))
+        torch.cuda.synchronize()
+    g = og.gradients_full(x, d)
+    for name, a, b in (("r", dr, g["r"]), ("T", dT.reshape(M, M), g["T"]), ("alpha", da, g["alpha"])):
+        e = np.abs(a - b).max() / np.abs(b).max()
+        _say(f"  {name}: relative max error {e:.2e}")
+        assert e < 1e-9, name
