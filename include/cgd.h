@@ -326,8 +326,12 @@ cgd_status cgd_bounds(const cgd_ctx *ctx, int32_t *grid, double *wrap_bound);
  * keeps, of each kind, the first shape within 2% of the fastest (so that
  * shapes that time alike do not flip between runs).  On the mixed path a class whose best FP32
  * pass is not below 0.5 of its best FP64 time is evaluated directly in FP64
- * (no FP32 error, nothing to factorise again).  Per class: every time (ms),
- * the chosen kernels and the precision. */
+ * (no FP32 error, nothing to factorise again).  On the sample the tuner also
+ * compares each FP32 item with its FP64 value: fp32_err_ratio_max is the largest
+ * difference in units of the assumed FP32 error of the block, and where it
+ * exceeds 0.5 the assumed error of the class's blocks is scaled up by
+ * ratio / 0.5 (the error bound only grows).  Per class: every time (ms),
+ * the chosen kernels, the precision and that ratio. */
 const char *cgd_tuning(const cgd_ctx *ctx);
 
 /* Pin the kernel shape of a size class (0..4: orders <= 32, 64, 96, 128, 144),

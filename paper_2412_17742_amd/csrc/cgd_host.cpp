@@ -26,7 +26,10 @@ namespace {
 // accretive matrix stored in FP32, log accumulated in FP64).  Measured on every
 // grid point of five workloads, the largest relative error was 0.56 tau; the
 // mixed-path tests check the model on workloads with other seeds and shapes.
+// The autotuner checks it again on its sample of each context's FP32 items and
+// scales tau up wherever the sample's largest error exceeds kTauMargin tau.
 constexpr double kTauScale = 2.0;
+constexpr double kTauMargin = 0.5;
 
 // moments mode: default number of points per axis on the circle in t
 constexpr int kMomentPoints = 24;
@@ -653,6 +656,7 @@ struct cgd_ctx {
     int big_ldw = 0, big_nwg = 0;
     // Hessenberg route
     std::vector<char> is_hess;
+    std::vector<double> tau_scale;   // per block: factor on the FP32 error model (1 unless the sample showed more)
     std::vector<HessDev> hess_all;
     std::vector<int64_t> hess_sprefix;
     int64_t hess_spts = 0, hess_ntab = 0, hess_nec = 0;
@@ -1271,6 +1275,7 @@ constexpr double kTuneTie = 0.02;
 cgd_status autotune(cgd_ctx *c) {
     for (int k = 0; k < kRegClasses; ++k) c->reg_var[k] = 0;
     for (int k = 0; k < kMfmaClasses; ++k) c->mfma_var[k] = 0;
+    c->tau_scale.assign(c->blocks.size(), 1.0);
     if (c->flags & CGD_FLAG_NO_AUTOTUNE) {
         c->tune_json = "{\"autotune\": false, \"classes\": []}";
         return make_lu_lists(c);
@@ -1356,8 +1361,36 @@ cgd_status autotune(cgd_ctx *c) {
                       t64[v]);
         LuLaunch a32 = a;
         a32.pool = c->d_pool32;
+        // the FP32 error model checked on the sample: each item's contribution
+        // (the block's term of log G at the point) from the FP32 kernel against
+        // the FP64 one, in units of the block's assumed relative error of G
+        std::vector<double2> c64;
+        if (n32 > 0 && e == hipSuccess) {
+            c64.resize(c->ncontrib);
+            e = hipMemcpy(c64.data(), c->d_contrib, sizeof(double2) * c->ncontrib, hipMemcpyDeviceToHost);
+        }
         for (int v = 0; v < n32 && e == hipSuccess; ++v)
             e = timed([&] { return launch_lu_mfma(k, v, a32, st); }, t32[v]);
+        double ratio32 = -1.0;
+        if (n32 > 0 && e == hipSuccess) {
+            std::vector<double2> c32(c->ncontrib);
+            e = hipMemcpy(c32.data(), c->d_contrib, sizeof(double2) * c->ncontrib, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) {
+                ratio32 = 0.0;
+                for (const int2 &it : items) {
+                    const BlockDev &d = c->blocks[it.x];
+                    const InstDev &I = c->inst[d.inst];
+                    const int64_t slot = I.c_off + (int64_t)it.y * I.nblocks + d.blk;
+                    const double dx = c32[slot].x - c64[slot].x, dy = c32[slot].y - c64[slot].y;
+                    const double tau_b = kTauScale * (d.nb + 1) * 5.9604644775390625e-08;
+                    ratio32 = std::max(ratio32, std::sqrt(dx * dx + dy * dy) / tau_b);
+                }
+                // keep a margin of two over what the sample shows (the model's own
+                // margin on the workloads that set it); the bound only ever grows
+                const double scale = std::max(1.0, ratio32 / kTauMargin);
+                for (int32_t b : blk) c->tau_scale[b] = scale;
+            }
+        }
         if (e != hipSuccess) {
             result = fail(CGD_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
             break;
@@ -1396,7 +1429,8 @@ cgd_status autotune(cgd_ctx *c) {
         rep += std::string(first ? "" : ", ") + "{\"class\": " + std::to_string(k) +
                ", \"max_order\": " + std::to_string(maxn) + ", \"items\": " + std::to_string((long long)total) +
                ", \"sample\": " + std::to_string((long long)S) + ", \"fp64_ms\": {" + f64s + "}, \"fp32_ms\": {" +
-               f32s + "}, \"fp64_kernel\": \"" + (k < kRegClasses ? reg_variant_name(k, b64) : "lu_big_f64") +
+               f32s + "}, " + (ratio32 >= 0.0 ? "\"fp32_err_ratio_max\": " + std::to_string(ratio32) + ", " : "") +
+               "\"fp64_kernel\": \"" + (k < kRegClasses ? reg_variant_name(k, b64) : "lu_big_f64") +
                "\", \"fp32_kernel\": \"" + (keep32 ? mfma_variant_name(k, b32) : "") + "\", \"precision\": \"" +
                (keep32 ? "fp32+fp64" : "fp64") + "\"}";
         first = false;
@@ -1409,8 +1443,10 @@ cgd_status autotune(cgd_ctx *c) {
     c->tune_json = rep + "]}";
     // tau of each instance from the blocks left with an FP32 pass
     for (InstDev &I : c->inst) I.tau = 0.0;
-    for (const BlockDev &d : c->blocks)
-        if (d.fp32) c->inst[d.inst].tau += kTauScale * (d.nb + 1) * 5.9604644775390625e-08;
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        const BlockDev &d = c->blocks[b];
+        if (d.fp32) c->inst[d.inst].tau += c->tau_scale[b] * kTauScale * (d.nb + 1) * 5.9604644775390625e-08;
+    }
     HIP_OK(hipMemcpy(c->d_blocks, c->blocks.data(), sizeof(BlockDev) * c->blocks.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->d_inst, c->inst.data(), sizeof(InstDev) * c->inst.size(), hipMemcpyHostToDevice));
     const cgd_status sl = make_lu_lists(c);

@@ -202,7 +202,8 @@ def _check_pick(times, chosen):
 
 def test_autotuner_report_and_choices():
     """The tuner's report names every size class it timed, keeps the first
-    kernel shape of each kind within 2% of the fastest, and sends a mixed class straight to FP64 unless
+    kernel shape of each kind within 2% of the fastest, checks the FP32 error
+    model on its sample, and sends a mixed class straight to FP64 unless
     its FP32 pass is below 0.5 of the FP64 time; the mixed result stays within
     its bound either way."""
     insts = W.uneven_batch(64)
@@ -219,6 +220,10 @@ def test_autotuner_report_and_choices():
                 if prec == "fp64":
                     assert not f32 and c["precision"] == "fp64"
                 elif f32:
+                    # the FP32 error model checked on the tuner's own sample: within
+                    # the model (the tuner scales tau up beyond half of it)
+                    _say(f"    class {c['class']}: largest sampled FP32 error / tau = {c['fp32_err_ratio_max']:.3f}")
+                    assert 0.0 <= c["fp32_err_ratio_max"] <= 1.0, c
                     fast32 = min(f32.values()) < 0.5 * min(f64.values())
                     assert c["precision"] == ("fp32+fp64" if fast32 else "fp64")
                     if fast32:
