@@ -563,6 +563,7 @@ struct LuClass {
     int64_t nitems = 0;
     int32_t *d_jobs = nullptr;
     int64_t *d_prefix = nullptr;
+    int32_t *d_hint = nullptr;  // per 64 items: the job of the first (LU range launches)
 };
 
 // Blocks that can take the Hessenberg route: the first bin eliminated through
@@ -762,8 +763,8 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_tpool); fr(c->d_dinst); fr(c->d_dprefix); fr(c->d_hprefix);
     fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list); fr(c->d_list_off);
     fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
-    for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); }
-    for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); }
+    for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
+    for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); fr(s.d_cdesc); fr(s.d_cprefix); }
     fr(c->d_tw);
     for (auto &s : c->adj_stages) { fr(s.d_desc); fr(s.d_prefix); }
@@ -1228,10 +1229,23 @@ cgd_status upload_lu_lists(cgd_ctx *c) {
         for (int k = 0; k < n; ++k) {
             fr(grp[k].d_jobs);
             fr(grp[k].d_prefix);
+            fr(grp[k].d_hint);
             grp[k].d_jobs = nullptr;
             grp[k].d_prefix = nullptr;
+            grp[k].d_hint = nullptr;
             if ((s = upload(&grp[k].d_jobs, grp[k].jobs)) != CGD_OK) return s;
             if ((s = upload(&grp[k].d_prefix, grp[k].prefix)) != CGD_OK) return s;
+            // the job of items 0, 64, 128, ...: the kernels start their job
+            // lookup there instead of a binary search over the whole prefix
+            const LuClass &g = grp[k];
+            std::vector<int32_t> hint((size_t)((g.nitems + 63) / 64));
+            int32_t j = 0;
+            for (size_t q = 0; q < hint.size(); ++q) {
+                const int64_t t = (int64_t)q * 64;
+                while (j + 1 < (int32_t)g.prefix.size() && g.prefix[j + 1] <= t) ++j;
+                hint[q] = j;
+            }
+            if (!hint.empty() && (s = upload(&grp[k].d_hint, hint)) != CGD_OK) return s;
         }
     }
     if (c->prec != CGD_PREC_MIXED) return CGD_OK;
@@ -2204,7 +2218,8 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
     auto launch64 = [&](int k, const int2 *list, const int *count, int64_t cap) -> hipError_t {
         const LuClass &g = c->g64[k];
         LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, list, count, cap, c->d_blocks,
-                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw};
+                   c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw,
+                   list ? nullptr : g.d_hint};
         return k < kRegClasses ? launch_lu_reg(k, c->reg_var[k], a, st)
                                : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
     };
@@ -2212,7 +2227,8 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         for (auto &g : c->g32) {
             if (g.nitems == 0) continue;
             LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, nullptr, nullptr, 0, c->d_blocks,
-                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw};
+                       c->d_inst, c->d_pool32, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw,
+                       g.d_hint};
             HIP_OK(mark_begin(lu_stage(g.cls)));
             HIP_OK(launch_lu_mfma(g.cls, c->mfma_var[g.cls], a, st));
             HIP_OK(mark(lu_stage(g.cls), 1));

@@ -173,6 +173,7 @@ struct LuLaunch {
     int *status;
     double2 *tpool;            // density mode: trailing Schur complements
     const double2 *tw;         // twiddles exp(-2 pi i m / G) (InstDev::tw_off), or nullptr
+    const int32_t *job_hint;   // per 64 items: the job of the chunk's first item (range launches), or nullptr
 };
 
 // launchers (cgd_kernels.hip)

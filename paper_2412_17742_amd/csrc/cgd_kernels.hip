@@ -132,13 +132,26 @@ __device__ __forceinline__ void point_w(const InstDev &I, int64_t p, int l, doub
 }
 
 // Largest c with prefix[c] <= item (prefix[0] = 0, strictly usable entries n).
-__device__ __forceinline__ int find_job(const int64_t *__restrict__ prefix, int n, int64_t item) {
-    int lo = 0, hi = n - 1;
+__device__ __forceinline__ int find_job(const int64_t *__restrict__ prefix, int n, int64_t item, int lo = 0) {
+    int hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+// The same from a hint: hint[item / 64] is the job of item 64 (item / 64), so
+// the answer is at most a few entries further; a short forward scan replaces
+// the chain of dependent loads of the binary search (which takes over when
+// the scan runs long).
+__device__ __forceinline__ int find_job_hinted(const int64_t *__restrict__ prefix, int n, int64_t item,
+                                               const int32_t *__restrict__ hint) {
+    int j = hint[item >> 6];
+    for (int step = 0; step < 4; ++step) {
+        if (j + 1 >= n || prefix[j + 1] > item) return j;
+        ++j;
+    }
+    return find_job(prefix, n, item, j);
 }
 
 // Block-wide sum of a complex value over NT threads (deterministic order).
@@ -261,6 +274,7 @@ struct LuArgs {
     int *status;
     double2 *tpool;           // density mode: trailing Schur complements (nkeep + bordered)^2 per point
     const double2 *tw;        // twiddle table (roots of unity read instead of computed), or nullptr
+    const int32_t *job_hint;  // job of item 64 c, per c (range launches), or nullptr
 };
 
 template <typename T, int PR, int PC, int TR, int TC>
@@ -293,7 +307,8 @@ __global__ void __launch_bounds__(PR *PC) lu_reg(const LuArgs A)
             bi = e.x;
             pt = e.y;
         } else {
-            const int job = find_job(A.job_prefix, A.njobs, item);
+            const int job = A.job_hint ? find_job_hinted(A.job_prefix, A.njobs, item, A.job_hint)
+                                      : find_job(A.job_prefix, A.njobs, item);
             bi = A.job_block[job];
             pt = item - A.job_prefix[job];
         }
@@ -680,7 +695,8 @@ __device__ __forceinline__ void lu_mfma_body(const LuArgs &A)
         bi = e.x;
         pt = e.y;
     } else {
-        const int job = find_job(A.job_prefix, A.njobs, item);
+        const int job = A.job_hint ? find_job_hinted(A.job_prefix, A.njobs, item, A.job_hint)
+                                      : find_job(A.job_prefix, A.njobs, item);
         bi = A.job_block[job];
         pt = item - A.job_prefix[job];
     }
@@ -2986,7 +3002,7 @@ __global__ void mixed_err(const InstDev *__restrict__ insts, const double2 *__re
 template <int PR, int PC, int TR, int TC>
 static hipError_t launch_reg(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw, a.job_hint};
     // one item per workgroup; for a device-built list the grid covers its capacity and
     // workgroups past the list's length return at once
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
@@ -3061,7 +3077,7 @@ hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st) {
 template <int NTILE, int WR, int WC, int OCC = 1>
 static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw, a.job_hint};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((lu_mfma_f32<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
@@ -3072,7 +3088,7 @@ static hipError_t launch_mfma(const LuLaunch &a, hipStream_t st) {
 template <int NTILE, int WR, int WC, int OCC>
 static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st) {
     LuArgs A{a.job_block, a.job_prefix, a.njobs, a.nitems, a.list, a.list_count, a.blocks, a.insts, a.pool,
-             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw};
+             a.rbpool, a.eigpool, a.contrib, a.status, a.tpool, a.tw, a.job_hint};
     const int64_t grid = a.list ? a.list_capacity : a.nitems;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((lu_mfma_f64<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
