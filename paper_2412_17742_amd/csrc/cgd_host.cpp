@@ -654,6 +654,7 @@ struct cgd_ctx {
     // mixed path: FP32 MFMA groups for the first pass
     LuClass g64[kG64];
     LuClass g32[kMfmaClasses];
+    LuClass g64one;  // FP64 blocks of order <= 16 (one tile) outside density mode: lu_mfma_f64<1,1,1>
     int big_ldw = 0, big_nwg = 0;
     // Hessenberg route
     std::vector<char> is_hess;
@@ -764,6 +765,7 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_work); fr(c->d_status); fr(c->d_pool32); fr(c->d_logg32); fr(c->d_list); fr(c->d_list_off);
     fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
+    fr(c->g64one.d_jobs); fr(c->g64one.d_prefix); fr(c->g64one.d_hint);
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); fr(s.d_cdesc); fr(s.d_cprefix); }
     fr(c->d_tw);
@@ -1166,6 +1168,10 @@ cgd_status make_lu_lists(cgd_ctx *c) {
         g.prefix.clear();
         g.nitems = 0;
     }
+    c->g64one.cls = 0;
+    c->g64one.jobs.clear();
+    c->g64one.prefix.clear();
+    c->g64one.nitems = 0;
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         const BlockDev &d = c->blocks[b];
         if (c->is_hess[b]) continue;
@@ -1178,6 +1184,10 @@ cgd_status make_lu_lists(cgd_ctx *c) {
         if (d.fp32) {
             lc = &c->g32[mfma_class_of(d.nb)];
             c->list_cap[d.cls] += np;
+        } else if (d.nb <= 16 && !d.nkeep) {
+            // one 16 x 16 tile: a kernel sized for it (a quarter of the
+            // registers and no panels, so several times the waves per CU)
+            lc = &c->g64one;
         }
         lc->prefix.push_back(lc->nitems);
         lc->jobs.push_back((int32_t)b);
@@ -1218,14 +1228,18 @@ void lu_work(cgd_ctx *c) {
             const BlockDev &d = c->blocks[bj];
             c->work_flops[lu_stage(k)] += lu_flops(d.nb) * c->inst[d.inst].npts;
         }
+    for (int32_t bj : c->g64one.jobs) {
+        const BlockDev &d = c->blocks[bj];
+        c->work_flops[lu_stage(0)] += block_flops(d) * c->inst[d.inst].npts;
+    }
 }
 
 // device copies of the work lists and the mixed path's list layout
 cgd_status upload_lu_lists(cgd_ctx *c) {
     auto fr = [](void *p) { if (p) (void)hipFree(p); };
     cgd_status s;
-    for (auto *grp : {&c->g64[0], &c->g32[0]}) {
-        const int n = grp == &c->g64[0] ? kG64 : kMfmaClasses;
+    for (auto *grp : {&c->g64[0], &c->g32[0], &c->g64one}) {
+        const int n = grp == &c->g64[0] ? kG64 : grp == &c->g32[0] ? kMfmaClasses : 1;
         for (int k = 0; k < n; ++k) {
             fr(grp[k].d_jobs);
             fr(grp[k].d_prefix);
@@ -2234,9 +2248,16 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
             HIP_OK(mark(lu_stage(g.cls), 1));
         }
     for (int k = 0; k < kG64; ++k) {
-        if (c->g64[k].nitems == 0) continue;
+        const bool one = k == 0 && c->g64one.nitems > 0;
+        if (c->g64[k].nitems == 0 && !one) continue;
         HIP_OK(mark_begin(lu_stage(k)));
-        HIP_OK(launch64(k, nullptr, nullptr, 0));
+        if (c->g64[k].nitems > 0) HIP_OK(launch64(k, nullptr, nullptr, 0));
+        if (one) {
+            const LuClass &g = c->g64one;
+            LuLaunch a{g.d_jobs, g.d_prefix, (int)g.jobs.size(), g.nitems, nullptr, nullptr, 0, c->d_blocks,
+                       c->d_inst, c->d_pool, c->d_rb, c->d_eig, b.contrib, c->d_status, b.tpool, c->d_tw, g.d_hint};
+            HIP_OK(launch_lu_one_tile(a, st));
+        }
         HIP_OK(mark(lu_stage(k), 1));
     }
     HIP_OK(mark(CGD_STAGE_COMBINE, 0));
@@ -2466,6 +2487,7 @@ cgd_status cgd_mixed_stats(cgd_ctx *c, int64_t *n_refactored, int64_t *n_total) 
         tot += h[k];
         all += c->g64[k].nitems;
     }
+    all += c->g64one.nitems;
     for (int k = 0; k < kMfmaClasses; ++k) all += c->g32[k].nitems;
     if (n_refactored) *n_refactored = tot;
     if (n_total) *n_total = all;

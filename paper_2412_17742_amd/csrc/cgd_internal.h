@@ -186,6 +186,8 @@ int reg_variants(int cls);
 int reg_kernel_variants(int cls);      // the first ones: register-kernel shapes (density mode needs one)
 const char *reg_variant_name(int cls, int v);
 hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st);
+// FP64 factorisations of order <= 16 (range launches): lu_mfma_f64<1,1,1>
+hipError_t launch_lu_one_tile(const LuLaunch &a, hipStream_t st);
 constexpr int kMfmaClasses = 6;
 int mfma_class_limit(int cls);         // max matrix order of FP32 MFMA class cls
 int mfma_variants(int cls);

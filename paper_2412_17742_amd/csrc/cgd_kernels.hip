@@ -651,9 +651,9 @@ struct MfmaLds {
     typedef cx2<T> C;
     static constexpr int N = 16 * NTILE;
     // The panels hold tile rows (X) and tile columns (W) 1 .. NTILE - 1 only:
-    // tile 0 is never below or right of a diagonal tile.
-    static_assert(NTILE >= 2, "one tile needs no panels");
-    static constexpr int NP = N - 16;  // panel width
+    // tile 0 is never below or right of a diagonal tile (one tile: no panels,
+    // a placeholder column).
+    static constexpr int NP = NTILE > 1 ? N - 16 : 1;  // panel width
     static constexpr int XS = NP + 1;  // padded stride of the transposed X panel
     C XT[16][XS];                      // -X^T of the step's tile column, tile rows 1 ..
     C W[16][NP];                       // W = D^-1 Y, tile columns 1 ..
@@ -3094,6 +3094,11 @@ static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st) {
     hipLaunchKernelGGL((lu_mfma_f64<NTILE, WR, WC, OCC>), dim3((unsigned)grid), dim3(64 * WR * WC),
                        sizeof(MfmaLds<double, NTILE, WR, WC>), st, A);
     return hipGetLastError();
+}
+
+hipError_t launch_lu_one_tile(const LuLaunch &a, hipStream_t st) {
+    if (a.list || a.nitems <= 0) return a.list ? hipErrorInvalidValue : hipSuccess;
+    return launch_mfma64<1, 1, 1>(a, st);
 }
 
 template <int NTILE, int WR, int WC, int OCC = 1>
