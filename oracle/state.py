@@ -15,6 +15,11 @@ squeezing of internal mode k follows the paper's two-mode relation
 (Eq. relation_between_sqz_par) generalised to K modes:
 tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j.
 
+Fully distinguishable inputs (App. D: spectrally orthogonal single-mode
+squeezed states interfering in the circuit): K = M internal modes, input j
+squeezed by r_j in internal mode j only (r_jk = r_j delta_jk), instance key
+"distinguishable".
+
 Everything is dense complex128 over all 2MK quadrature indices; no block
 structure is exploited here.
 """
@@ -33,7 +38,14 @@ def squeezing_per_internal_mode(r: np.ndarray, schmidt) -> np.ndarray:
     return np.arctanh(np.sqrt(ratio)[None, :] * np.tanh(r)[:, None])
 
 
-def output_moments(T, r, alpha=None, schmidt=None):
+def n_internal(inst) -> int:
+    """K of an instance: M for fully distinguishable inputs, else len(schmidt) (1 if none)."""
+    if inst.get("distinguishable", 0):
+        return np.asarray(inst["T"]).shape[0]
+    return 1 if inst.get("schmidt") is None else len(inst["schmidt"])
+
+
+def output_moments(T, r, alpha=None, schmidt=None, distinguishable=False):
     """Normally ordered moments of the output modes.
 
     Inputs are single-mode squeezed vacua S(r)|0> (S(xi) = exp[(xi a^dag^2 -
@@ -45,7 +57,11 @@ def output_moments(T, r, alpha=None, schmidt=None):
     Returns (N, M, beta) over the M*K output modes, external-major."""
     T = np.asarray(T, dtype=np.complex128)
     m = T.shape[0]
-    rk = squeezing_per_internal_mode(r, schmidt)
+    if distinguishable:
+        assert schmidt is None and alpha is None
+        rk = np.diag(np.asarray(r, dtype=np.float64))  # r_jk = r_j delta_jk
+    else:
+        rk = squeezing_per_internal_mode(r, schmidt)
     K = rk.shape[1]
     Tfull = np.kron(T, np.eye(K))  # a_out[i*K+k] = sum_j T[i,j] a_in[j*K+k]
     n_in = np.sinh(rk).ravel() ** 2
@@ -108,7 +124,7 @@ def marginal(Sigma, zbar, keep):
 def fine_bins(inst) -> np.ndarray:
     """Bin index for each of the M*K fine (internal-resolved) modes."""
     M = inst["T"].shape[0]
-    K = 1 if inst["schmidt"] is None else len(inst["schmidt"])
+    K = n_internal(inst)
     b = np.asarray(inst["bin_of"], dtype=np.int64)
     if inst.get("resolve_internal", 0):
         assert b.shape[0] == M * K
@@ -120,7 +136,8 @@ def fine_bins(inst) -> np.ndarray:
 def assemble(inst):
     """Full dense state of an instance: dict with Sigma, zbar, A, gamma, pr0,
     and the per-fine-mode bin index."""
-    N, Mm, beta = output_moments(inst["T"], inst["r"], inst.get("alpha"), inst.get("schmidt"))
+    N, Mm, beta = output_moments(inst["T"], inst["r"], inst.get("alpha"), inst.get("schmidt"),
+                                 bool(inst.get("distinguishable", 0)))
     Sigma, zbar = covariance_and_means(N, Mm, beta)
     A, gamma = adjacency(Sigma, zbar)
     pr0 = vacuum_probability(A, gamma)

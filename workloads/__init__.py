@@ -60,12 +60,14 @@ def schmidt_geometric(K: int, ratio: float) -> np.ndarray | None:
 
 
 def make_instance(T, r, alpha=None, schmidt=None, bin_of=None, cutoff=None, grid=None,
-                  resolve_internal=0, fock_cutoff=None) -> dict:
+                  resolve_internal=0, fock_cutoff=None, distinguishable=0) -> dict:
     T = np.ascontiguousarray(T, dtype=np.complex128)
     M = T.shape[0]
     cutoff = np.asarray(cutoff, dtype=np.int32)
     grid = cutoff + 1 if grid is None else np.asarray(grid, dtype=np.int32)
     extra = {} if fock_cutoff is None else {"fock_cutoff": int(fock_cutoff)}
+    if distinguishable:
+        extra["distinguishable"] = 1
     return dict(**extra,
         T=T,
         r=np.ascontiguousarray(r, dtype=np.float64),
@@ -79,7 +81,21 @@ def make_instance(T, r, alpha=None, schmidt=None, bin_of=None, cutoff=None, grid
 
 
 def n_internal(inst: dict) -> int:
+    if inst.get("distinguishable", 0):
+        return inst["T"].shape[0]
     return 1 if inst["schmidt"] is None else len(inst["schmidt"])
+
+
+def distinguishable_instance(M, seed, bins, cutoff, grid=None, eta=0.6, r_range=(0.3, 0.9)) -> dict:
+    """M single-mode squeezed vacua in mutually orthogonal spectral modes
+    (fully distinguishable, App. D) on sqrt(eta) x Haar: input j squeezed
+    (r_j ~ U[r_range]) in its own internal mode j; contiguous bins of the
+    given sizes, detectors blind to the internal mode."""
+    rng = rng_for(7000 + seed)
+    U = haar_unitary(M, rng)
+    r = rng.uniform(r_range[0], r_range[1], M)
+    return make_instance(np.sqrt(eta) * U, r, bin_of=contiguous_bins(bins), cutoff=cutoff, grid=grid,
+                         distinguishable=1)
 
 
 # ---------------------------------------------------------------------------
