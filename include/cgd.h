@@ -104,6 +104,8 @@ typedef enum {
    so the aliasing of the coefficients scales as 4^-G_l (cgd_bounds reports it
    as wrap_bound) and rounding grows as (4 / log(1/||H||))^{|p|} p!.  FP64 only,
    no CGD_FLAG_GRAD. */
+#define CGD_FLAG_NO_LOWRANK 256u   /* factorise low-rank blocks like the others (see
+                                      "Low-rank blocks"; for tests)                        */
 #define CGD_FLAG_NO_AUTOTUNE 32u   /* skip the autotuner of cgd_create: default kernel shape
                                       per size class, FP32 pass for every eligible class on
                                       the mixed path (see cgd_tuning)                      */
@@ -111,7 +113,7 @@ typedef enum {
 /* One instance (a Gaussian state plus its binning).  Sec. VI A (set partition
  * Lambda, coarse pattern b), Sec. VI B (internal modes). */
 typedef struct {
-    int32_t M;               /* external modes, >= 1                                          */
+    int32_t M;               /* external modes, >= 1; M*K <= 4096 (M <= 512 if distinguishable) */
     int32_t K;               /* internal (Schmidt) modes per external mode, >= 1              */
     int32_t L;               /* bins, 1..8                                                    */
     const double *T;         /* M*M complex: a_out[i] = sum_j T[i*M+j] a_in[j]; ||T||_2 <= 1  */
@@ -132,6 +134,10 @@ typedef struct {
                                 binned probabilities (needs a finite tol > 0; G_l <= 4096)    */
     int32_t fock_cutoff;     /* with kept modes: Fock cutoff N >= 0 of every kept mode; ignored
                                 otherwise                                                      */
+    int32_t distinguishable; /* 1: fully distinguishable inputs (App. D): input j carries its
+                                squeezing r_j in its own internal mode j and vacuum in the
+                                others, so K must equal M; schmidt and alpha must be NULL.
+                                Each internal block then has rank 2 (see "Low-rank blocks")    */
 } cgd_instance;
 
 #define CGD_KEEP (-2)
@@ -162,6 +168,25 @@ typedef struct {
  * CGD_FLAG_CUMULANTS; 2 g <= 16; D^2 <= 2^22; every internal block of order
  * <= 144 (heralding rows left after eliminating one bin, plus 2 g_k + 1 border
  * rows); at most 2^31 values per instance (grid points times D^2). */
+
+/* Low-rank blocks (App. D; Sec. VI B for the internal-mode blocks).  An
+ * internal block in which q inputs are squeezed has Sigma - I, and so
+ * H = I - Sigma^-1, of rank at most 2q: every block of an instance with
+ * distinguishable != 0 has rank 2 (its one squeezed input), and a K = 1
+ * instance with one or two squeezed inputs has rank 2 or 4.  When the rank
+ * r = 2q is at most 4 and at most half the block's order, the block has no
+ * displacement, no kept mode and CGD_FLAG_GRAD is off, cgd_create writes
+ * H = V diag(lambda) V^H over its r nonzero eigenvalues (it checks that the
+ * others vanish, |lambda| <= 1e-13, else the block takes the general route)
+ * and keeps the (L + 1) matrices G_g = diag(lambda) V^H E_g V of order r
+ * (E_g: the rows of bin g; one more for the traced rows).  Per grid point
+ * det(I - D(w) H) = det(I_r - G_t - sum_l w_l G_l) (Sylvester's identity), an
+ * r x r unpivoted LU in FP64 on both precision paths; the pivots lie in the
+ * right half-plane (I_r - C is a diagonal similarity transform of an
+ * accretive matrix), so the sum of their principal logarithms is the same
+ * continuous branch as the factorisation's.  CGD_FLAG_NO_LOWRANK sends these
+ * blocks through the general factorisation instead (results agree to
+ * rounding).  cgd_tuning's lowrank_blocks counts the blocks taken this way. */
 
 /* Assemble the states (FP64, host) and upload everything the evaluation
  * needs.  n_inst instances are evaluated together by cgd_eval.
@@ -331,7 +356,8 @@ cgd_status cgd_bounds(const cgd_ctx *ctx, int32_t *grid, double *wrap_bound);
  * difference in units of the assumed FP32 error of the block, and where it
  * exceeds 0.5 the assumed error of the class's blocks is scaled up by
  * ratio / 0.5 (the error bound only grows).  Per class: every time (ms),
- * the chosen kernels, the precision and that ratio. */
+ * the chosen kernels, the precision and that ratio.  lowrank_blocks counts
+ * the internal blocks evaluated by the low-rank route (no factorisation). */
 const char *cgd_tuning(const cgd_ctx *ctx);
 
 /* Pin the kernel shape of a size class (0..4: orders <= 32, 64, 96, 128, 144),

@@ -28,6 +28,7 @@ FLAG_NO_HESSENBERG = 16
 FLAG_NO_AUTOTUNE = 32
 FLAG_MOMENTS = 64
 FLAG_CUMULANTS = 128
+FLAG_NO_LOWRANK = 256
 KEEP = -2  # bin_of value of a kept mode (heralded density matrices)
 # launch stages of one evaluation (per-stage timing); LU stages are order buckets
 STAGES = ["schur", "lu_le32", "lu_le64", "lu_le96", "lu_le128", "lu_le144", "lu_gt144", "combine", "dft", "fix",
@@ -56,7 +57,7 @@ class CgdInstance(ctypes.Structure):
         ("schmidt", ctypes.c_void_p), ("bin_of", ctypes.c_void_p),
         ("resolve_internal", ctypes.c_int32),
         ("cutoff", ctypes.c_void_p), ("grid", ctypes.c_void_p),
-        ("fock_cutoff", ctypes.c_int32),
+        ("fock_cutoff", ctypes.c_int32), ("distinguishable", ctypes.c_int32),
     ]
 
 
@@ -118,10 +119,17 @@ def _as(arr, dtype):
     return None if arr is None else np.ascontiguousarray(arr, dtype=dtype)
 
 
+def _internal_modes(inst: dict) -> int:
+    """K: M for fully distinguishable inputs, else the number of Schmidt weights (1 if none)."""
+    if inst.get("distinguishable", 0):
+        return int(np.asarray(inst["T"]).shape[0])
+    return 1 if inst.get("schmidt") is None else len(inst["schmidt"])
+
+
 def _marshal(inst: dict, keep: list) -> CgdInstance:
     T = _as(inst["T"], np.complex128)
     M = T.shape[0]
-    K = 1 if inst.get("schmidt") is None else len(inst["schmidt"])
+    K = _internal_modes(inst)
     arrays = dict(
         T=T, r=_as(inst["r"], np.float64), alpha=_as(inst.get("alpha"), np.complex128),
         schmidt=_as(inst.get("schmidt"), np.float64), bin_of=_as(inst["bin_of"], np.int32),
@@ -131,13 +139,13 @@ def _marshal(inst: dict, keep: list) -> CgdInstance:
     ptr = {k: (None if v is None else v.ctypes.data) for k, v in arrays.items()}
     return CgdInstance(M, K, len(arrays["cutoff"]), ptr["T"], ptr["r"], ptr["alpha"], ptr["schmidt"],
                        ptr["bin_of"], int(inst.get("resolve_internal", 0)), ptr["cutoff"], ptr["grid"],
-                       int(inst.get("fock_cutoff", 0)))
+                       int(inst.get("fock_cutoff", 0)), int(inst.get("distinguishable", 0)))
 
 
 def _density_dim(inst: dict):
     """D = (fock_cutoff + 1)^g for an instance with g kept modes, else None."""
     b = np.asarray(inst["bin_of"])
-    K = 1 if inst.get("schmidt") is None else len(inst["schmidt"])
+    K = _internal_modes(inst)
     g = int((b == KEEP).sum()) * (1 if inst.get("resolve_internal", 0) else K)
     return (int(inst.get("fock_cutoff", 0)) + 1) ** g if g else None
 
@@ -172,7 +180,7 @@ class Context:
         self.shapes = [tuple(int(c) + 1 for c in x["cutoff"]) for x in instances]
         self.density_dims = [_density_dim(x) for x in instances]
         self._M = [np.asarray(x["T"]).shape[0] for x in instances]
-        self._K = [1 if x.get("schmidt") is None else len(x["schmidt"]) for x in instances]
+        self._K = [_internal_modes(x) for x in instances]
 
     def eval(self, probs=None, err=None):
         """Wrapped distributions of all instances, concatenated (device float64)."""

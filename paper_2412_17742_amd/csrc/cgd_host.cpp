@@ -60,6 +60,8 @@ struct HostBlock {
     int schur_axis = -1;        // eliminated bin
     std::vector<double> eig;    // its eigenvalues
     CMat P, Q;                  // H_BA V and V^H H_AB
+    int lowrank = 0;            // > 0: rank of H (low-rank route, no factorisation per point)
+    std::vector<cplx> lr;       // then G_g = diag(lambda) V^H E_g V, g = traced rows, bins 0..L-1
 };
 
 // Gradient data of one internal block: the full (bordered) matrix before any
@@ -238,9 +240,16 @@ std::vector<int> kept_fine_modes(const cgd_instance &in) {
 cgd_status validate(const cgd_instance &in, int idx) {
     const std::string at = "instance " + std::to_string(idx) + ": ";
     if (in.M < 1 || in.K < 1 || in.L < 1 || in.L > kMaxBins) return fail(CGD_ERR_ARG, at + "need M >= 1, K >= 1, 1 <= L <= 8");
-    if ((int64_t)in.M * in.K > 4096) return fail(CGD_ERR_ARG, at + "M*K too large");
+    // M internal blocks of order 2M when the inputs are distinguishable, else K of order 2M (or one of 2MK)
+    if (in.distinguishable ? in.M > 512 : (int64_t)in.M * in.K > 4096)
+        return fail(CGD_ERR_ARG, at + (in.distinguishable ? "M > 512 with distinguishable inputs" : "M*K too large"));
     if (!in.T || !in.r || !in.bin_of || !in.cutoff) return fail(CGD_ERR_ARG, at + "T, r, bin_of and cutoff are required");
-    if (in.K > 1 && !in.schmidt) return fail(CGD_ERR_ARG, at + "schmidt weights required when K > 1");
+    if (in.distinguishable) {
+        if (in.K != in.M || in.schmidt || in.alpha)
+            return fail(CGD_ERR_ARG, at + "distinguishable inputs need K == M and no schmidt or alpha");
+    } else if (in.K > 1 && !in.schmidt) {
+        return fail(CGD_ERR_ARG, at + "schmidt weights required when K > 1");
+    }
     for (int i = 0; i < in.M * in.M * 2; ++i)
         if (!std::isfinite(in.T[i])) return fail(CGD_ERR_ARG, at + "T not finite");
     for (int i = 0; i < in.M; ++i) {
@@ -293,7 +302,8 @@ cgd_status validate(const cgd_instance &in, int idx) {
 // eigenbasis.
 cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int> &kset, bool dense,
                           bool use_schur, const std::vector<std::vector<double>> &rk, HostInst &hi,
-                          std::vector<HostBlock> &out, std::vector<GradHost> *grads, bool want_hnorm) {
+                          std::vector<HostBlock> &out, std::vector<GradHost> *grads, bool want_hnorm,
+                          bool lowrank_ok) {
     const int M = in.M;
     const int nk = (int)kset.size();
     const int m = M * nk;  // modes in this block
@@ -385,6 +395,60 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
     const double ld = logdet_hpd(Sig);
     if (!std::isfinite(ld)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": log det Sigma");
     hi.logpr0 += -0.5 * quad.real() - 0.5 * ld;  // Eq. vacuum_probability
+
+    // Low-rank blocks.  With q squeezed inputs in this internal mode, Sigma - I
+    // and so H = I - Sigma^-1 have rank at most 2q (every internal block of
+    // fully distinguishable inputs, App. D: rank 2).  With H = V diag(lambda)
+    // V^H over its r = 2q largest eigenvalues, det(I - D H) = det(I_r -
+    // diag(lambda) V^H D V) (Sylvester), and D is constant over the rows of a
+    // bin (1 on the traced rows), so per point the factor is the r x r
+    // determinant of I - (G_t + sum_l w_l G_l), G_g = diag(lambda) V^H E_g V
+    // (E_g: the rows of bin g, or the traced rows).  No matrix of order 2M
+    // is factorised per point.
+    if (lowrank_ok && kset.size() == 1 && !displaced && grads == nullptr) {
+        int nsq = 0;
+        for (int q = 0; q < M; ++q)
+            if (rk[q][kset[0]] != 0.0) ++nsq;
+        bool keeps = false;
+        for (int i = 0; i < n2; ++i)
+            if (bin_of_row(in, i, m, kset, dense) == CGD_KEEP) keeps = true;
+        const int r = 2 * nsq;
+        std::vector<double> lam;
+        std::vector<int> ord;
+        CMat V;
+        bool low = !keeps && r <= kLowRankMax && 2 * r <= n2;
+        if (low) {
+            CMat H(n2, n2);
+            for (int i = 0; i < n2; ++i)
+                for (int j = 0; j < n2; ++j) H(i, j) = (i == j ? 1.0 : 0.0) - Sinv(i, j);
+            if (!hermitian_eig_ql(H, lam, V)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+            ord.resize(n2);
+            for (int a = 0; a < n2; ++a) ord[a] = a;
+            std::sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(lam[a]) > std::fabs(lam[b]); });
+            // the eigenvalues past the r-th vanish up to rounding; otherwise the general route
+            low = std::fabs(lam[ord[r]]) <= 1e-13;
+        }
+        if (low) {
+            HostBlock hb;
+            hb.inst = idx;
+            hb.blk = hi.nblocks;
+            hb.nb = 0;
+            hb.lowrank = std::max(r, 1);
+            const int rr = hb.lowrank;
+            hb.lr.assign((size_t)(in.L + 1) * rr * rr, cplx(0, 0));
+            for (int i = 0; i < n2; ++i) {
+                const int b = bin_of_row(in, i, m, kset, dense);
+                const int g = b < 0 ? 0 : b + 1;
+                for (int a = 0; a < r; ++a)
+                    for (int c2 = 0; c2 < r; ++c2)
+                        hb.lr[((size_t)g * rr + a) * rr + c2] +=
+                            lam[ord[a]] * std::conj(V(i, ord[a])) * V(i, ord[c2]);
+            }
+            hi.nblocks++;
+            out.push_back(std::move(hb));
+            return CGD_OK;
+        }
+    }
 
     // Bordered H' over the state rows srow (every row that is not kept): H,
     // column -X gamma = -Sigma^-1 zbar, row -gamma^T (last).  Density mode: the
@@ -655,6 +719,11 @@ struct cgd_ctx {
     LuClass g64[kG64];
     LuClass g32[kMfmaClasses];
     LuClass g64one;  // FP64 blocks of order <= 16 (one tile) outside density mode: lu_mfma_f64<1,1,1>
+    std::vector<int32_t> lowrank_jobs;   // low-rank blocks and the prefix of their points
+    std::vector<int64_t> lowrank_prefix;
+    int64_t lowrank_items = 0;
+    int32_t *d_lowrank_jobs = nullptr;
+    int64_t *d_lowrank_prefix = nullptr;
     int big_ldw = 0, big_nwg = 0;
     // Hessenberg route
     std::vector<char> is_hess;
@@ -766,6 +835,7 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
     fr(c->g64one.d_jobs); fr(c->g64one.d_prefix); fr(c->g64one.d_hint);
+    fr(c->d_lowrank_jobs); fr(c->d_lowrank_prefix);
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); fr(s.d_cdesc); fr(s.d_cprefix); }
     fr(c->d_tw);
@@ -804,8 +874,12 @@ bool choose_hessenberg(const cgd_ctx *c, const std::vector<HostBlock> &hb, std::
                        std::vector<int> &pbins) {
     bool any = false;
     for (size_t b = 0; b < hb.size(); ++b) {
-        hbins[b] = hess_bin(hb[b]);
         pbins[b] = -1;
+        if (hb[b].lowrank) {  // no factorisation to replace
+            hbins[b] = -1;
+            continue;
+        }
+        hbins[b] = hess_bin(hb[b]);
         if (hbins[b] < 0 && !pair_bins(hb[b], c->inst[hb[b].inst], pbins[b], hbins[b])) {
             hbins[b] = -1;
             pbins[b] = -1;
@@ -1174,7 +1248,7 @@ cgd_status make_lu_lists(cgd_ctx *c) {
     c->g64one.nitems = 0;
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         const BlockDev &d = c->blocks[b];
-        if (c->is_hess[b]) continue;
+        if (c->is_hess[b] || d.lowrank) continue;
         if (d.cls == kRegClasses) {
             if (d.nb > 480) return fail(CGD_ERR_ARG, "matrix order above 480 per block is not supported");
             c->big_ldw = std::max(c->big_ldw, d.nb);
@@ -1304,11 +1378,12 @@ cgd_status autotune(cgd_ctx *c) {
     for (int k = 0; k < kRegClasses; ++k) c->reg_var[k] = 0;
     for (int k = 0; k < kMfmaClasses; ++k) c->mfma_var[k] = 0;
     c->tau_scale.assign(c->blocks.size(), 1.0);
+    const std::string nlow = "\"lowrank_blocks\": " + std::to_string(c->lowrank_jobs.size()) + ", ";
     if (c->flags & CGD_FLAG_NO_AUTOTUNE) {
-        c->tune_json = "{\"autotune\": false, \"classes\": []}";
+        c->tune_json = "{\"autotune\": false, " + nlow + "\"classes\": []}";
         return make_lu_lists(c);
     }
-    std::string rep = "{\"autotune\": true, \"classes\": [";
+    std::string rep = "{\"autotune\": true, " + nlow + "\"classes\": [";
     bool first = true;
     hipStream_t st = c->stream;
     const bool mixed = c->prec == CGD_PREC_MIXED;
@@ -1351,7 +1426,7 @@ cgd_status autotune(cgd_ctx *c) {
         }
         for (size_t b = 0; b < c->blocks.size(); ++b) {
             const BlockDev &d = c->blocks[b];
-            if (c->is_hess[b] || d.cls != k) continue;
+            if (c->is_hess[b] || d.lowrank || d.cls != k) continue;
             if (any32 && !(d.fp32 && mfma_class_of(d.nb) == k)) continue;
             blk.push_back((int32_t)b);
             total += c->inst[d.inst].npts;
@@ -1489,9 +1564,14 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     const bool dense = c->flags & CGD_FLAG_DENSE_INTERNAL;
     const bool use_schur = !(c->flags & CGD_FLAG_NO_SCHUR);
     const bool want_grad = c->flags & CGD_FLAG_GRAD;
+    const bool lowrank_ok = !(c->flags & CGD_FLAG_NO_LOWRANK) && !want_grad;
     const bool moments = c->flags & (CGD_FLAG_MOMENTS | CGD_FLAG_CUMULANTS);
     if (moments && (want_grad || c->prec != CGD_PREC_FP64))
         return fail(CGD_ERR_ARG, "CGD_FLAG_MOMENTS / CGD_FLAG_CUMULANTS need CGD_PREC_FP64 and no CGD_FLAG_GRAD");
+    if (dense)
+        for (int i = 0; i < n_inst; ++i)
+            if ((int64_t)inst[i].M * inst[i].K > 4096)
+                return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": M*K too large for CGD_FLAG_DENSE_INTERNAL");
     if (want_grad && dense)
         for (int i = 0; i < n_inst; ++i)
             if (inst[i].K > 1) return fail(CGD_ERR_ARG, "CGD_FLAG_GRAD works with internal-mode blocks (no CGD_FLAG_DENSE_INTERNAL)");
@@ -1511,6 +1591,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         InstOut &o = outs[i];
         cgd_status s = validate(in, i);
         if (s != CGD_OK) return s;
+        if (in.distinguishable && want_grad)
+            return fail(CGD_ERR_ARG, "instance " + std::to_string(i) + ": distinguishable inputs do not support CGD_FLAG_GRAD");
         HostInst &hi = hinst[i];
         hi.L = in.L;
         hi.nvar = 2 * (int)kept_fine_modes(in).size();
@@ -1528,10 +1610,15 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
                 hi.G[l] = std::max(kMomentPoints, 2 * (in.cutoff[l] + 1));
             }
         }
-        // per internal mode squeezing: tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j
+        // per internal mode squeezing: tanh^2 r_jk = (lambda_k / lambda_0) tanh^2 r_j;
+        // fully distinguishable inputs (App. D): r_jk = r_j delta_jk
         std::vector<std::vector<double>> rk(in.M, std::vector<double>(in.K));
         for (int j = 0; j < in.M; ++j)
             for (int k = 0; k < in.K; ++k) {
+                if (in.distinguishable) {
+                    rk[j][k] = j == k ? in.r[j] : 0.0;
+                    continue;
+                }
                 const double ratio = in.K == 1 ? 1.0 : in.schmidt[k] / in.schmidt[0];
                 const double t = std::sqrt(ratio) * std::tanh(in.r[j]);
                 if (!(t < 1.0)) return fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(i) + ": Schmidt weights");
@@ -1555,12 +1642,12 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             std::vector<int> ks(in.K);
             for (int k = 0; k < in.K; ++k) ks[k] = k;
             s = assemble_block(in, i, ks, in.K > 1, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr,
-                               moments);
+                               moments, lowrank_ok);
             if (s != CGD_OK) return s;
         } else {
             for (int k = 0; k < in.K; ++k) {
                 s = assemble_block(in, i, {k}, false, use_schur, rk, hi, o.blocks, want_grad ? &o.grads : nullptr,
-                                   moments);
+                                   moments, lowrank_ok);
                 if (s != CGD_OK) return s;
             }
         }
@@ -1758,6 +1845,18 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
         d.nb = h.nb;
         d.bordered = h.bordered;
         d.nkeep = h.nkeep;
+        if (h.lowrank) {
+            // no factorisation: its (L + 1) r x r matrices to the pool, its points to lowrank_points
+            d.lowrank = h.lowrank;
+            d.fp32 = 0;
+            d.schur_axis = -1;
+            d.lr_off = (int64_t)pool.size();
+            for (const cplx &z : h.lr) pool.push_back(make_double2(z.real(), z.imag()));
+            c->lowrank_jobs.push_back((int32_t)b);
+            c->lowrank_prefix.push_back(c->lowrank_items);
+            c->lowrank_items += I0.npts;
+            continue;
+        }
         if (h.nkeep) {
             if (d.cls >= kRegClasses)
                 return fail(CGD_ERR_ARG, "instance " + std::to_string(h.inst) + ": a block with kept modes has order " +
@@ -2031,6 +2130,8 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     }
     if ((s = upload(&c->d_rb, rbpool)) != CGD_OK) return s;
     if ((s = upload(&c->d_eig, eigpool)) != CGD_OK) return s;
+    if ((s = upload(&c->d_lowrank_jobs, c->lowrank_jobs)) != CGD_OK) return s;
+    if ((s = upload(&c->d_lowrank_prefix, c->lowrank_prefix)) != CGD_OK) return s;
     for (auto &st : c->stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
@@ -2105,7 +2206,8 @@ cgd_status cgd_create(cgd_ctx **out, const cgd_instance *inst, int32_t n_inst, c
     if (prec != CGD_PREC_FP64 && prec != CGD_PREC_MIXED) return fail(CGD_ERR_ARG, "unknown precision");
     if (prec == CGD_PREC_MIXED && !(tol > 0)) return fail(CGD_ERR_ARG, "mixed precision needs tol > 0");
     if (flags & ~(CGD_FLAG_DENSE_INTERNAL | CGD_FLAG_NO_SCHUR | CGD_FLAG_GRAD | CGD_FLAG_HESSENBERG |
-                  CGD_FLAG_NO_HESSENBERG | CGD_FLAG_NO_AUTOTUNE | CGD_FLAG_MOMENTS | CGD_FLAG_CUMULANTS))
+                  CGD_FLAG_NO_HESSENBERG | CGD_FLAG_NO_AUTOTUNE | CGD_FLAG_MOMENTS | CGD_FLAG_CUMULANTS |
+                  CGD_FLAG_NO_LOWRANK))
         return fail(CGD_ERR_ARG, "unknown flags");
     if ((flags & CGD_FLAG_MOMENTS) && (flags & CGD_FLAG_CUMULANTS))
         return fail(CGD_ERR_ARG, "CGD_FLAG_MOMENTS and CGD_FLAG_CUMULANTS together");
@@ -2237,6 +2339,14 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         return k < kRegClasses ? launch_lu_reg(k, c->reg_var[k], a, st)
                                : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
     };
+    if (c->lowrank_items > 0) {
+        // low-rank blocks: FP64 in both paths, no second pass
+        HIP_OK(mark_begin(lu_stage(0)));
+        HIP_OK(launch_lowrank_points(c->d_lowrank_jobs, c->d_lowrank_prefix, (int)c->lowrank_jobs.size(),
+                                     c->lowrank_items, c->d_blocks, c->d_inst, c->d_pool, c->d_tw, b.contrib,
+                                     c->d_status, st));
+        HIP_OK(mark(lu_stage(0), 1));
+    }
     if (mixed)
         for (auto &g : c->g32) {
             if (g.nitems == 0) continue;
@@ -2517,7 +2627,7 @@ cgd_status cgd_set_kernel_shape(cgd_ctx *c, int32_t size_class, int32_t fp64_sha
     bool keeps = false, fp32 = false;
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         const BlockDev &d = c->blocks[b];
-        if (c->is_hess[b] || d.cls != k) continue;
+        if (c->is_hess[b] || d.lowrank || d.cls != k) continue;
         keeps |= d.nkeep > 0;
         fp32 |= d.fp32 && mfma_class_of(d.nb) == k;
     }

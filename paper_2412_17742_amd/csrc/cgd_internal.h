@@ -61,7 +61,12 @@ struct BlockDev {
     int32_t pad;
     int64_t t_off;            // density mode: trailing Schur complement (nkeep + bordered)^2 per point
     int64_t kv_off;           // density mode: nkeep generating-function variable indices (in rbpool)
+    int32_t lowrank;          // > 0: low-rank block of that rank (no factorisation; lowrank_points)
+    int32_t pad2;
+    int64_t lr_off;           // its (L + 1) r x r matrices G_t, G_0 .. G_{L-1} in the pool
 };
+
+constexpr int kLowRankMax = 4;  // largest rank taken by the low-rank route (two squeezed inputs)
 
 // Build of the Schur matrices C(w_A) = H_BB + P diag(w_A / (1 - w_A lambda)) Q
 // for every value k of the eliminated bin A (P = H_BA V, Q = V^H H_AB with
@@ -186,6 +191,10 @@ int reg_variants(int cls);
 int reg_kernel_variants(int cls);      // the first ones: register-kernel shapes (density mode needs one)
 const char *reg_variant_name(int cls, int v);
 hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st);
+// low-rank blocks: per (block, point) the r x r determinant det(I - G_t - sum_l w_l G_l)
+hipError_t launch_lowrank_points(const int32_t *jobs, const int64_t *prefix, int njobs, int64_t nitems,
+                                 const BlockDev *blocks, const InstDev *insts, const double2 *pool,
+                                 const double2 *tw, double2 *contrib, int *status, hipStream_t st);
 // FP64 factorisations of order <= 16 (range launches): lu_mfma_f64<1,1,1>
 hipError_t launch_lu_one_tile(const LuLaunch &a, hipStream_t st);
 constexpr int kMfmaClasses = 6;

@@ -3096,6 +3096,104 @@ static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Kernel R: low-rank blocks (fully distinguishable inputs, App. D).  When H =
+// V diag(lambda) V^H has rank r <= kLowRankMax, det(I - D H) = det(I_r - C)
+// with C = G_t + sum_l w_l G_l (Sylvester), the r x r matrices G_g =
+// diag(lambda) V^H E_g V coming from the host.  One thread per (block, point):
+// C from (L + 1) r^2 complex multiply-adds, then the unpivoted LU of I_r - C
+// in registers.  With s = sign(lambda), I_r - C is the diagonal similarity
+// transform (by |lambda|^1/2) of I_r - s |lambda|^1/2 V^H D V |lambda|^1/2,
+// whose second term has norm at most ||H|| max|w| < 1: it is accretive, and
+// a diagonal similarity keeps every principal minor, so the pivots lie in the
+// right half-plane and the sum of their principal logarithms is the
+// continuous branch, exactly as for S itself.  Two pivots of the right
+// half-plane have a product whose argument stays inside (-pi, pi), so the
+// logarithms are taken pairwise.
+template <int R>
+__device__ __forceinline__ double2 lowrank_logdet(const InstDev &I, const double2 *__restrict__ G, int64_t pt,
+                                                  const double2 *__restrict__ tw, bool &bad) {
+    double2 m[R][R];
+    #pragma unroll
+    for (int a = 0; a < R; ++a)
+        #pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const double2 g = G[a * R + c];
+            m[a][c] = cmk((a == c ? 1.0 : 0.0) - g.x, -g.y);
+        }
+    for (int l = 0; l < I.L; ++l) {
+        double2 w;
+        point_w(I, pt, l, w, tw);
+        const double2 *__restrict__ Gl = G + (l + 1) * R * R;
+        #pragma unroll
+        for (int a = 0; a < R; ++a)
+            #pragma unroll
+            for (int c = 0; c < R; ++c) m[a][c] = cfnms(m[a][c], w, Gl[a * R + c]);
+    }
+    double2 acc = cmk(0.0, 0.0), held = cmk(1.0, 0.0);
+    #pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const double2 p = m[k][k];
+        if (!(p.x > 0.0) || !isfinite(p.x) || !isfinite(p.y)) bad = true;
+        if (k % 2 == 0) {
+            held = p;
+        } else {
+            const double2 q = clog(cmul(held, p));
+            acc.x += q.x;
+            acc.y += q.y;
+        }
+        if (k + 1 < R) {
+            const double2 pinv = cinv(p);
+            #pragma unroll
+            for (int i = k + 1; i < R; ++i) {
+                const double2 li = cmul(m[i][k], pinv);
+                #pragma unroll
+                for (int j = k + 1; j < R; ++j) m[i][j] = cfnms(m[i][j], li, m[k][j]);
+            }
+        }
+    }
+    if (R % 2 == 1) {
+        const double2 q = clog(held);
+        acc.x += q.x;
+        acc.y += q.y;
+    }
+    return acc;
+}
+
+__global__ void __launch_bounds__(256) lowrank_points(const int32_t *__restrict__ jobs, const int64_t *__restrict__ prefix,
+                                                      int njobs, int64_t nitems, const BlockDev *__restrict__ blocks,
+                                                      const InstDev *__restrict__ insts, const double2 *__restrict__ pool,
+                                                      const double2 *__restrict__ tw, double2 *__restrict__ contrib,
+                                                      int *__restrict__ status) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= nitems) return;
+    const int j = find_job(prefix, njobs, item);
+    const BlockDev &B = blocks[jobs[j]];
+    const InstDev &I = insts[B.inst];
+    const int64_t pt = item - prefix[j];
+    const double2 *__restrict__ G = pool + B.lr_off;
+    bool bad = false;
+    double2 acc;
+    switch (B.lowrank) {
+        case 1: acc = lowrank_logdet<1>(I, G, pt, tw, bad); break;
+        case 2: acc = lowrank_logdet<2>(I, G, pt, tw, bad); break;
+        case 3: acc = lowrank_logdet<3>(I, G, pt, tw, bad); break;
+        default: acc = lowrank_logdet<4>(I, G, pt, tw, bad); break;
+    }
+    contrib[I.c_off + pt * I.nblocks + B.blk] = cmk(-0.5 * acc.x, -0.5 * acc.y);
+    if (bad) atomicOr(status, 1);
+}
+
+hipError_t launch_lowrank_points(const int32_t *jobs, const int64_t *prefix, int njobs, int64_t nitems,
+                                 const BlockDev *blocks, const InstDev *insts, const double2 *pool,
+                                 const double2 *tw, double2 *contrib, int *status, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (njobs <= 0 || jobs == nullptr || prefix == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lowrank_points, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, st, jobs, prefix,
+                       njobs, nitems, blocks, insts, pool, tw, contrib, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_lu_one_tile(const LuLaunch &a, hipStream_t st) {
     if (a.list || a.nitems <= 0) return a.list ? hipErrorInvalidValue : hipSuccess;
     return launch_mfma64<1, 1, 1>(a, st);

@@ -1,6 +1,7 @@
 // Small dense complex linear algebra for the one-off FP64 state assembly on the
 // host (per instance, O(n^3) once; the per-grid-point work runs on the GPU).
 #pragma once
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -256,13 +257,21 @@ inline void hermitian_tridiag(const CMat &Ain, std::vector<double> &d, std::vect
 // rotations.  Returns false if an eigenvalue takes more than 60 iterations.
 inline bool tridiag_ql(std::vector<double> &d, std::vector<double> e, std::vector<double> *Z) {
     const int n = (int)d.size();
+    // a subdiagonal entry is negligible next to its two diagonal neighbours, or
+    // at rounding level of the matrix norm (half an ulp, as in EISPACK's tql2):
+    // rotations through the large eigenvalues keep about that much noise in the
+    // entries of a cluster of eigenvalues near zero (a matrix of low rank), which
+    // the relative test alone never accepts
+    double anorm = 0.0;
+    for (int i = 0; i < n; ++i) anorm = std::max(anorm, std::fabs(d[i]) + (i + 1 < n ? std::fabs(e[i]) : 0.0));
+    const double floor_e = 1.1102230246251565e-16 * anorm;
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         for (;;) {
             int m = l;
             for (; m + 1 < n; ++m) {
                 const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-16 * dd) break;
+                if (std::fabs(e[m]) <= 1e-16 * dd || std::fabs(e[m]) <= floor_e) break;
             }
             if (m == l) break;
             if (++iter > 60) return false;

@@ -111,3 +111,30 @@ def test_density_mode_arguments_are_checked_before_the_device():
 def test_set_kernel_shape_checks_its_arguments():
     L = cgd.lib()
     assert L.cgd_set_kernel_shape(None, 0, 0, -1) == cgd.CGD_ERR_ARG
+
+
+def test_distinguishable_instances_are_checked_before_the_device():
+    """Fully distinguishable inputs (App. D): K == M, no Schmidt weights, no
+    displacement, no gradient; an unknown flag bit is still refused."""
+    base = W.distinguishable_instance(4, 0, [2, 2], [3, 3])
+    assert W.n_internal(base) == 4 and base["distinguishable"] == 1
+    for mutate in [
+        lambda x: x.update(schmidt=np.full(4, 0.25)),
+        lambda x: x.update(alpha=np.full(4, 0.1 + 0.0j)),
+    ]:
+        x = dict(base)
+        mutate(x)
+        st, h, msg = _create(x)
+        assert st == cgd.CGD_ERR_ARG and "distinguishable" in msg, msg
+        assert h.value is None
+    keep = []
+    one = cgd._marshal(base, keep)
+    one.K = 3
+    arr = (cgd.CgdInstance * 1)(one)
+    h = ctypes.c_void_p()
+    assert cgd.lib().cgd_create(ctypes.byref(h), arr, 1, 0, 1e-9, 0, None) == cgd.CGD_ERR_ARG
+    assert "distinguishable" in cgd.lib().cgd_last_error().decode()
+    st, h, msg = _create(base, flags=cgd.FLAG_GRAD)
+    assert st == cgd.CGD_ERR_ARG and "distinguishable" in msg, msg
+    st, h, msg = _create(base, flags=1 << 9)
+    assert st == cgd.CGD_ERR_ARG and "flags" in msg, msg

@@ -229,7 +229,7 @@ def test_autotuner_report_and_choices():
                     if fast32:
                         _check_pick(f32, c["fp32_kernel"])
     with cgd.Context(insts, flags=cgd.FLAG_NO_AUTOTUNE) as ctx:
-        assert ctx.tuning() == {"autotune": False, "classes": []}
+        assert ctx.tuning() == {"autotune": False, "lowrank_blocks": 0, "classes": []}
     pm, errm, _, offs = _run(insts, "mixed", flags=cgd.FLAG_NO_HESSENBERG)
     p64, _, _, _ = _run(insts, "fp64", flags=cgd.FLAG_NO_HESSENBERG)
     d = _per_instance_maxdiff(pm, p64, offs)

@@ -53,13 +53,21 @@ def _hermitian(n, rng, kind):
         U = W.haar_unitary(m, rng)
         S = st.assemble(W.make_instance(np.sqrt(0.6) * U, rng.uniform(0.2, 1.0, m), bin_of=np.zeros(m), cutoff=[3]))
         return np.eye(2 * m) - np.linalg.inv(S["Sigma"])
+    if kind == "lowrank":  # the same with one squeezed input: rank 2, a cluster of n - 2 zeros
+        import workloads as W
+        from oracle import state as st
+        m = n // 2
+        r = np.zeros(m)
+        r[rng.integers(m)] = rng.uniform(0.4, 1.2)
+        S = st.assemble(W.make_instance(np.sqrt(0.3) * W.haar_unitary(m, rng), r, bin_of=np.zeros(m), cutoff=[3]))
+        return np.eye(2 * m) - np.linalg.inv(S["Sigma"])
     raise ValueError(kind)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 96])
-@pytest.mark.parametrize("kind", ["random", "degenerate", "diagonal", "state"])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 96, 288])
+@pytest.mark.parametrize("kind", ["random", "degenerate", "diagonal", "state", "lowrank"])
 def test_hermitian_eigensolver_matches_numpy(driver, n, kind):
-    if kind == "state" and n % 2:
+    if kind in ("state", "lowrank") and n % 2:
         pytest.skip("state matrices have even order")
     rng = np.random.default_rng(1000 * n + len(kind))
     A = _hermitian(n, rng, kind)
