@@ -176,9 +176,11 @@ typedef struct {
  * instance with one or two squeezed inputs has rank 2 or 4.  When the rank
  * r = 2q is at most 4 and at most half the block's order, the block has no
  * displacement, no kept mode and CGD_FLAG_GRAD is off, cgd_create writes
- * H = V diag(lambda) V^H over its r nonzero eigenvalues (it checks that the
- * others vanish, |lambda| <= 1e-13, else the block takes the general route)
- * and keeps the (L + 1) matrices G_g = diag(lambda) V^H E_g V of order r
+ * Sigma - I = Y C Y^H (Y: 2M x r from the squeezed inputs' columns of T, C:
+ * their sinh^2 and sinh cosh), takes H = V diag(lambda) V^H from the order-r
+ * matrix |Y| C |Y| (Woodbury; O(M r^2) work per block, no matrix of order 2M;
+ * a numerically rank-deficient Y sends the block to the general route) and
+ * keeps the (L + 1) matrices G_g = diag(lambda) V^H E_g V of order r
  * (E_g: the rows of bin g; one more for the traced rows).  Per grid point
  * det(I - D(w) H) = det(I_r - G_t - sum_l w_l G_l) (Sylvester's identity), an
  * r x r unpivoted LU in FP64 on both precision paths; the pivots lie in the

@@ -295,6 +295,153 @@ cgd_status validate(const cgd_instance &in, int idx) {
     return CGD_OK;
 }
 
+// Low-rank blocks.  With q squeezed inputs in internal mode k and no
+// displacement, Sigma - I = Y C Y^H (Sec. II moments): Y has the columns
+// a_j = (t_j, 0) and b_j = (0, conj t_j) for every squeezed input j (t_j:
+// column j of T) and C is block diagonal with [[sinh^2, sinh cosh], [sinh cosh,
+// sinh^2]] of r_jk per input.  H = I - Sigma^-1 then has rank r = 2q, and
+// with |Y| = (Y^H Y)^1/2 and Z = |Y| C |Y| = W diag(z) W^H (order r):
+//   H = V diag(z / (1 + z)) V^H,  V = Y |Y|^-1 W (orthonormal columns),
+//   log det Sigma = sum log(1 + z),  Sigma > I/2  <=>  z > -1/2,
+// and a bin's marginal Y_b C Y_b^H has the nonzero spectrum of |Y_b| C |Y_b|.
+// det(I - D H) = det(I_r - diag(lambda) V^H D V) (Sylvester), D constant over
+// the rows of a bin (1 on the traced rows), so per point the block's factor is
+// the r x r determinant of I - (G_t + sum_l w_l G_l), G_g = diag(lambda) V^H
+// E_g V (E_g: the rows of bin g, or the traced rows).  Everything here costs
+// O(M r^2): no matrix of order 2M is formed.  Returns false (nothing written)
+// when the block does not qualify or Y is numerically rank deficient.
+bool lowrank_block(const cgd_instance &in, int idx, int k, const std::vector<std::vector<double>> &rk,
+                   HostInst &hi, std::vector<HostBlock> &out, bool want_hnorm, cgd_status &st) {
+    st = CGD_OK;
+    const int M = in.M, n2 = 2 * M;
+    if (k == 0 && in.alpha)
+        for (int q = 0; q < M; ++q)
+            if (cx(in.alpha, q) != cplx(0, 0)) return false;
+    const std::vector<int> ks{k};
+    for (int i = 0; i < M; ++i)
+        if (bin_of_row(in, i, M, ks, false) == CGD_KEEP) return false;
+    std::vector<int> sq;
+    for (int q = 0; q < M; ++q)
+        if (rk[q][k] != 0.0) sq.push_back(q);
+    const int r = 2 * (int)sq.size();
+    if (r > kLowRankMax || 2 * r > n2) return false;
+    const int rr = std::max(r, 1);
+    HostBlock hb;
+    hb.inst = idx;
+    hb.blk = hi.nblocks;
+    hb.nb = 0;
+    hb.lowrank = rr;
+    hb.lr.assign((size_t)(in.L + 1) * rr * rr, cplx(0, 0));
+    if (r == 0) {  // vacuum in this internal mode: H = 0, factor 1
+        for (int l = 0; l < in.L; ++l) {
+            bool any = false;
+            for (int i = 0; i < M; ++i) any |= bin_of_row(in, i, M, ks, false) == l;
+            if (any) hi.marg[l].push_back(BinMarginal{});
+        }
+        hi.nblocks++;
+        out.push_back(std::move(hb));
+        return true;
+    }
+    CMat Y(n2, r), C(r, r);
+    for (size_t a = 0; a < sq.size(); ++a) {
+        const int q = sq[a];
+        for (int i = 0; i < M; ++i) {
+            const cplx t = cx(in.T, (size_t)i * M + q);
+            Y(i, 2 * a) = t;
+            Y(M + i, 2 * a + 1) = std::conj(t);
+        }
+        const double sh = std::sinh(rk[q][k]), ch = std::cosh(rk[q][k]);
+        C(2 * a, 2 * a) = C(2 * a + 1, 2 * a + 1) = sh * sh;
+        C(2 * a, 2 * a + 1) = C(2 * a + 1, 2 * a) = sh * ch;
+    }
+    // |Y_rows| for a set of rows (all, or one bin's): Gram^1/2 and, when asked, its inverse
+    auto abs_y = [&](const std::vector<int> &rows, CMat &S, CMat *Sinv) -> bool {
+        CMat Gm(r, r);
+        for (int i : rows)
+            for (int a = 0; a < r; ++a)
+                for (int b = 0; b < r; ++b) Gm(a, b) += std::conj(Y(i, a)) * Y(i, b);
+        std::vector<double> g;
+        CMat U;
+        if (!hermitian_eig_ql(Gm, g, U)) return false;
+        double gmax = 0.0, gmin = INFINITY;
+        for (double v : g) { gmax = std::max(gmax, v); gmin = std::min(gmin, v); }
+        if (Sinv && !(gmin > 1e-12 * gmax)) return false;
+        S = CMat(r, r);
+        if (Sinv) *Sinv = CMat(r, r);
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b)
+                for (int c2 = 0; c2 < r; ++c2) {
+                    const cplx u = U(a, c2) * std::conj(U(b, c2));
+                    S(a, b) += u * std::sqrt(std::max(g[c2], 0.0));
+                    if (Sinv) (*Sinv)(a, b) += u / std::sqrt(g[c2]);
+                }
+        return true;
+    };
+    auto sandwich = [&](const CMat &S) {  // S C S
+        CMat Z(r, r);
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b)
+                for (int c1 = 0; c1 < r; ++c1)
+                    for (int c2 = 0; c2 < r; ++c2) Z(a, b) += S(a, c1) * C(c1, c2) * S(c2, b);
+        return Z;
+    };
+    std::vector<int> all(n2);
+    for (int i = 0; i < n2; ++i) all[i] = i;
+    CMat S, Sinv, W;
+    if (!abs_y(all, S, &Sinv)) return false;
+    std::vector<double> z;
+    if (!hermitian_eig_ql(sandwich(S), z, W)) {
+        st = fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+        return true;
+    }
+    double ld = 0.0;
+    std::vector<double> lam(r);
+    for (int a = 0; a < r; ++a) {
+        if (!(z[a] > -0.5)) {
+            st = fail(CGD_ERR_NONPHYSICAL, "instance " + std::to_string(idx) + ": covariance violates Sigma > I/2");
+            return true;
+        }
+        ld += std::log1p(z[a]);
+        lam[a] = z[a] / (1.0 + z[a]);
+        if (want_hnorm) hi.hnorm = std::max(hi.hnorm, std::fabs(lam[a]));
+    }
+    hi.logpr0 += -0.5 * ld;  // Eq. vacuum_probability, no displacement
+    // marginal of every bin: a tridiagonal form of |Y_b| C |Y_b| (same nonzero spectrum)
+    for (int l = 0; l < in.L; ++l) {
+        std::vector<int> rows;
+        for (int i = 0; i < n2; ++i)
+            if (bin_of_row(in, i, M, ks, false) == l) rows.push_back(i);
+        if (rows.empty()) continue;
+        CMat Sb;
+        if (!abs_y(rows, Sb, nullptr)) {
+            st = fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
+            return true;
+        }
+        BinMarginal bm;
+        hermitian_tridiag(sandwich(Sb), bm.d, bm.e, nullptr);
+        hi.marg[l].push_back(std::move(bm));
+    }
+    // V = Y |Y|^-1 W, then G_g = diag(lambda) V^H E_g V
+    CMat P(r, r);
+    for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b)
+            for (int c2 = 0; c2 < r; ++c2) P(a, b) += Sinv(a, c2) * W(c2, b);
+    std::vector<cplx> v(r);
+    for (int i = 0; i < n2; ++i) {
+        for (int b = 0; b < r; ++b) {
+            v[b] = cplx(0, 0);
+            for (int a = 0; a < r; ++a) v[b] += Y(i, a) * P(a, b);
+        }
+        const int bn = bin_of_row(in, i, M, ks, false);
+        const int g = bn < 0 ? 0 : bn + 1;
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b) hb.lr[((size_t)g * rr + a) * rr + b] += lam[a] * std::conj(v[a]) * v[b];
+    }
+    hi.nblocks++;
+    out.push_back(std::move(hb));
+    return true;
+}
+
 // Assemble one internal-mode block (all K modes when dense) of instance `in`:
 // covariance matrix Sigma = I + [[N^T, M],[M^*, N]] (Sec. II), H = I - Sigma^-1,
 // gamma = X Sigma^-1 zbar, the vacuum-probability term, unmeasured modes
@@ -304,6 +451,10 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
                           bool use_schur, const std::vector<std::vector<double>> &rk, HostInst &hi,
                           std::vector<HostBlock> &out, std::vector<GradHost> *grads, bool want_hnorm,
                           bool lowrank_ok) {
+    if (lowrank_ok && kset.size() == 1 && grads == nullptr) {
+        cgd_status st = CGD_OK;
+        if (lowrank_block(in, idx, kset[0], rk, hi, out, want_hnorm, st)) return st;
+    }
     const int M = in.M;
     const int nk = (int)kset.size();
     const int m = M * nk;  // modes in this block
@@ -395,60 +546,6 @@ cgd_status assemble_block(const cgd_instance &in, int idx, const std::vector<int
     const double ld = logdet_hpd(Sig);
     if (!std::isfinite(ld)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": log det Sigma");
     hi.logpr0 += -0.5 * quad.real() - 0.5 * ld;  // Eq. vacuum_probability
-
-    // Low-rank blocks.  With q squeezed inputs in this internal mode, Sigma - I
-    // and so H = I - Sigma^-1 have rank at most 2q (every internal block of
-    // fully distinguishable inputs, App. D: rank 2).  With H = V diag(lambda)
-    // V^H over its r = 2q largest eigenvalues, det(I - D H) = det(I_r -
-    // diag(lambda) V^H D V) (Sylvester), and D is constant over the rows of a
-    // bin (1 on the traced rows), so per point the factor is the r x r
-    // determinant of I - (G_t + sum_l w_l G_l), G_g = diag(lambda) V^H E_g V
-    // (E_g: the rows of bin g, or the traced rows).  No matrix of order 2M
-    // is factorised per point.
-    if (lowrank_ok && kset.size() == 1 && !displaced && grads == nullptr) {
-        int nsq = 0;
-        for (int q = 0; q < M; ++q)
-            if (rk[q][kset[0]] != 0.0) ++nsq;
-        bool keeps = false;
-        for (int i = 0; i < n2; ++i)
-            if (bin_of_row(in, i, m, kset, dense) == CGD_KEEP) keeps = true;
-        const int r = 2 * nsq;
-        std::vector<double> lam;
-        std::vector<int> ord;
-        CMat V;
-        bool low = !keeps && r <= kLowRankMax && 2 * r <= n2;
-        if (low) {
-            CMat H(n2, n2);
-            for (int i = 0; i < n2; ++i)
-                for (int j = 0; j < n2; ++j) H(i, j) = (i == j ? 1.0 : 0.0) - Sinv(i, j);
-            if (!hermitian_eig_ql(H, lam, V)) return fail(CGD_ERR_NUMERIC, "instance " + std::to_string(idx) + ": eigensolver");
-            ord.resize(n2);
-            for (int a = 0; a < n2; ++a) ord[a] = a;
-            std::sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(lam[a]) > std::fabs(lam[b]); });
-            // the eigenvalues past the r-th vanish up to rounding; otherwise the general route
-            low = std::fabs(lam[ord[r]]) <= 1e-13;
-        }
-        if (low) {
-            HostBlock hb;
-            hb.inst = idx;
-            hb.blk = hi.nblocks;
-            hb.nb = 0;
-            hb.lowrank = std::max(r, 1);
-            const int rr = hb.lowrank;
-            hb.lr.assign((size_t)(in.L + 1) * rr * rr, cplx(0, 0));
-            for (int i = 0; i < n2; ++i) {
-                const int b = bin_of_row(in, i, m, kset, dense);
-                const int g = b < 0 ? 0 : b + 1;
-                for (int a = 0; a < r; ++a)
-                    for (int c2 = 0; c2 < r; ++c2)
-                        hb.lr[((size_t)g * rr + a) * rr + c2] +=
-                            lam[ord[a]] * std::conj(V(i, ord[a])) * V(i, ord[c2]);
-            }
-            hi.nblocks++;
-            out.push_back(std::move(hb));
-            return CGD_OK;
-        }
-    }
 
     // Bordered H' over the state rows srow (every row that is not kept): H,
     // column -X gamma = -Sigma^-1 zbar, row -gamma^T (last).  Density mode: the
