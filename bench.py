@@ -45,9 +45,26 @@ WORKLOADS = {
              lambda: [W.lossy_m16_k3()]),
     "uneven512": ("512 uneven instances: M~U{8..64}, K~U{1..4}, L~U{1..4}, cutoffs~U{4..12}", W.uneven_batch),
     "mesh32_k4": ("64 parameter sets: M=32, K=4, 2 bins of 16, cutoff 12 (256x256 complex per point)", W.mesh_batch),
+    "dist144_3bins": ("the gbs144_3bins circuit with its 144 inputs fully distinguishable (App. D, K=M=144): "
+                      "144 internal blocks of rank 2 per point (low-rank route), 3 bins of 48, cutoff 40, grid 41^3",
+                      lambda: [W.dist_m144()]),
 }
 # reported beside the main workload in the same JSON line
-EXTRA = ["gbs144_2bins", "gbs144_3bins", "lossy16_k3", "mesh32_k4"]
+EXTRA = ["gbs144_2bins", "gbs144_3bins", "lossy16_k3", "mesh32_k4", "dist144_3bins"]
+
+
+def lowrank_vs_factorisation(cgd, steps):
+    """dist144_3bins at cutoff 12 (13^3 grid): the low-rank route against the
+    general factorisation of the same 144 blocks of order 288 per point."""
+    insts = [W.dist_m144(12)]
+    out, probs = {"workload": "dist144_3bins at cutoff 12, grid 13^3"}, {}
+    for name, flags in (("lowrank", 0), ("factorised", cgd.FLAG_NO_LOWRANK)):
+        with cgd.Context(insts, flags=flags) as ctx:
+            out[name + "_ms"], _, p = run(ctx, steps, 1)
+            probs[name] = p.clone()
+            out["evaluated_points"] = ctx.n_points
+    out["max_abs_diff"] = float((probs["lowrank"] - probs["factorised"]).abs().max().item())
+    return out
 
 
 def recorded_traffic(kernel: str, workload: str):
@@ -448,6 +465,9 @@ def main():
             if name != args.workload:
                 out["other_workloads"][name] = extra_workload(cgd, name, args.steps, args.warmup, args.tol,
                                                               grad=name == "mesh32_k4")
+        if "dist144_3bins" in out["other_workloads"]:
+            out["other_workloads"]["dist144_3bins"]["vs_factorisation"] = lowrank_vs_factorisation(
+                cgd, max(2, args.steps // 4))
     if not args.no_extra:
         out["total_photon"] = total_photon_sweep(cgd, args.steps, args.warmup, args.tol)
         out["heralded_density"] = heralded_density(cgd, args.steps, args.warmup)

@@ -161,6 +161,14 @@ def gbs_m144(bins: int = 2) -> dict:
     return make_instance(np.sqrt(0.3) * U, r, bin_of=contiguous_bins([48, 48, 48]), cutoff=[40, 40, 40])
 
 
+def dist_m144(cutoff: int = 40) -> dict:
+    """The circuit and squeezers of gbs_m144(3) with the 144 inputs fully
+    distinguishable (App. D: input j in its own internal mode j, K = M = 144):
+    3 bins of 48, the given cutoff per bin."""
+    x = gbs_m144(3)
+    return make_instance(x["T"], x["r"], bin_of=x["bin_of"], cutoff=[cutoff] * 3, distinguishable=1)
+
+
 # --- total photon number of a GBS setup (the paper's Sec. VIII C) ----------
 
 # cutoffs N_max the paper uses for M = 16 .. 256 (Fig. total_probs_time_comparison)
