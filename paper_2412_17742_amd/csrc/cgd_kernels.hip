@@ -3110,9 +3110,17 @@ static hipError_t launch_mfma64(const LuLaunch &a, hipStream_t st) {
 // continuous branch, exactly as for S itself.  Two pivots of the right
 // half-plane have a product whose argument stays inside (-pi, pi), so the
 // logarithms are taken pairwise.
+//
+// A workgroup takes 16 blocks of one instance and a run of kLrRun tiles of 16
+// points: the blocks' G matrices and the run's values of w are staged in LDS
+// once, then lane t takes block t mod 16 of point t / 16 of each tile, so that
+// a wave writes four runs of 16 adjacent contribution slots and the chain of
+// descriptor loads is paid once per 16 x 16 kLrRun items.
+constexpr int kLrTile = 16;
+constexpr int kLrRun = 8;
+
 template <int R>
-__device__ __forceinline__ double2 lowrank_logdet(const InstDev &I, const double2 *__restrict__ G, int64_t pt,
-                                                  const double2 *__restrict__ tw, bool &bad) {
+__device__ __forceinline__ double2 lowrank_logdet(const double2 *G, const double2 *w, int L, bool &bad) {
     double2 m[R][R];
     #pragma unroll
     for (int a = 0; a < R; ++a)
@@ -3121,14 +3129,13 @@ __device__ __forceinline__ double2 lowrank_logdet(const InstDev &I, const double
             const double2 g = G[a * R + c];
             m[a][c] = cmk((a == c ? 1.0 : 0.0) - g.x, -g.y);
         }
-    for (int l = 0; l < I.L; ++l) {
-        double2 w;
-        point_w(I, pt, l, w, tw);
-        const double2 *__restrict__ Gl = G + (l + 1) * R * R;
+    for (int l = 0; l < L; ++l) {
+        const double2 wl = w[l];
+        const double2 *Gl = G + (l + 1) * R * R;
         #pragma unroll
         for (int a = 0; a < R; ++a)
             #pragma unroll
-            for (int c = 0; c < R; ++c) m[a][c] = cfnms(m[a][c], w, Gl[a * R + c]);
+            for (int c = 0; c < R; ++c) m[a][c] = cfnms(m[a][c], wl, Gl[a * R + c]);
     }
     double2 acc = cmk(0.0, 0.0), held = cmk(1.0, 0.0);
     #pragma unroll
@@ -3160,37 +3167,81 @@ __device__ __forceinline__ double2 lowrank_logdet(const InstDev &I, const double
     return acc;
 }
 
-__global__ void __launch_bounds__(256) lowrank_points(const int32_t *__restrict__ jobs, const int64_t *__restrict__ prefix,
-                                                      int njobs, int64_t nitems, const BlockDev *__restrict__ blocks,
-                                                      const InstDev *__restrict__ insts, const double2 *__restrict__ pool,
-                                                      const double2 *__restrict__ tw, double2 *__restrict__ contrib,
-                                                      int *__restrict__ status) {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= nitems) return;
-    const int j = find_job(prefix, njobs, item);
-    const BlockDev &B = blocks[jobs[j]];
-    const InstDev &I = insts[B.inst];
-    const int64_t pt = item - prefix[j];
-    const double2 *__restrict__ G = pool + B.lr_off;
-    bool bad = false;
-    double2 acc;
-    switch (B.lowrank) {
-        case 1: acc = lowrank_logdet<1>(I, G, pt, tw, bad); break;
-        case 2: acc = lowrank_logdet<2>(I, G, pt, tw, bad); break;
-        case 3: acc = lowrank_logdet<3>(I, G, pt, tw, bad); break;
-        default: acc = lowrank_logdet<4>(I, G, pt, tw, bad); break;
+__global__ void __launch_bounds__(kLrTile * kLrTile)
+lowrank_points(const int2 *__restrict__ jobs, const int64_t *__restrict__ prefix, int njobs,
+               const int32_t *__restrict__ lrblk, const BlockDev *__restrict__ blocks,
+               const InstDev *__restrict__ insts, const double2 *__restrict__ pool,
+               const double2 *__restrict__ tw, double2 *__restrict__ contrib, int *__restrict__ status,
+               int gstride, int wstride) {
+    extern __shared__ double2 s_lr[];
+    double2 *s_g = s_lr;                               // 16 blocks x gstride
+    double2 *s_w = s_lr + kLrTile * gstride;           // kLrRun x 16 points x wstride
+    // the tile (uniform over the workgroup): job j covers blocks lrblk[x .. x + y)
+    // of one instance, its tiles ordered (point run, block tile)
+    const int64_t tile = blockIdx.x;
+    const int j = find_job(prefix, njobs, tile);
+    const int2 jc = jobs[j];
+    const int nbt = (jc.y + kLrTile - 1) / kLrTile;
+    const int64_t local = tile - prefix[j];
+    const int64_t p0 = (local / nbt) * (kLrTile * kLrRun);
+    const int q0 = (int)(local % nbt) * kLrTile;
+    const InstDev &I = insts[blocks[lrblk[jc.x]].inst];
+    const int L = I.L;
+    const int64_t npts = I.npts;
+    const int t = threadIdx.x;
+    {
+        // 16 threads per block slot copy its (L + 1) r^2 matrices; then w of the run's points
+        const int slot = t / kLrTile, e0 = t % kLrTile;
+        if (q0 + slot < jc.y) {
+            const BlockDev &B = blocks[lrblk[jc.x + q0 + slot]];
+            const int n = (L + 1) * B.lowrank * B.lowrank;
+            for (int e = e0; e < n; e += kLrTile) s_g[slot * gstride + e] = pool[B.lr_off + e];
+        }
+        for (int e = t; e < kLrTile * kLrRun * L; e += kLrTile * kLrTile) {
+            const int ps = e / L, l = e - ps * L;
+            if (p0 + ps < npts) point_w(I, p0 + ps, l, s_w[ps * wstride + l], tw);
+        }
     }
-    contrib[I.c_off + pt * I.nblocks + B.blk] = cmk(-0.5 * acc.x, -0.5 * acc.y);
+    __syncthreads();
+    const int qs = t % kLrTile;
+    if (q0 + qs >= jc.y) return;
+    const BlockDev &B = blocks[lrblk[jc.x + q0 + qs]];
+    const int r = B.lowrank;
+    const int64_t slot_off = I.c_off + B.blk;
+    const double2 *G = s_g + qs * gstride;
+    bool bad = false;
+    for (int ps = t / kLrTile; ps < kLrTile * kLrRun; ps += kLrTile) {
+        const int64_t pt = p0 + ps;
+        if (pt >= npts) break;
+        const double2 *w = s_w + ps * wstride;
+        double2 acc;
+        switch (r) {
+            case 1: acc = lowrank_logdet<1>(G, w, L, bad); break;
+            case 2: acc = lowrank_logdet<2>(G, w, L, bad); break;
+            case 3: acc = lowrank_logdet<3>(G, w, L, bad); break;
+            default: acc = lowrank_logdet<4>(G, w, L, bad); break;
+        }
+        contrib[slot_off + pt * I.nblocks] = cmk(-0.5 * acc.x, -0.5 * acc.y);
+    }
     if (bad) atomicOr(status, 1);
 }
 
-hipError_t launch_lowrank_points(const int32_t *jobs, const int64_t *prefix, int njobs, int64_t nitems,
-                                 const BlockDev *blocks, const InstDev *insts, const double2 *pool,
-                                 const double2 *tw, double2 *contrib, int *status, hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
-    if (njobs <= 0 || jobs == nullptr || prefix == nullptr) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(lowrank_points, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, st, jobs, prefix,
-                       njobs, nitems, blocks, insts, pool, tw, contrib, status);
+size_t lowrank_lds_bytes(int gstride, int wstride) {
+    return sizeof(double2) * ((size_t)kLrTile * gstride + (size_t)kLrTile * kLrRun * wstride);
+}
+int lowrank_points_per_tile() { return kLrTile * kLrRun; }
+
+hipError_t launch_lowrank_points(const int2 *jobs, const int64_t *prefix, int njobs, int64_t ntiles,
+                                 const int32_t *lrblk, const BlockDev *blocks, const InstDev *insts,
+                                 const double2 *pool, const double2 *tw, double2 *contrib, int *status,
+                                 int gstride, int wstride, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    if (njobs <= 0 || jobs == nullptr || prefix == nullptr || lrblk == nullptr || ntiles > 0x7fffffff ||
+        gstride < 1 || gstride > (kMaxBins + 1) * kLowRankMax * kLowRankMax || wstride < 1 || wstride > kMaxBins)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lowrank_points, dim3((unsigned)ntiles), dim3(kLrTile * kLrTile),
+                       lowrank_lds_bytes(gstride, wstride), st, jobs, prefix, njobs, lrblk, blocks, insts, pool, tw,
+                       contrib, status, gstride, wstride);
     return hipGetLastError();
 }
 
