@@ -816,16 +816,20 @@ struct cgd_ctx {
     LuClass g64[kG64];
     LuClass g32[kMfmaClasses];
     LuClass g64one;  // FP64 blocks of order <= 16 (one tile) outside density mode: lu_mfma_f64<1,1,1>
-    // low-rank blocks: one job per instance, (first, count) into lowrank_blk;
-    // lowrank_prefix / lowrank_items count tiles of 16 blocks x 16 points
-    std::vector<int32_t> lowrank_blk;
-    std::vector<int2> lowrank_jobs;
-    std::vector<int64_t> lowrank_prefix;
-    int64_t lowrank_items = 0;
-    int lowrank_gstride = 1, lowrank_wstride = 1;  // LDS entries per block / per point
-    int32_t *d_lowrank_blk = nullptr;
-    int2 *d_lowrank_jobs = nullptr;
-    int64_t *d_lowrank_prefix = nullptr;
+    // low-rank blocks, one list per rank (a kernel instance each): one job per
+    // instance, (first, count) into blk; prefix / ntiles count tiles of 16
+    // blocks x a run of points
+    struct LowRankList {
+        std::vector<int32_t> blk;
+        std::vector<int2> jobs;
+        std::vector<int64_t> prefix;
+        int64_t ntiles = 0;
+        int gstride = 1, wstride = 1;  // LDS entries per block / per point
+        int32_t *d_blk = nullptr;
+        int2 *d_jobs = nullptr;
+        int64_t *d_prefix = nullptr;
+    } lowrank[kLowRankMax];
+    size_t lowrank_blocks = 0;
     int big_ldw = 0, big_nwg = 0;
     // Hessenberg route
     std::vector<char> is_hess;
@@ -937,7 +941,7 @@ void free_ctx(cgd_ctx *c) {
     fr(c->d_counts); fr(c->d_hist); fr(c->d_cut);
     for (auto &k : c->g64) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
     fr(c->g64one.d_jobs); fr(c->g64one.d_prefix); fr(c->g64one.d_hint);
-    fr(c->d_lowrank_blk); fr(c->d_lowrank_jobs); fr(c->d_lowrank_prefix);
+    for (auto &lr : c->lowrank) { fr(lr.d_blk); fr(lr.d_jobs); fr(lr.d_prefix); }
     for (auto &k : c->g32) { fr(k.d_jobs); fr(k.d_prefix); fr(k.d_hint); }
     for (auto &s : c->stages) { fr(s.d_desc); fr(s.d_prefix); fr(s.d_cdesc); fr(s.d_cprefix); }
     fr(c->d_tw);
@@ -1480,7 +1484,7 @@ cgd_status autotune(cgd_ctx *c) {
     for (int k = 0; k < kRegClasses; ++k) c->reg_var[k] = 0;
     for (int k = 0; k < kMfmaClasses; ++k) c->mfma_var[k] = 0;
     c->tau_scale.assign(c->blocks.size(), 1.0);
-    const std::string nlow = "\"lowrank_blocks\": " + std::to_string(c->lowrank_blk.size()) + ", ";
+    const std::string nlow = "\"lowrank_blocks\": " + std::to_string(c->lowrank_blocks) + ", ";
     if (c->flags & CGD_FLAG_NO_AUTOTUNE) {
         c->tune_json = "{\"autotune\": false, " + nlow + "\"classes\": []}";
         return make_lu_lists(c);
@@ -1954,10 +1958,12 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
             d.schur_axis = -1;
             d.lr_off = (int64_t)pool.size();
             for (const cplx &z : h.lr) pool.push_back(make_double2(z.real(), z.imag()));
-            if (c->lowrank_jobs.empty() || c->blocks[c->lowrank_blk[c->lowrank_jobs.back().x]].inst != h.inst)
-                c->lowrank_jobs.push_back(make_int2((int)c->lowrank_blk.size(), 0));
-            c->lowrank_blk.push_back((int32_t)b);
-            c->lowrank_jobs.back().y++;
+            auto &lr = c->lowrank[h.lowrank - 1];
+            if (lr.jobs.empty() || c->blocks[lr.blk[lr.jobs.back().x]].inst != h.inst)
+                lr.jobs.push_back(make_int2((int)lr.blk.size(), 0));
+            lr.blk.push_back((int32_t)b);
+            lr.jobs.back().y++;
+            c->lowrank_blocks++;
             continue;
         }
         if (h.nkeep) {
@@ -2233,20 +2239,20 @@ cgd_status build(cgd_ctx *c, const cgd_instance *inst, int32_t n_inst) {
     }
     if ((s = upload(&c->d_rb, rbpool)) != CGD_OK) return s;
     if ((s = upload(&c->d_eig, eigpool)) != CGD_OK) return s;
-    for (const int2 &j : c->lowrank_jobs) {  // tiles of 16 blocks x a run of points
-        c->lowrank_prefix.push_back(c->lowrank_items);
-        const InstDev &I = c->inst[c->blocks[c->lowrank_blk[j.x]].inst];
-        const int64_t run = lowrank_points_per_tile();
-        c->lowrank_items += ((I.npts + run - 1) / run) * ((j.y + 15) / 16);
-        c->lowrank_wstride = std::max(c->lowrank_wstride, I.L);
-        for (int q = 0; q < j.y; ++q) {
-            const int r = c->blocks[c->lowrank_blk[j.x + q]].lowrank;
-            c->lowrank_gstride = std::max(c->lowrank_gstride, (I.L + 1) * r * r);
+    for (int r = 1; r <= kLowRankMax; ++r) {
+        auto &lr = c->lowrank[r - 1];
+        for (const int2 &j : lr.jobs) {  // tiles of 16 blocks x a run of points
+            lr.prefix.push_back(lr.ntiles);
+            const InstDev &I = c->inst[c->blocks[lr.blk[j.x]].inst];
+            const int64_t run = lowrank_points_per_tile();
+            lr.ntiles += ((I.npts + run - 1) / run) * ((j.y + 15) / 16);
+            lr.wstride = std::max(lr.wstride, I.L);
+            lr.gstride = std::max(lr.gstride, (I.L + 1) * r * r);
         }
+        if ((s = upload(&lr.d_blk, lr.blk)) != CGD_OK) return s;
+        if ((s = upload(&lr.d_jobs, lr.jobs)) != CGD_OK) return s;
+        if ((s = upload(&lr.d_prefix, lr.prefix)) != CGD_OK) return s;
     }
-    if ((s = upload(&c->d_lowrank_blk, c->lowrank_blk)) != CGD_OK) return s;
-    if ((s = upload(&c->d_lowrank_jobs, c->lowrank_jobs)) != CGD_OK) return s;
-    if ((s = upload(&c->d_lowrank_prefix, c->lowrank_prefix)) != CGD_OK) return s;
     for (auto &st : c->stages) {
         if ((s = upload(&st.d_desc, st.desc)) != CGD_OK) return s;
         if ((s = upload(&st.d_prefix, st.prefix)) != CGD_OK) return s;
@@ -2454,12 +2460,16 @@ cgd_status enqueue_eval(cgd_ctx *c, hipStream_t st, double *d_probs, double *d_e
         return k < kRegClasses ? launch_lu_reg(k, c->reg_var[k], a, st)
                                : launch_lu_big(a, c->d_work, c->big_ldw, c->big_nwg, st);
     };
-    if (c->lowrank_items > 0) {
+    if (c->lowrank_blocks > 0) {
         // low-rank blocks: FP64 in both paths, no second pass
         HIP_OK(mark_begin(lu_stage(0)));
-        HIP_OK(launch_lowrank_points(c->d_lowrank_jobs, c->d_lowrank_prefix, (int)c->lowrank_jobs.size(),
-                                     c->lowrank_items, c->d_lowrank_blk, c->d_blocks, c->d_inst, c->d_pool, c->d_tw, b.contrib,
-                                     c->d_status, c->lowrank_gstride, c->lowrank_wstride, st));
+        for (int r = 1; r <= kLowRankMax; ++r) {
+            const auto &lr = c->lowrank[r - 1];
+            if (lr.ntiles == 0) continue;
+            HIP_OK(launch_lowrank_points(r, lr.d_jobs, lr.d_prefix, (int)lr.jobs.size(), lr.ntiles, lr.d_blk,
+                                         c->d_blocks, c->d_inst, c->d_pool, c->d_tw, b.contrib, c->d_status,
+                                         lr.gstride, lr.wstride, st));
+        }
         HIP_OK(mark(lu_stage(0), 1));
     }
     if (mixed)

@@ -191,11 +191,11 @@ int reg_variants(int cls);
 int reg_kernel_variants(int cls);      // the first ones: register-kernel shapes (density mode needs one)
 const char *reg_variant_name(int cls, int v);
 hipError_t launch_lu_reg(int cls, int v, const LuLaunch &a, hipStream_t st);
-// low-rank blocks: per (block, point) the r x r determinant det(I - G_t - sum_l w_l G_l);
-// job j covers blocks lrblk[jobs[j].x .. + jobs[j].y) of one instance, in tiles of
-// 16 blocks x lowrank_points_per_tile() points (prefix: tiles before job j; ntiles in
-// all); gstride >= (L + 1) r^2 and wstride >= L over every job
-hipError_t launch_lowrank_points(const int2 *jobs, const int64_t *prefix, int njobs, int64_t ntiles,
+// low-rank blocks of rank r (1..kLowRankMax): per (block, point) the r x r determinant
+// det(I - G_t - sum_l w_l G_l); job j covers blocks lrblk[jobs[j].x .. + jobs[j].y) of
+// one instance, in tiles of 16 blocks x lowrank_points_per_tile() points (prefix: tiles
+// before job j; ntiles in all); gstride >= (L + 1) r^2 and wstride >= L over every job
+hipError_t launch_lowrank_points(int r, const int2 *jobs, const int64_t *prefix, int njobs, int64_t ntiles,
                                  const int32_t *lrblk, const BlockDev *blocks, const InstDev *insts,
                                  const double2 *pool, const double2 *tw, double2 *contrib, int *status,
                                  int gstride, int wstride, hipStream_t st);

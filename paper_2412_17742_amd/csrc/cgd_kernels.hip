@@ -3167,6 +3167,7 @@ __device__ __forceinline__ double2 lowrank_logdet(const double2 *G, const double
     return acc;
 }
 
+template <int R>
 __global__ void __launch_bounds__(kLrTile * kLrTile)
 lowrank_points(const int2 *__restrict__ jobs, const int64_t *__restrict__ prefix, int njobs,
                const int32_t *__restrict__ lrblk, const BlockDev *__restrict__ blocks,
@@ -3194,7 +3195,7 @@ lowrank_points(const int2 *__restrict__ jobs, const int64_t *__restrict__ prefix
         const int slot = t / kLrTile, e0 = t % kLrTile;
         if (q0 + slot < jc.y) {
             const BlockDev &B = blocks[lrblk[jc.x + q0 + slot]];
-            const int n = (L + 1) * B.lowrank * B.lowrank;
+            const int n = (L + 1) * R * R;
             for (int e = e0; e < n; e += kLrTile) s_g[slot * gstride + e] = pool[B.lr_off + e];
         }
         for (int e = t; e < kLrTile * kLrRun * L; e += kLrTile * kLrTile) {
@@ -3206,7 +3207,6 @@ lowrank_points(const int2 *__restrict__ jobs, const int64_t *__restrict__ prefix
     const int qs = t % kLrTile;
     if (q0 + qs >= jc.y) return;
     const BlockDev &B = blocks[lrblk[jc.x + q0 + qs]];
-    const int r = B.lowrank;
     const int64_t slot_off = I.c_off + B.blk;
     const double2 *G = s_g + qs * gstride;
     bool bad = false;
@@ -3214,13 +3214,7 @@ lowrank_points(const int2 *__restrict__ jobs, const int64_t *__restrict__ prefix
         const int64_t pt = p0 + ps;
         if (pt >= npts) break;
         const double2 *w = s_w + ps * wstride;
-        double2 acc;
-        switch (r) {
-            case 1: acc = lowrank_logdet<1>(G, w, L, bad); break;
-            case 2: acc = lowrank_logdet<2>(G, w, L, bad); break;
-            case 3: acc = lowrank_logdet<3>(G, w, L, bad); break;
-            default: acc = lowrank_logdet<4>(G, w, L, bad); break;
-        }
+        const double2 acc = lowrank_logdet<R>(G, w, L, bad);
         contrib[slot_off + pt * I.nblocks] = cmk(-0.5 * acc.x, -0.5 * acc.y);
     }
     if (bad) atomicOr(status, 1);
@@ -3231,17 +3225,26 @@ size_t lowrank_lds_bytes(int gstride, int wstride) {
 }
 int lowrank_points_per_tile() { return kLrTile * kLrRun; }
 
-hipError_t launch_lowrank_points(const int2 *jobs, const int64_t *prefix, int njobs, int64_t ntiles,
+hipError_t launch_lowrank_points(int r, const int2 *jobs, const int64_t *prefix, int njobs, int64_t ntiles,
                                  const int32_t *lrblk, const BlockDev *blocks, const InstDev *insts,
                                  const double2 *pool, const double2 *tw, double2 *contrib, int *status,
                                  int gstride, int wstride, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (njobs <= 0 || jobs == nullptr || prefix == nullptr || lrblk == nullptr || ntiles > 0x7fffffff ||
-        gstride < 1 || gstride > (kMaxBins + 1) * kLowRankMax * kLowRankMax || wstride < 1 || wstride > kMaxBins)
+    if (r < 1 || r > kLowRankMax || njobs <= 0 || jobs == nullptr || prefix == nullptr || lrblk == nullptr ||
+        ntiles > 0x7fffffff || gstride < 1 || gstride > (kMaxBins + 1) * r * r || wstride < 1 || wstride > kMaxBins)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(lowrank_points, dim3((unsigned)ntiles), dim3(kLrTile * kLrTile),
-                       lowrank_lds_bytes(gstride, wstride), st, jobs, prefix, njobs, lrblk, blocks, insts, pool, tw,
-                       contrib, status, gstride, wstride);
+    const dim3 grid((unsigned)ntiles), block(kLrTile * kLrTile);
+    const size_t lds = lowrank_lds_bytes(gstride, wstride);
+    switch (r) {
+        case 1: hipLaunchKernelGGL(lowrank_points<1>, grid, block, lds, st, jobs, prefix, njobs, lrblk, blocks, insts,
+                                   pool, tw, contrib, status, gstride, wstride); break;
+        case 2: hipLaunchKernelGGL(lowrank_points<2>, grid, block, lds, st, jobs, prefix, njobs, lrblk, blocks, insts,
+                                   pool, tw, contrib, status, gstride, wstride); break;
+        case 3: hipLaunchKernelGGL(lowrank_points<3>, grid, block, lds, st, jobs, prefix, njobs, lrblk, blocks, insts,
+                                   pool, tw, contrib, status, gstride, wstride); break;
+        default: hipLaunchKernelGGL(lowrank_points<4>, grid, block, lds, st, jobs, prefix, njobs, lrblk, blocks, insts,
+                                    pool, tw, contrib, status, gstride, wstride); break;
+    }
     return hipGetLastError();
 }
 
