@@ -53,6 +53,25 @@ WORKLOADS = {
 EXTRA = ["gbs144_2bins", "gbs144_3bins", "lossy16_k3", "mesh32_k4", "dist144_3bins"]
 
 
+def lowrank_profile(cgd, steps, warmup):
+    """dist144_3bins on the low-rank route (FP64): time per evaluation, the
+    stages, and the low-rank kernel's rate against HBM: 16 B of contribution
+    written per (block, point), its only HBM traffic of any size (the blocks'
+    G matrices and w stay in LDS)."""
+    insts = [W.dist_m144()]
+    with cgd.Context(insts) as ctx:
+        ms, _, _ = run(ctx, steps, warmup)
+        stages = stage_profile(ctx, max(3, min(steps, 10)))
+        items = ctx.n_points * ctx.tuning()["lowrank_blocks"]  # one instance, every block low-rank
+    lr_ms = stages.get("lu_le32", 0.0)
+    out = {"workload": "dist144_3bins", "ms_per_step": ms, "stage_ms": stages, "block_points": items}
+    if lr_ms > 0:
+        gbs = 16.0 * items / (lr_ms * 1e-3) / 1e9
+        out["lowrank_points"] = {"ms": lr_ms, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
+    return out
+
+
 def lowrank_vs_factorisation(cgd, steps):
     """dist144_3bins at cutoff 12 (13^3 grid): the low-rank route against the
     general factorisation of the same 144 blocks of order 288 per point."""
@@ -336,7 +355,13 @@ def main():
                     help="paths to time (the JSON line needs both for the mixed-vs-FP64 check)")
     ap.add_argument("--heralded-density-only", action="store_true",
                     help="time only the heralded density-matrix workloads and print their JSON (for profiling)")
+    ap.add_argument("--lowrank-only", action="store_true",
+                    help="time only dist144_3bins on the low-rank route and print its JSON (for profiling)")
     args = ap.parse_args()
+    if args.lowrank_only:
+        import paper_2412_17742_amd as cgd
+        print(json.dumps(lowrank_profile(cgd, args.steps, args.warmup)), flush=True)
+        return
     if args.heralded_density_only:
         import paper_2412_17742_amd as cgd
         print(json.dumps(heralded_density(cgd, args.steps, args.warmup)), flush=True)
@@ -468,6 +493,8 @@ def main():
         if "dist144_3bins" in out["other_workloads"]:
             out["other_workloads"]["dist144_3bins"]["vs_factorisation"] = lowrank_vs_factorisation(
                 cgd, max(2, args.steps // 4))
+            out["other_workloads"]["dist144_3bins"]["lowrank_kernel"] = lowrank_profile(cgd, args.steps,
+                                                                                        args.warmup)
     if not args.no_extra:
         out["total_photon"] = total_photon_sweep(cgd, args.steps, args.warmup, args.tol)
         out["heralded_density"] = heralded_density(cgd, args.steps, args.warmup)
