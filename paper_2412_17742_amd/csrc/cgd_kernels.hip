@@ -569,6 +569,22 @@ __device__ __forceinline__ void group_reg_transpose(const f32x4 &in, float (&out
     swap16(a2, a3, out[2], out[3]);
 }
 
+// old with lane L replaced by the wave-uniform x: one v_writelane per 32 bits
+// with an immediate lane (the builtin form is turned into a select on a lane
+// mask, which costs a mask per lane kept in registers)
+template <int L> __device__ __forceinline__ unsigned write_lane_u(unsigned old, unsigned x) {
+    unsigned r;
+    asm("v_writelane_b32 %0, %1, %2" : "=v"(r) : "s"(x), "i"(L), "0"(old));
+    return r;
+}
+template <int L> __device__ __forceinline__ float write_lane(float old, float x) {
+    return __builtin_bit_cast(float, write_lane_u<L>(__builtin_bit_cast(unsigned, old), __builtin_bit_cast(unsigned, x)));
+}
+template <int L> __device__ __forceinline__ double write_lane(double old, double x) {
+    const uint2 o = __builtin_bit_cast(uint2, old), u = __builtin_bit_cast(uint2, x);
+    return __builtin_bit_cast(double, make_uint2(write_lane_u<L>(o.x, u.x), write_lane_u<L>(o.y, u.y)));
+}
+
 __device__ __forceinline__ float uniform_read(float x, int src_lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src_lane));
 }
@@ -631,19 +647,21 @@ __device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T 
 template <typename T, int... K>
 __device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &pvr, T &pvi, int kstop,
                                        std::integer_sequence<int, K...>) {
-    const int lane = g * 16 + c;
     T rowr, rowi;
     group_to_all_pair<0>(ar[0], ai[0], rowr, rowi);
     T pr = uniform_read(ar[0], 0), pi = uniform_read(ai[0], 0);
     pvr = pr;
     pvi = pi;
-    auto keep = [&](int k) {
-        if (lane == k) {
-            pvr = pr;
-            pvi = pi;
+    // pivot k (wave-uniform after its step) into lane k
+    auto keep = [&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (k < 16) {
+            pvr = write_lane<k>(pvr, pr);
+            pvi = write_lane<k>(pvi, pi);
         }
     };
-    ((K < kstop ? (gj_step<K>(ar, ai, g, c, rowr, rowi, pr, pi), keep(K + 1)) : void()), ...);
+    ((K < kstop ? (gj_step<K>(ar, ai, g, c, rowr, rowi, pr, pi), keep(std::integral_constant<int, K + 1>{}))
+                : void()), ...);
 }
 
 template <typename T, int NTILE, int WR, int WC>
