@@ -543,6 +543,24 @@ __device__ __forceinline__ void group_to_all_pair(double x, double y, double &ox
     oy = __builtin_bit_cast(double, b);
 }
 
+// The same broadcast (row G of 16 lanes to all four rows, lane c reading lane
+// 16 G + c) through ds_bpermute: one LDS-pipe instruction per 32 bits in place
+// of three lane swaps and their register copies on the VALU.
+template <int G> __device__ __forceinline__ unsigned group_bcast_u(unsigned x, int c) {
+    return (unsigned)__builtin_amdgcn_ds_bpermute((G * 16 + c) * 4, (int)x);
+}
+template <int G>
+__device__ __forceinline__ void group_bcast_pair(float x, float y, int c, float &ox, float &oy) {
+    ox = __builtin_bit_cast(float, group_bcast_u<G>(__builtin_bit_cast(unsigned, x), c));
+    oy = __builtin_bit_cast(float, group_bcast_u<G>(__builtin_bit_cast(unsigned, y), c));
+}
+template <int G>
+__device__ __forceinline__ void group_bcast_pair(double x, double y, int c, double &ox, double &oy) {
+    const uint2 u = __builtin_bit_cast(uint2, x), v = __builtin_bit_cast(uint2, y);
+    ox = __builtin_bit_cast(double, make_uint2(group_bcast_u<G>(u.x, c), group_bcast_u<G>(u.y, c)));
+    oy = __builtin_bit_cast(double, make_uint2(group_bcast_u<G>(v.x, c), group_bcast_u<G>(v.y, c)));
+}
+
 // 4 x 4 transpose between the lane group (lane / 16) and the register index:
 // out[s] in lane group g is in[g] of lane group s, same lane within the group.
 // v_permlane32_swap exchanges groups (2, 3) of its first operand with groups
@@ -627,7 +645,7 @@ __device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T 
     };
     if (K < 15) {
         upd(V1);  // row K+1 (on group G1) first
-        group_to_all_pair<G1>(ar[V1], ai[V1], rowr, rowi);
+        group_bcast_pair<G1>(ar[V1], ai[V1], c, rowr, rowi);
         pr = uniform_read(ar[V1], G1 * 16 + K + 1);
         pi = uniform_read(ai[V1], G1 * 16 + K + 1);
     }
@@ -648,7 +666,7 @@ template <typename T, int... K>
 __device__ __forceinline__ void gj_all(T (&ar)[4], T (&ai)[4], int g, int c, T &pvr, T &pvi, int kstop,
                                        std::integer_sequence<int, K...>) {
     T rowr, rowi;
-    group_to_all_pair<0>(ar[0], ai[0], rowr, rowi);
+    group_bcast_pair<0>(ar[0], ai[0], c, rowr, rowi);
     T pr = uniform_read(ar[0], 0), pi = uniform_read(ai[0], 0);
     pvr = pr;
     pvi = pi;
