@@ -512,40 +512,10 @@ __device__ __forceinline__ double row_bcast(double x) {  // one 64-bit DPP move 
     return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + K, 0xf, 0xf, true);
 }
 
-// 16-lane row G of a pair of registers (x, y) to all four rows of both, in
-// three lane swaps: the 32-lane swap of (x, y) gives (x0 x1 y0 y1) and
-// (x2 x3 y2 y3); the 16-lane swap of the half holding row G spreads it to
-// (xG xG yG yG); a last 32-lane swap separates (xG xG xG xG) and
-// (yG yG yG yG).  VALU only.
-template <int G> __device__ __forceinline__ void group_to_all_pair_u(unsigned x, unsigned y, unsigned &ox, unsigned &oy) {
-    const auto h = __builtin_amdgcn_permlane32_swap(x, y, false, false);
-    const unsigned z = (G < 2) ? h[0] : h[1];
-    const auto q = __builtin_amdgcn_permlane16_swap(z, z, false, false);
-    const unsigned t = (G & 1) ? q[1] : q[0];
-    const auto r = __builtin_amdgcn_permlane32_swap(t, t, false, false);
-    ox = r[0];
-    oy = r[1];
-}
-template <int G>
-__device__ __forceinline__ void group_to_all_pair(float x, float y, float &ox, float &oy) {
-    unsigned a, b;
-    group_to_all_pair_u<G>(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y), a, b);
-    ox = __builtin_bit_cast(float, a);
-    oy = __builtin_bit_cast(float, b);
-}
-template <int G>
-__device__ __forceinline__ void group_to_all_pair(double x, double y, double &ox, double &oy) {
-    const uint2 u = __builtin_bit_cast(uint2, x), v = __builtin_bit_cast(uint2, y);
-    uint2 a, b;
-    group_to_all_pair_u<G>(u.x, v.x, a.x, b.x);
-    group_to_all_pair_u<G>(u.y, v.y, a.y, b.y);
-    ox = __builtin_bit_cast(double, a);
-    oy = __builtin_bit_cast(double, b);
-}
-
-// The same broadcast (row G of 16 lanes to all four rows, lane c reading lane
-// 16 G + c) through ds_bpermute: one LDS-pipe instruction per 32 bits in place
-// of three lane swaps and their register copies on the VALU.
+// 16-lane row G of a pair of registers (x, y) to all four rows of both (lane
+// c of every row reads lane 16 G + c) through ds_bpermute: one LDS-pipe
+// instruction per 32 bits, off the VALU (three lane swaps and their register
+// copies did the same on the VALU at 172 more VALU instructions per wave).
 template <int G> __device__ __forceinline__ unsigned group_bcast_u(unsigned x, int c) {
     return (unsigned)__builtin_amdgcn_ds_bpermute((G * 16 + c) * 4, (int)x);
 }
@@ -618,9 +588,9 @@ __device__ __forceinline__ double uniform_read(double x, int src_lane) {
 // a[k][c] <- a[k][c]/p, a[r][k] <- -a[r][k]/p, a[k][k] <- 1/p and
 // a[r][c] <- a[r][c] - a[r][k] a[k][c]/p elsewhere.  After the 16 steps the
 // tile holds its inverse; p is the k-th pivot of the unpivoted LU.  Row k
-// (real and imaginary part together) reaches every lane by three lane swaps
-// and column k by DPP row_newbcast, all in VALU; each step updates row k+1 first, so that its
-// broadcast overlaps the rest.
+// reaches every lane group by ds_bpermute and column k every lane of its row
+// by DPP row_newbcast; each step updates row k+1 first, so that its broadcast
+// overlaps the rest of the step.
 template <int K, typename T>
 __device__ __forceinline__ void gj_step(T (&ar)[4], T (&ai)[4], int g, int c, T &rowr, T &rowi, T &pr, T &pi) {
     constexpr int KG = K >> 2, KV = K & 3;
