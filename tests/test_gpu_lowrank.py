@@ -165,3 +165,26 @@ def test_gbs144_distinguishable_every_grid_value_against_the_factorisation():
     assert na == 144 and nb == 0
     assert np.abs(np.exp(a) - np.exp(b)).max() <= TOL_FP64
     assert np.abs(a - b).max() <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lowrank_repeated_and_static_evaluations_are_bitwise_equal(precision):
+    """The low-rank launch inside the captured evaluation: replays of cgd_eval
+    and a cgd_eval_static call (no allocation) give the same bits, with a
+    factorised instance in the batch."""
+    import torch
+    cases = _cases()
+    insts = [cases["dist_m6_3bins"][0], cases["k1_two_squeezers_rank4"][0], W.plain_m4()]
+    _say("low-rank blocks: eval replays and eval_static,", precision)
+    with cgd.Context(insts, precision=precision, tol=1e-9, flags=cgd.FLAG_NO_AUTOTUNE) as ctx:
+        first = ctx.eval().clone()
+        for _ in range(3):
+            again = ctx.eval()
+            torch.cuda.synchronize()
+            assert torch.equal(again, first)
+        static = ctx.eval_static()
+        torch.cuda.synchronize()
+        assert torch.equal(static, first)
+        P = [x.cpu().numpy() for x in ctx.split(first)]
+    for x, p in zip(insts, P):
+        assert np.abs(p - pgf.wrapped_distribution(x)).max() <= (TOL_FP64 if precision == "fp64" else 1e-9)
