@@ -379,8 +379,8 @@ def main():
         print(json.dumps({"copy_bytes_per_call": n * 8, "calls": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU layout is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): sharding instances or grid "
+              "slabs over several GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -99,8 +99,9 @@ def distinguishable_instance(M, seed, bins, cutoff, grid=None, eta=0.6, r_range=
 
 
 # ---------------------------------------------------------------------------
-# The five benchmark workloads (shapes and distributions as specified for this
-# build; see the design doc for the input recipe).
+# The benchmark workloads: seeded synthetic inputs with the shapes and value
+# distributions of the paper's settings (lossy interferometers, Schmidt
+# modes, GBS scale, uneven batches, parameter meshes).
 # ---------------------------------------------------------------------------
 
 def plain_m4(grid=None) -> dict:
