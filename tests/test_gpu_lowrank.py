@@ -16,6 +16,7 @@ import pytest
 
 import paper_2412_17742_amd as cgd
 import workloads as W
+from oracle import moments as om
 from oracle import pgf
 from oracle import state as st
 
@@ -188,3 +189,22 @@ def test_lowrank_repeated_and_static_evaluations_are_bitwise_equal(precision):
         P = [x.cpu().numpy() for x in ctx.split(first)]
     for x, p in zip(insts, P):
         assert np.abs(p - pgf.wrapped_distribution(x)).max() <= (TOL_FP64 if precision == "fp64" else 1e-9)
+
+
+@pytest.mark.parametrize("M, bins", [(4, [2, 2]), (5, [2, 2, 1])])
+def test_distinguishable_cumulants_and_moments_against_the_series(M, bins):
+    """Joint moments and cumulants of fully distinguishable inputs (App. D, row
+    f4) on the low-rank route against the oracle's series of log M (Eq. M), at
+    the moments tests' relative bar."""
+    import torch
+    x = W.distinguishable_instance(M, 5 + M, bins, list(bins))
+    x["grid"] = None
+    ref = om.cumulants_series(x, x["cutoff"])
+    _say("distinguishable cumulants and moments, M =", M)
+    for flag, want in ((cgd.FLAG_CUMULANTS, ref), (cgd.FLAG_MOMENTS, om.moments_from_cumulants(ref))):
+        with cgd.Context([x], flags=flag) as ctx:
+            got = ctx.split(ctx.eval())[0].cpu().numpy().copy()
+            torch.cuda.synchronize()
+            assert ctx.tuning()["lowrank_blocks"] == M
+        err = np.abs(got - want) / np.maximum(1.0, np.abs(want))
+        assert err.max() <= 1e-9, (flag, err.max())
